@@ -1,0 +1,315 @@
+"""Python binding of libacp.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module converts torch
+tensors (device memory, column-major views) and numpy arrays (host memory) to
+the plain pointers of the C ABI declared in include/acp.h, and turns status
+codes into exceptions.  There is no fallback: if the library is missing or the
+device is not a GPU, calls fail loudly.
+
+Column-major convention: a matrix with m rows and n columns is a torch tensor
+of shape (m, n) and strides (1, m).  ``colmajor(t)`` produces one.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libacp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "acp.h")
+
+ACP_OK, ACP_EINVAL, ACP_ENOMEM, ACP_EDEVICE, ACP_ENOCONV, ACP_ENOTSPD, ACP_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "ACP_OK", -1: "ACP_EINVAL", -2: "ACP_ENOMEM", -3: "ACP_EDEVICE",
+                -4: "ACP_ENOCONV", -5: "ACP_ENOTSPD", -6: "ACP_ESTATE"}
+PREC_FP64, PREC_FP32_REFINE = 0, 1
+SOLVER_CG, SOLVER_MINRES = 0, 1
+NODES_CHEBYSHEV, NODES_OCCUPIED = 0, 1
+
+
+class ACPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class AcpGrid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 2), ("h", C.c_double), ("kappa", C.c_double),
+                ("eps0", C.c_double), ("occ", C.c_double)]
+
+
+class AcpOpts(C.Structure):
+    _fields_ = [("n_cheb", C.c_int), ("n_mu", C.c_int), ("sketch_r", C.c_int),
+                ("isdf_tol", C.c_double), ("node_mode", C.c_int), ("tol", C.c_double),
+                ("max_iter", C.c_int), ("solver", C.c_int), ("precision", C.c_int),
+                ("dyson_max_iter", C.c_int), ("dyson_tol", C.c_double),
+                ("inner_tol", C.c_double)]
+
+
+class AcpStats(C.Structure):
+    _fields_ = [("systems_solved", C.c_int64), ("system_iterations", C.c_int64),
+                ("tile_iterations", C.c_int64), ("iters_min", C.c_int), ("iters_max", C.c_int),
+                ("max_rel_residual", C.c_double), ("dyson_iters", C.c_int),
+                ("refinements", C.c_int), ("ms_isdf", C.c_double), ("ms_rhs", C.c_double),
+                ("ms_solve", C.c_double), ("ms_w", C.c_double), ("ms_dyson_small", C.c_double),
+                ("ms_dynmat", C.c_double), ("ms_solve_kernel", C.c_double),
+                ("solve_kernel_launches", C.c_int64), ("d_asymmetry", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libacp.so (torch is imported first so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    I = C.c_int
+    sig = {
+        "acp_default_opts": (None, [C.POINTER(AcpOpts)]),
+        "acp_version": (C.c_char_p, []),
+        "acp_setup": (I, [C.POINTER(P), C.POINTER(AcpGrid), C.POINTER(AcpOpts), P, P, I, P, P]),
+        "acp_set_opts": (I, [P, C.POINTER(AcpOpts)]),
+        "acp_apply_h": (I, [P, P, I, P, P]),
+        "acp_apply_vc": (I, [P, I, P, P]),
+        "acp_apply_vc_inv": (I, [P, I, P, P]),
+        "acp_sternheimer": (I, [P, P, I, P, P, P]),
+        "acp_compress": (I, [P, P, I, P, P, P]),
+        "acp_compress_get": (I, [P, I, P, P]),
+        "acp_apply_chi0": (I, [P, P, I, P]),
+        "acp_dyson": (I, [P, P, I, P, P, P, P, P]),
+        "acp_dynmat": (I, [P, P, P, I, P, P, P, P]),
+        "acp_get_stats": (I, [P, C.POINTER(AcpStats)]),
+        "acp_reset_stats": (None, [P]),
+        "acp_last_error": (C.c_char_p, [P]),
+        "acp_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols(path: str = HEADER) -> list:
+    """Entry points declared in include/acp.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(acp_[a-z0-9_]+)\s*\(", text)))
+
+
+def colmajor(t):
+    """Same values, column-major storage (strides (1, m)) for a 2-D tensor."""
+    if t.dim() == 1:
+        return t.contiguous()
+    if t.stride(0) == 1 and t.stride(1) == t.shape[0]:
+        return t
+    return t.t().contiguous().t()
+
+
+def _dptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ACPError(ACP_EINVAL, "device argument must be a torch tensor on a GPU")
+    if t.dtype != torch.float64:
+        raise ACPError(ACP_EINVAL, "device argument must be float64")
+    return t.data_ptr()
+
+
+def _hostd(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _hptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+class Context:
+    """One acp_ctx: the occupied space of H[V_eff] on a grid, on one stream."""
+
+    def __init__(self, grid: dict, opts: dict, psi, eps, veff, stream=None):
+        import torch
+        self.lib = load_library()
+        self._ctx = C.c_void_p()
+        g = AcpGrid()
+        g.dim = int(grid["dim"])
+        n = list(grid["n"]) + [1]
+        g.n[0], g.n[1] = int(n[0]), int(n[1])
+        g.h, g.kappa, g.eps0, g.occ = (float(grid["h"]), float(grid["kappa"]),
+                                       float(grid["eps0"]), float(grid["occ"]))
+        self.grid = g
+        self.opts = self.make_opts(**opts)
+        self.psi = colmajor(psi)
+        self.veff = veff.contiguous()
+        self.eps = _hostd(eps)
+        self.n_g = self.psi.shape[0]
+        self.n_e = self.psi.shape[1]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        st = self.lib.acp_setup(C.byref(self._ctx), C.byref(g), C.byref(self.opts),
+                                _dptr(self.psi), _hptr(self.eps), self.n_e, _dptr(self.veff),
+                                C.c_void_p(stream.cuda_stream))
+        if st != ACP_OK:
+            msg = self.lib.acp_last_error(self._ctx).decode() if self._ctx else ""
+            self.lib.acp_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+            raise ACPError(st, msg)
+
+    # -- helpers --------------------------------------------------------------
+    def make_opts(self, **kw) -> AcpOpts:
+        o = AcpOpts()
+        self.lib.acp_default_opts(C.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        return o
+
+    def _check(self, st: int, allow=(ACP_OK,)):
+        if st not in allow:
+            raise ACPError(st, self.lib.acp_last_error(self._ctx).decode())
+        return st
+
+    def _empty(self, m, n):
+        import torch
+        return torch.empty((n, m), dtype=torch.float64, device=self.psi.device).t()
+
+    def set_opts(self, **kw):
+        self.opts = self.make_opts(**{**{f: getattr(self.opts, f) for f, _ in AcpOpts._fields_}, **kw})
+        self._check(self.lib.acp_set_opts(self._ctx, C.byref(self.opts)))
+
+    # -- entry points -----------------------------------------------------------
+    def apply_h(self, X, shifts: Optional[Sequence[float]] = None):
+        X = colmajor(X)
+        Y = self._empty(*X.shape)
+        sh = None if shifts is None else _hostd(shifts)
+        self._check(self.lib.acp_apply_h(self._ctx, None if sh is None else _hptr(sh), X.shape[1],
+                                         _dptr(X), _dptr(Y)))
+        return Y
+
+    def apply_vc(self, X):
+        X = colmajor(X)
+        Y = self._empty(*X.shape)
+        self._check(self.lib.acp_apply_vc(self._ctx, X.shape[1], _dptr(X), _dptr(Y)))
+        return Y
+
+    def apply_vc_inv(self, X):
+        X = colmajor(X)
+        Y = self._empty(*X.shape)
+        self._check(self.lib.acp_apply_vc_inv(self._ctx, X.shape[1], _dptr(X), _dptr(Y)))
+        return Y
+
+    def sternheimer(self, shifts, B, allow_noconv=False):
+        B = colmajor(B)
+        n = B.shape[1]
+        sh = _hostd(shifts)
+        assert sh.shape == (n,)
+        X = self._empty(*B.shape)
+        iters = np.zeros(n, dtype=np.int32)
+        allow = (ACP_OK, ACP_ENOCONV) if allow_noconv else (ACP_OK,)
+        st = self._check(self.lib.acp_sternheimer(self._ctx, _hptr(sh), n, _dptr(B), _dptr(X),
+                                                  iters.ctypes.data), allow)
+        return X, iters, st
+
+    def compress(self, G, omega, sel_in=None):
+        G = colmajor(G)
+        omega = colmajor(omega)
+        n_mu = self.opts.n_mu
+        sel = np.zeros(n_mu, dtype=np.int32)
+        si = None
+        if sel_in is not None:
+            si = np.ascontiguousarray(np.asarray(sel_in, dtype=np.int32))
+        self._check(self.lib.acp_compress(self._ctx, _dptr(G), G.shape[1], _dptr(omega),
+                                          None if si is None else si.ctypes.data, sel.ctypes.data))
+        return sel
+
+    def compress_get(self, what: str):
+        idx = {"xi": 0, "rhs": 1, "w": 2, "z": 3}[what]
+        n_mu = self.opts.n_mu
+        nc = self.n_shifts()
+        cols = n_mu * nc if what == "z" else n_mu
+        out = self._empty(self.n_g, cols)
+        shifts = np.zeros(max(nc, 1))
+        self._check(self.lib.acp_compress_get(self._ctx, idx, _dptr(out), _hptr(shifts)))
+        return out
+
+    def shifts(self) -> np.ndarray:
+        nc = self.n_shifts()
+        out = np.zeros(nc)
+        self._check(self.lib.acp_compress_get(self._ctx, 0, None, _hptr(out)), (ACP_OK,))
+        return out
+
+    def n_shifts(self) -> int:
+        if self.opts.node_mode == NODES_OCCUPIED:
+            return len(np.unique(self.eps))
+        lo, hi = self.eps[0], self.eps[-1]
+        if self.opts.n_cheb == 1 or hi - lo <= 1e-14 * max(1.0, abs(lo)):
+            return 1
+        return self.opts.n_cheb
+
+    def apply_chi0(self, X):
+        X = colmajor(X)
+        Y = self._empty(*X.shape)
+        self._check(self.lib.acp_apply_chi0(self._ctx, _dptr(X), X.shape[1], _dptr(Y)))
+        return Y
+
+    def dyson(self, G, omega, sel_hist_in=None):
+        G = colmajor(G)
+        omega = colmajor(omega)
+        kmax, n_mu = self.opts.dyson_max_iter, self.opts.n_mu
+        hist = np.zeros((kmax, n_mu), dtype=np.int32)
+        hin = None
+        if sel_hist_in is not None:
+            hin = np.ascontiguousarray(np.asarray(sel_hist_in, dtype=np.int32).reshape(kmax, n_mu))
+        U = self._empty(*G.shape)
+        iters = C.c_int(0)
+        self._check(self.lib.acp_dyson(self._ctx, _dptr(G), G.shape[1], _dptr(omega),
+                                       None if hin is None else hin.ctypes.data,
+                                       hist.ctypes.data, _dptr(U), C.byref(iters)))
+        return U, iters.value, hist[: iters.value]
+
+    def dynmat(self, G, U=None, K_local=None, mass=None):
+        G = colmajor(G)
+        n_p = G.shape[1]
+        K = None if K_local is None else np.asfortranarray(np.asarray(K_local, dtype=np.float64))
+        m = None if mass is None else _hostd(mass)
+        D = np.zeros((n_p, n_p), order="F")
+        w2 = np.zeros(n_p)
+        Up = None if U is None else _dptr(colmajor(U))
+        self._check(self.lib.acp_dynmat(self._ctx, _dptr(G), Up, n_p,
+                                        None if K is None else K.ctypes.data,
+                                        None if m is None else _hptr(m), D.ctypes.data,
+                                        _hptr(w2)))
+        return D, w2
+
+    def stats(self) -> dict:
+        s = AcpStats()
+        self._check(self.lib.acp_get_stats(self._ctx, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in AcpStats._fields_}
+
+    def reset_stats(self):
+        self.lib.acp_reset_stats(self._ctx)
+
+    def close(self):
+        if self._ctx:
+            self.lib.acp_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,808 @@
+// Host orchestration behind the C ABI of include/acp.h.
+//
+// Order of work follows the paper: Alg. 3 (compression of chi0 for a given G)
+// inside Alg. 4 (adaptive compression of the Dyson equation), then the
+// dynamical matrix of Sec. 2.2.  Every arithmetic step on grid data runs in the
+// kernels of this directory; the host computes only the N_c Chebyshev shifts
+// and the N_c x N_e Lagrange weights (Sec. 3.1), sizes and launch bookkeeping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "acp_internal.h"
+
+using namespace acp;
+
+namespace acp {
+void *ensure(DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return b.p;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return nullptr;
+    }
+    b.bytes = bytes;
+    return b.p;
+}
+void release(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+}  // namespace acp
+
+struct acp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    acp_grid grid{};
+    acp_opts opts{};
+    GridDesc gd{};
+    int ng = 0, ne = 0, nep = 0;
+    std::vector<double> eps;
+    std::vector<double> nodes;      // shifts eps~_c
+    std::vector<double> lw;         // N_c x N_e Lagrange weights, row c contiguous
+    DevBuf phi_cm, phi_rm, veff, lw_dev;
+    bool vc_ready = false;
+    DevBuf fx, fy, svc;
+    bool have_chi0 = false;
+    int nmu = 0, nmu_pad = 0;
+    std::vector<int> sel_host;
+    DevBuf sel_dev, forced_dev, xi, rhs, z, w;
+    DevBuf u_last;
+    int u_np = 0;
+    DevBuf gt, lchol, diag, isdf_scratch, l11, linv, c1, bc, tmp1, tmp2, tmp3, shifts_dev;
+    DevBuf kx, kr, kpa, kpb, kw1, kw2, krhs, kiters, kresid, kflags, ktile;
+    DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm;
+    DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym;
+    acp_stats stats{};
+    std::string err;
+    hipEvent_t ev[8]{};
+};
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+acp_status fail(acp_ctx *ctx, acp_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+#define HIPCHK(x)                                                                             \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, ACP_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+#define ENSURE(buf, bytes)                                                                    \
+    do {                                                                                      \
+        if (!ensure((buf), (bytes))) return fail(ctx, ACP_ENOMEM, "device allocation failed"); \
+    } while (0)
+
+#define CHECK(st)                                                                             \
+    do {                                                                                      \
+        acp_status s_ = (st);                                                                 \
+        if (s_ != ACP_OK) return s_;                                                          \
+    } while (0)
+
+template <class T>
+T *dp(DevBuf &b) { return (T *)b.p; }
+
+// Sec. 3.1: eps~_c = (eps_1 + eps_Ne)/2 + (eps_1 - eps_Ne)/2 cos(pi (c - 1/2)/N_c) and
+// L_c(eps_i) = prod_{c' != c} (eps_i - eps~_c') / (eps~_c - eps~_c')  (Eq. (3.4)).
+void shifts_and_weights(const std::vector<double> &eps, int n_c, int mode,
+                        std::vector<double> &nodes, std::vector<double> &lw) {
+    const int ne = (int)eps.size();
+    const double lo = eps.front(), hi = eps.back();
+    nodes.clear();
+    if (mode == ACP_NODES_OCCUPIED) {
+        for (int i = 0; i < ne; ++i)
+            if (nodes.empty() || eps[i] != nodes.back()) nodes.push_back(eps[i]);
+    } else if (n_c == 1 || hi - lo <= 1e-14 * std::max(1.0, std::fabs(lo))) {
+        nodes.push_back(0.5 * (lo + hi));
+    } else {
+        for (int c = 1; c <= n_c; ++c)
+            nodes.push_back(0.5 * (lo + hi) + 0.5 * (lo - hi) * std::cos(kPi * (c - 0.5) / n_c));
+    }
+    const int nc = (int)nodes.size();
+    lw.assign((size_t)nc * ne, 1.0);
+    if (nc == 1) return;
+    for (int c = 0; c < nc; ++c)
+        for (int i = 0; i < ne; ++i) {
+            double v = 1.0;
+            for (int cp = 0; cp < nc; ++cp)
+                if (cp != c) v *= (eps[i] - nodes[cp]) / (nodes[c] - nodes[cp]);
+            lw[(size_t)c * ne + i] = v;
+        }
+}
+
+float event_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+}
+
+acp_status validate_opts(acp_ctx *ctx, const acp_opts *o) {
+    if (o->n_cheb < 1) return fail(ctx, ACP_EINVAL, "n_cheb must be >= 1");
+    if (o->sketch_r < 1) return fail(ctx, ACP_EINVAL, "sketch_r must be >= 1");
+    if (!(o->tol > 0.0)) return fail(ctx, ACP_EINVAL, "tol must be > 0");
+    if (o->max_iter < 1) return fail(ctx, ACP_EINVAL, "max_iter must be >= 1");
+    if (o->solver != ACP_SOLVER_CG && o->solver != ACP_SOLVER_MINRES)
+        return fail(ctx, ACP_EINVAL, "unknown solver");
+    if (o->precision != ACP_PREC_FP64 && o->precision != ACP_PREC_FP32_REFINE)
+        return fail(ctx, ACP_EINVAL, "unknown precision");
+    if (o->dyson_max_iter < 1) return fail(ctx, ACP_EINVAL, "dyson_max_iter must be >= 1");
+    if (o->node_mode != ACP_NODES_CHEBYSHEV && o->node_mode != ACP_NODES_OCCUPIED)
+        return fail(ctx, ACP_EINVAL, "unknown node_mode");
+    if (o->isdf_tol < 0.0) return fail(ctx, ACP_EINVAL, "isdf_tol must be >= 0");
+    return ACP_OK;
+}
+
+acp_status upload_weights(acp_ctx *ctx) {
+    shifts_and_weights(ctx->eps, ctx->opts.n_cheb, ctx->opts.node_mode, ctx->nodes, ctx->lw);
+    ENSURE(ctx->lw_dev, ctx->lw.size() * 8);
+    HIPCHK(hipMemcpyAsync(ctx->lw_dev.p, ctx->lw.data(), ctx->lw.size() * 8,
+                          hipMemcpyHostToDevice, ctx->stream));
+    return ACP_OK;
+}
+
+// v_c = (4 pi/eps0)(-Delta_h + kappa^2)^{-1} = F diag(S) F^T with F the tensor
+// product of real orthonormal Fourier bases (exact: the periodic FD Laplacian is
+// diagonal in that basis), applied as dense products on the matrix cores.
+acp_status vc_prepare(acp_ctx *ctx) {
+    if (ctx->vc_ready) return ACP_OK;
+    const int nx = ctx->gd.nx, ny = ctx->gd.ny;
+    ENSURE(ctx->fx, (size_t)nx * nx * 8);
+    HIPCHK(launch_fourier_basis(nx, dp<double>(ctx->fx), ctx->stream));
+    if (ny > 1) {
+        ENSURE(ctx->fy, (size_t)ny * ny * 8);
+        HIPCHK(launch_fourier_basis(ny, dp<double>(ctx->fy), ctx->stream));
+    }
+    ENSURE(ctx->svc, (size_t)ctx->ng * 8);
+    HIPCHK(launch_fourier_symbol(ctx->gd, ctx->grid.kappa, ctx->grid.eps0, dp<double>(ctx->svc),
+                                 ctx->stream));
+    ctx->vc_ready = true;
+    return ACP_OK;
+}
+
+acp_status vc_apply(acp_ctx *ctx, int n, const double *X, double *Y) {
+    CHECK(vc_prepare(ctx));
+    const int nx = ctx->gd.nx, ny = ctx->gd.ny, ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    ENSURE(ctx->tmp3, (size_t)ng * n * 8);
+    double *T = dp<double>(ctx->tmp3);
+    const double *Fx = dp<double>(ctx->fx);
+    // T = Fx^T X   (X viewed as nx x (ny n))
+    HIPCHK(gemm(Op::T, Op::N, nx, ny * n, nx, 1.0, Fx, nx, 0, X, nx, 0, 0.0, T, nx, 0, 1, s));
+    if (ny > 1) {
+        const double *Fy = dp<double>(ctx->fy);
+        HIPCHK(gemm(Op::N, Op::N, nx, ny, ny, 1.0, T, nx, ng, Fy, ny, 0, 0.0, Y, nx, ng, n, s));
+        HIPCHK(launch_mul_symbol(ng, n, dp<double>(ctx->svc), Y, s));
+        HIPCHK(gemm(Op::N, Op::T, nx, ny, ny, 1.0, Y, nx, ng, Fy, ny, 0, 0.0, T, nx, ng, n, s));
+    } else {
+        HIPCHK(launch_mul_symbol(ng, n, dp<double>(ctx->svc), T, s));
+    }
+    HIPCHK(gemm(Op::N, Op::N, nx, ny * n, nx, 1.0, Fx, nx, 0, T, nx, 0, 0.0, Y, nx, 0, 1, s));
+    return ACP_OK;
+}
+
+// Batched projected shifted solve on tiled right-hand sides already in ctx->krhs.
+acp_status solve_tiled(acp_ctx *ctx, int ntiles, int rhs_tiles, const double *shifts_dev,
+                       int *flags_or) {
+    const int ng = ctx->ng;
+    const size_t vbytes = (size_t)ntiles * ng * kTile * 8;
+    ENSURE(ctx->kx, vbytes);
+    ENSURE(ctx->kr, vbytes);
+    ENSURE(ctx->kpa, vbytes);
+    ENSURE(ctx->kpb, vbytes);
+    if (ctx->opts.solver == ACP_SOLVER_MINRES) {
+        ENSURE(ctx->kw1, vbytes);
+        ENSURE(ctx->kw2, vbytes);
+    }
+    const int ncols = ntiles * kTile;
+    ENSURE(ctx->kiters, (size_t)ncols * 4);
+    ENSURE(ctx->kresid, (size_t)ncols * 8);
+    ENSURE(ctx->kflags, (size_t)ncols * 4);
+    ENSURE(ctx->ktile, (size_t)ntiles * 4);
+    KrylovArgs a{};
+    a.g = ctx->gd;
+    a.ne = ctx->nep;
+    a.ntiles = ntiles;
+    a.rhs_tiles = rhs_tiles;
+    a.phi_rm = dp<double>(ctx->phi_rm);
+    a.phi_cm = dp<double>(ctx->phi_cm);
+    a.veff = dp<double>(ctx->veff);
+    a.shift = shifts_dev;
+    a.rhs = dp<double>(ctx->krhs);
+    a.x = dp<double>(ctx->kx);
+    a.r = dp<double>(ctx->kr);
+    a.pa = dp<double>(ctx->kpa);
+    a.pb = dp<double>(ctx->kpb);
+    a.w1 = dp<double>(ctx->kw1);
+    a.w2 = dp<double>(ctx->kw2);
+    a.iters = dp<int>(ctx->kiters);
+    a.resid = dp<double>(ctx->kresid);
+    a.flags = dp<int>(ctx->kflags);
+    a.tol = ctx->opts.tol;
+    a.max_iter = ctx->opts.max_iter;
+    a.tile_iters = dp<int>(ctx->ktile);
+    HIPCHK(hipEventRecord(ctx->ev[6], ctx->stream));
+    if (ctx->opts.solver == ACP_SOLVER_MINRES) {
+        HIPCHK(launch_minres_fp64(a, ctx->stream));
+    } else {
+        HIPCHK(launch_cg_fp64(a, ctx->stream));
+    }
+    HIPCHK(hipEventRecord(ctx->ev[7], ctx->stream));
+    std::vector<int> it(ncols), fl(ncols), ti(ntiles);
+    HIPCHK(hipMemcpyAsync(it.data(), a.iters, ncols * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(fl.data(), a.flags, ncols * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ti.data(), a.tile_iters, ntiles * 4, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->stats.ms_solve_kernel += event_ms(ctx->ev[6], ctx->ev[7]);
+    ctx->stats.solve_kernel_launches += 1;
+    int f = 0, imin = 1 << 30, imax = 0;
+    long long sum = 0;
+    for (int j = 0; j < ncols; ++j) {
+        f |= fl[j];
+        imin = std::min(imin, it[j]);
+        imax = std::max(imax, it[j]);
+        sum += it[j];
+    }
+    long long tsum = 0;
+    for (int t = 0; t < ntiles; ++t) tsum += ti[t];
+    ctx->stats.system_iterations += sum;
+    ctx->stats.tile_iterations += tsum;
+    ctx->stats.iters_min = imin;
+    ctx->stats.iters_max = imax;
+    *flags_or = f;
+    return ACP_OK;
+}
+
+// A X = Q (H - s_j) Q X for column-major X (n columns); result in Y.
+acp_status apply_operator(acp_ctx *ctx, int n, const double *shifts_dev, const double *X,
+                          double *Y) {
+    const int ng = ctx->ng, ne = ctx->ne;
+    hipStream_t s = ctx->stream;
+    ENSURE(ctx->tmp2, (size_t)ng * n * 8);
+    ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+    double *QX = dp<double>(ctx->tmp2), *C = dp<double>(ctx->c1);
+    const double *phi = dp<double>(ctx->phi_cm);
+    HIPCHK(gemm(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, 0, X, ng, 0, 0.0, C, ne, 0, 1, s));
+    HIPCHK(launch_scale_copy(ng, n, 1.0, X, ng, QX, ng, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, QX, ng, 0, 1, s));
+    HIPCHK(launch_stencil(ctx->gd, n, QX, ng, Y, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
+                          shifts_dev, s));
+    HIPCHK(gemm(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, 0, Y, ng, 0, 0.0, C, ne, 0, 1, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, Y, ng, 0, 1, s));
+    return ACP_OK;
+}
+
+// max_j ||B_j - A X_j|| / ||B_j||, FP64, from freshly recomputed residuals.
+acp_status true_residual(acp_ctx *ctx, int n, const double *shifts_dev, const double *B,
+                         const double *X, double *max_rel) {
+    const int ng = ctx->ng;
+    ENSURE(ctx->tmp1, (size_t)ng * n * 8);
+    CHECK(apply_operator(ctx, n, shifts_dev, X, dp<double>(ctx->tmp1)));
+    ENSURE(ctx->dy_norm, (size_t)2 * n * 8);
+    double *rn = dp<double>(ctx->dy_norm), *bn = rn + n;
+    HIPCHK(launch_col_diff_sqnorm(ng, n, B, ng, dp<double>(ctx->tmp1), ng, rn, ctx->stream));
+    HIPCHK(launch_col_sqnorm(ng, n, B, ng, bn, ctx->stream));
+    std::vector<double> h(2 * n);
+    HIPCHK(hipMemcpyAsync(h.data(), rn, 2 * n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double m = 0.0;
+    for (int j = 0; j < n; ++j)
+        if (h[n + j] > 0.0) m = std::max(m, std::sqrt(h[j] / h[n + j]));
+    *max_rel = m;
+    return ACP_OK;
+}
+
+acp_status flags_status(acp_ctx *ctx, int f) {
+    if (f & 2) return fail(ctx, ACP_ENOTSPD, "non-positive curvature in a shifted solve");
+    if (f & 1) return fail(ctx, ACP_ENOCONV, "a shifted solve reached max_iter");
+    return ACP_OK;
+}
+
+
+acp_status setup_impl(acp_ctx *ctx, const acp_grid *grid, const acp_opts *opts, const double *psi,
+                      const double *eps, int n_e, const double *veff, void *stream) {
+    if (grid->dim != 1 && grid->dim != 2) return fail(ctx, ACP_EINVAL, "dim must be 1 or 2");
+    if (grid->n[0] < 9 || (grid->dim == 2 && grid->n[1] < 9))
+        return fail(ctx, ACP_EINVAL, "need at least 9 points per axis");
+    if (!(grid->h > 0) || !(grid->kappa > 0) || !(grid->eps0 > 0) || !(grid->occ > 0))
+        return fail(ctx, ACP_EINVAL, "h, kappa, eps0, occ must be > 0");
+    ctx->grid = *grid;
+    ctx->gd.dim = grid->dim;
+    ctx->gd.nx = grid->n[0];
+    ctx->gd.ny = grid->dim == 2 ? grid->n[1] : 1;
+    ctx->gd.ng = ctx->gd.nx * ctx->gd.ny;
+    ctx->gd.h = grid->h;
+    ctx->ng = ctx->gd.ng;
+    if (n_e < 1 || n_e >= ctx->ng) return fail(ctx, ACP_EINVAL, "n_e out of range");
+    if (n_e > 256) return fail(ctx, ACP_EINVAL, "n_e > 256 is not supported by this build");
+    CHECK(validate_opts(ctx, opts));
+    ctx->opts = *opts;
+    ctx->ne = n_e;
+    ctx->nep = (n_e + 15) / 16 * 16;
+    ctx->eps.assign(eps, eps + n_e);
+    for (int i = 1; i < n_e; ++i)
+        if (!(ctx->eps[i] >= ctx->eps[i - 1])) return fail(ctx, ACP_EINVAL, "eps must be ascending");
+    HIPCHK(hipGetDevice(&ctx->device));
+    ctx->stream = (hipStream_t)stream;
+    for (auto &e : ctx->ev) HIPCHK(hipEventCreate(&e));
+    const int ng = ctx->ng, nep = ctx->nep;
+    hipStream_t s = ctx->stream;
+    ENSURE(ctx->phi_cm, (size_t)ng * nep * 8);
+    ENSURE(ctx->phi_rm, (size_t)ng * nep * 8);
+    ENSURE(ctx->veff, (size_t)ng * 8);
+    HIPCHK(hipMemsetAsync(ctx->phi_cm.p, 0, (size_t)ng * nep * 8, s));
+    HIPCHK(hipMemcpyAsync(ctx->phi_cm.p, psi, (size_t)ng * n_e * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_transpose(ng, nep, dp<double>(ctx->phi_cm), ng, dp<double>(ctx->phi_rm), nep, s));
+    HIPCHK(hipMemcpyAsync(ctx->veff.p, veff, (size_t)ng * 8, hipMemcpyDeviceToDevice, s));
+    // orthonormality: max |Psi^T Psi - I| <= 1e-10
+    ENSURE(ctx->c1, (size_t)n_e * n_e * 8);
+    ENSURE(ctx->dy_norm, 16);
+    HIPCHK(gemm(Op::T, Op::N, n_e, n_e, ng, 1.0, dp<double>(ctx->phi_cm), ng, 0,
+                dp<double>(ctx->phi_cm), ng, 0, 0.0, dp<double>(ctx->c1), n_e, 0, 1, s));
+    HIPCHK(launch_gram_check(n_e, 0, dp<double>(ctx->c1), dp<double>(ctx->dy_norm), s));
+    double dev = 0.0;
+    HIPCHK(hipMemcpyAsync(&dev, ctx->dy_norm.p, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(dev <= 1e-10)) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "psi is not orthonormal: max |Psi^T Psi - I| = %.3e", dev);
+        return fail(ctx, ACP_EINVAL, buf);
+    }
+    CHECK(upload_weights(ctx));
+    HIPCHK(hipStreamSynchronize(s));
+    return ACP_OK;
+}
+
+// Alg. 2 (sketched) for the columns of G: fills ctx->sel_dev / sel_host, ctx->xi.
+acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega,
+                     const int *sel_in) {
+    const int ng = ctx->ng, r = ctx->opts.sketch_r;
+    hipStream_t s = ctx->stream;
+    int nmu = ctx->opts.n_mu;
+    const int rank_bound = std::min(r * ctx->ne, ng);
+    if (nmu < 1 || nmu > rank_bound)
+        return fail(ctx, ACP_EINVAL, "n_mu must satisfy 1 <= n_mu <= min(r n_e, N_g)");
+    // G~ = G Omega
+    ENSURE(ctx->gt, (size_t)ng * r * 8);
+    HIPCHK(gemm(Op::N, Op::N, ng, r, n_p, 1.0, G, ng, 0, omega, n_p, 0, 0.0, dp<double>(ctx->gt),
+                ng, 0, 1, s));
+    ENSURE(ctx->lchol, (size_t)ng * nmu * 8);
+    ENSURE(ctx->diag, (size_t)ng * 8);
+    ENSURE(ctx->isdf_scratch, 64);
+    ENSURE(ctx->sel_dev, (size_t)nmu * 4);
+    const int *forced = nullptr;
+    if (sel_in) {
+        for (int k = 0; k < nmu; ++k)
+            if (sel_in[k] < 0 || sel_in[k] >= ng) return fail(ctx, ACP_EINVAL, "sel_in out of range");
+        ENSURE(ctx->forced_dev, (size_t)nmu * 4);
+        HIPCHK(hipMemcpyAsync(ctx->forced_dev.p, sel_in, (size_t)nmu * 4, hipMemcpyHostToDevice, s));
+        forced = dp<int>(ctx->forced_dev);
+    }
+    int got = 0;
+    HIPCHK(isdf_pivoted_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), ng, dp<double>(ctx->gt),
+                                 ng, nmu, sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol),
+                                 ng, dp<double>(ctx->diag), dp<int>(ctx->sel_dev), forced, &got,
+                                 ctx->isdf_scratch.p, s));
+    if (got < 1) return fail(ctx, ACP_EINVAL, "interpolative decomposition found no pivot");
+    if (sel_in && got < nmu)
+        return fail(ctx, ACP_EINVAL, "forced selection is rank deficient or repeats a point");
+    nmu = got;
+    ctx->nmu = nmu;
+    ctx->nmu_pad = (nmu + kTile - 1) / kTile * kTile;
+    ctx->sel_host.resize(nmu);
+    HIPCHK(hipMemcpyAsync(ctx->sel_host.data(), ctx->sel_dev.p, (size_t)nmu * 4,
+                          hipMemcpyDeviceToHost, s));
+    // Xi = L L11^{-1}, Xi(Pi, :) = I
+    ENSURE(ctx->l11, (size_t)nmu * nmu * 8);
+    ENSURE(ctx->linv, (size_t)nmu * nmu * 8);
+    HIPCHK(launch_gather_lower(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->lchol), ng,
+                               dp<double>(ctx->l11), s));
+    HIPCHK(launch_tri_inverse_lower(nmu, dp<double>(ctx->l11), nmu, dp<double>(ctx->linv), s));
+    ENSURE(ctx->xi, (size_t)ng * nmu * 8);
+    HIPCHK(gemm(Op::N, Op::N, ng, nmu, nmu, 1.0, dp<double>(ctx->lchol), ng, 0,
+                dp<double>(ctx->linv), nmu, 0, 0.0, dp<double>(ctx->xi), ng, 0, 1, s));
+    HIPCHK(launch_scatter_identity(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->xi), ng, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ACP_OK;
+}
+
+// Alg. 3 steps 2-3 given ctx->xi: right-hand sides, the N_c N_mu shifted
+// solves, and W of Eq. (3.7).
+acp_status solve_and_assemble(acp_ctx *ctx) {
+    const int ng = ctx->ng, ne = ctx->ne, nmu = ctx->nmu, nmp = ctx->nmu_pad;
+    const int nc = (int)ctx->nodes.size();
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipEventRecord(ctx->ev[1], s));
+    // R = -Q Xi = Phi (Phi^T Xi) - Xi
+    ENSURE(ctx->rhs, (size_t)ng * nmu * 8);
+    ENSURE(ctx->c1, (size_t)ctx->nep * nmu * 8);
+    double *R = dp<double>(ctx->rhs), *C = dp<double>(ctx->c1);
+    const double *phi = dp<double>(ctx->phi_cm);
+    HIPCHK(gemm(Op::T, Op::N, ne, nmu, ng, 1.0, phi, ng, 0, dp<double>(ctx->xi), ng, 0, 0.0, C, ne,
+                0, 1, s));
+    HIPCHK(launch_scale_copy(ng, nmu, -1.0, dp<double>(ctx->xi), ng, R, ng, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, nmu, ne, 1.0, phi, ng, 0, C, ne, 0, 1.0, R, ng, 0, 1, s));
+    HIPCHK(hipEventRecord(ctx->ev[2], s));
+    // tiled right-hand sides (one copy, shared by every shift) and per-column shifts
+    const int rhs_tiles = nmp / kTile;
+    const int ntiles = rhs_tiles * nc;
+    ENSURE(ctx->krhs, (size_t)rhs_tiles * ng * kTile * 8);
+    HIPCHK(launch_to_tiled(ng, nmu, nmp, R, ng, dp<double>(ctx->krhs), s));
+    std::vector<double> sh((size_t)ntiles * kTile);
+    for (int c = 0; c < nc; ++c)
+        for (int j = 0; j < nmp; ++j) sh[(size_t)c * nmp + j] = ctx->nodes[c];
+    ENSURE(ctx->shifts_dev, sh.size() * 8);
+    HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, sh.data(), sh.size() * 8, hipMemcpyHostToDevice, s));
+    int flags = 0;
+    CHECK(solve_tiled(ctx, ntiles, rhs_tiles, dp<double>(ctx->shifts_dev), &flags));
+    ctx->stats.systems_solved += (long long)nc * nmu;
+    // Z (column-major, block c = shift c)
+    ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
+    double *Z = dp<double>(ctx->z);
+    for (int c = 0; c < nc; ++c)
+        HIPCHK(launch_from_tiled(ng, nmu, dp<double>(ctx->kx) + (size_t)c * rhs_tiles * ng * kTile,
+                                 Z + (size_t)c * nmu * ng, ng, s));
+    HIPCHK(hipEventRecord(ctx->ev[3], s));
+    // W = (2 f / h^d) sum_c Z_c o (Phi diag(L_c) Phi(Pi,:)^T)
+    ENSURE(ctx->w, (size_t)ng * nmu * 8);
+    ENSURE(ctx->bc, (size_t)ne * nmu * 8);
+    double *W = dp<double>(ctx->w);
+    HIPCHK(hipMemsetAsync(W, 0, (size_t)ng * nmu * 8, s));
+    const double pref = 2.0 * ctx->grid.occ / std::pow(ctx->grid.h, ctx->grid.dim);
+    for (int c = 0; c < nc; ++c) {
+        HIPCHK(launch_weighted_rows(ne, nmu, dp<double>(ctx->lw_dev) + (size_t)c * ne,
+                                    dp<int>(ctx->sel_dev), phi, ng, dp<double>(ctx->bc), s));
+        HIPCHK(gemm(Op::N, Op::N, ng, nmu, ne, pref, phi, ng, 0, dp<double>(ctx->bc), ne, 0, 0.0, W,
+                    ng, 0, 1, s, Epi::HadamardAcc, Z + (size_t)c * nmu * ng, ng, 0));
+    }
+    HIPCHK(hipEventRecord(ctx->ev[4], s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->stats.ms_rhs += event_ms(ctx->ev[1], ctx->ev[2]);
+    ctx->stats.ms_solve += event_ms(ctx->ev[2], ctx->ev[3]);
+    ctx->stats.ms_w += event_ms(ctx->ev[3], ctx->ev[4]);
+    // true residual of every system (FP64), reported in the statistics
+    {
+        const int ncols = nc * nmu;
+        ENSURE(ctx->tmp3, (size_t)ng * ncols * 8);
+        double *Bfull = dp<double>(ctx->tmp3);
+        std::vector<double> shc((size_t)ncols);
+        for (int c = 0; c < nc; ++c) {
+            HIPCHK(hipMemcpyAsync(Bfull + (size_t)c * nmu * ng, R, (size_t)ng * nmu * 8,
+                                  hipMemcpyDeviceToDevice, s));
+            for (int j = 0; j < nmu; ++j) shc[(size_t)c * nmu + j] = ctx->nodes[c];
+        }
+        DevBuf &shb = ctx->dy_s;
+        ENSURE(shb, shc.size() * 8);
+        HIPCHK(hipMemcpyAsync(shb.p, shc.data(), shc.size() * 8, hipMemcpyHostToDevice, s));
+        double mr = 0.0;
+        CHECK(true_residual(ctx, ncols, dp<double>(shb), Bfull, Z, &mr));
+        ctx->stats.max_rel_residual = mr;
+    }
+    ctx->have_chi0 = true;
+    return flags_status(ctx, flags);
+}
+
+acp_status compress_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega,
+                         const int *sel_in, int *sel_out) {
+    if (!G || !omega || n_p < 1) return fail(ctx, ACP_EINVAL, "G, omega, n_p");
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    CHECK(isdf_impl(ctx, G, n_p, omega, sel_in));
+    HIPCHK(hipEventRecord(ctx->ev[5], s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->stats.ms_isdf += event_ms(ctx->ev[0], ctx->ev[5]);
+    acp_status st = solve_and_assemble(ctx);
+    if (sel_out) std::memcpy(sel_out, ctx->sel_host.data(), (size_t)ctx->nmu * 4);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+void acp_default_opts(acp_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->n_cheb = 8;
+    o->n_mu = 0;
+    o->sketch_r = 8;
+    o->isdf_tol = 0.0;
+    o->node_mode = ACP_NODES_CHEBYSHEV;
+    o->tol = 1e-8;
+    o->max_iter = 2000;
+    o->solver = ACP_SOLVER_CG;
+    o->precision = ACP_PREC_FP64;
+    o->dyson_max_iter = 4;
+    o->dyson_tol = 0.0;
+    o->inner_tol = 1e-5;
+}
+
+const char *acp_version(void) { return "acp-gfx950 0.1"; }
+
+acp_status acp_setup(acp_ctx **out, const acp_grid *grid, const acp_opts *opts, const double *psi,
+                     const double *eps, int n_e, const double *veff, void *stream) {
+    if (!out) return ACP_EINVAL;
+    *out = nullptr;
+    acp_ctx *ctx = new (std::nothrow) acp_ctx();
+    if (!ctx) return ACP_ENOMEM;
+    *out = ctx;
+    if (!grid || !opts || !psi || !eps || !veff) return fail(ctx, ACP_EINVAL, "null argument");
+    return setup_impl(ctx, grid, opts, psi, eps, n_e, veff, stream);
+}
+
+acp_status acp_set_opts(acp_ctx *ctx, const acp_opts *opts) {
+    if (!ctx || !opts) return ACP_EINVAL;
+    CHECK(validate_opts(ctx, opts));
+    ctx->opts = *opts;
+    CHECK(upload_weights(ctx));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_apply_h(acp_ctx *ctx, const double *shift, int n, const double *X, double *Y) {
+    if (!ctx || !X || !Y || n < 0) return ACP_EINVAL;
+    if (n == 0) return ACP_OK;
+    const double *sd = nullptr;
+    if (shift) {
+        ENSURE(ctx->dy_s, (size_t)n * 8);
+        HIPCHK(hipMemcpyAsync(ctx->dy_s.p, shift, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+        sd = dp<double>(ctx->dy_s);
+    }
+    HIPCHK(launch_stencil(ctx->gd, n, X, ctx->ng, Y, ctx->ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
+                          sd, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_apply_vc(acp_ctx *ctx, int n, const double *X, double *Y) {
+    if (!ctx || !X || !Y || n < 0) return ACP_EINVAL;
+    if (n == 0) return ACP_OK;
+    CHECK(vc_apply(ctx, n, X, Y));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_apply_vc_inv(acp_ctx *ctx, int n, const double *X, double *Y) {
+    if (!ctx || !X || !Y || n < 0) return ACP_EINVAL;
+    if (n == 0) return ACP_OK;
+    const double a = ctx->grid.eps0 / (4.0 * kPi);
+    HIPCHK(launch_stencil(ctx->gd, n, X, ctx->ng, Y, ctx->ng, nullptr, -a,
+                          0.0, a * ctx->grid.kappa * ctx->grid.kappa, nullptr, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const double *B, double *X,
+                           int *iters) {
+    if (!ctx || !shift || !B || !X || n < 0) return ACP_EINVAL;
+    if (n == 0) return ACP_OK;
+    const int ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    const int ntiles = (n + kTile - 1) / kTile;
+    const int npad = ntiles * kTile;
+    ENSURE(ctx->krhs, (size_t)npad * ng * 8);
+    HIPCHK(launch_to_tiled(ng, n, npad, B, ng, dp<double>(ctx->krhs), s));
+    std::vector<double> sh(npad, shift[n - 1]);
+    for (int j = 0; j < n; ++j) sh[j] = shift[j];
+    ENSURE(ctx->shifts_dev, (size_t)npad * 8);
+    HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, sh.data(), (size_t)npad * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(ctx->ev[2], s));
+    int flags = 0;
+    CHECK(solve_tiled(ctx, ntiles, ntiles, dp<double>(ctx->shifts_dev), &flags));
+    HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), X, ng, s));
+    HIPCHK(hipEventRecord(ctx->ev[3], s));
+    if (iters) HIPCHK(hipMemcpyAsync(iters, ctx->kiters.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->stats.ms_solve += event_ms(ctx->ev[2], ctx->ev[3]);
+    ctx->stats.systems_solved += n;
+    double mr = 0.0;
+    CHECK(true_residual(ctx, n, dp<double>(ctx->shifts_dev), B, X, &mr));
+    ctx->stats.max_rel_residual = mr;
+    return flags_status(ctx, flags);
+}
+
+acp_status acp_compress(acp_ctx *ctx, const double *G, int n_p, const double *omega,
+                        const int *sel_in, int *sel_out) {
+    if (!ctx) return ACP_EINVAL;
+    return compress_impl(ctx, G, n_p, omega, sel_in, sel_out);
+}
+
+acp_status acp_compress_get(acp_ctx *ctx, int what, double *dst, double *shifts) {
+    if (!ctx) return ACP_EINVAL;
+    if (!ctx->have_chi0) return fail(ctx, ACP_ESTATE, "no compression yet");
+    const size_t ng = ctx->ng, nmu = ctx->nmu, nc = ctx->nodes.size();
+    if (shifts) std::memcpy(shifts, ctx->nodes.data(), nc * 8);
+    if (dst) {
+        const void *src = nullptr;
+        size_t bytes = ng * nmu * 8;
+        switch (what) {
+            case 0: src = ctx->xi.p; break;
+            case 1: src = ctx->rhs.p; break;
+            case 2: src = ctx->w.p; break;
+            case 3: src = ctx->z.p; bytes *= nc; break;
+            default: return fail(ctx, ACP_EINVAL, "unknown item");
+        }
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return ACP_OK;
+}
+
+acp_status acp_apply_chi0(acp_ctx *ctx, const double *X, int n, double *Y) {
+    if (!ctx || !X || !Y || n < 0) return ACP_EINVAL;
+    if (!ctx->have_chi0) return fail(ctx, ACP_ESTATE, "acp_apply_chi0 before acp_compress");
+    if (n == 0) return ACP_OK;
+    const int ng = ctx->ng, nmu = ctx->nmu;
+    hipStream_t s = ctx->stream;
+    ENSURE(ctx->tmp1, (size_t)nmu * n * 8);
+    HIPCHK(launch_gather_rows(nmu, n, dp<int>(ctx->sel_dev), X, ng, dp<double>(ctx->tmp1), nmu, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, n, nmu, 1.0, dp<double>(ctx->w), ng, 0, dp<double>(ctx->tmp1), nmu,
+                0, 0.0, Y, ng, 0, 1, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ACP_OK;
+}
+
+acp_status acp_dyson(acp_ctx *ctx, const double *G, int n_p, const double *omega,
+                     const int *sel_hist_in, int *sel_hist_out, double *U, int *iters_out) {
+    if (!ctx || !G || !omega || !U || n_p < 1) return ACP_EINVAL;
+    const int ng = ctx->ng;
+    const int kmax = ctx->opts.dyson_max_iter;
+    hipStream_t s = ctx->stream;
+    // G^k lives in dy_gk; iteration 0 compresses v_hxc U~^0 = v_c B = G itself.
+    ENSURE(ctx->dy_gk, (size_t)ng * n_p * 8);
+    ENSURE(ctx->u_last, (size_t)ng * n_p * 8);
+    double *Gk = dp<double>(ctx->dy_gk);
+    double *Uprev = dp<double>(ctx->u_last);
+    HIPCHK(hipMemcpyAsync(Gk, G, (size_t)ng * n_p * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(Uprev, 0, (size_t)ng * n_p * 8, s));
+    ctx->u_np = n_p;
+    acp_status last = ACP_OK;
+    int it = 0;
+    for (it = 1; it <= kmax; ++it) {
+        const int *forced = sel_hist_in ? sel_hist_in + (size_t)(it - 1) * ctx->opts.n_mu : nullptr;
+        acp_status st = compress_impl(ctx, Gk, n_p, omega, forced, nullptr);
+        if (st != ACP_OK && st != ACP_ENOCONV) return st;
+        if (st == ACP_ENOCONV) last = st;
+        if (sel_hist_out)
+            std::memcpy(sel_hist_out + (size_t)(it - 1) * ctx->opts.n_mu, ctx->sel_host.data(),
+                        (size_t)ctx->nmu * 4);
+        const int nmu = ctx->nmu;
+        HIPCHK(hipEventRecord(ctx->ev[0], s));
+        // V = v_c W
+        ENSURE(ctx->dy_v, (size_t)ng * nmu * 8);
+        double *V = dp<double>(ctx->dy_v);
+        CHECK(vc_apply(ctx, nmu, dp<double>(ctx->w), V));
+        // T = I - V(Pi, :),  S = G(Pi, :)
+        ENSURE(ctx->dy_t, (size_t)nmu * nmu * 8);
+        ENSURE(ctx->dy_g, (size_t)nmu * n_p * 8);
+        double *T = dp<double>(ctx->dy_t), *S = dp<double>(ctx->dy_g);
+        HIPCHK(launch_gather_rows(nmu, nmu, dp<int>(ctx->sel_dev), V, ng, T, nmu, s));
+        HIPCHK(launch_add_identity_neg(nmu, T, nmu, s));
+        HIPCHK(launch_gather_rows(nmu, n_p, dp<int>(ctx->sel_dev), G, ng, S, nmu, s));
+        HIPCHK(gauss_jordan_solve(nmu, n_p, T, nmu, S, nmu, nullptr, s));
+        // U^{k+1} = W S (into tmp1), G^{k+1} = G + V S
+        ENSURE(ctx->tmp1, (size_t)ng * n_p * 8);
+        double *Un = dp<double>(ctx->tmp1);
+        HIPCHK(gemm(Op::N, Op::N, ng, n_p, nmu, 1.0, dp<double>(ctx->w), ng, 0, S, nmu, 0, 0.0, Un,
+                    ng, 0, 1, s));
+        HIPCHK(hipMemcpyAsync(Gk, G, (size_t)ng * n_p * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(gemm(Op::N, Op::N, ng, n_p, nmu, 1.0, V, ng, 0, S, nmu, 0, 1.0, Gk, ng, 0, 1, s));
+        // relative change ||U^{k+1} - U^k|| / ||U^{k+1}||
+        ENSURE(ctx->dy_norm, 16);
+        HIPCHK(launch_diff_sqnorm(ng, n_p, Un, Uprev, ng, dp<double>(ctx->dy_norm), s));
+        HIPCHK(hipMemcpyAsync(Uprev, Un, (size_t)ng * n_p * 8, hipMemcpyDeviceToDevice, s));
+        double nrm[2];
+        HIPCHK(hipMemcpyAsync(nrm, ctx->dy_norm.p, 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ctx->ev[1], s));
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->stats.ms_dyson_small += event_ms(ctx->ev[0], ctx->ev[1]);
+        const double change = nrm[1] > 0 ? std::sqrt(nrm[0] / nrm[1]) : 0.0;
+        if (ctx->opts.dyson_tol > 0.0 && change <= ctx->opts.dyson_tol) {
+            ++it;
+            break;
+        }
+    }
+    const int done = std::min(it - 1, kmax);
+    ctx->stats.dyson_iters = done;
+    if (iters_out) *iters_out = done;
+    HIPCHK(hipMemcpyAsync(U, Uprev, (size_t)ng * n_p * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return last;
+}
+
+acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
+                      const double *K_local, const double *mass, double *D, double *omega2) {
+    if (!ctx || !G || n_p < 1 || !D || !omega2) return ACP_EINVAL;
+    if (!U) {
+        if (ctx->u_np != n_p || !ctx->u_last.p) return fail(ctx, ACP_ESTATE, "no Dyson result");
+        U = dp<double>(ctx->u_last);
+    }
+    if (n_p % ctx->grid.dim != 0) return fail(ctx, ACP_EINVAL, "n_p must be a multiple of dim");
+    const int ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    const size_t nn = (size_t)n_p * n_p;
+    ENSURE(ctx->dm_phi, nn * 8);
+    ENSURE(ctx->dm_d, nn * 8);
+    ENSURE(ctx->dm_eig, (size_t)n_p * 8);
+    ENSURE(ctx->dm_work, (size_t)(n_p + 2) * 16);
+    ENSURE(ctx->dm_asym, 16);
+    const double dv = std::pow(ctx->grid.h, ctx->grid.dim);
+    HIPCHK(gemm(Op::T, Op::N, n_p, n_p, ng, dv, G, ng, 0, U, ng, 0, 0.0, dp<double>(ctx->dm_phi), n_p,
+                0, 1, s));
+    const double *Kd = nullptr, *Md = nullptr;
+    if (K_local) {
+        ENSURE(ctx->dm_k, nn * 8);
+        HIPCHK(hipMemcpyAsync(ctx->dm_k.p, K_local, nn * 8, hipMemcpyHostToDevice, s));
+        Kd = dp<double>(ctx->dm_k);
+    }
+    if (mass) {
+        const int na = n_p / ctx->grid.dim;
+        for (int i = 0; i < na; ++i)
+            if (!(mass[i] > 0)) return fail(ctx, ACP_EINVAL, "masses must be > 0");
+        ENSURE(ctx->dm_mass, (size_t)na * 8);
+        HIPCHK(hipMemcpyAsync(ctx->dm_mass.p, mass, (size_t)na * 8, hipMemcpyHostToDevice, s));
+        Md = dp<double>(ctx->dm_mass);
+    }
+    HIPCHK(launch_dynmat_assemble(n_p, ctx->grid.dim, dp<double>(ctx->dm_phi), Kd, Md,
+                                  dp<double>(ctx->dm_d), dp<double>(ctx->dm_asym), s));
+    HIPCHK(hipMemcpyAsync(D, ctx->dm_d.p, nn * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(jacobi_eigvals(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig),
+                          dp<double>(ctx->dm_work), s));
+    HIPCHK(hipMemcpyAsync(omega2, ctx->dm_eig.p, (size_t)n_p * 8, hipMemcpyDeviceToHost, s));
+    double asym[2];
+    HIPCHK(hipMemcpyAsync(asym, ctx->dm_asym.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(ctx->ev[1], s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->stats.ms_dynmat += event_ms(ctx->ev[0], ctx->ev[1]);
+    ctx->stats.d_asymmetry = asym[1] > 0 ? std::sqrt(asym[0] / asym[1]) : 0.0;
+    return ACP_OK;
+}
+
+acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out) {
+    if (!ctx || !out) return ACP_EINVAL;
+    *out = ctx->stats;
+    return ACP_OK;
+}
+
+void acp_reset_stats(acp_ctx *ctx) {
+    if (ctx) ctx->stats = acp_stats{};
+}
+
+const char *acp_last_error(const acp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void acp_destroy(acp_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
+    DevBuf *bufs[] = {&ctx->phi_cm, &ctx->phi_rm, &ctx->veff, &ctx->lw_dev, &ctx->fx, &ctx->fy,
+                      &ctx->svc, &ctx->sel_dev, &ctx->forced_dev, &ctx->xi, &ctx->rhs, &ctx->z,
+                      &ctx->w, &ctx->u_last, &ctx->gt, &ctx->lchol, &ctx->diag,
+                      &ctx->isdf_scratch, &ctx->l11, &ctx->linv, &ctx->c1, &ctx->bc, &ctx->tmp1,
+                      &ctx->tmp2, &ctx->tmp3, &ctx->shifts_dev, &ctx->kx, &ctx->kr, &ctx->kpa,
+                      &ctx->kpb, &ctx->kw1, &ctx->kw2, &ctx->krhs, &ctx->kiters, &ctx->kresid,
+                      &ctx->kflags, &ctx->ktile, &ctx->dy_v, &ctx->dy_t, &ctx->dy_s, &ctx->dy_g,
+                      &ctx->dy_gk, &ctx->dy_norm, &ctx->dm_phi, &ctx->dm_k, &ctx->dm_mass,
+                      &ctx->dm_d, &ctx->dm_eig, &ctx->dm_work, &ctx->dm_asym};
+    for (DevBuf *b : bufs) release(*b);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+}  // extern "C"

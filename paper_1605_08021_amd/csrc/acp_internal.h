@@ -1,0 +1,141 @@
+// Internal declarations shared by the host orchestration and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/acp.h"
+
+namespace acp {
+
+// Column tile width of the Krylov layout: a tile holds 16 consecutive systems,
+// stored row-interleaved (element (row, col) at ((col/16) * N_g + row) * 16 + col%16),
+// so that one grid row of a tile is one 128-byte line.
+constexpr int kTile = 16;
+
+// 8th-order central coefficients of the second derivative, c_0 .. c_4:
+// u''(x) ~ h^-2 sum_{s=-4..4} c_|s| u(x + s h).
+__host__ __device__ constexpr double fd8(int k) {
+    return k == 0 ? -205.0 / 72.0
+         : k == 1 ? 8.0 / 5.0
+         : k == 2 ? -1.0 / 5.0
+         : k == 3 ? 8.0 / 315.0
+                  : -1.0 / 560.0;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Grow-only device buffer; returns nullptr on failure.
+void *ensure(DevBuf &b, size_t bytes);
+void release(DevBuf &b);
+
+struct GridDesc {
+    int dim;
+    int nx, ny;       // ny = 1 in 1D
+    int ng;
+    double h;
+};
+
+// ---------------------------------------------------------------- stencil (K1)
+// Y(:,j) = c_lap * Delta_h X(:,j) + (c_v * V + c_0 - shift[j]) X(:,j), column-major.
+hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, double *Y,
+                          int ldy, const double *V, double c_lap, double c_v, double c_0,
+                          const double *shift_dev, hipStream_t s);
+
+// ---------------------------------------------------------------- GEMM (FP64 MFMA)
+enum class Op { N, T };
+enum class Epi { Store, HadamardAcc };
+// C = alpha op(A) op(B) + beta C   (Store)
+// C += alpha (op(A) op(B)) o E     (HadamardAcc; beta ignored)
+// batched with strides sa, sb, sc, se (in elements).
+hipError_t gemm(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
+                long long sa, const double *B, int ldb, long long sb, double beta, double *C,
+                int ldc, long long sc, int batch, hipStream_t s, Epi epi = Epi::Store,
+                const double *E = nullptr, int lde = 0, long long se = 0);
+
+// ---------------------------------------------------------------- small utilities
+hipError_t launch_scale_copy(int m, int n, double alpha, const double *X, int ldx, double *Y,
+                             int ldy, hipStream_t s);                      // Y = alpha X
+hipError_t launch_gather_rows(int nsel, int n, const int *sel, const double *X, int ldx,
+                              double *Y, int ldy, hipStream_t s);          // Y = X(sel, :)
+hipError_t launch_scatter_identity(int nsel, const int *sel, double *Xi, int ld,
+                                   hipStream_t s);                         // Xi(sel,:) = I
+hipError_t launch_add_identity_neg(int n, double *T, int ld, hipStream_t s);  // T = I - T
+hipError_t launch_col_sqnorm(int m, int n, const double *X, int ldx, double *out,
+                             hipStream_t s);                               // out[j] = ||X(:,j)||^2
+hipError_t launch_col_diff_sqnorm(int m, int n, const double *X, int ldx, const double *Y,
+                                  int ldy, double *out, hipStream_t s);  // ||X(:,j)-Y(:,j)||^2
+hipError_t launch_axpby(int m, int n, double a, const double *X, int ldx, double b, double *Y,
+                        int ldy, hipStream_t s);                           // Y = a X + b Y
+hipError_t launch_diff_sqnorm(int m, int n, const double *X, const double *Y, int ld,
+                              double *out2, hipStream_t s);  // out2[0]=||X-Y||^2, out2[1]=||X||^2
+hipError_t launch_weighted_rows(int ne, int nmu, const double *L, const int *sel,
+                                const double *phi, int ldphi, double *Bc, hipStream_t s);
+hipError_t launch_gram_check(int n, int unused, const double *G, double *maxdev, hipStream_t s);
+hipError_t launch_transpose(int m, int n, const double *A, int lda, double *B, int ldb,
+                            hipStream_t s);                                // B = A^T
+
+// ---------------------------------------------------------------- Krylov layout
+hipError_t launch_to_tiled(int ng, int ncols, int ncols_pad, const double *X, int ldx,
+                           double *T, hipStream_t s);
+hipError_t launch_from_tiled(int ng, int ncols, const double *T, double *X, int ldx,
+                             hipStream_t s);
+
+struct KrylovArgs {
+    GridDesc g;
+    int ne;
+    int ntiles;             // number of 16-column tiles to solve
+    int rhs_tiles;          // tiles of the right-hand side; tile t uses rhs tile t % rhs_tiles
+    const double *phi_rm;   // N_g x N_e row-major (orbitals contiguous)
+    const double *phi_cm;   // N_g x N_e column-major
+    const double *veff;     // N_g
+    const double *shift;    // per column (ntiles * 16)
+    const double *rhs;      // tiled right-hand sides
+    double *x, *r, *pa, *pb;    // tiled state
+    double *w1, *w2, *w3;       // extra tiled vectors (MINRES)
+    int *iters;             // per column
+    double *resid;          // per column: final recurrence residual / ||b||
+    int *flags;             // per column: bit0 not converged, bit1 non-positive curvature
+    double tol;
+    int max_iter;
+    int *tile_iters;        // per tile: iterations executed by its workgroup
+};
+hipError_t launch_cg_fp64(const KrylovArgs &a, hipStream_t s);
+hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s);
+
+// ---------------------------------------------------------------- ISDF (K4)
+// Greedy pivoted Cholesky of the implicit Hadamard Gram matrix; forced (dev,
+// nmu_max entries) replaces the argmax by the given pivots.  scratch >= 32 bytes.
+hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, int ldphi,
+                                 const double *gt, int ldg, int nmu_max, double tol,
+                                 double *L, int ldl, double *diag, int *sel_dev,
+                                 const int *forced, int *nmu_out_host, void *scratch,
+                                 hipStream_t s);
+hipError_t launch_tri_inverse_lower(int n, const double *L, int ldl, double *Linv, hipStream_t s);
+hipError_t launch_gather_lower(int n, const int *sel, const double *L, int ldl, double *L11,
+                               hipStream_t s);
+
+// ---------------------------------------------------------------- dense FP64
+// Solve A X = B in place (A n x n, B n x nrhs) by Gauss-Jordan with partial pivoting.
+hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, int ldb,
+                              int *piv_scratch, hipStream_t s);
+// Symmetric eigenvalues (cyclic Jacobi), A overwritten; eig sorted ascending;
+// work holds n + 2 doubles + n + 2 ints.
+hipError_t jacobi_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s);
+hipError_t launch_dynmat_assemble(int np, int dim, const double *Phi_el, const double *K_local,
+                                  const double *mass, double *D, double *asym2,
+                                  hipStream_t s);
+
+// ---------------------------------------------------------------- v_c by Fourier GEMMs
+hipError_t launch_fourier_basis(int n, double *F, hipStream_t s);
+hipError_t launch_fourier_symbol(const GridDesc &g, double kappa, double eps0, double *S,
+                                 hipStream_t s);
+hipError_t launch_mul_symbol(int ng, int n, const double *S, double *X, hipStream_t s);
+
+}  // namespace acp

@@ -1,0 +1,203 @@
+// FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// Used for every dense contraction around the solve: the right-hand sides
+// -Q Xi (Alg. 3 step 2), the W assembly of Eq. (3.7) (Hadamard-accumulate
+// epilogue), the interpolation vectors of Alg. 2, the Fourier form of v_c, the
+// Dyson update of Eq. (3.13) and G^T U of Eq. (2.11).
+//
+// Tile 64 x 64 x 16, 256 threads (4 waves of 64).  Each wave owns a 32 x 32
+// quarter = 2 x 2 MFMA blocks of 16 x 16.  Operands are staged k-major in LDS so
+// that the 16 lanes feeding one MFMA row read consecutive addresses.  The next
+// k-slab is prefetched into registers while the current one is multiplied.  The
+// epilogue goes through LDS so global stores are coalesced along columns.
+//
+// MFMA f64 16x16x4 lane layout (measured on gfx950): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and receives D[l/16 + 4 j][l%16], j = 0..3.
+#include "acp_internal.h"
+
+namespace acp {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int LDA_S = BM + 2;   // padded LDS strides (elements)
+constexpr int LDB_S = BN + 2;
+constexpr int LDC_S = BM + 1;
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(
+    int M, int N, int K, double alpha, const double *__restrict__ A, int lda, long long sa,
+    const double *__restrict__ B, int ldb, long long sb, double beta, double *__restrict__ C,
+    int ldc, long long sc, const double *__restrict__ E, int lde, long long se) {
+    __shared__ double smem[2 * BK * LDA_S > BN * LDC_S ? 2 * BK * LDA_S : BN * LDC_S];
+    double *As = smem;                  // [BK][LDA_S]
+    double *Bs = smem + BK * LDA_S;     // [BK][LDB_S]
+
+    const int bz = blockIdx.z;
+    A += bz * sa;
+    B += bz * sb;
+    C += bz * sc;
+    if (EPI == 1) E += bz * se;
+
+    const int m0 = blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int wm = (wave & 1) * 32;
+    const int wn = (wave >> 1) * 32;
+
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    double ra[4], rb[4];
+    auto load_tiles = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int mm, kk;
+            if (!TA) { mm = t & 63; kk = (t >> 6) + 4 * q; }
+            else     { kk = t & 15; mm = (t >> 4) + 16 * q; }
+            int gm = m0 + mm, gk = k0 + kk;
+            double v = 0.0;
+            if (gm < M && gk < K) v = TA ? A[gk + (long long)gm * lda] : A[gm + (long long)gk * lda];
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int nn, kk;
+            if (!TB) { kk = t & 15; nn = (t >> 4) + 16 * q; }
+            else     { nn = t & 63; kk = (t >> 6) + 4 * q; }
+            int gn = n0 + nn, gk = k0 + kk;
+            double v = 0.0;
+            if (gn < N && gk < K) v = TB ? B[gn + (long long)gk * ldb] : B[gk + (long long)gn * ldb];
+            rb[q] = v;
+        }
+    };
+    auto store_tiles = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int mm, kk;
+            if (!TA) { mm = t & 63; kk = (t >> 6) + 4 * q; }
+            else     { kk = t & 15; mm = (t >> 4) + 16 * q; }
+            As[kk * LDA_S + mm] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int nn, kk;
+            if (!TB) { kk = t & 15; nn = (t >> 4) + 16 * q; }
+            else     { nn = t & 63; kk = (t >> 6) + 4 * q; }
+            Bs[kk * LDB_S + nn] = rb[q];
+        }
+    };
+
+    load_tiles(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (k0 + BK < K) load_tiles(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int ka = kk + (lane >> 4);
+            double a0 = As[ka * LDA_S + wm + (lane & 15)];
+            double a1 = As[ka * LDA_S + wm + 16 + (lane & 15)];
+            double b0 = Bs[ka * LDB_S + wn + (lane & 15)];
+            double b1 = Bs[ka * LDB_S + wn + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+
+    // epilogue through LDS: Cs[col][row]
+    __syncthreads();
+    double *Cs = smem;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int row = wm + 16 * i + (lane >> 4) + 4 * e;
+                int col = wn + 16 * j + (lane & 15);
+                Cs[col * LDC_S + row] = acc[i][j][e];
+            }
+    __syncthreads();
+    for (int idx = t; idx < BM * BN; idx += NT) {
+        int row = idx & (BM - 1);
+        int col = idx >> 6;
+        int gm = m0 + row, gn = n0 + col;
+        if (gm < M && gn < N) {
+            double v = alpha * Cs[col * LDC_S + row];
+            double *cp = C + gm + (long long)gn * ldc;
+            if (EPI == 0) {
+                if (beta != 0.0) v += beta * (*cp);
+                *cp = v;
+            } else {
+                *cp += v * E[gm + (long long)gn * lde];
+            }
+        }
+    }
+}
+
+template <bool TA, bool TB>
+hipError_t dispatch_epi(int m, int n, int k, double alpha, const double *A, int lda, long long sa,
+                        const double *B, int ldb, long long sb, double beta, double *C, int ldc,
+                        long long sc, int batch, hipStream_t s, Epi epi, const double *E,
+                        int lde, long long se) {
+    dim3 grid((m + BM - 1) / BM, (n + BN - 1) / BN, batch);
+    if (epi == Epi::Store)
+        hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 0>), grid, dim3(NT), 0, s, m, n, k, alpha, A,
+                           lda, sa, B, ldb, sb, beta, C, ldc, sc, E, lde, se);
+    else
+        hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 1>), grid, dim3(NT), 0, s, m, n, k, alpha, A,
+                           lda, sa, B, ldb, sb, beta, C, ldc, sc, E, lde, se);
+    return hipGetLastError();
+}
+
+__global__ void scale_kernel(int m, int n, double beta, double *C, int ldc) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long tot = (long long)m * n;
+    if (idx < tot) {
+        int i = (int)(idx % m);
+        long long j = idx / m;
+        double *p = C + i + j * ldc;
+        *p = (beta == 0.0) ? 0.0 : beta * (*p);
+    }
+}
+
+}  // namespace
+
+hipError_t gemm(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
+                long long sa, const double *B, int ldb, long long sb, double beta, double *C,
+                int ldc, long long sc, int batch, hipStream_t s, Epi epi, const double *E,
+                int lde, long long se) {
+    if (m <= 0 || n <= 0 || batch <= 0) return hipSuccess;
+    if (k <= 0) {
+        if (epi == Epi::HadamardAcc) return hipSuccess;
+        for (int b = 0; b < batch; ++b) {
+            long long tot = (long long)m * n;
+            hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                               m, n, beta, C + b * sc, ldc);
+        }
+        return hipGetLastError();
+    }
+    if (ta == Op::N && tb == Op::N)
+        return dispatch_epi<false, false>(m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc,
+                                          batch, s, epi, E, lde, se);
+    if (ta == Op::T && tb == Op::N)
+        return dispatch_epi<true, false>(m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc,
+                                         batch, s, epi, E, lde, se);
+    if (ta == Op::N && tb == Op::T)
+        return dispatch_epi<false, true>(m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc,
+                                         batch, s, epi, E, lde, se);
+    return dispatch_epi<true, true>(m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc,
+                                    batch, s, epi, E, lde, se);
+}
+
+}  // namespace acp

@@ -1,0 +1,496 @@
+// Batched solvers for the projected shifted Sternheimer equations
+//   Q (H - s_j) Q z_j = b_j,   b_j in range(Q),  z_j(0) = 0        (Eq. (3.6))
+// H = -1/2 Delta_h + diag(V_eff), Q = I - Phi Phi^T.
+//
+// Design (gfx950):
+//  * Each workgroup owns one tile of 16 systems for the whole solve and all
+//    N_g rows, so every reduction of the method (Phi^T y, p^T A p, |r|^2) is
+//    workgroup-local: no grid synchronisation, no per-iteration launches, and a
+//    tile leaves the loop as soon as its 16 systems have converged.
+//  * Vectors use the 16-column row-interleaved layout: one grid row of a tile
+//    is a 128-byte line, so a wave touching 4 rows x 16 systems issues fully
+//    coalesced loads, and the 64 values a wave holds are exactly the B operand
+//    of one v_mfma_f64_16x16x4 (k = row, n = system).
+//  * The stencil (8th-order Laplacian + V_eff - shift) is fused with the
+//    projector: pass 1 forms p, y = (H - s) p and C = Phi^T y on the matrix
+//    cores (waves split the orbital blocks, y staged through LDS); pass 2
+//    recomputes y from p, forms A p = y - Phi C on the matrix cores and updates
+//    x and r in the same sweep.  y and A p never touch memory.
+//  * p^T A p is taken as p^T y: p stays in range(Q) to rounding, and the
+//    neglected term (Phi^T p)^T (Phi^T y) is second order in that rounding.
+//
+// CG (the operator is positive definite on range(Q) when every shift lies
+// below the lowest unoccupied eigenvalue): 8 vector sweeps per iteration
+// (read r, p_old; write p | read p, x, r; write x, r).  p is double-buffered so
+// the stencil in pass 1 can recompute p = r + beta p_old at neighbour rows
+// without a race.
+//
+// MINRES (the solver the paper uses, Sec. 2.2 after Eq. (2.18)): Lanczos
+// three-term recurrence with the tridiagonal least-squares problem reduced by
+// Givens rotations, per system; three sweeps per iteration.
+#include "acp_internal.h"
+
+namespace acp {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;       // threads per workgroup (4 waves)
+constexpr int CH = 64;        // rows per chunk
+constexpr int MAXNB = 16;     // up to 256 (padded) orbitals
+
+__device__ __forceinline__ int wrap(int i, int n) {
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    return i;
+}
+
+// y = (H - s) p at rows R..R+3 of one system; pf(row) returns p(row).
+// Rows >= ng give y = p = 0.
+template <int DIM, class PF>
+__device__ __forceinline__ void stencil4(PF pf, int R, const GridDesc &g, const double *__restrict__ V,
+                                         double s, double (&y)[4], double (&pc)[4]) {
+    const double c2 = -0.5 / (g.h * g.h);
+    if (DIM == 1) {
+        double w[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            // rows past the end (last chunk) are computed but unused; keep every
+            // load inside [0, ng) for any grid size
+            int rr = (R - 4 + q) % g.ng;
+            if (rr < 0) rr += g.ng;
+            w[q] = pf(rr);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double lap = fd8(0) * w[4 + j];
+#pragma unroll
+            for (int k = 1; k <= 4; ++k) lap += fd8(k) * (w[4 + j + k] + w[4 + j - k]);
+            const bool ok = (R + j) < g.ng;
+            pc[j] = ok ? w[4 + j] : 0.0;
+            y[j] = ok ? (c2 * lap + (V[ok ? R + j : 0] - s) * w[4 + j]) : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = R + j;
+            if (row >= g.ng) { y[j] = 0.0; pc[j] = 0.0; continue; }
+            const int ix = row % g.nx, iy = row / g.nx;
+            const double c = pf(row);
+            double lap = 2.0 * fd8(0) * c;
+#pragma unroll
+            for (int k = 1; k <= 4; ++k) {
+                lap += fd8(k) * (pf(iy * g.nx + wrap(ix + k, g.nx)) + pf(iy * g.nx + wrap(ix - k, g.nx)));
+                lap += fd8(k) * (pf(wrap(iy + k, g.ny) * g.nx + ix) + pf(wrap(iy - k, g.ny) * g.nx + ix));
+            }
+            pc[j] = c;
+            y[j] = c2 * lap + (V[row] - s) * c;
+        }
+    }
+}
+
+// Sum over the 16 threads of one column (threads t with t % 16 == col) of a
+// per-thread value, in a fixed order.  Returns the total to threads col < 16
+// through red_out[col].
+__device__ __forceinline__ void column_reduce(double v, double *red, double *red_out) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < kTile) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT / kTile; ++k) s += red[threadIdx.x + kTile * k];
+        red_out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Pass "projected apply", part 1: given p (via pf), stage y per chunk in LDS and
+// accumulate C = Phi^T y on the matrix cores; returns this thread's share of p^T y.
+template <int DIM, int NB, class PF>
+__device__ __forceinline__ double apply_pass1(PF pf, const KrylovArgs &a, double s, double *ys,
+                                              double *Cs, d4 (&acc)[(NB + 3) / 4], double *pstore) {
+    const int t = threadIdx.x;
+    const int col = t & 15;
+    const int grp = t >> 4;         // 0..15 -> 4 rows each
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    constexpr int NBW = (NB + 3) / 4;
+    const int nep = NB * 16;
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+    double pty = 0.0;
+    for (int r0 = 0; r0 < a.g.ng; r0 += CH) {
+        const int R = r0 + 4 * grp;
+        double y[4], pc[4];
+        stencil4<DIM>(pf, R, a.g, a.veff, s, y, pc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            ys[(4 * grp + j) * kTile + col] = y[j];
+            pty += pc[j] * y[j];
+            if (pstore && R + j < a.g.ng) pstore[(R + j) * kTile + col] = pc[j];
+        }
+        __syncthreads();
+        // C(orb, col) += sum_rows Phi(row, orb) y(row, col): waves split orbital blocks
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+            const int mb = wave + 4 * b;
+            if (mb < NB) {
+#pragma unroll 4
+                for (int ks = 0; ks < CH / 4; ++ks) {
+                    const int row = r0 + 4 * ks + (lane >> 4);
+                    const double av = (row < a.g.ng) ? a.phi_rm[(long long)row * nep + mb * 16 + (lane & 15)] : 0.0;
+                    const double bv = ys[(4 * ks + (lane >> 4)) * kTile + (lane & 15)];
+                    acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // publish C to LDS: Cs[orb * 16 + col]
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
+        const int mb = wave + 4 * b;
+        if (mb < NB) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Cs[(mb * 16 + (lane >> 4) + 4 * e) * kTile + (lane & 15)] = acc[b][e];
+        }
+    }
+    return pty;
+}
+
+// Part 2 helper: for the 16-row block starting at row0, D = Phi(rows,:) C on
+// the matrix cores.  The f64 MFMA returns D[l/16 + 4 e][l%16] to lane l, so the
+// A operand feeds grid row 4 (m % 4) + m / 4 into MFMA row m: lane l then holds
+// the consecutive grid rows row0 + 4*(l/16) + e of system l % 16.
+template <int NB>
+__device__ __forceinline__ d4 project_block(const KrylovArgs &a, const double *Cs, int row0) {
+    const int lane = threadIdx.x & 63;
+    const int nep = NB * 16;
+    d4 d = d4{0.0, 0.0, 0.0, 0.0};
+    const int m = lane & 15;
+    const int row = row0 + 4 * (m & 3) + (m >> 2);
+    const bool ok = row < a.g.ng;
+#pragma unroll 8
+    for (int k = 0; k < nep; k += 4) {
+        const int orb = k + (lane >> 4);
+        const double av = ok ? a.phi_cm[(long long)orb * a.g.ng + row] : 0.0;
+        const double bv = Cs[orb * kTile + (lane & 15)];
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+    }
+    return d;
+}
+
+template <int DIM, int NB>
+__global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
+    __shared__ double ys[CH * kTile];
+    __shared__ double Cs[NB * 16 * kTile];
+    __shared__ double red[NT];
+    __shared__ double s_rr[kTile], s_alpha[kTile], s_beta[kTile], s_bn[kTile], s_tmp[kTile];
+    __shared__ int s_active[kTile], s_iters[kTile], s_flag[kTile], s_any;
+
+    const int tile = blockIdx.x;
+    const int t = threadIdx.x;
+    const int col = t & 15;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const long long base = (long long)tile * a.g.ng * kTile;
+    const double *__restrict__ b = a.rhs + (long long)(tile % a.rhs_tiles) * a.g.ng * kTile;
+    double *__restrict__ x = a.x + base;
+    double *__restrict__ r = a.r + base;
+    double *pA = a.pa + base;
+    double *pB = a.pb + base;
+    const double s = a.shift[tile * kTile + col];
+
+    // init: x = 0, r = b, p_old = 0, rr = |b|^2
+    double part = 0.0;
+    for (int idx = t; idx < a.g.ng * kTile; idx += NT) {
+        const double bv = b[idx];
+        x[idx] = 0.0;
+        r[idx] = bv;
+        pA[idx] = 0.0;
+        part += bv * bv;   // idx % 16 == t % 16 == col since NT % 16 == 0
+    }
+    column_reduce(part, red, s_rr);
+    if (t < kTile) {
+        s_bn[t] = sqrt(s_rr[t]);
+        s_beta[t] = 0.0;
+        s_iters[t] = 0;
+        s_flag[t] = 0;
+        s_active[t] = (s_bn[t] > 0.0) ? 1 : 0;
+    }
+    __syncthreads();
+
+    d4 acc[(NB + 3) / 4];
+    int it = 0;
+    for (; it < a.max_iter; ++it) {
+        if (t == 0) {
+            int any = 0;
+            for (int c = 0; c < kTile; ++c) any |= s_active[c];
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) break;
+        // ---- pass 1: p = r + beta p_old (into pB), y = (H - s) p, C = Phi^T y, p^T y
+        const double beta = s_beta[col];
+        auto pf1 = [&](int row) { return r[row * kTile + col] + beta * pA[row * kTile + col]; };
+        double pty = apply_pass1<DIM, NB>(pf1, a, s, ys, Cs, acc, pB);
+        column_reduce(pty, red, s_tmp);
+        if (t < kTile) {
+            double al = 0.0;
+            if (s_active[t]) {
+                if (s_tmp[t] > 0.0) {
+                    al = s_rr[t] / s_tmp[t];
+                } else {
+                    s_flag[t] |= 2;
+                    s_active[t] = 0;
+                }
+            }
+            s_alpha[t] = al;
+        }
+        __syncthreads();
+        // ---- pass 2: A p = y - Phi C; x += alpha p; r -= alpha A p; |r|^2
+        double rr_part = 0.0;
+        for (int r0 = 0; r0 < a.g.ng; r0 += CH) {
+            const int row0 = r0 + 16 * wave;
+            const d4 d = project_block<NB>(a, Cs, row0);
+            const int R = row0 + 4 * (lane >> 4);
+            const int c = lane & 15;
+            auto pf2 = [&](int row) { return pB[row * kTile + c]; };
+            double y[4], pc[4];
+            stencil4<DIM>(pf2, R, a.g, a.veff, a.shift[tile * kTile + c], y, pc);
+            const double al = s_alpha[c];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = R + e;
+                if (row < a.g.ng) {
+                    const double ap = y[e] - d[e];
+                    const double xn = x[row * kTile + c] + al * pc[e];
+                    const double rn = r[row * kTile + c] - al * ap;
+                    x[row * kTile + c] = xn;
+                    r[row * kTile + c] = rn;
+                    rr_part += rn * rn;
+                }
+            }
+        }
+        // lane's column is lane & 15 == t & 15: column_reduce applies
+        column_reduce(rr_part, red, s_tmp);
+        if (t < kTile) {
+            if (s_active[t]) {
+                s_beta[t] = s_tmp[t] / s_rr[t];
+                s_rr[t] = s_tmp[t];
+                s_iters[t] += 1;
+                if (sqrt(s_rr[t]) <= a.tol * s_bn[t]) s_active[t] = 0;
+            } else {
+                s_beta[t] = 0.0;
+            }
+        }
+        __syncthreads();
+        double *tmp = pA; pA = pB; pB = tmp;
+    }
+    if (t < kTile) {
+        const int gc = tile * kTile + t;
+        a.iters[gc] = s_iters[t];
+        a.resid[gc] = (s_bn[t] > 0.0) ? sqrt(s_rr[t]) / s_bn[t] : 0.0;
+        a.flags[gc] = s_flag[t] | (s_active[t] ? 1 : 0);
+    }
+    if (t == 0) a.tile_iters[tile] = it;
+}
+
+// MINRES: v (current Lanczos vector), vo (previous, overwritten by the next),
+// w, wo (direction vectors), x.  Buffers: pa = v, pb = vo, w1 = w, w2 = wo.
+template <int DIM, int NB>
+__global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
+    __shared__ double ys[CH * kTile];
+    __shared__ double Cs[NB * 16 * kTile];
+    __shared__ double red[NT];
+    __shared__ double s_beta[kTile], s_alpha[kTile], s_bn[kTile], s_tmp[kTile];
+    __shared__ double s_cs[kTile], s_sn[kTile], s_dbar[kTile], s_epsn[kTile], s_phibar[kTile];
+    __shared__ double s_delta[kTile], s_gamma[kTile], s_epsk[kTile], s_phi[kTile], s_binv[kTile];
+    __shared__ int s_active[kTile], s_iters[kTile], s_flag[kTile], s_any;
+
+    const int tile = blockIdx.x;
+    const int t = threadIdx.x;
+    const int col = t & 15;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const long long base = (long long)tile * a.g.ng * kTile;
+    const double *__restrict__ b = a.rhs + (long long)(tile % a.rhs_tiles) * a.g.ng * kTile;
+    double *__restrict__ x = a.x + base;
+    double *v = a.pa + base;
+    double *vo = a.pb + base;
+    double *w = a.w1 + base;
+    double *wo = a.w2 + base;
+    const double s = a.shift[tile * kTile + col];
+
+    double part = 0.0;
+    for (int idx = t; idx < a.g.ng * kTile; idx += NT) {
+        const double bv = b[idx];
+        part += bv * bv;
+    }
+    column_reduce(part, red, s_tmp);
+    if (t < kTile) {
+        const double bn = sqrt(s_tmp[t]);
+        s_bn[t] = bn;
+        s_binv[t] = bn > 0.0 ? 1.0 / bn : 0.0;
+        s_beta[t] = bn;
+        s_cs[t] = -1.0;
+        s_sn[t] = 0.0;
+        s_dbar[t] = 0.0;
+        s_epsn[t] = 0.0;
+        s_phibar[t] = bn;
+        s_iters[t] = 0;
+        s_flag[t] = 0;
+        s_active[t] = bn > 0.0 ? 1 : 0;
+    }
+    __syncthreads();
+    for (int idx = t; idx < a.g.ng * kTile; idx += NT) {
+        x[idx] = 0.0;
+        v[idx] = b[idx] * s_binv[col];
+        vo[idx] = 0.0;
+        w[idx] = 0.0;
+        wo[idx] = 0.0;
+    }
+    __syncthreads();
+
+    d4 acc[(NB + 3) / 4];
+    int it = 0;
+    for (; it < a.max_iter; ++it) {
+        if (t == 0) {
+            int any = 0;
+            for (int c = 0; c < kTile; ++c) any |= s_active[c];
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) break;
+        // ---- pass 1: y = (H - s) v, C = Phi^T y, alpha = v^T y
+        auto pf1 = [&](int row) { return v[row * kTile + col]; };
+        double vty = apply_pass1<DIM, NB>(pf1, a, s, ys, Cs, acc, nullptr);
+        column_reduce(vty, red, s_alpha);
+        // ---- pass 2: v_new = (y - Phi C) - alpha v - beta v_old  (into vo), |v_new|^2
+        double nn = 0.0;
+        for (int r0 = 0; r0 < a.g.ng; r0 += CH) {
+            const int row0 = r0 + 16 * wave;
+            const d4 d = project_block<NB>(a, Cs, row0);
+            const int R = row0 + 4 * (lane >> 4);
+            const int c = lane & 15;
+            auto pf2 = [&](int row) { return v[row * kTile + c]; };
+            double y[4], pc[4];
+            stencil4<DIM>(pf2, R, a.g, a.veff, a.shift[tile * kTile + c], y, pc);
+            const double al = s_alpha[c], be = s_beta[c];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = R + e;
+                if (row < a.g.ng) {
+                    const double vn = (y[e] - d[e]) - al * pc[e] - be * vo[row * kTile + c];
+                    vo[row * kTile + c] = vn;
+                    nn += vn * vn;
+                }
+            }
+        }
+        column_reduce(nn, red, s_tmp);
+        // ---- rotations (per system)
+        if (t < kTile) {
+            const double beta_new = sqrt(s_tmp[t]);
+            const double al = s_alpha[t];
+            const double cs = s_cs[t], sn = s_sn[t];
+            const double epsk = s_epsn[t];
+            const double delta = cs * s_dbar[t] + sn * al;
+            const double gbar = sn * s_dbar[t] - cs * al;
+            const double epsn = sn * beta_new;
+            const double dbar = -cs * beta_new;
+            double gamma = sqrt(gbar * gbar + beta_new * beta_new);
+            if (!(gamma > 0.0)) gamma = 1e-300;
+            const double csn = gbar / gamma, snn = beta_new / gamma;
+            const double phi = csn * s_phibar[t];
+            s_delta[t] = delta;
+            s_epsk[t] = epsk;
+            s_gamma[t] = gamma;
+            s_phi[t] = s_active[t] ? phi : 0.0;
+            if (s_active[t]) {
+                s_phibar[t] = snn * s_phibar[t];
+                s_cs[t] = csn;
+                s_sn[t] = snn;
+                s_epsn[t] = epsn;
+                s_dbar[t] = dbar;
+                s_beta[t] = beta_new;
+                s_binv[t] = beta_new > 0.0 ? 1.0 / beta_new : 0.0;
+                s_iters[t] += 1;
+            }
+        }
+        __syncthreads();
+        // ---- pass 3: w_new = (v - eps_k wo - delta w) / gamma (into wo); x += phi w_new;
+        //      v_old <- v, v <- v_new / beta_new   (swap by copying the scaled vector)
+        for (int idx = t; idx < a.g.ng * kTile; idx += NT) {
+            const int c = idx & 15;
+            if (s_active[c]) {
+                const double vv = v[idx];
+                const double wn = (vv - s_epsk[c] * wo[idx] - s_delta[c] * w[idx]) / s_gamma[c];
+                wo[idx] = w[idx];
+                w[idx] = wn;
+                x[idx] += s_phi[c] * wn;
+                const double vn = vo[idx] * s_binv[c];
+                vo[idx] = vv;
+                v[idx] = vn;
+            }
+        }
+        __syncthreads();
+        if (t < kTile && s_active[t]) {
+            if (fabs(s_phibar[t]) <= a.tol * s_bn[t]) s_active[t] = 0;
+        }
+        __syncthreads();
+    }
+    if (t < kTile) {
+        const int gc = tile * kTile + t;
+        a.iters[gc] = s_iters[t];
+        a.resid[gc] = (s_bn[t] > 0.0) ? fabs(s_phibar[t]) / s_bn[t] : 0.0;
+        a.flags[gc] = s_flag[t] | (s_active[t] ? 1 : 0);
+    }
+    if (t == 0) a.tile_iters[tile] = it;
+}
+
+#define ACP_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+hipError_t launch_cg_impl(const KrylovArgs &a, hipStream_t s) {
+    const int nb = (a.ne + 15) / 16;
+    dim3 grid(a.ntiles), block(NT);
+#define CASE(N)                                                                              \
+    if (nb == N) {                                                                           \
+        if (a.g.dim == 1) hipLaunchKernelGGL((cg_kernel<1, N>), grid, block, 0, s, a);       \
+        else hipLaunchKernelGGL((cg_kernel<2, N>), grid, block, 0, s, a);                    \
+        return hipGetLastError();                                                            \
+    }
+    ACP_NB_CASES(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_minres_impl(const KrylovArgs &a, hipStream_t s) {
+    const int nb = (a.ne + 15) / 16;
+    dim3 grid(a.ntiles), block(NT);
+#define CASE(N)                                                                              \
+    if (nb == N) {                                                                           \
+        if (a.g.dim == 1) hipLaunchKernelGGL((minres_kernel<1, N>), grid, block, 0, s, a);   \
+        else hipLaunchKernelGGL((minres_kernel<2, N>), grid, block, 0, s, a);                \
+        return hipGetLastError();                                                            \
+    }
+    ACP_NB_CASES(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_cg_fp64(const KrylovArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ne > MAXNB * 16) return hipErrorInvalidValue;
+    return launch_cg_impl(a, s);
+}
+
+hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ne > MAXNB * 16) return hipErrorInvalidValue;
+    return launch_minres_impl(a, s);
+}
+
+}  // namespace acp

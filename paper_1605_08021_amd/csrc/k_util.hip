@@ -1,0 +1,436 @@
+// Grid operators and small device utilities.
+//
+//  * stencil (column-major): Y = c_lap Delta_h X + (c_v V + c_0 - shift_j) X with the
+//    periodic 8th-order central Laplacian; used for H - shift (Eq. (2.5) on the
+//    grid) and for v_c^{-1} = (eps0/4pi)(-Delta_h + kappa^2), the change of
+//    variables B = v_hxc^{-1} G of Sec. 3.2.
+//  * the real orthonormal Fourier basis and the symbol of v_c, which turn
+//    v_c X into dense products on the matrix cores.
+//  * conversions between column-major grid vectors and the 16-column
+//    row-interleaved layout of the Krylov kernels, gathers, scatters and
+//    deterministic reductions.
+#include "acp_internal.h"
+
+namespace acp {
+
+namespace {
+
+__global__ void stencil_kernel(int dim, int nx, int ny, int ng, int n, const double *__restrict__ X,
+                               int ldx, double *__restrict__ Y, int ldy,
+                               const double *__restrict__ V, double c_lap_h2, double c_v,
+                               double c_0, const double *__restrict__ shift) {
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    int col = blockIdx.y;
+    if (row >= ng || col >= n) return;
+    const double *x = X + (long long)col * ldx;
+    int ix = row % nx;
+    int iy = row / nx;
+    double lap = 0.0;
+    double xc = x[row];
+    // x direction
+    {
+        double s = fd8(0) * xc;  // c_0 x, once per axis
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            int ip = ix + k; if (ip >= nx) ip -= nx;
+            int im = ix - k; if (im < 0) im += nx;
+            s += fd8(k) * (x[iy * nx + ip] + x[iy * nx + im]);
+        }
+        lap += s;
+    }
+    if (dim == 2) {
+        double s = fd8(0) * xc;
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            int jp = iy + k; if (jp >= ny) jp -= ny;
+            int jm = iy - k; if (jm < 0) jm += ny;
+            s += fd8(k) * (x[jp * nx + ix] + x[jm * nx + ix]);
+        }
+        lap += s;
+    }
+    double diag = c_0 - (shift ? shift[col] : 0.0);
+    if (c_v != 0.0) diag += c_v * V[row];
+    Y[(long long)col * ldy + row] = c_lap_h2 * lap + diag * xc;
+}
+
+__global__ void scale_copy_kernel(int m, int n, double alpha, const double *X, int ldx, double *Y,
+                                  int ldy) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)m * n) return;
+    int i = (int)(idx % m);
+    long long j = idx / m;
+    Y[i + j * ldy] = alpha * X[i + j * ldx];
+}
+
+__global__ void gather_rows_kernel(int nsel, int n, const int *sel, const double *X, int ldx,
+                                   double *Y, int ldy) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)nsel * n) return;
+    int i = (int)(idx % nsel);
+    long long j = idx / nsel;
+    Y[i + j * ldy] = X[sel[i] + j * ldx];
+}
+
+__global__ void scatter_identity_kernel(int nsel, const int *sel, double *Xi, int ld) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)nsel * nsel) return;
+    int k = (int)(idx % nsel);      // row index in sel
+    long long j = idx / nsel;       // column
+    Xi[sel[k] + j * ld] = (k == j) ? 1.0 : 0.0;
+}
+
+__global__ void add_identity_neg_kernel(int n, double *T, int ld) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n * n) return;
+    int i = (int)(idx % n);
+    long long j = idx / n;
+    double *p = T + i + j * ld;
+    *p = ((i == j) ? 1.0 : 0.0) - *p;
+}
+
+// One block per column; fixed-order tree reduction (deterministic).
+__global__ void col_sqnorm_kernel(int m, const double *X, int ldx, double *out) {
+    __shared__ double red[256];
+    const double *x = X + (long long)blockIdx.x * ldx;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) s += x[i] * x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// One block per column: out[j] = ||X(:,j) - Y(:,j)||^2 (deterministic).
+__global__ void col_diff_sqnorm_kernel(int m, const double *X, int ldx, const double *Y, int ldy,
+                                       double *out) {
+    __shared__ double red[256];
+    const double *x = X + (long long)blockIdx.x * ldx;
+    const double *y = Y + (long long)blockIdx.x * ldy;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        double d = x[i] - y[i];
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ void axpby_kernel(int m, int n, double a, const double *X, int ldx, double b, double *Y,
+                             int ldy) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)m * n) return;
+    int i = (int)(idx % m);
+    long long j = idx / m;
+    Y[i + j * ldy] = a * X[i + j * ldx] + b * Y[i + j * ldy];
+}
+
+// Single block: out[0] = ||X - Y||_F^2, out[1] = ||X||_F^2 (deterministic).
+__global__ void diff_sqnorm_kernel(long long tot, int m, int ld, const double *X, const double *Y,
+                                   double *out) {
+    __shared__ double r0[1024], r1[1024];
+    double a = 0.0, b = 0.0;
+    for (long long idx = threadIdx.x; idx < tot; idx += 1024) {
+        int i = (int)(idx % m);
+        long long j = idx / m;
+        double x = X[i + j * ld], y = Y[i + j * ld];
+        a += (x - y) * (x - y);
+        b += x * x;
+    }
+    r0[threadIdx.x] = a;
+    r1[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            r0[threadIdx.x] += r0[threadIdx.x + w];
+            r1[threadIdx.x] += r1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = r0[0]; out[1] = r1[0]; }
+}
+
+// Bc(i, mu) = L(i) * phi(sel[mu], i): the N_e x N_mu factor diag(L_c) Phi(Pi,:)^T of Eq. (3.7).
+__global__ void weighted_rows_kernel(int ne, int nmu, const double *L, const int *sel,
+                                     const double *phi, int ldphi, double *Bc) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)ne * nmu) return;
+    int i = (int)(idx % ne);
+    long long mu = idx / ne;
+    Bc[i + mu * ne] = L[i] * phi[sel[mu] + (long long)i * ldphi];
+}
+
+// max |G - I| of a n x n matrix (single block).
+__global__ void max_dev_identity_kernel(int n, const double *G, double *out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (long long idx = threadIdx.x; idx < (long long)n * n; idx += 256) {
+        int i = (int)(idx % n);
+        long long j = idx / n;
+        double v = fabs(G[idx] - ((i == j) ? 1.0 : 0.0));
+        m = fmax(m, v);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Column-major (ld = ldx) -> 16-column row-interleaved tiles; padded columns are zero.
+// Block: 16 columns x 64 rows through LDS.
+__global__ void to_tiled_kernel(int ng, int ncols, const double *__restrict__ X, int ldx,
+                                double *__restrict__ T) {
+    __shared__ double buf[kTile][65];
+    const int tile = blockIdx.y;
+    const int r0 = blockIdx.x * 64;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int r = t & 63, c = (t >> 6) + 4 * q;
+        int gr = r0 + r, gc = tile * kTile + c;
+        double v = 0.0;
+        if (gr < ng && gc < ncols) v = X[gr + (long long)gc * ldx];
+        buf[c][r] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int c = t & 15, r = (t >> 4) + 16 * q;
+        int gr = r0 + r;
+        if (gr < ng) T[((long long)tile * ng + gr) * kTile + c] = buf[c][r];
+    }
+}
+
+__global__ void from_tiled_kernel(int ng, int ncols, const double *__restrict__ T,
+                                  double *__restrict__ X, int ldx) {
+    __shared__ double buf[kTile][65];
+    const int tile = blockIdx.y;
+    const int r0 = blockIdx.x * 64;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int c = t & 15, r = (t >> 4) + 16 * q;
+        int gr = r0 + r;
+        buf[c][r] = (gr < ng) ? T[((long long)tile * ng + gr) * kTile + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int r = t & 63, c = (t >> 6) + 4 * q;
+        int gr = r0 + r, gc = tile * kTile + c;
+        if (gr < ng && gc < ncols) X[gr + (long long)gc * ldx] = buf[c][r];
+    }
+}
+
+// Real orthonormal Fourier basis of R^n: column 0 constant, columns 2k-1 / 2k
+// cos / sin of frequency k, and for even n the alternating column last.
+__device__ int mode_freq(int c, int n) {
+    if (c == 0) return 0;
+    if ((n % 2 == 0) && c == n - 1) return n / 2;
+    return (c + 1) / 2;
+}
+
+__global__ void fourier_basis_kernel(int n, double *F) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n * n) return;
+    int j = (int)(idx % n);     // grid point
+    int c = (int)(idx / n);     // basis column
+    double v;
+    if (c == 0) {
+        v = 1.0 / sqrt((double)n);
+    } else if ((n % 2 == 0) && c == n - 1) {
+        v = ((j & 1) ? -1.0 : 1.0) / sqrt((double)n);
+    } else {
+        int k = (c + 1) / 2;
+        long long kj = ((long long)k * j) % n;
+        double arg = 2.0 * (double)kj / (double)n;   // in units of pi
+        v = sqrt(2.0 / n) * ((c & 1) ? cospi(arg) : sinpi(arg));
+    }
+    F[idx] = v;
+}
+
+__device__ double neg_lap_symbol(int k, int n, double h) {
+    double s = -fd8(0);
+#pragma unroll
+    for (int q = 1; q <= 4; ++q) {
+        long long kq = ((long long)k * q) % n;
+        s -= 2.0 * fd8(q) * cospi(2.0 * (double)kq / (double)n);
+    }
+    return s / (h * h);
+}
+
+__global__ void fourier_symbol_kernel(int nx, int ny, double h, double kappa, double eps0,
+                                      double *S) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nx * ny) return;
+    int cx = idx % nx, cy = idx / nx;
+    double lam = neg_lap_symbol(mode_freq(cx, nx), nx, h);
+    if (ny > 1) lam += neg_lap_symbol(mode_freq(cy, ny), ny, h);
+    S[idx] = (4.0 * M_PI / eps0) / (lam + kappa * kappa);
+}
+
+__global__ void mul_symbol_kernel(int ng, long long tot, const double *S, double *X) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    X[idx] *= S[idx % ng];
+}
+
+// B = A^T (A m x n, B n x m), 32 x 32 tiles through LDS.
+__global__ void transpose_kernel(int m, int n, const double *A, int lda, double *B, int ldb) {
+    __shared__ double tileb[32][33];
+    int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+    for (int k = ty; k < 32; k += 8) {
+        int i = bx + tx, j = by + k;
+        tileb[k][tx] = (i < m && j < n) ? A[i + (long long)j * lda] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        int j = by + tx, i = bx + k;
+        if (i < m && j < n) B[j + (long long)i * ldb] = tileb[tx][k];
+    }
+}
+
+inline unsigned nblk(long long tot, int b) { return (unsigned)((tot + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_transpose(int m, int n, const double *A, int lda, double *B, int ldb,
+                            hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    dim3 grid(nblk(m, 32), nblk(n, 32));
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, m, n, A, lda, B, ldb);
+    return hipGetLastError();
+}
+
+hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, double *Y, int ldy,
+                          const double *V, double c_lap, double c_v, double c_0,
+                          const double *shift_dev, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid(nblk(g.ng, 256), n);
+    hipLaunchKernelGGL(stencil_kernel, grid, dim3(256), 0, s, g.dim, g.nx, g.ny, g.ng, n, X, ldx,
+                       Y, ldy, V, c_lap / (g.h * g.h), c_v, c_0, shift_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(int m, int n, double alpha, const double *X, int ldx, double *Y,
+                             int ldy, hipStream_t s) {
+    long long tot = (long long)m * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, alpha, X,
+                       ldx, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int nsel, int n, const int *sel, const double *X, int ldx, double *Y,
+                              int ldy, hipStream_t s) {
+    long long tot = (long long)nsel * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, nsel, n, sel, X,
+                       ldx, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_identity(int nsel, const int *sel, double *Xi, int ld, hipStream_t s) {
+    long long tot = (long long)nsel * nsel;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_identity_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, nsel, sel,
+                       Xi, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_identity_neg(int n, double *T, int ld, hipStream_t s) {
+    long long tot = (long long)n * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(add_identity_neg_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, n, T, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_sqnorm(int m, int n, const double *X, int ldx, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_sqnorm_kernel, dim3(n), dim3(256), 0, s, m, X, ldx, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_diff_sqnorm(int m, int n, const double *X, int ldx, const double *Y,
+                                  int ldy, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_diff_sqnorm_kernel, dim3(n), dim3(256), 0, s, m, X, ldx, Y, ldy, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(int m, int n, double a, const double *X, int ldx, double b, double *Y,
+                        int ldy, hipStream_t s) {
+    long long tot = (long long)m * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(axpby_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, a, X, ldx, b, Y,
+                       ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_sqnorm(int m, int n, const double *X, const double *Y, int ld, double *out2,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(diff_sqnorm_kernel, dim3(1), dim3(1024), 0, s, (long long)m * n, m, ld, X,
+                       Y, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_weighted_rows(int ne, int nmu, const double *L, const int *sel,
+                                const double *phi, int ldphi, double *Bc, hipStream_t s) {
+    long long tot = (long long)ne * nmu;
+    hipLaunchKernelGGL(weighted_rows_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, ne, nmu, L,
+                       sel, phi, ldphi, Bc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_check(int n, int /*unused*/, const double *G, double *maxdev,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(max_dev_identity_kernel, dim3(1), dim3(256), 0, s, n, G, maxdev);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_tiled(int ng, int ncols, int ncols_pad, const double *X, int ldx, double *T,
+                           hipStream_t s) {
+    dim3 grid(nblk(ng, 64), ncols_pad / kTile);
+    hipLaunchKernelGGL(to_tiled_kernel, grid, dim3(256), 0, s, ng, ncols, X, ldx, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_tiled(int ng, int ncols, const double *T, double *X, int ldx,
+                             hipStream_t s) {
+    dim3 grid(nblk(ng, 64), (ncols + kTile - 1) / kTile);
+    hipLaunchKernelGGL(from_tiled_kernel, grid, dim3(256), 0, s, ng, ncols, T, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_basis(int n, double *F, hipStream_t s) {
+    long long tot = (long long)n * n;
+    hipLaunchKernelGGL(fourier_basis_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, n, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_symbol(const GridDesc &g, double kappa, double eps0, double *S,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(fourier_symbol_kernel, dim3(nblk(g.ng, 256)), dim3(256), 0, s, g.nx, g.ny,
+                       g.h, kappa, eps0, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_mul_symbol(int ng, int n, const double *S, double *X, hipStream_t s) {
+    long long tot = (long long)ng * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mul_symbol_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, ng, tot, S, X);
+    return hipGetLastError();
+}
+
+}  // namespace acp
