@@ -1,0 +1,196 @@
+"""Benchmark: Sternheimer right-hand-side x shift systems solved per second.
+
+One step = one pass of the whole ACP hot path on the workload: Alg. 4 with
+k_max compressions (each: ISDF point selection, right-hand sides, the N_c N_mu
+projected shifted solves to a relative residual of 1e-8, W), the Dyson updates,
+then the dynamical matrix and its eigenvalues.  value = shifted systems solved
+per second over the timed steps (whole job; inputs already in HBM).
+
+Input preparation (ground state, perturbations, local Hessian terms) is done
+once, untimed, by paper_1605_08021_amd.workload_model.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fast|plain]
+                       [--no-cpu-baseline] [--profile-steps]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector and matrix), vendor figure
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(inp, sample_cols: int, tol: float):
+    """The oracle's plain batched CG (test infrastructure), timed on the host on a
+    bounded sample of the same shifted systems.  Returns the JSON object."""
+    import numpy as np
+    from oracle import acp as OA
+    from oracle import krylov as OK
+    from oracle.model import Grid, Model
+
+    cfg = inp.cfg
+    grid = Grid(tuple(cfg.n), cfg.h)
+    m = Model(grid, inp.R, inp.Z, inp.n_e, sigma=cfg.sigma, kappa=cfg.kappa, eps0=cfg.eps0,
+              f=cfg.f)
+    t0 = time.perf_counter()
+    dec = OA.isdf_qrcp(inp.phi, inp.G, inp.omega, cfg.n_mu)
+    nodes, _ = OA.shifts_and_weights(inp.eps[: inp.n_e], cfg.n_cheb)
+    R = OA.rhs(inp.phi, dec.xi)
+    t_prep = time.perf_counter() - t0
+    # sample: the first sample_cols // N_c right-hand sides at every shift
+    per = max(1, sample_cols // len(nodes))
+    B = np.tile(R[:, :per], (1, len(nodes)))
+    shifts = np.repeat(nodes, per)
+    op = OK.make_operator(m, inp.veff, inp.phi, shifts)
+    t0 = time.perf_counter()
+    x, it, _ = OK.cg(op, B, tol)
+    t = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": B.shape[1] / t, "unit": "systems/s", "cores": cores, "kind": "oracle",
+            "sample": f"{B.shape[1]} of the {len(nodes) * cfg.n_mu} shifted systems of one "
+                      f"compression ({per} right-hand sides x {len(nodes)} shifts), plain batched "
+                      f"CG to {tol:g}, numpy/OpenBLAS; mean iterations {float(it.mean()):.0f}; "
+                      f"solve {t:.1f} s (ISDF+RHS preparation {t_prep:.1f} s not counted)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--form", choices=["fast", "plain"], default="fast")
+    ap.add_argument("--dyson-iters", type=int, default=4)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the shifted systems are independent, see the design notes for sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1605_08021_amd import acp
+    from paper_1605_08021_amd.workload_model import build_inputs
+    from workload.seeds import get_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = get_config(args.config)
+    log(f"building inputs for workload {args.config}: {cfg.name}")
+    t0 = time.perf_counter()
+    inp = build_inputs(cfg)
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s; gap {inp.gap:.5f}, "
+        f"self-consistent {inp.self_consistent}")
+    dev = torch.device("cuda:0")
+
+    def T(a):
+        a = np.asarray(a, dtype=np.float64)
+        if a.ndim == 2:
+            return torch.from_numpy(np.ascontiguousarray(a.T)).to(dev).t()
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    phi, veff, G, om = T(inp.phi), T(inp.veff), T(inp.G), T(inp.omega)
+    solver = acp.SOLVER_CG if args.form == "fast" else acp.SOLVER_MINRES
+    opts = dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol, max_iter=20000,
+                solver=solver, dyson_max_iter=args.dyson_iters)
+    ctx = acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0,
+                           occ=cfg.f), opts, phi, inp.eps[: inp.n_e], veff)
+    masses = np.ones(inp.R.shape[0])
+
+    def step():
+        U, iters, _ = ctx.dyson(G, om)
+        D, w2 = ctx.dynmat(G, U, inp.K_local, masses)
+        return iters, w2
+
+    for i in range(args.warmup):
+        log(f"warmup step {i + 1}/{args.warmup}")
+        step()
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        iters, w2 = step()
+        log(f"step {i + 1}/{args.steps} done ({iters} compressions)")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = ctx.stats()
+    systems = st["systems_solved"]
+    value = systems / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+
+    # roofline of the dominant kernel: the fused batched Krylov solver
+    ng = inp.phi.shape[0]
+    ne = inp.n_e
+    vectors = 8 if solver == acp.SOLVER_CG else 12
+    launches = max(st["solve_kernel_launches"], 1)
+    sys_it_per_launch = st["system_iterations"] / launches
+    bytes_per_launch = vectors * 8.0 * ng * sys_it_per_launch
+    ms_per_launch = st["ms_solve_kernel"] / launches
+    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
+    flops_per_launch = 4.0 * ng * ne * sys_it_per_launch
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "cg_kernel (fused stencil + projector + CG)" if solver == acp.SOLVER_CG
+                else "minres_kernel (fused stencil + projector + MINRES)",
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "mfma_fp64_tflops": round(flops_per_launch / (ms_per_launch * 1e-3) / 1e12, 2),
+                "ms_per_launch": round(ms_per_launch, 3),
+                "system_iterations_per_launch": sys_it_per_launch,
+                "tile_iteration_efficiency": round(st["system_iterations"] /
+                                                   max(16 * st["tile_iterations"], 1), 3)}
+    log(f"stats: {json.dumps(st)}")
+    out = {
+        "metric": "Sternheimer RHS*shifts solved/s at 1e-8 residual",
+        "value": round(value, 1),
+        "unit": "systems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
+                               f"ground state, gap {inp.gap:.5f} Ha",
+                   "form": ("batched FP64 CG" if solver == acp.SOLVER_CG
+                            else "plain FP64 MINRES"),
+                   "dyson_iterations": st["dyson_iters"], "n_g": ng, "n_e": ne,
+                   "n_p": int(inp.G.shape[1]), "n_c": cfg.n_cheb, "n_mu": cfg.n_mu,
+                   "tol": args.tol},
+        "max_true_rel_residual": st["max_rel_residual"],
+        "iters_min_max_last_solve": [st["iters_min"], st["iters_max"]],
+        "phase_ms_per_step": {k: round(st[k] / args.steps, 2) for k in
+                              ("ms_isdf", "ms_rhs", "ms_solve", "ms_w", "ms_dyson_small",
+                               "ms_dynmat")},
+        "roofline": roofline,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle CG on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(inp, args.cpu_sample, args.tol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -36,9 +36,9 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int NT = 256;       // threads per workgroup (4 waves)
-constexpr int CH = 64;        // rows per chunk
-constexpr int MAXNB = 16;     // up to 256 (padded) orbitals
+constexpr int NW = 8;             // waves per workgroup (2 per SIMD)
+constexpr int NT = 64 * NW;       // threads per workgroup
+constexpr int MAXNB = 16;         // up to 256 (padded) orbitals
 
 __device__ __forceinline__ int wrap(int i, int n) {
     if (i < 0) i += n;
@@ -46,53 +46,75 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return i;
 }
 
-// y = (H - s) p at rows R..R+3 of one system; pf(row) returns p(row).
-// Rows >= ng give y = p = 0.
-template <int DIM, class PF>
-__device__ __forceinline__ void stencil4(PF pf, int R, const GridDesc &g, const double *__restrict__ V,
-                                         double s, double (&y)[4], double (&pc)[4]) {
-    const double c2 = -0.5 / (g.h * g.h);
-    if (DIM == 1) {
-        double w[12];
+// Neighbour rows of the 4-row group R..R+3 of one system, for the 8th-order
+// stencil.  1D: rows R-4 .. R+7 (12 rows, periodic).  2D: for each of the 4 rows
+// its 8 x-neighbours and 8 y-neighbours.  Every index is clamped into [0, ng)
+// so that all loads can be issued unconditionally (rows past the end of the grid
+// in the last block are computed but never stored).
+template <int DIM>
+struct Nbr {
+    static constexpr int N = DIM == 1 ? 12 : 4 * 17;
+    int idx[N];
+    __device__ __forceinline__ Nbr(int R, const GridDesc &g) {
+        if (DIM == 1) {
 #pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            // rows past the end (last chunk) are computed but unused; keep every
-            // load inside [0, ng) for any grid size
-            int rr = (R - 4 + q) % g.ng;
-            if (rr < 0) rr += g.ng;
-            w[q] = pf(rr);
+            for (int q = 0; q < 12; ++q) {
+                int rr = R - 4 + q;
+                rr = rr < 0 ? rr + g.ng : rr;
+                rr = rr >= g.ng ? rr - g.ng : rr;
+                idx[q] = rr < g.ng ? rr : g.ng - 1;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int row = R + j;
+                row = row < g.ng ? row : g.ng - 1;
+                const int ix = row % g.nx, iy = row - ix;
+                idx[17 * j] = row;
+#pragma unroll
+                for (int k = 1; k <= 4; ++k) {
+                    idx[17 * j + k] = iy + wrap(ix + k, g.nx);
+                    idx[17 * j + 4 + k] = iy + wrap(ix - k, g.nx);
+                    const int iyk = iy / g.nx;
+                    idx[17 * j + 8 + k] = wrap(iyk + k, g.ny) * g.nx + ix;
+                    idx[17 * j + 12 + k] = wrap(iyk - k, g.ny) * g.nx + ix;
+                }
+            }
         }
+    }
+};
+
+// y = (H - s) p at rows R..R+3 from gathered values w[] laid out as in Nbr.
+template <int DIM>
+__device__ __forceinline__ void stencil_from(const double (&w)[Nbr<DIM>::N], int R,
+                                             const GridDesc &g, const double *__restrict__ V,
+                                             double s, double (&y)[4], double (&pc)[4]) {
+    const double c2 = -0.5 / (g.h * g.h);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double lap = fd8(0) * w[4 + j];
+    for (int j = 0; j < 4; ++j) {
+        const int row = R + j;
+        const bool ok = row < g.ng;
+        const double v = V[ok ? row : g.ng - 1];
+        double c, lap;
+        if (DIM == 1) {
+            c = w[4 + j];
+            lap = fd8(0) * c;
 #pragma unroll
             for (int k = 1; k <= 4; ++k) lap += fd8(k) * (w[4 + j + k] + w[4 + j - k]);
-            const bool ok = (R + j) < g.ng;
-            pc[j] = ok ? w[4 + j] : 0.0;
-            y[j] = ok ? (c2 * lap + (V[ok ? R + j : 0] - s) * w[4 + j]) : 0.0;
-        }
-    } else {
+        } else {
+            c = w[17 * j];
+            lap = 2.0 * fd8(0) * c;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int row = R + j;
-            if (row >= g.ng) { y[j] = 0.0; pc[j] = 0.0; continue; }
-            const int ix = row % g.nx, iy = row / g.nx;
-            const double c = pf(row);
-            double lap = 2.0 * fd8(0) * c;
-#pragma unroll
-            for (int k = 1; k <= 4; ++k) {
-                lap += fd8(k) * (pf(iy * g.nx + wrap(ix + k, g.nx)) + pf(iy * g.nx + wrap(ix - k, g.nx)));
-                lap += fd8(k) * (pf(wrap(iy + k, g.ny) * g.nx + ix) + pf(wrap(iy - k, g.ny) * g.nx + ix));
-            }
-            pc[j] = c;
-            y[j] = c2 * lap + (V[row] - s) * c;
+            for (int k = 1; k <= 4; ++k)
+                lap += fd8(k) * (w[17 * j + k] + w[17 * j + 4 + k] + w[17 * j + 8 + k] + w[17 * j + 12 + k]);
         }
+        pc[j] = ok ? c : 0.0;
+        y[j] = ok ? (c2 * lap + (v - s) * c) : 0.0;
     }
 }
 
-// Sum over the 16 threads of one column (threads t with t % 16 == col) of a
-// per-thread value, in a fixed order.  Returns the total to threads col < 16
-// through red_out[col].
+// Sum over the threads of one column (threads t with t % 16 == col) of a
+// per-thread value, in a fixed order; the total lands in red_out[col].
 __device__ __forceinline__ void column_reduce(double v, double *red, double *red_out) {
     red[threadIdx.x] = v;
     __syncthreads();
@@ -105,86 +127,135 @@ __device__ __forceinline__ void column_reduce(double v, double *red, double *red
     __syncthreads();
 }
 
-// Pass "projected apply", part 1: given p (via pf), stage y per chunk in LDS and
-// accumulate C = Phi^T y on the matrix cores; returns this thread's share of p^T y.
-template <int DIM, int NB, class PF>
-__device__ __forceinline__ double apply_pass1(PF pf, const KrylovArgs &a, double s, double *ys,
-                                              double *Cs, d4 (&acc)[(NB + 3) / 4], double *pstore) {
+// LDS slots for the cross-wave reduction of C = Phi^T y (64 KB in total).
+template <int NB>
+struct Slots {
+    static constexpr int NEP = NB * 16;
+    static constexpr int N = (512 / NEP) < NW ? (512 / NEP) : NW;
+    static constexpr int ELEMS = NEP * kTile;
+};
+
+// Pass 1 of the projected apply.  Each wave owns the 16-row blocks b = wave,
+// wave + NW, ...; lane l (q = l/16) computes p and y = (H - s) p at the four
+// consecutive rows 16 b + 4 q + j of system l % 16 and feeds y(row) to the
+// MFMA k-step j, whose k index q stands for that row (the contraction runs
+// over rows, so any row order works as long as the A operand follows it).
+// C = Phi^T y is reduced across waves in LDS into slots[0] (orbital-major,
+// 16 systems per orbital).  Returns this thread's share of p^T y.
+template <int DIM, int NB>
+__device__ __forceinline__ double apply_pass1(const double *__restrict__ rv, const double *__restrict__ pv,
+                                              double beta, const KrylovArgs &a, double s,
+                                              double *slots, double *__restrict__ pstore) {
     const int t = threadIdx.x;
-    const int col = t & 15;
-    const int grp = t >> 4;         // 0..15 -> 4 rows each
     const int lane = t & 63;
     const int wave = t >> 6;
-    constexpr int NBW = (NB + 3) / 4;
-    const int nep = NB * 16;
+    const int col = lane & 15;
+    const int q = lane >> 4;
+    constexpr int nep = NB * 16;
+    constexpr int NN = Nbr<DIM>::N;
+    d4 acc[NB];
 #pragma unroll
-    for (int b = 0; b < NBW; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
     double pty = 0.0;
-    for (int r0 = 0; r0 < a.g.ng; r0 += CH) {
-        const int R = r0 + 4 * grp;
-        double y[4], pc[4];
-        stencil4<DIM>(pf, R, a.g, a.veff, s, y, pc);
+    for (int blk = wave; blk * 16 < a.g.ng; blk += NW) {
+        const int R = blk * 16 + 4 * q;
+        const Nbr<DIM> nb(R, a.g);
+        // issue every load of the block before any use
+        double w[NN], wp[NN];
+#pragma unroll
+        for (int k = 0; k < NN; ++k) w[k] = rv[nb.idx[k] * kTile + col];
+        if (pv) {
+#pragma unroll
+            for (int k = 0; k < NN; ++k) wp[k] = pv[nb.idx[k] * kTile + col];
+        }
+        double av[4][NB];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            ys[(4 * grp + j) * kTile + col] = y[j];
+            const int row = R + j < a.g.ng ? R + j : a.g.ng - 1;
+            const double *ph = a.phi_rm + (long long)row * nep + col;
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb) av[j][mb] = ph[mb * 16];
+        }
+        if (pv) {
+#pragma unroll
+            for (int k = 0; k < NN; ++k) w[k] += beta * wp[k];
+        }
+        double y[4], pc[4];
+        stencil_from<DIM>(w, R, a.g, a.veff, s, y, pc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
             pty += pc[j] * y[j];
             if (pstore && R + j < a.g.ng) pstore[(R + j) * kTile + col] = pc[j];
         }
-        __syncthreads();
-        // C(orb, col) += sum_rows Phi(row, orb) y(row, col): waves split orbital blocks
+        // rows past the end contribute y = 0, so their (clamped) Phi rows are harmless
 #pragma unroll
-        for (int b = 0; b < NBW; ++b) {
-            const int mb = wave + 4 * b;
-            if (mb < NB) {
-#pragma unroll 4
-                for (int ks = 0; ks < CH / 4; ++ks) {
-                    const int row = r0 + 4 * ks + (lane >> 4);
-                    const double av = (row < a.g.ng) ? a.phi_rm[(long long)row * nep + mb * 16 + (lane & 15)] : 0.0;
-                    const double bv = ys[(4 * ks + (lane >> 4)) * kTile + (lane & 15)];
-                    acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb)
+                acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][mb], y[j], acc[mb], 0, 0, 0);
+    }
+    // deterministic cross-wave reduction: phases of Slots::N waves
+    using S = Slots<NB>;
+#pragma unroll 1
+    for (int ph = 0; ph < NW / S::N; ++ph) {
+        if (wave / S::N == ph) {
+            double *dst = slots + (wave % S::N) * S::ELEMS;
+#pragma unroll
+            for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int idx = (mb * 16 + q + 4 * e) * kTile + col;
+                    if (ph == 0) dst[idx] = acc[mb][e];
+                    else dst[idx] += acc[mb][e];
                 }
-            }
         }
         __syncthreads();
     }
-    // publish C to LDS: Cs[orb * 16 + col]
+    for (int idx = t; idx < S::ELEMS; idx += NT) {
+        double v = slots[idx];
 #pragma unroll
-    for (int b = 0; b < NBW; ++b) {
-        const int mb = wave + 4 * b;
-        if (mb < NB) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) Cs[(mb * 16 + (lane >> 4) + 4 * e) * kTile + (lane & 15)] = acc[b][e];
-        }
+        for (int k = 1; k < S::N; ++k) v += slots[k * S::ELEMS + idx];
+        slots[idx] = v;
     }
     return pty;
 }
 
-// Part 2 helper: for the 16-row block starting at row0, D = Phi(rows,:) C on
+// Pass 2 helper: for the 16-row block starting at row0, D = Phi(rows,:) C on
 // the matrix cores.  The f64 MFMA returns D[l/16 + 4 e][l%16] to lane l, so the
 // A operand feeds grid row 4 (m % 4) + m / 4 into MFMA row m: lane l then holds
 // the consecutive grid rows row0 + 4*(l/16) + e of system l % 16.
 template <int NB>
 __device__ __forceinline__ d4 project_block(const KrylovArgs &a, const double *Cs, int row0) {
     const int lane = threadIdx.x & 63;
-    const int nep = NB * 16;
-    d4 d = d4{0.0, 0.0, 0.0, 0.0};
+    constexpr int nep = NB * 16;
     const int m = lane & 15;
-    const int row = row0 + 4 * (m & 3) + (m >> 2);
-    const bool ok = row < a.g.ng;
-#pragma unroll 8
-    for (int k = 0; k < nep; k += 4) {
-        const int orb = k + (lane >> 4);
-        const double av = ok ? a.phi_cm[(long long)orb * a.g.ng + row] : 0.0;
-        const double bv = Cs[orb * kTile + (lane & 15)];
-        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+    int row = row0 + 4 * (m & 3) + (m >> 2);
+    row = row < a.g.ng ? row : a.g.ng - 1;   // clamped rows feed outputs that are never stored
+    const double *ph = a.phi_cm + row + (long long)(lane >> 4) * a.g.ng;
+    double av[nep / 4];
+#pragma unroll
+    for (int k = 0; k < nep / 4; ++k) av[k] = ph[(long long)(4 * k) * a.g.ng];
+    d4 d = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < nep / 4; ++k) {
+        const double bv = Cs[(4 * k + (lane >> 4)) * kTile + (lane & 15)];
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv, d, 0, 0, 0);
     }
     return d;
 }
 
+// Gather the stencil neighbourhood of rows R..R+3 of one system from v.
+template <int DIM>
+__device__ __forceinline__ void gather(const double *__restrict__ v, int R, const GridDesc &g,
+                                       int col, double (&w)[Nbr<DIM>::N]) {
+    const Nbr<DIM> nb(R, g);
+#pragma unroll
+    for (int k = 0; k < Nbr<DIM>::N; ++k) w[k] = v[nb.idx[k] * kTile + col];
+}
+
 template <int DIM, int NB>
 __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
-    __shared__ double ys[CH * kTile];
-    __shared__ double Cs[NB * 16 * kTile];
+    __shared__ double slots[Slots<NB>::N * Slots<NB>::ELEMS];
     __shared__ double red[NT];
     __shared__ double s_rr[kTile], s_alpha[kTile], s_beta[kTile], s_bn[kTile], s_tmp[kTile];
     __shared__ int s_active[kTile], s_iters[kTile], s_flag[kTile], s_any;
@@ -221,7 +292,6 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
     }
     __syncthreads();
 
-    d4 acc[(NB + 3) / 4];
     int it = 0;
     for (; it < a.max_iter; ++it) {
         if (t == 0) {
@@ -233,8 +303,7 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
         if (!s_any) break;
         // ---- pass 1: p = r + beta p_old (into pB), y = (H - s) p, C = Phi^T y, p^T y
         const double beta = s_beta[col];
-        auto pf1 = [&](int row) { return r[row * kTile + col] + beta * pA[row * kTile + col]; };
-        double pty = apply_pass1<DIM, NB>(pf1, a, s, ys, Cs, acc, pB);
+        const double pty = apply_pass1<DIM, NB>(r, pA, beta, a, s, slots, pB);
         column_reduce(pty, red, s_tmp);
         if (t < kTile) {
             double al = 0.0;
@@ -251,29 +320,34 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
         __syncthreads();
         // ---- pass 2: A p = y - Phi C; x += alpha p; r -= alpha A p; |r|^2
         double rr_part = 0.0;
-        for (int r0 = 0; r0 < a.g.ng; r0 += CH) {
-            const int row0 = r0 + 16 * wave;
-            const d4 d = project_block<NB>(a, Cs, row0);
+        const double al = s_alpha[col];
+        for (int blk = wave; blk * 16 < a.g.ng; blk += NW) {
+            const int row0 = blk * 16;
             const int R = row0 + 4 * (lane >> 4);
-            const int c = lane & 15;
-            auto pf2 = [&](int row) { return pB[row * kTile + c]; };
-            double y[4], pc[4];
-            stencil4<DIM>(pf2, R, a.g, a.veff, a.shift[tile * kTile + c], y, pc);
-            const double al = s_alpha[c];
+            double w[Nbr<DIM>::N];
+            gather<DIM>(pB, R, a.g, col, w);
+            double xo[4], ro[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = R + e;
-                if (row < a.g.ng) {
-                    const double ap = y[e] - d[e];
-                    const double xn = x[row * kTile + c] + al * pc[e];
-                    const double rn = r[row * kTile + c] - al * ap;
-                    x[row * kTile + c] = xn;
-                    r[row * kTile + c] = rn;
+                const int row = R + e < a.g.ng ? R + e : a.g.ng - 1;
+                xo[e] = x[row * kTile + col];
+                ro[e] = r[row * kTile + col];
+            }
+            const d4 d = project_block<NB>(a, slots, row0);
+            double y[4], pc[4];
+            stencil_from<DIM>(w, R, a.g, a.veff, s, y, pc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double ap = y[e] - d[e];
+                const double xn = xo[e] + al * pc[e];
+                const double rn = ro[e] - al * ap;
+                if (R + e < a.g.ng) {
+                    x[(R + e) * kTile + col] = xn;
+                    r[(R + e) * kTile + col] = rn;
                     rr_part += rn * rn;
                 }
             }
         }
-        // lane's column is lane & 15 == t & 15: column_reduce applies
         column_reduce(rr_part, red, s_tmp);
         if (t < kTile) {
             if (s_active[t]) {
@@ -301,8 +375,7 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
 // w, wo (direction vectors), x.  Buffers: pa = v, pb = vo, w1 = w, w2 = wo.
 template <int DIM, int NB>
 __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
-    __shared__ double ys[CH * kTile];
-    __shared__ double Cs[NB * 16 * kTile];
+    __shared__ double slots[Slots<NB>::N * Slots<NB>::ELEMS];
     __shared__ double red[NT];
     __shared__ double s_beta[kTile], s_alpha[kTile], s_bn[kTile], s_tmp[kTile];
     __shared__ double s_cs[kTile], s_sn[kTile], s_dbar[kTile], s_epsn[kTile], s_phibar[kTile];
@@ -353,7 +426,6 @@ __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
     }
     __syncthreads();
 
-    d4 acc[(NB + 3) / 4];
     int it = 0;
     for (; it < a.max_iter; ++it) {
         if (t == 0) {
@@ -364,26 +436,30 @@ __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
         __syncthreads();
         if (!s_any) break;
         // ---- pass 1: y = (H - s) v, C = Phi^T y, alpha = v^T y
-        auto pf1 = [&](int row) { return v[row * kTile + col]; };
-        double vty = apply_pass1<DIM, NB>(pf1, a, s, ys, Cs, acc, nullptr);
+        const double vty = apply_pass1<DIM, NB>(v, nullptr, 0.0, a, s, slots, nullptr);
         column_reduce(vty, red, s_alpha);
         // ---- pass 2: v_new = (y - Phi C) - alpha v - beta v_old  (into vo), |v_new|^2
         double nn = 0.0;
-        for (int r0 = 0; r0 < a.g.ng; r0 += CH) {
-            const int row0 = r0 + 16 * wave;
-            const d4 d = project_block<NB>(a, Cs, row0);
+        const double al = s_alpha[col], be = s_beta[col];
+        for (int blk = wave; blk * 16 < a.g.ng; blk += NW) {
+            const int row0 = blk * 16;
             const int R = row0 + 4 * (lane >> 4);
-            const int c = lane & 15;
-            auto pf2 = [&](int row) { return v[row * kTile + c]; };
-            double y[4], pc[4];
-            stencil4<DIM>(pf2, R, a.g, a.veff, a.shift[tile * kTile + c], y, pc);
-            const double al = s_alpha[c], be = s_beta[c];
+            double w[Nbr<DIM>::N];
+            gather<DIM>(v, R, a.g, col, w);
+            double vold[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = R + e;
-                if (row < a.g.ng) {
-                    const double vn = (y[e] - d[e]) - al * pc[e] - be * vo[row * kTile + c];
-                    vo[row * kTile + c] = vn;
+                const int row = R + e < a.g.ng ? R + e : a.g.ng - 1;
+                vold[e] = vo[row * kTile + col];
+            }
+            const d4 d = project_block<NB>(a, slots, row0);
+            double y[4], pc[4];
+            stencil_from<DIM>(w, R, a.g, a.veff, s, y, pc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double vn = (y[e] - d[e]) - al * pc[e] - be * vold[e];
+                if (R + e < a.g.ng) {
+                    vo[(R + e) * kTile + col] = vn;
                     nn += vn * vn;
                 }
             }
@@ -392,11 +468,11 @@ __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
         // ---- rotations (per system)
         if (t < kTile) {
             const double beta_new = sqrt(s_tmp[t]);
-            const double al = s_alpha[t];
+            const double alk = s_alpha[t];
             const double cs = s_cs[t], sn = s_sn[t];
             const double epsk = s_epsn[t];
-            const double delta = cs * s_dbar[t] + sn * al;
-            const double gbar = sn * s_dbar[t] - cs * al;
+            const double delta = cs * s_dbar[t] + sn * alk;
+            const double gbar = sn * s_dbar[t] - cs * alk;
             const double epsn = sn * beta_new;
             const double dbar = -cs * beta_new;
             double gamma = sqrt(gbar * gbar + beta_new * beta_new);
@@ -420,16 +496,17 @@ __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
         }
         __syncthreads();
         // ---- pass 3: w_new = (v - eps_k wo - delta w) / gamma (into wo); x += phi w_new;
-        //      v_old <- v, v <- v_new / beta_new   (swap by copying the scaled vector)
-        for (int idx = t; idx < a.g.ng * kTile; idx += NT) {
-            const int c = idx & 15;
-            if (s_active[c]) {
+        //      v_old <- v, v <- v_new / beta_new
+        if (s_active[col]) {
+            const double ek = s_epsk[col], dl = s_delta[col], gi = 1.0 / s_gamma[col];
+            const double ph = s_phi[col], bi = s_binv[col];
+            for (int idx = t; idx < a.g.ng * kTile; idx += NT) {
                 const double vv = v[idx];
-                const double wn = (vv - s_epsk[c] * wo[idx] - s_delta[c] * w[idx]) / s_gamma[c];
+                const double wn = (vv - ek * wo[idx] - dl * w[idx]) * gi;
                 wo[idx] = w[idx];
                 w[idx] = wn;
-                x[idx] += s_phi[c] * wn;
-                const double vn = vo[idx] * s_binv[c];
+                x[idx] += ph * wn;
+                const double vn = vo[idx] * bi;
                 vo[idx] = vv;
                 v[idx] = vn;
             }

@@ -1,0 +1,207 @@
+"""Synthetic inputs for the library (outside the hot path, not timed).
+
+The library consumes a ground state {phi_i, eps_i} of H[V_eff], the
+perturbation vectors G and, for the dynamical matrix, the non-response part of
+the Hessian.  This module builds them for a workload configuration from the
+discrete model of Sec. 4.1 (Gaussian pseudocharges, Eq. (4.2); Yukawa kernel,
+Eq. (4.3)-(4.4); H of Eq. (4.1)) on the same 8th-order finite-difference grid
+as the library.  It is independent of the test oracle.
+
+Ground state.  By default the potential is Harris-type (not self-consistent):
+V_eff = v_c(rho_at + m) with rho_at the superposition of neutral-atom densities
+obtained from one isolated-atom SCF, scaled by Z_I / Z_ref.  The orbitals and
+eigenvalues are then the exact lowest eigenpairs of H[V_eff], which is all the
+ACP hot path requires.  ``scf_iters > 0`` continues with Kerker-preconditioned
+density mixing.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg as sla
+
+from workload.seeds import Config, draw_sites
+
+_C = (-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0)
+
+
+def _second_derivative_matrix(n: int, h: float) -> np.ndarray:
+    """Periodic 8th-order central second-derivative matrix (n x n)."""
+    D = np.zeros((n, n))
+    for s in range(-4, 5):
+        c = _C[abs(s)] / h ** 2
+        idx = np.arange(n)
+        D[idx, (idx + s) % n] += c
+    return D
+
+
+def _lap_symbol(n: int, h: float) -> np.ndarray:
+    k = np.arange(n)
+    th = 2.0 * np.pi * k / n
+    return (-_C[0] - 2.0 * sum(_C[s] * np.cos(s * th) for s in range(1, 5))) / h ** 2
+
+
+@dataclasses.dataclass
+class Inputs:
+    cfg: Config
+    n: tuple
+    h: float
+    R: np.ndarray
+    Z: np.ndarray
+    n_e: int
+    phi: np.ndarray      # N_g x N_e
+    eps: np.ndarray      # N_e + 1 lowest eigenvalues
+    veff: np.ndarray
+    rho: np.ndarray
+    G: np.ndarray        # N_g x d N_A
+    K_local: np.ndarray  # d N_A x d N_A
+    omega: np.ndarray    # sketch, from the shared seeded draws
+    self_consistent: bool
+
+    @property
+    def gap(self) -> float:
+        return float(self.eps[self.n_e] - self.eps[self.n_e - 1])
+
+
+class _Grid:
+    def __init__(self, n, h, kappa, eps0):
+        self.n = tuple(n)
+        self.h = h
+        self.d = len(n)
+        self.ng = int(np.prod(n))
+        self.dv = h ** self.d
+        self.shape = tuple(reversed(self.n))          # C order, x fastest
+        sym = _lap_symbol(n[0], h)
+        if self.d == 2:
+            sym = _lap_symbol(n[1], h)[:, None] + sym[None, :]
+        self.vc_sym = (4.0 * np.pi / eps0) / (sym + kappa ** 2)
+
+    def coords(self):
+        ax = [np.arange(k) * self.h for k in self.n]
+        mesh = np.meshgrid(*ax, indexing="ij")
+        return np.stack([q.ravel(order="F") for q in mesh], axis=1)
+
+    def vc(self, x):
+        extra = x.shape[1:]
+        xx = x.reshape(self.shape + extra)
+        axes = tuple(range(self.d))
+        s = self.vc_sym.reshape(self.vc_sym.shape + (1,) * len(extra))
+        return np.fft.ifftn(np.fft.fftn(xx, axes=axes) * s, axes=axes).real.reshape(x.shape)
+
+    def kinetic_dense(self):
+        """-1/2 Delta_h as a dense matrix."""
+        if self.d == 1:
+            return -0.5 * _second_derivative_matrix(self.n[0], self.h)
+        Dx = _second_derivative_matrix(self.n[0], self.h)
+        Dy = _second_derivative_matrix(self.n[1], self.h)
+        return -0.5 * (np.kron(np.eye(self.n[1]), Dx) + np.kron(Dy, np.eye(self.n[0])))
+
+
+def _gaussians(grid: _Grid, R, Z, sigma):
+    X = grid.coords()
+    L = np.array([k * grid.h for k in grid.n])
+    D = X[:, None, :] - R[None, :, :]
+    D -= L * np.round(D / L)
+    r2 = (D ** 2).sum(axis=2)
+    m_each = -Z[None, :] * (2 * np.pi * sigma ** 2) ** (-grid.d / 2) * np.exp(-r2 / (2 * sigma ** 2))
+    return m_each, D
+
+
+def _lowest(H, k):
+    return sla.eigh(H, subset_by_index=[0, k - 1], driver="evr")
+
+
+def _kerker(grid: _Grid, q0: float = 0.3) -> np.ndarray:
+    q2 = np.zeros(grid.shape)
+    for ax, k in enumerate(reversed(grid.n)):
+        q = 2 * np.pi * np.fft.fftfreq(k, d=grid.h)
+        sh = [1] * grid.d
+        sh[ax] = k
+        q2 = q2 + (q ** 2).reshape(sh)
+    return q2 / (q2 + q0 ** 2)
+
+
+def _scf(grid: _Grid, T, m, rho, n_occ, f, iters, tol, beta=0.3, hist=10):
+    """Density mixing: Pulay extrapolation over the last residuals, then a
+    Kerker-preconditioned step.  Returns (rho, eigenvalues, vectors, converged)."""
+    kk = _kerker(grid)
+    xs, fs = [], []
+    conv = False
+    for _ in range(iters):
+        V = grid.vc(rho + m)
+        w, v = _lowest(T + np.diag(V), n_occ + 1)
+        out = (f / grid.dv) * (v[:, :n_occ] ** 2).sum(axis=1)
+        res = out - rho
+        if np.abs(res).max() <= tol * out.max():
+            conv = True
+            break
+        xs.append(rho.copy())
+        fs.append(res.copy())
+        if len(xs) > hist:
+            xs.pop(0)
+            fs.pop(0)
+        if len(xs) > 1:
+            dX = np.stack([xs[i + 1] - xs[i] for i in range(len(xs) - 1)], 1)
+            dF = np.stack([fs[i + 1] - fs[i] for i in range(len(fs) - 1)], 1)
+            g, *_ = np.linalg.lstsq(dF, res, rcond=None)
+            rb, fb = rho - dX @ g, res - dF @ g
+        else:
+            rb, fb = rho, res
+        rho = rb + beta * np.fft.ifftn(np.fft.fftn(fb.reshape(grid.shape)) * kk).real.ravel()
+    V = grid.vc(rho + m)
+    w, v = _lowest(T + np.diag(V), n_occ + 1)
+    return rho, V, w, v, conv
+
+
+def _atom_density(cfg: Config, z_ref: float) -> tuple:
+    """Density of one neutral atom (charge z_ref) from an SCF in an isolated box
+    of 4 lattice spacings per axis; returned as a radial table (r, rho)."""
+    box_sites = 4
+    n = tuple(int(round(box_sites * cfg.a / cfg.h)) for _ in range(cfg.dim))
+    grid = _Grid(n, cfg.h, cfg.kappa, cfg.eps0)
+    c = np.array([[0.5 * box_sites * cfg.a] * cfg.dim])
+    m_each, D = _gaussians(grid, c, np.array([z_ref]), cfg.sigma)
+    m = m_each[:, 0]
+    n_occ = max(1, int(round(z_ref / cfg.f)))
+    rho, _, _, v, conv = _scf(grid, grid.kinetic_dense(), m, -m.copy(), n_occ, cfg.f, 300, 1e-10)
+    if not conv:
+        raise RuntimeError("isolated-atom SCF did not converge")
+    r = np.sqrt((D[:, 0, :] ** 2).sum(axis=1))
+    order = np.argsort(r)
+    return r[order], rho[order]
+
+
+def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
+    R, Z, n_e = draw_sites(cfg)
+    grid = _Grid(cfg.n, cfg.h, cfg.kappa, cfg.eps0)
+    m_each, D = _gaussians(grid, R, Z, cfg.sigma)
+    m = m_each.sum(axis=1)
+    z_ref = cfg.f
+    r_tab, rho_tab = _atom_density(cfg, z_ref)
+    dist = np.sqrt((D ** 2).sum(axis=2))
+    rho = np.zeros(grid.ng)
+    for I in range(R.shape[0]):
+        rho += (Z[I] / z_ref) * np.interp(dist[:, I], r_tab, rho_tab, right=0.0)
+    # exact neutrality of the start
+    rho *= (cfg.f * n_e) / (rho.sum() * grid.dv)
+    T = grid.kinetic_dense()
+    rho, V, w, v, sc = _scf(grid, T, m, rho, n_e, cfg.f, max(scf_iters, 0) + 1, 1e-8)
+    phi = np.ascontiguousarray(v[:, :n_e])
+    rho_gs = (cfg.f / grid.dv) * (phi ** 2).sum(axis=1)
+    # perturbations g_{I,a} = v_c d m_I / d R_{I,a} and the local Hessian terms
+    d = cfg.dim
+    n_a = R.shape[0]
+    dm = (m_each[:, :, None] * D / cfg.sigma ** 2).reshape(grid.ng, n_a * d)
+    G = grid.vc(dm)
+    K = grid.dv * (dm.T @ G)
+    pot = grid.vc(rho_gs + m)
+    own = grid.vc(m_each)
+    for I in range(n_a):
+        d2 = m_each[:, I, None, None] * (D[:, I, :, None] * D[:, I, None, :] / cfg.sigma ** 4
+                                          - np.eye(d)[None] / cfg.sigma ** 2)
+        K[d * I:d * I + d, d * I:d * I + d] = grid.dv * np.einsum("gab,g->ab", d2, pot - own[:, I])
+    from workload.seeds import draw_sketch
+    return Inputs(cfg=cfg, n=tuple(cfg.n), h=cfg.h, R=R, Z=Z, n_e=n_e, phi=phi, eps=w,
+                  veff=V, rho=rho_gs, G=G, K_local=K, omega=draw_sketch(cfg, n_a * d),
+                  self_consistent=sc)
