@@ -62,7 +62,7 @@ struct acp_ctx {
     DevBuf gt, lchol, diag, isdf_scratch, l11, linv, c1, bc, tmp1, tmp2, tmp3, shifts_dev;
     DevBuf kx, kr, kpa, kpb, kw1, kw2, krhs, kiters, kresid, kflags, ktile;
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm;
-    DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym;
+    DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     acp_stats stats{};
     std::string err;
     hipEvent_t ev[8]{};
@@ -378,13 +378,13 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
     const int rank_bound = std::min(r * ctx->ne, ng);
     if (nmu < 1 || nmu > rank_bound)
         return fail(ctx, ACP_EINVAL, "n_mu must satisfy 1 <= n_mu <= min(r n_e, N_g)");
-    // G~ = G Omega
+    // G~ = G Omega, stored row-major (r x N_g column-major): G~^T = Omega^T G^T
     ENSURE(ctx->gt, (size_t)ng * r * 8);
-    HIPCHK(gemm(Op::N, Op::N, ng, r, n_p, 1.0, G, ng, 0, omega, n_p, 0, 0.0, dp<double>(ctx->gt),
-                ng, 0, 1, s));
+    HIPCHK(gemm(Op::T, Op::T, r, ng, n_p, 1.0, omega, n_p, 0, G, ng, 0, 0.0, dp<double>(ctx->gt),
+                r, 0, 1, s));
     ENSURE(ctx->lchol, (size_t)ng * nmu * 8);
     ENSURE(ctx->diag, (size_t)ng * 8);
-    ENSURE(ctx->isdf_scratch, 64);
+    ENSURE(ctx->isdf_scratch, isdf_scratch_bytes(ng));
     ENSURE(ctx->sel_dev, (size_t)nmu * 4);
     const int *forced = nullptr;
     if (sel_in) {
@@ -395,9 +395,10 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
         forced = dp<int>(ctx->forced_dev);
     }
     int got = 0;
-    HIPCHK(isdf_pivoted_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), ng, dp<double>(ctx->gt),
-                                 ng, nmu, sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol),
-                                 ng, dp<double>(ctx->diag), dp<int>(ctx->sel_dev), forced, &got,
+    const int ldl = nmu;
+    HIPCHK(isdf_pivoted_cholesky(ng, ctx->nep, r, dp<double>(ctx->phi_rm), dp<double>(ctx->gt), nmu,
+                                 sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol), ldl,
+                                 dp<double>(ctx->diag), dp<int>(ctx->sel_dev), forced, &got,
                                  ctx->isdf_scratch.p, s));
     if (got < 1) return fail(ctx, ACP_EINVAL, "interpolative decomposition found no pivot");
     if (sel_in && got < nmu)
@@ -409,13 +410,12 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
     HIPCHK(hipMemcpyAsync(ctx->sel_host.data(), ctx->sel_dev.p, (size_t)nmu * 4,
                           hipMemcpyDeviceToHost, s));
     // Xi = L L11^{-1}, Xi(Pi, :) = I
-    ENSURE(ctx->l11, (size_t)nmu * nmu * 8);
     ENSURE(ctx->linv, (size_t)nmu * nmu * 8);
-    HIPCHK(launch_gather_lower(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->lchol), ng,
-                               dp<double>(ctx->l11), s));
-    HIPCHK(launch_tri_inverse_lower(nmu, dp<double>(ctx->l11), nmu, dp<double>(ctx->linv), s));
+    HIPCHK(launch_tri_inverse_rows(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->lchol), ldl,
+                                   dp<double>(ctx->linv), s));
     ENSURE(ctx->xi, (size_t)ng * nmu * 8);
-    HIPCHK(gemm(Op::N, Op::N, ng, nmu, nmu, 1.0, dp<double>(ctx->lchol), ng, 0,
+    // Xi = L L11^{-1} with L row-major (= L^T column-major, leading dimension ldl)
+    HIPCHK(gemm(Op::T, Op::N, ng, nmu, nmu, 1.0, dp<double>(ctx->lchol), ldl, 0,
                 dp<double>(ctx->linv), nmu, 0, 0.0, dp<double>(ctx->xi), ng, 0, 1, s));
     HIPCHK(launch_scatter_identity(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->xi), ng, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -434,8 +434,9 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     ENSURE(ctx->c1, (size_t)ctx->nep * nmu * 8);
     double *R = dp<double>(ctx->rhs), *C = dp<double>(ctx->c1);
     const double *phi = dp<double>(ctx->phi_cm);
-    HIPCHK(gemm(Op::T, Op::N, ne, nmu, ng, 1.0, phi, ng, 0, dp<double>(ctx->xi), ng, 0, 0.0, C, ne,
-                0, 1, s));
+    ENSURE(ctx->splitk, (size_t)64 * ne * nmu * 8);
+    HIPCHK(gemm_splitk(Op::T, Op::N, ne, nmu, ng, 1.0, phi, ng, dp<double>(ctx->xi), ng, 0.0, C, ne,
+                       dp<double>(ctx->splitk), ctx->splitk.bytes / 8, s));
     HIPCHK(launch_scale_copy(ng, nmu, -1.0, dp<double>(ctx->xi), ng, R, ng, s));
     HIPCHK(gemm(Op::N, Op::N, ng, nmu, ne, 1.0, phi, ng, 0, C, ne, 0, 1.0, R, ng, 0, 1, s));
     HIPCHK(hipEventRecord(ctx->ev[2], s));
@@ -744,8 +745,9 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
     ENSURE(ctx->dm_work, (size_t)(n_p + 2) * 16);
     ENSURE(ctx->dm_asym, 16);
     const double dv = std::pow(ctx->grid.h, ctx->grid.dim);
-    HIPCHK(gemm(Op::T, Op::N, n_p, n_p, ng, dv, G, ng, 0, U, ng, 0, 0.0, dp<double>(ctx->dm_phi), n_p,
-                0, 1, s));
+    ENSURE(ctx->splitk, (size_t)64 * n_p * n_p * 8);
+    HIPCHK(gemm_splitk(Op::T, Op::N, n_p, n_p, ng, dv, G, ng, U, ng, 0.0, dp<double>(ctx->dm_phi), n_p,
+                       dp<double>(ctx->splitk), ctx->splitk.bytes / 8, s));
     const double *Kd = nullptr, *Md = nullptr;
     if (K_local) {
         ENSURE(ctx->dm_k, nn * 8);
@@ -798,7 +800,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->kpb, &ctx->kw1, &ctx->kw2, &ctx->krhs, &ctx->kiters, &ctx->kresid,
                       &ctx->kflags, &ctx->ktile, &ctx->dy_v, &ctx->dy_t, &ctx->dy_s, &ctx->dy_g,
                       &ctx->dy_gk, &ctx->dy_norm, &ctx->dm_phi, &ctx->dm_k, &ctx->dm_mass,
-                      &ctx->dm_d, &ctx->dm_eig, &ctx->dm_work, &ctx->dm_asym};
+                      &ctx->dm_d, &ctx->dm_eig, &ctx->dm_work, &ctx->dm_asym, &ctx->splitk};
     for (DevBuf *b : bufs) release(*b);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);

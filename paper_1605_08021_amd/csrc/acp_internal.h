@@ -59,6 +59,13 @@ hipError_t gemm(Op ta, Op tb, int m, int n, int k, double alpha, const double *A
                 int ldc, long long sc, int batch, hipStream_t s, Epi epi = Epi::Store,
                 const double *E = nullptr, int lde = 0, long long se = 0);
 
+// Same product for outputs with few 64 x 64 tiles and a long K: the K range is
+// split into slices whose partial products (work, >= nsplit m n elements) are
+// summed in a fixed order.  Op::N/Op::T as above; beta applies to C.
+hipError_t gemm_splitk(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
+                       const double *B, int ldb, double beta, double *C, int ldc, double *work,
+                       size_t work_elems, hipStream_t s);
+
 // ---------------------------------------------------------------- small utilities
 hipError_t launch_scale_copy(int m, int n, double alpha, const double *X, int ldx, double *Y,
                              int ldy, hipStream_t s);                      // Y = alpha X
@@ -110,14 +117,17 @@ hipError_t launch_cg_fp64(const KrylovArgs &a, hipStream_t s);
 hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s);
 
 // ---------------------------------------------------------------- ISDF (K4)
-// Greedy pivoted Cholesky of the implicit Hadamard Gram matrix; forced (dev,
-// nmu_max entries) replaces the argmax by the given pivots.  scratch >= 32 bytes.
-hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, int ldphi,
-                                 const double *gt, int ldg, int nmu_max, double tol,
-                                 double *L, int ldl, double *diag, int *sel_dev,
-                                 const int *forced, int *nmu_out_host, void *scratch,
-                                 hipStream_t s);
-hipError_t launch_tri_inverse_lower(int n, const double *L, int ldl, double *Linv, hipStream_t s);
+// Greedy pivoted Cholesky of the implicit Hadamard Gram matrix (row-major
+// inputs phi_rm N_g x nep, gt_rm N_g x r; factor L row-major N_g x ldl);
+// forced (dev, nmu_max entries) replaces the argmax by the given pivots.
+hipError_t isdf_pivoted_cholesky(int ng, int nep, int r, const double *phi_rm, const double *gt_rm,
+                                 int nmu_max, double tol, double *L, int ldl, double *diag,
+                                 int *sel_dev, const int *forced, int *nmu_out_host,
+                                 void *scratch, hipStream_t s);
+size_t isdf_scratch_bytes(int ng);
+// Linv = L11^{-1} for L11(i, :) = L_rm(sel[i], 0..i) (row-major factor, leading dimension ldl).
+hipError_t launch_tri_inverse_rows(int n, const int *sel, const double *L, int ldl, double *Linv,
+                                  hipStream_t s);
 hipError_t launch_gather_lower(int n, const int *sel, const double *L, int ldl, double *L11,
                                hipStream_t s);
 

@@ -26,110 +26,184 @@ namespace {
 
 inline unsigned nblk(long long tot, int b) { return (unsigned)((tot + b - 1) / b); }
 
-// diag(alpha) = |phi(alpha,:)|^2 |G~(alpha,:)|^2
-__global__ void isdf_diag_kernel(int ng, int ne, int r, const double *phi, int ldphi,
-                                 const double *gt, int ldg, double *diag) {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ng) return;
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = 0; i < ne; ++i) {
-        double v = phi[a + (long long)i * ldphi];
-        s1 += v * v;
-    }
-    for (int j = 0; j < r; ++j) {
-        double v = gt[a + (long long)j * ldg];
-        s2 += v * v;
-    }
-    diag[a] = s1 * s2;
+// The ISDF kernels work on row-major data: phi_rm (N_g x nep), gt_rm (N_g x r)
+// and L_rm (N_g x ldl), so that one grid row is contiguous.  A wave handles 4
+// rows with 16 lanes per row; dot products over orbitals, sketch columns and
+// previous pivots are split over the 16 lanes and reduced by shuffles in a
+// fixed order.  Each block leaves its best remaining diagonal entry as a
+// candidate (value, row); every block of the next step reduces the candidates
+// itself, so one launch per pivot suffices.
+constexpr int ISDF_NT = 256;
+constexpr int ISDF_ROWS = ISDF_NT / 16;   // rows per block
+
+struct Cand {
+    double v;
+    int i;
+    int pad;
+};
+
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) v += __shfl_xor(v, m, 16);
+    return v;
 }
 
-// One workgroup: pivot for step k = argmax diag (ties -> smallest index), unless a
-// forced selection is given.  state[0] = number of accepted pivots, state[1] = stop flag.
-// dvals[0] = first pivot value (for the rank rule).
-__global__ void isdf_pivot_kernel(int ng, int k, const double *diag, int *sel, const int *forced,
-                                  double tol2, int *state, double *dvals) {
-    __shared__ double bv[1024];
-    __shared__ int bi[1024];
+__device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
+    return v > bv || (v == bv && i < bi);
+}
+
+// Block-level candidate of the rows owned by this block (LDS reduction).
+__device__ void block_candidate(double v, int i, Cand *out) {
+    __shared__ double sv[ISDF_ROWS];
+    __shared__ int si[ISDF_ROWS];
     const int t = threadIdx.x;
-    if (state[1]) return;
-    double best = -1.0;
-    int besti = 0x7fffffff;
-    if (forced) {
-        if (t == 0) { best = diag[forced[k]]; besti = forced[k]; }
-    } else {
-        for (int a = t; a < ng; a += 1024) {
-            double v = diag[a];
-            if (v > best) { best = v; besti = a; }   // ascending a: first max kept
-        }
-    }
-    bv[t] = best;
-    bi[t] = besti;
+    if ((t & 15) == 0) { sv[t >> 4] = v; si[t >> 4] = i; }
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) {
-            double o = bv[t + w];
-            int oi = bi[t + w];
-            if (o > bv[t] || (o == bv[t] && oi < bi[t])) { bv[t] = o; bi[t] = oi; }
-        }
+    if (t == 0) {
+        double bv = sv[0];
+        int bi = si[0];
+        for (int k = 1; k < ISDF_ROWS; ++k)
+            if (better(sv[k], si[k], bv, bi)) { bv = sv[k]; bi = si[k]; }
+        out[blockIdx.x].v = bv;
+        out[blockIdx.x].i = bi;
+    }
+}
+
+// diag(alpha) = |phi(alpha,:)|^2 |G~(alpha,:)|^2 and the first candidates.
+__global__ __launch_bounds__(ISDF_NT) void isdf_init_kernel(int ng, int nep, int r,
+                                                            const double *phi_rm, const double *gt_rm,
+                                                            double *diag, Cand *cand) {
+    const int t = threadIdx.x;
+    const int l16 = t & 15;
+    const int a = blockIdx.x * ISDF_ROWS + (t >> 4);
+    double s1 = 0.0, s2 = 0.0;
+    if (a < ng) {
+        for (int i = l16; i < nep; i += 16) { const double v = phi_rm[(long long)a * nep + i]; s1 += v * v; }
+        for (int j = l16; j < r; j += 16) { const double v = gt_rm[(long long)a * r + j]; s2 += v * v; }
+    }
+    s1 = sum16(s1);
+    s2 = sum16(s2);
+    const double d = s1 * s2;
+    if (a < ng && l16 == 0) diag[a] = d;
+    block_candidate(a < ng ? d : -2.0, a < ng ? a : 0x7fffffff, cand);
+}
+
+// Step k of the greedy pivoted Cholesky of K = (Phi Phi^T) o (G~ G~^T):
+//   p = argmax diag (ties -> smallest index), or forced[k];
+//   L(a,k) = (K(a,p) - sum_{j<k} L(a,j) L(p,j)) / sqrt(diag(p)), diag(a) -= L(a,k)^2.
+// state[0] = accepted pivots, state[1] = stopped; dvals[0] = first pivot value.
+__global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
+    int ng, int nep, int r, int k, int nblk, const double *phi_rm, const double *gt_rm, double *L,
+    int ldl, double *diag, int *sel, const int *forced, double tol2, int *state, double *dvals,
+    const Cand *cand_in, Cand *cand_out) {
+    __shared__ double s_piv;
+    __shared__ int s_p, s_stop;
+    __shared__ double rv[ISDF_NT];
+    __shared__ int ri[ISDF_NT];
+    const int t = threadIdx.x;
+    const int stopped = state[1];
+    if (!forced && !stopped) {
+        // every block reduces the previous step's candidates (fixed tree order)
+        double bv = -2.0;
+        int bi = 0x7fffffff;
+        for (int b = t; b < nblk; b += ISDF_NT)
+            if (better(cand_in[b].v, cand_in[b].i, bv, bi)) { bv = cand_in[b].v; bi = cand_in[b].i; }
+        rv[t] = bv;
+        ri[t] = bi;
         __syncthreads();
+        for (int w = ISDF_NT / 2; w > 0; w >>= 1) {
+            if (t < w && better(rv[t + w], ri[t + w], rv[t], ri[t])) { rv[t] = rv[t + w]; ri[t] = ri[t + w]; }
+            __syncthreads();
+        }
     }
     if (t == 0) {
-        double piv = bv[0];
-        if (k == 0) dvals[0] = piv;
-        bool stop = !(piv > 0.0);
-        if (!forced && tol2 > 0.0 && k > 0 && piv < tol2 * dvals[0]) stop = true;
-        if (stop) {
-            state[1] = 1;
-        } else {
-            sel[k] = bi[0];
-            dvals[1] = piv;
-            state[0] = k + 1;
+        int stop = stopped;
+        double bv = -2.0;
+        int bi = 0x7fffffff;
+        if (!stop) {
+            if (forced) {
+                bi = forced[k];
+                bv = diag[bi];
+            } else {
+                bv = rv[0];
+                bi = ri[0];
+            }
+            if (!(bv > 0.0)) stop = 1;
+            if (!forced && tol2 > 0.0 && k > 0 && bv < tol2 * dvals[0]) stop = 1;
+        }
+        s_piv = bv;
+        s_p = bi;
+        s_stop = stop;
+        if (blockIdx.x == 0) {
+            if (stop) {
+                state[1] = 1;
+            } else {
+                sel[k] = bi;
+                state[0] = k + 1;
+                if (k == 0) dvals[0] = bv;
+            }
         }
     }
+    __syncthreads();
+    if (s_stop) return;
+    const int p = s_p;
+    const double rsq = 1.0 / sqrt(s_piv);
+    const int l16 = t & 15;
+    const int a = blockIdx.x * ISDF_ROWS + (t >> 4);
+    const int ac = a < ng ? a : ng - 1;
+    double s1 = 0.0, s2 = 0.0, y = 0.0;
+    for (int i = l16; i < nep; i += 16) s1 += phi_rm[(long long)ac * nep + i] * phi_rm[(long long)p * nep + i];
+    for (int j = l16; j < r; j += 16) s2 += gt_rm[(long long)ac * r + j] * gt_rm[(long long)p * r + j];
+    for (int j = l16; j < k; j += 16) y += L[(long long)ac * ldl + j] * L[(long long)p * ldl + j];
+    s1 = sum16(s1);
+    s2 = sum16(s2);
+    y = sum16(y);
+    double dnew = -2.0;
+    if (a < ng) {
+        const double lk = (s1 * s2 - y) * rsq;
+        dnew = (a == p) ? -1.0 : diag[a] - lk * lk;
+        if (l16 == 0) {
+            L[(long long)a * ldl + k] = lk;
+            diag[a] = dnew;
+        }
+    }
+    block_candidate(dnew, a < ng ? a : 0x7fffffff, cand_out);
 }
 
-// Column k of L: L(a,k) = (K(a,p) - sum_{j<k} L(a,j) L(p,j)) / sqrt(d_p);
-// diag(a) -= L(a,k)^2; the pivot row is retired.
-__global__ void isdf_column_kernel(int ng, int ne, int r, int k, const double *phi, int ldphi,
-                                   const double *gt, int ldg, double *L, int ldl, double *diag,
-                                   const int *sel, const int *state, const double *dvals) {
-    if (state[0] != k + 1) return;   // stopped before this step
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= ng) return;
-    const int p = sel[k];
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = 0; i < ne; ++i) s1 += phi[a + (long long)i * ldphi] * phi[p + (long long)i * ldphi];
-    for (int j = 0; j < r; ++j) s2 += gt[a + (long long)j * ldg] * gt[p + (long long)j * ldg];
-    double g = s1 * s2;
-    for (int j = 0; j < k; ++j) g -= L[a + (long long)j * ldl] * L[p + (long long)j * ldl];
-    const double piv = dvals[1];
-    const double lk = g / sqrt(piv);
-    L[a + (long long)k * ldl] = lk;
-    if (a == p) diag[a] = -1.0;
-    else diag[a] -= lk * lk;
-}
-
-// L11(i, j) = L(sel[i], j) for j <= i, 0 above the diagonal.
+// L11(i, j) = L(sel[i], j) for j <= i, 0 above the diagonal (L row-major, ld ldl).
 __global__ void gather_lower_kernel(int n, const int *sel, const double *L, int ldl, double *L11) {
     long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)n * n) return;
     int i = (int)(idx % n);
     int j = (int)(idx / n);
-    L11[idx] = (j <= i) ? L[sel[i] + (long long)j * ldl] : 0.0;
+    L11[idx] = (j <= i) ? L[(long long)sel[i] * ldl + j] : 0.0;
 }
 
-// Inverse of a lower-triangular matrix, one thread per column.
-__global__ void tri_inverse_lower_kernel(int n, const double *L, int ldl, double *X) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    double *x = X + (long long)j * n;
-    for (int i = 0; i < j; ++i) x[i] = 0.0;
-    x[j] = 1.0 / L[j + (long long)j * ldl];
+// Inverse of the lower-triangular L11 (row i = L_rm(sel[i], 0..i)), one wave per
+// column j:  x_j = 1 / L_jj,  x_i = -(sum_{l=j}^{i-1} L_il x_l) / L_ii.  Each dot
+// product is split over the 64 lanes (contiguous row of L) and reduced by
+// shuffles in a fixed order; x lives in LDS.
+constexpr int TRI_MAX = 4096;
+__global__ __launch_bounds__(64) void tri_inverse_rows_kernel(int n, const int *sel, const double *L,
+                                                              int ldl, double *X) {
+    __shared__ double x[TRI_MAX];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < n; i += 64) x[i] = 0.0;
+    __syncthreads();
+    const double *Lj = L + (long long)sel[j] * ldl;
+    if (lane == 0) x[j] = 1.0 / Lj[j];
+    __syncthreads();
     for (int i = j + 1; i < n; ++i) {
-        double s = 0.0;
-        for (int l = j; l < i; ++l) s += L[i + (long long)l * ldl] * x[l];
-        x[i] = -s / L[i + (long long)i * ldl];
+        const double *Li = L + (long long)sel[i] * ldl;
+        double sacc = 0.0;
+        for (int l = j + lane; l < i; l += 64) sacc += Li[l] * x[l];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) sacc += __shfl_xor(sacc, m, 64);
+        if (lane == 0) x[i] = -sacc / Li[i];
+        __syncthreads();
     }
+    for (int i = lane; i < n; i += 64) X[i + (long long)j * n] = x[i];
 }
 
 // ------------------------------------------------------------ Gauss-Jordan
@@ -216,29 +290,11 @@ __global__ void jacobi_kernel(int n, double *A, int lda, double *eig, double *wo
     double *cs = work;
     double *sn = work + half;
     int *pq = (int *)(work + N);
-    __shared__ double red[1024];
-    __shared__ int s_done;
+    __shared__ int s_rot;
     const int t = threadIdx.x;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (long long idx = t; idx < (long long)n * n; idx += 1024) {
-            int i = (int)(idx % n), j = (int)(idx / n);
-            double v = A[i + (long long)j * lda];
-            tot += v * v;
-            if (i != j) off += v * v;
-        }
-        red[t] = off;
+        if (t == 0) s_rot = 0;
         __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) { if (t < w) red[t] += red[t + w]; __syncthreads(); }
-        const double offs = red[0];
-        __syncthreads();
-        red[t] = tot;
-        __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) { if (t < w) red[t] += red[t + w]; __syncthreads(); }
-        const double tots = red[0];
-        if (t == 0) s_done = (offs <= tol * tol * tots) ? 1 : 0;
-        __syncthreads();
-        if (s_done) break;
         for (int round = 0; round < N - 1; ++round) {
             for (int k = t; k < half; k += 1024) {
                 int a = (k == 0) ? 0 : 1 + (k - 1 + round) % (N - 1);
@@ -247,8 +303,9 @@ __global__ void jacobi_kernel(int n, double *A, int lda, double *eig, double *wo
                 double c = 1.0, s = 0.0;
                 if (q < n) {
                     double apq = A[p + (long long)q * lda];
-                    if (apq != 0.0) {
-                        double app = A[p + (long long)p * lda], aqq = A[q + (long long)q * lda];
+                    double app = A[p + (long long)p * lda], aqq = A[q + (long long)q * lda];
+                    if (fabs(apq) > tol * sqrt(fabs(app * aqq)) && apq != 0.0) {
+                        atomicAdd(&s_rot, 1);
                         double theta = (aqq - app) / (2.0 * apq);
                         double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
                         c = 1.0 / sqrt(tt * tt + 1.0);
@@ -286,6 +343,8 @@ __global__ void jacobi_kernel(int n, double *A, int lda, double *eig, double *wo
             }
             __syncthreads();
         }
+        if (s_rot == 0) break;
+        __syncthreads();
     }
     // rank sort of the diagonal (ties broken by index)
     for (int i = t; i < n; i += 1024) {
@@ -293,6 +352,88 @@ __global__ void jacobi_kernel(int n, double *A, int lda, double *eig, double *wo
         int rank = 0;
         for (int j = 0; j < n; ++j) {
             double u = A[j + (long long)j * lda];
+            if (u < v || (u == v && j < i)) ++rank;
+        }
+        eig[rank] = v;
+    }
+}
+
+// Same cyclic Jacobi with the whole matrix resident in LDS (n <= 128): one
+// workgroup, row stride n + 1 to spread the column accesses over the banks.
+constexpr int JAC_LDS_MAX = 128;
+__global__ __launch_bounds__(1024) void jacobi_lds_kernel(int n, const double *Ain, int lda,
+                                                          double *eig, int max_sweeps, double tol) {
+    __shared__ double A[JAC_LDS_MAX * (JAC_LDS_MAX + 1)];
+    __shared__ double cs[JAC_LDS_MAX / 2 + 1], sn[JAC_LDS_MAX / 2 + 1];
+    __shared__ int pp[JAC_LDS_MAX / 2 + 1], qq[JAC_LDS_MAX / 2 + 1];
+    __shared__ int s_rot;
+    const int t = threadIdx.x;
+    const int ld = n + 1;
+    const int N = n + (n & 1);
+    const int half = N / 2;
+    for (int idx = t; idx < n * n; idx += 1024) {
+        const int i = idx % n, j = idx / n;
+        A[i + j * ld] = Ain[i + (long long)j * lda];
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (t == 0) s_rot = 0;
+        __syncthreads();
+        for (int round = 0; round < N - 1; ++round) {
+            if (t < half) {
+                const int k = t;
+                const int a = (k == 0) ? 0 : 1 + (k - 1 + round) % (N - 1);
+                const int b = 1 + (N - 2 - k + round) % (N - 1);
+                const int p = a < b ? a : b;
+                int q = a < b ? b : a;
+                double c = 1.0, sv = 0.0;
+                if (q < n) {
+                    const double apq = A[p + q * ld];
+                    if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(A[p + p * ld] * A[q + q * ld]))) {
+                        atomicAdd(&s_rot, 1);
+                        const double theta = (A[q + q * ld] - A[p + p * ld]) / (2.0 * apq);
+                        const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(tt * tt + 1.0);
+                        sv = tt * c;
+                    }
+                } else {
+                    q = -1;
+                }
+                pp[k] = p;
+                qq[k] = q;
+                cs[k] = c;
+                sn[k] = sv;
+            }
+            __syncthreads();
+            for (int idx = t; idx < half * n; idx += 1024) {
+                const int k = idx / n, i = idx % n;
+                const int p = pp[k], q = qq[k];
+                if (q < 0) continue;
+                const double c = cs[k], sv = sn[k];
+                const double aip = A[i + p * ld], aiq = A[i + q * ld];
+                A[i + p * ld] = c * aip - sv * aiq;
+                A[i + q * ld] = sv * aip + c * aiq;
+            }
+            __syncthreads();
+            for (int idx = t; idx < half * n; idx += 1024) {
+                const int k = idx / n, j = idx % n;
+                const int p = pp[k], q = qq[k];
+                if (q < 0) continue;
+                const double c = cs[k], sv = sn[k];
+                const double apj = A[p + j * ld], aqj = A[q + j * ld];
+                A[p + j * ld] = c * apj - sv * aqj;
+                A[q + j * ld] = sv * apj + c * aqj;
+            }
+            __syncthreads();
+        }
+        if (s_rot == 0) break;
+        __syncthreads();
+    }
+    for (int i = t; i < n; i += 1024) {
+        const double v = A[i + i * ld];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double u = A[j + j * ld];
             if (u < v || (u == v && j < i)) ++rank;
         }
         eig[rank] = v;
@@ -326,23 +467,25 @@ __global__ void dynmat_assemble_kernel(int np, int dim, const double *Phi, const
 
 }  // namespace
 
-hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, int ldphi,
-                                 const double *gt, int ldg, int nmu_max, double tol, double *L,
-                                 int ldl, double *diag, int *sel_dev, const int *forced,
-                                 int *nmu_out_host, void *scratch, hipStream_t s) {
-    // scratch: int state[2] | pad | double dvals[2]
+hipError_t isdf_pivoted_cholesky(int ng, int nep, int r, const double *phi_rm, const double *gt_rm,
+                                 int nmu_max, double tol, double *L, int ldl, double *diag,
+                                 int *sel_dev, const int *forced, int *nmu_out_host, void *scratch,
+                                 hipStream_t s) {
+    // scratch: int state[2] | pad | double dvals[2] | Cand[2][nblk]
+    const int nblk = (ng + ISDF_ROWS - 1) / ISDF_ROWS;
     int *state = (int *)scratch;
     double *dvals = (double *)((char *)scratch + 16);
+    Cand *c0 = (Cand *)((char *)scratch + 32);
+    Cand *c1 = c0 + nblk;
     hipError_t e = hipMemsetAsync(state, 0, 2 * sizeof(int), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(isdf_diag_kernel, dim3(nblk(ng, 256)), dim3(256), 0, s, ng, ne, r, phi,
-                       ldphi, gt, ldg, diag);
+    hipLaunchKernelGGL(isdf_init_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, nep, r, phi_rm, gt_rm,
+                       diag, c0);
     const double tol2 = tol * tol;
     for (int k = 0; k < nmu_max; ++k) {
-        hipLaunchKernelGGL(isdf_pivot_kernel, dim3(1), dim3(1024), 0, s, ng, k, diag, sel_dev,
-                           forced, tol2, state, dvals);
-        hipLaunchKernelGGL(isdf_column_kernel, dim3(nblk(ng, 256)), dim3(256), 0, s, ng, ne, r, k,
-                           phi, ldphi, gt, ldg, L, ldl, diag, sel_dev, state, dvals);
+        hipLaunchKernelGGL(isdf_step_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, nep, r, k, nblk,
+                           phi_rm, gt_rm, L, ldl, diag, sel_dev, forced, tol2, state, dvals,
+                           (k & 1) ? c1 : c0, (k & 1) ? c0 : c1);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -355,9 +498,15 @@ hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, int l
     return hipSuccess;
 }
 
-hipError_t launch_tri_inverse_lower(int n, const double *L, int ldl, double *Linv, hipStream_t s) {
-    hipLaunchKernelGGL(tri_inverse_lower_kernel, dim3(nblk(n, 64)), dim3(64), 0, s, n, L, ldl,
-                       Linv);
+size_t isdf_scratch_bytes(int ng) {
+    const int nblk = (ng + ISDF_ROWS - 1) / ISDF_ROWS;
+    return 32 + 2 * (size_t)nblk * sizeof(Cand);
+}
+
+hipError_t launch_tri_inverse_rows(int n, const int *sel, const double *L, int ldl, double *Linv,
+                                  hipStream_t s) {
+    if (n > TRI_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tri_inverse_rows_kernel, dim3(n), dim3(64), 0, s, n, sel, L, ldl, Linv);
     return hipGetLastError();
 }
 
@@ -385,7 +534,11 @@ hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, in
 }
 
 hipError_t jacobi_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s) {
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, n, A, lda, eig, work, 40, 1e-15);
+    if (n <= JAC_LDS_MAX) {
+        hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(1024), 0, s, n, A, lda, eig, 40, 1e-16);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, n, A, lda, eig, work, 40, 1e-16);
     return hipGetLastError();
 }
 

@@ -171,7 +171,50 @@ __global__ void scale_kernel(int m, int n, double beta, double *C, int ldc) {
     }
 }
 
+// C = alpha * sum_s W_s + beta C over the split-K partial products W (fixed order).
+__global__ void splitk_reduce_kernel(int m, int n, int nsplit, const double *W, double alpha,
+                                     double beta, double *C, int ldc) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long tot = (long long)m * n;
+    if (idx >= tot) return;
+    int i = (int)(idx % m);
+    long long j = idx / m;
+    double v = 0.0;
+    for (int sidx = 0; sidx < nsplit; ++sidx) v += W[sidx * tot + idx];
+    double *cp = C + i + j * ldc;
+    *cp = alpha * v + ((beta != 0.0) ? beta * (*cp) : 0.0);
+}
+
 }  // namespace
+
+hipError_t gemm_splitk(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
+                       const double *B, int ldb, double beta, double *C, int ldc, double *work,
+                       size_t work_elems, hipStream_t s) {
+    // split so that the grid has >= ~256 workgroups; each slice handles a multiple of 64 of K
+    const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    int nsplit = (256 + tiles - 1) / tiles;
+    const int kmax_split = (k + 63) / 64;
+    if (nsplit > kmax_split) nsplit = kmax_split;
+    while (nsplit > 1 && (size_t)nsplit * m * n > work_elems) --nsplit;
+    if (nsplit <= 1)
+        return gemm(ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, s);
+    const int kc = ((k + nsplit - 1) / nsplit + 63) / 64 * 64;
+    nsplit = (k + kc - 1) / kc;
+    hipError_t e;
+    for (int sidx = 0; sidx < nsplit; ++sidx) {
+        const int k0 = sidx * kc;
+        const int kk = (k - k0) < kc ? (k - k0) : kc;
+        const double *As = (ta == Op::N) ? A + (long long)k0 * lda : A + k0;
+        const double *Bs = (tb == Op::N) ? B + k0 : B + (long long)k0 * ldb;
+        e = gemm(ta, tb, m, n, kk, 1.0, As, lda, 0, Bs, ldb, 0, 0.0, work + (size_t)sidx * m * n, m,
+                 0, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    long long tot = (long long)m * n;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       m, n, nsplit, work, alpha, beta, C, ldc);
+    return hipGetLastError();
+}
 
 hipError_t gemm(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
                 long long sa, const double *B, int ldb, long long sb, double beta, double *C,

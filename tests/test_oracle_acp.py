@@ -133,6 +133,9 @@ def test_acp_is_exact_dfpt_with_identity_isdf_and_occupied_nodes(sys_):
                       node_mode="occupied")
     assert np.abs(res.W_hist[0] - X0).max() < 1e-11 * np.abs(X0).max()
     assert np.linalg.norm(res.U - U_exact) < 1e-10 * np.linalg.norm(U_exact)
+    # chi0~ X = W X(Pi, :) is then chi0 X
+    Y = A.chi0_tilde_apply(res.W_hist[0], sel, G)
+    assert np.abs(Y - X0 @ G).max() < 1e-11 * np.abs(X0 @ G).max()
 
 
 def test_smw_update_equals_dense_inverse(sys_):
@@ -183,3 +186,7 @@ def test_krylov_solvers_match_exact(sys_, solver):
     assert K.true_residual(op, x, B).max() < 2e-11
     ex = np.concatenate([A.ExactShiftedSolver(w, v, gs.n_e)(s, R) for s in nodes], axis=1)
     assert np.abs(x - ex).max() < 1e-8 * np.abs(ex).max()
+    # the dense factorisation of Q(H - s)Q + Phi Phi^T gives the same solutions
+    dense = A.DenseShiftedSolver(m.hamiltonian_dense(gs.veff), gs.phi)
+    ex2 = np.concatenate([dense(s, R) for s in nodes], axis=1)
+    assert np.abs(ex2 - ex).max() < 1e-9 * np.abs(ex).max()

@@ -118,3 +118,18 @@ def test_hessian_matches_frozen_phonon():
     D, lam = C.dynamical_matrix(H, np.ones(4), 1)
     assert abs(lam[0]) < 1e-9 * lam[-1]          # one acoustic mode at zero
     assert lam[1] > 0                             # stable chain
+
+
+def test_dynamical_matrix_with_masses_is_generalised_eigenproblem():
+    """D = M^{-1/2} Hess M^{-1/2} has the eigenvalues of Hess u = omega^2 M u
+    (a library routine for the symmetric-definite generalised problem)."""
+    import scipy.linalg as sla
+    rng = np.random.default_rng(4)
+    d, n_a = 2, 5
+    H = rng.standard_normal((d * n_a, d * n_a))
+    masses = rng.uniform(1.0, 30.0, n_a)
+    D, lam = C.dynamical_matrix(H, masses, d)
+    Hs = 0.5 * (H + H.T)
+    ref = sla.eigh(Hs, np.diag(np.repeat(masses, d)), eigvals_only=True)
+    assert np.allclose(lam, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    assert np.allclose(D, D.T)
