@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--form", choices=["fast", "plain"], default="fast")
+    ap.add_argument("--form", choices=["fast", "single", "plain"], default="fast")
     ap.add_argument("--dyson-iters", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -109,7 +109,8 @@ def main():
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     phi, veff, G, om = T(inp.phi), T(inp.veff), T(inp.G), T(inp.omega)
-    solver = acp.SOLVER_CG if args.form == "fast" else acp.SOLVER_MINRES
+    solver = {"fast": acp.SOLVER_CG, "single": acp.SOLVER_CG_SINGLE,
+              "plain": acp.SOLVER_MINRES}[args.form]
     opts = dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol, max_iter=20000,
                 solver=solver, dyson_max_iter=args.dyson_iters)
     ctx = acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0,
@@ -137,26 +138,27 @@ def main():
     value = systems / elapsed
     ms_step = 1e3 * elapsed / args.steps
 
-    # roofline of the dominant kernel: the fused batched Krylov solver
+    # roofline of the dominant kernel: the fused batched Krylov solver.  The library
+    # accumulates the algorithmic bytes (vector sweeps x 8 B x N_g per system-iteration)
+    # and the projector flops of every launch, and times each launch with HIP events
+    # on its own stream.
     ng = inp.phi.shape[0]
     ne = inp.n_e
-    vectors = 8 if solver == acp.SOLVER_CG else 12
     launches = max(st["solve_kernel_launches"], 1)
-    sys_it_per_launch = st["system_iterations"] / launches
-    bytes_per_launch = vectors * 8.0 * ng * sys_it_per_launch
+    bytes_per_launch = st["krylov_bytes"] / launches
+    flops_per_launch = st["krylov_flops"] / launches
     ms_per_launch = st["ms_solve_kernel"] / launches
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
-    flops_per_launch = 4.0 * ng * ne * sys_it_per_launch
+    kname = {acp.SOLVER_CG: "mscg_kernel (multi-shift CG: fused stencil + projector, shifted updates)",
+             acp.SOLVER_MINRES: "minres_kernel (fused stencil + projector + MINRES)",
+             acp.SOLVER_CG_SINGLE: "cg_kernel (fused stencil + projector + CG)"}[solver]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "cg_kernel (fused stencil + projector + CG)" if solver == acp.SOLVER_CG
-                else "minres_kernel (fused stencil + projector + MINRES)",
+                "kernel": kname,
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "mfma_fp64_tflops": round(flops_per_launch / (ms_per_launch * 1e-3) / 1e12, 2),
                 "ms_per_launch": round(ms_per_launch, 3),
-                "system_iterations_per_launch": sys_it_per_launch,
-                "tile_iteration_efficiency": round(st["system_iterations"] /
-                                                   max(16 * st["tile_iterations"], 1), 3)}
+                "workgroups_per_tile": st["krylov_group"]}
     log(f"stats: {json.dumps(st)}")
     out = {
         "metric": "Sternheimer RHS*shifts solved/s at 1e-8 residual",
@@ -173,8 +175,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
                                f"ground state, gap {inp.gap:.5f} Ha",
-                   "form": ("batched FP64 CG" if solver == acp.SOLVER_CG
-                            else "plain FP64 MINRES"),
+                   "form": {acp.SOLVER_CG: "batched FP64 multi-shift CG",
+                            acp.SOLVER_CG_SINGLE: "batched FP64 CG, one sequence per system",
+                            acp.SOLVER_MINRES: "plain FP64 MINRES"}[solver],
                    "dyson_iterations": st["dyson_iters"], "n_g": ng, "n_e": ne,
                    "n_p": int(inp.G.shape[1]), "n_c": cfg.n_cheb, "n_mu": cfg.n_mu,
                    "tol": args.tol},

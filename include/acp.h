@@ -57,7 +57,14 @@ typedef enum {
     ACP_PREC_FP32_REFINE = 1   /* FP32 inner solves, FP64 residual refinement */
 } acp_precision;
 
-typedef enum { ACP_SOLVER_CG = 0, ACP_SOLVER_MINRES = 1 } acp_solver;
+typedef enum {
+    ACP_SOLVER_CG = 0,        /* conjugate gradients; in acp_compress / acp_dyson all N_c
+                                 shifts of one right-hand side share one Krylov sequence
+                                 (multi-shift CG, exact in exact arithmetic because the
+                                 Krylov space of H - s does not depend on s) */
+    ACP_SOLVER_MINRES = 1,    /* MINRES, one sequence per shifted system (the paper's solver) */
+    ACP_SOLVER_CG_SINGLE = 2  /* conjugate gradients, one sequence per shifted system */
+} acp_solver;
 
 typedef enum {
     ACP_NODES_CHEBYSHEV = 0,   /* Chebyshev nodes on [eps_1, eps_Ne] (Sec. 3.1) */
@@ -100,6 +107,9 @@ typedef struct {
     double ms_solve_kernel;      /* accumulated time inside the Krylov kernel launches */
     int64_t solve_kernel_launches;
     double d_asymmetry;          /* ||Phi_el - Phi_el^T||_F / ||Phi_el||_F of the last dynmat */
+    double krylov_bytes;         /* algorithmic HBM bytes of the Krylov kernels (accumulated) */
+    double krylov_flops;         /* algorithmic FP64 flops of their projector products */
+    int krylov_group;            /* workgroups per 16-system tile in the last multi-shift solve */
 } acp_stats;
 
 typedef struct acp_ctx acp_ctx;

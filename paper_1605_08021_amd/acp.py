@@ -26,7 +26,7 @@ ACP_OK, ACP_EINVAL, ACP_ENOMEM, ACP_EDEVICE, ACP_ENOCONV, ACP_ENOTSPD, ACP_ESTAT
 STATUS_NAMES = {0: "ACP_OK", -1: "ACP_EINVAL", -2: "ACP_ENOMEM", -3: "ACP_EDEVICE",
                 -4: "ACP_ENOCONV", -5: "ACP_ENOTSPD", -6: "ACP_ESTATE"}
 PREC_FP64, PREC_FP32_REFINE = 0, 1
-SOLVER_CG, SOLVER_MINRES = 0, 1
+SOLVER_CG, SOLVER_MINRES, SOLVER_CG_SINGLE = 0, 1, 2
 NODES_CHEBYSHEV, NODES_OCCUPIED = 0, 1
 
 
@@ -56,7 +56,9 @@ class AcpStats(C.Structure):
                 ("refinements", C.c_int), ("ms_isdf", C.c_double), ("ms_rhs", C.c_double),
                 ("ms_solve", C.c_double), ("ms_w", C.c_double), ("ms_dyson_small", C.c_double),
                 ("ms_dynmat", C.c_double), ("ms_solve_kernel", C.c_double),
-                ("solve_kernel_launches", C.c_int64), ("d_asymmetry", C.c_double)]
+                ("solve_kernel_launches", C.c_int64), ("d_asymmetry", C.c_double),
+                ("krylov_bytes", C.c_double), ("krylov_flops", C.c_double),
+                ("krylov_group", C.c_int)]
 
 
 _lib = None

@@ -18,11 +18,13 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libacp.so")
 ARCH = os.environ.get("ACP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["acp_api.cpp", "k_util.hip", "k_gemm.hip", "k_krylov.hip", "k_dense.hip"]
+SOURCES = ["acp_api.cpp", "k_util.hip", "k_gemm.hip", "k_krylov.hip", "k_mscg.hip", "k_dense.hip"]
 
 # Packed FP32 instructions are disabled for all device code (see the design notes).
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+if os.environ.get("ACP_PHASE_CLOCKS"):   # per-phase timers in the multi-shift kernel (tuning)
+    HIP_FLAGS.append("-DACP_PHASE_CLOCKS")
 
 
 def _hipcc() -> str:

@@ -114,6 +114,40 @@ struct KrylovArgs {
     int *tile_iters;        // per tile: iterations executed by its workgroup
 };
 hipError_t launch_cg_fp64(const KrylovArgs &a, hipStream_t s);
+
+// Multi-shift CG: every tile of 16 right-hand sides solves all nshift shifts;
+// a group of K workgroups shares a tile (cooperative launch of ntiles * K).
+struct MsArgs {
+    GridDesc g;
+    int ne;                 // padded orbital count (multiple of 16)
+    int ntiles;             // right-hand-side tiles
+    int K;                  // workgroups per tile
+    int nshift, base;       // shifts; index of the base (largest) shift
+    const double *shift;    // device, nshift
+    const double *phi_rm, *phi_cm, *veff;
+    const double *rhs;      // tiled right-hand sides, ntiles tiles
+    double *x, *p;          // [nshift][ntiles] tiles each
+    double *r;              // residual ring: [kMsWindow][ntiles] tiles
+    double *pa, *pb;        // ntiles tiles each
+    double *gbuf;           // ntiles * 2 * K * slot doubles
+    unsigned *cnt;          // ntiles counters, zero at launch
+    int *abort_flag;        // set if a group barrier wait expired
+    int *iters;             // [nshift][ntiles * 16]
+    double *resid;
+    int *flags;
+    int *tile_iters;        // ntiles
+    double tol;
+    int max_iter;
+    unsigned long long *phase_clock;   // 8 phase timers of workgroup 0 (ACP_PHASE_CLOCKS builds)
+};
+// Iterations per window of the deferred solution updates of the multi-shift solver
+// (the residual ring holds this many residuals per tile).
+constexpr int kMsWindow = 8;
+hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s);
+int mscg_resident_capacity(int dim, int ne);   // workgroups the device can hold at once
+size_t mscg_group_slot(int ne);                // doubles per group partial
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
+hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);
 hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s);
 
 // ---------------------------------------------------------------- ISDF (K4)

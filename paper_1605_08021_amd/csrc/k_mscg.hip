@@ -1,0 +1,579 @@
+// Multi-shift conjugate gradients for the compressed shifted equations of
+// Eq. (3.6):  for one right-hand side b = -Q xi_mu and every Chebyshev shift,
+//   (A + sigma_c I) z_c = b,   A = Q (H - s_base) Q,  sigma_c = s_base - s_c >= 0,
+// where s_base is the shift closest to the LUMO (the slowest system).  The
+// Krylov space of A + sigma I does not depend on sigma, so one CG sequence on A
+// generates every shifted solution: the shifted residuals stay collinear,
+// r_c = zeta_c r, and (Jegerlehner's recurrences)
+//   zeta_{k+1} = zeta_k zeta_{k-1} a_{k-1} /
+//                (a_k b_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} a_{k-1} (1 + sigma a_k))
+//   a^c_k = a_k zeta_{k+1} / zeta_k,   b^c_k = b_k (zeta_{k+1} / zeta_k)^2
+//   p_c <- zeta_k r_k + b^c_{k-1} p_c,   x_c += a^c_k p_c.
+// Only the base sequence applies the stencil and the projector.  The vector
+// updates of p_c and x_c (the base's x included) depend on the base residuals
+// and on scalars only, so they are deferred: the residuals of a window of
+// kMsWindow iterations stay in a ring, the step scalars in LDS, and once per
+// window every p_c, x_c is read once, advanced through the window's steps in
+// registers and written back.  That replaces 4 vector sweeps per shift and
+// iteration by (4 per shift + the window's residuals) per window.
+//
+// Work decomposition (gfx950): a tile of 16 right-hand sides is shared by a
+// group of K workgroups (8 waves each); workgroup k owns the 16-row blocks
+// blk = k (mod K).  The two reductions of every iteration (Phi^T y with p^T y,
+// and |r|^2) are reduced inside each workgroup in LDS, then across the group
+// through global memory behind a counter barrier; every workgroup sums the K
+// partials in the same order, so all of them hold identical scalars.  The
+// kernel is launched cooperatively, which guarantees that all workgroups of a
+// group are resident; every barrier wait is bounded and aborts the launch on
+// expiry.
+#include "krylov_common.h"
+
+namespace acp {
+namespace {
+
+using namespace kry;
+
+constexpr unsigned kSpinLimit = 1u << 22;   // ~seconds: a wait this long means a lost group
+constexpr int MAXSH = 16;                   // shifts per right-hand side
+constexpr int WS = kMsWindow;
+
+struct GroupSync {
+    unsigned *cnt;      // per-tile counter (monotonic)
+    double *buf;        // per tile: [2 parities][K][slot]
+    int slot;           // doubles per partial
+    int K;
+    int kg;
+    unsigned phase;     // number of completed group barriers
+};
+
+// This workgroup's partial buffer for the next group barrier.
+__device__ __forceinline__ double *group_mine(const GroupSync &gs, int tile) {
+    const size_t par = gs.phase & 1u;
+    return gs.buf + (((size_t)tile * 2 + par) * gs.K + gs.kg) * (size_t)gs.slot;
+}
+
+// All threads, after writing this workgroup's partial to group_mine(): wait for
+// the group and leave the ordered sum of the K partials (n doubles) in LDS dst.
+// Returns false if the wait expired (the launch is then abandoned).
+__device__ bool group_sum(GroupSync &gs, int tile, double *dst, int n, int *abort_flag) {
+    const double *base = gs.buf + ((size_t)tile * 2 + (gs.phase & 1u)) * (size_t)gs.K * gs.slot;
+    // every wave's stores complete before the barrier; thread 0's release then
+    // publishes them (and the workgroup's halo rows) to the other workgroups
+    __syncthreads();
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(gs.cnt + tile, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (gs.phase + 1) * (unsigned)gs.K;
+        unsigned spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(gs.cnt + tile, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+        }
+        if (!ok) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_ok = ok;
+    }
+    // thread 0's acquire (same compute unit, so it also covers the other waves' reads)
+    __syncthreads();
+    gs.phase += 1;
+    if (!s_ok) return false;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        double v = 0.0;
+        for (int k = 0; k < gs.K; ++k) v += base[(size_t)k * gs.slot + i];
+        dst[i] = v;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Column sums of a per-thread value (threads with equal t % 16), fixed order,
+// written to out[0..15] (LDS or global).
+__device__ __forceinline__ void column_partial(double v, double *red, double *out) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < kTile) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT / kTile; ++k) s += red[threadIdx.x + kTile * k];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+#ifdef ACP_PHASE_CLOCKS
+// Per-phase timers of workgroup 0, thread 0 (tuning builds only).
+#define PHASE_MARK(i)                                                          \
+    do {                                                                       \
+        if (prof) {                                                            \
+            const unsigned long long now_ = wall_clock64();                    \
+            prof_acc[i] += now_ - prof_last;                                   \
+            prof_last = now_;                                                  \
+        }                                                                      \
+    } while (0)
+#else
+#define PHASE_MARK(i) do {} while (0)
+#endif
+
+template <int DIM, int NB>
+__global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
+    using S = Slots<NB>;
+    static_assert(S::N * S::ELEMS >= S::ELEMS + kTile, "slots hold C and p^T y");
+    __shared__ double slots[S::N * S::ELEMS];
+    __shared__ double red[NT];
+    __shared__ double s_rr[kTile], s_bn[kTile], s_al[kTile], s_btp[kTile], s_alp[kTile],
+        s_tmp[kTile];
+    __shared__ double s_z[MAXSH][kTile], s_zp[MAXSH][kTile], s_bs[MAXSH][kTile],
+        s_res[MAXSH][kTile];
+    // step scalars of the current window: p = wz r + wb p, x += wa p
+    __shared__ double s_wz[MAXSH][WS][kTile], s_wb[MAXSH][WS][kTile], s_wa[MAXSH][WS][kTile];
+    __shared__ int s_act[MAXSH][kTile], s_it[MAXSH][kTile], s_wn[MAXSH][kTile], s_flag[kTile],
+        s_colact[kTile], s_any, s_abort;
+
+    const int K = a.K;
+    // group members blockIdx = tile + ntiles * k: with workgroups dealt round-robin
+    // to the XCDs, a group whose ntiles is a multiple of the XCD count stays on one
+    // XCD (one L2) for its barriers and halo exchange
+    const int tile = blockIdx.x % a.ntiles;
+    const int kg = blockIdx.x / a.ntiles;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int col = lane & 15;
+    const int q = lane >> 4;
+    const int ns = a.nshift;
+    const int bs = a.base;
+    const int ng = a.g.ng;
+    const long long tstride = (long long)ng * kTile;
+    const double *__restrict__ b = a.rhs + (long long)tile * tstride;
+    double *pA = a.pa + (long long)tile * tstride;
+    double *pB = a.pb + (long long)tile * tstride;
+    // shift c of this tile: X[c] at a.x + (c * ntiles + tile) * tstride, same for P;
+    // residual of iteration k at ring slot k % WS
+    auto Xs = [&](int c) { return a.x + ((long long)c * a.ntiles + tile) * tstride; };
+    auto Ps = [&](int c) { return a.p + ((long long)c * a.ntiles + tile) * tstride; };
+    auto Rs = [&](int k) { return a.r + ((long long)(k % WS) * a.ntiles + tile) * tstride; };
+    const double sbase = a.shift[bs];
+    GroupSync gs{a.cnt, a.gbuf, S::ELEMS + kTile, K, kg, 0u};
+    const int nblk = (ng + 15) / 16;
+    // rows of this workgroup in the flat walk of the deferred updates
+    const int own_rows = ((nblk - kg + K - 1) / K) * 16;
+
+#ifdef ACP_PHASE_CLOCKS
+    const bool prof = a.phase_clock && blockIdx.x == 0 && t == 0;
+    unsigned long long prof_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long prof_last = prof ? wall_clock64() : 0ull;
+#endif
+
+    // Deferred updates of the window that started at iteration k0 (n_steps
+    // steps, uniform over the group): every thread walks this workgroup's rows
+    // for system j = t % 16, four rows at a time, and for every shift with
+    // recorded steps reads p_c, x_c once, applies the steps and writes them back.
+    // The next shift's loads are issued before the current shift's arithmetic.
+    auto flush = [&](int k0, int n_steps) {
+        const int j = t & 15;
+        constexpr int RR = 4;
+        constexpr int RSTEP = NT / kTile;
+        for (int rl0 = t >> 4; rl0 < own_rows; rl0 += RR * RSTEP) {
+            long long id[RR];
+            bool ok[RR];
+#pragma unroll
+            for (int i = 0; i < RR; ++i) {
+                const int rl = rl0 + i * RSTEP;
+                const int row = (kg + K * (rl >> 4)) * 16 + (rl & 15);
+                ok[i] = rl < own_rows && row < ng;
+                id[i] = (long long)(ok[i] ? row : 0) * kTile + j;   // row 0 always exists
+            }
+            double rw[WS][RR];
+#pragma unroll
+            for (int w = 0; w < WS; ++w) {
+                if (w < n_steps) {
+                    const double *rk = Rs(k0 + w);
+#pragma unroll
+                    for (int i = 0; i < RR; ++i) rw[w][i] = rk[id[i]];
+                }
+            }
+            double pn[RR] = {}, xn[RR] = {};
+            int nn = s_wn[0][j];
+            if (nn > 0) {
+#pragma unroll
+                for (int i = 0; i < RR; ++i) {
+                    pn[i] = Ps(0)[id[i]];
+                    xn[i] = Xs(0)[id[i]];
+                }
+            }
+            for (int c = 0; c < ns; ++c) {
+                const int n = nn;
+                double pv[RR], xv[RR];
+#pragma unroll
+                for (int i = 0; i < RR; ++i) {
+                    pv[i] = pn[i];
+                    xv[i] = xn[i];
+                }
+                if (c + 1 < ns) {
+                    nn = s_wn[c + 1][j];
+                    if (nn > 0) {
+#pragma unroll
+                        for (int i = 0; i < RR; ++i) {
+                            pn[i] = Ps(c + 1)[id[i]];
+                            xn[i] = Xs(c + 1)[id[i]];
+                        }
+                    }
+                }
+                if (n > 0) {
+#pragma unroll
+                    for (int w = 0; w < WS; ++w) {
+                        if (w < n) {
+                            const double wz = s_wz[c][w][j], wb = s_wb[c][w][j], wa = s_wa[c][w][j];
+#pragma unroll
+                            for (int i = 0; i < RR; ++i) {
+                                pv[i] = wb * pv[i] + wz * rw[w][i];
+                                xv[i] += wa * pv[i];
+                            }
+                        }
+                    }
+                    double *pc = Ps(c), *xc = Xs(c);
+#pragma unroll
+                    for (int i = 0; i < RR; ++i)
+                        if (ok[i]) {
+                            pc[id[i]] = pv[i];
+                            xc[id[i]] = xv[i];
+                        }
+                }
+            }
+        }
+        __syncthreads();
+        if (t < kTile * MAXSH) s_wn[t / kTile][t % kTile] = 0;
+        __syncthreads();
+    };
+
+    if (t == 0) s_abort = 0;
+    // ---- init (own rows): r_0 = b, x_c = 0, p_c = 0, p_old = 0; |b|^2
+    double bb = 0.0;
+    {
+        double *r0 = Rs(0);
+        for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
+            const int R = blk * 16 + 4 * q;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = R + j;
+                if (row < ng) {
+                    const int id = row * kTile + col;
+                    const double bv = b[id];
+                    r0[id] = bv;
+                    pA[id] = 0.0;
+                    for (int c = 0; c < ns; ++c) {
+                        Xs(c)[id] = 0.0;
+                        Ps(c)[id] = 0.0;
+                    }
+                    bb += bv * bv;
+                }
+            }
+        }
+    }
+    column_partial(bb, red, group_mine(gs, tile));
+    if (!group_sum(gs, tile, s_tmp, kTile, a.abort_flag)) return;
+    if (t < kTile) {
+        const double bn = sqrt(s_tmp[t]);
+        s_bn[t] = bn;
+        s_rr[t] = s_tmp[t];
+        s_alp[t] = 1.0;
+        s_btp[t] = 0.0;
+        s_flag[t] = 0;
+        for (int c = 0; c < ns; ++c) {
+            s_z[c][t] = 1.0;
+            s_zp[c][t] = 1.0;
+            s_bs[c][t] = 0.0;
+            s_res[c][t] = -1.0;
+            s_act[c][t] = bn > 0.0 ? 1 : 0;
+            s_it[c][t] = 0;
+        }
+    }
+    if (t < kTile * MAXSH) s_wn[t / kTile][t % kTile] = 0;
+    __syncthreads();
+
+    int it = 0, k0 = 0;
+    for (; it < a.max_iter; ++it) {
+        // a right-hand side whose shifts have all converged stops its base sequence too
+        if (t < kTile) {
+            int ca = 0;
+            for (int c = 0; c < ns; ++c) ca |= s_act[c][t];
+            s_colact[t] = ca;
+            if (!ca) s_btp[t] = 0.0;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int any = 0;
+            for (int j = 0; j < kTile; ++j) any |= s_colact[j];
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) break;
+        const double *rcur = Rs(it);
+        // ---- pass 1: base p = r + beta p_old (-> pB), y = (H - s_base) p, C = Phi^T y, p^T y
+        constexpr int nep = NB * 16;
+        constexpr int NN = Nbr<DIM>::N;
+        const double beta = s_btp[col];
+        d4 acc[NB];
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) acc[mb] = d4{0.0, 0.0, 0.0, 0.0};
+        double pty = 0.0;
+        for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
+            const int R = blk * 16 + 4 * q;
+            const Nbr<DIM> nb(R, a.g);
+            double w[NN], wp[NN];
+#pragma unroll
+            for (int k = 0; k < NN; ++k) w[k] = rcur[nb.idx[k] * kTile + col];
+#pragma unroll
+            for (int k = 0; k < NN; ++k) wp[k] = pA[nb.idx[k] * kTile + col];
+            double av[4][NB];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = R + j < ng ? R + j : ng - 1;
+                const double *ph = a.phi_rm + (long long)row * nep + col;
+#pragma unroll
+                for (int mb = 0; mb < NB; ++mb) av[j][mb] = ph[mb * 16];
+            }
+#pragma unroll
+            for (int k = 0; k < NN; ++k) w[k] += beta * wp[k];
+            double y[4], pc[4];
+            stencil_from<DIM>(w, R, a.g, a.veff, sbase, y, pc);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                pty += pc[j] * y[j];
+                if (R + j < ng) pB[(R + j) * kTile + col] = pc[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int mb = 0; mb < NB; ++mb)
+                    acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][mb], y[j], acc[mb], 0, 0, 0);
+        }
+        PHASE_MARK(0);
+        // workgroup reduction of C through the LDS slots (fixed order), published
+        // with p^T y as this workgroup's partial
+#pragma unroll 1
+        for (int ph = 0; ph < NW / S::N; ++ph) {
+            if (wave / S::N == ph) {
+                double *dst = slots + (wave % S::N) * S::ELEMS;
+#pragma unroll
+                for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int idx = (mb * 16 + q + 4 * e) * kTile + col;
+                        if (ph == 0) dst[idx] = acc[mb][e];
+                        else dst[idx] += acc[mb][e];
+                    }
+            }
+            __syncthreads();
+        }
+        {
+            double *mine = group_mine(gs, tile);
+            for (int idx = t; idx < S::ELEMS; idx += NT) {
+                double v = slots[idx];
+#pragma unroll
+                for (int k = 1; k < S::N; ++k) v += slots[k * S::ELEMS + idx];
+                mine[idx] = v;
+            }
+            column_partial(pty, red, mine + S::ELEMS);
+        }
+        PHASE_MARK(1);
+        // group reduction: slots[0..ELEMS) = C, slots[ELEMS..) = p^T y
+        if (!group_sum(gs, tile, slots, S::ELEMS + kTile, a.abort_flag)) {
+            if (t == 0) s_abort = 1;
+            break;
+        }
+        PHASE_MARK(2);
+        // scalars: base alpha per right-hand side (a non-positive curvature stops
+        // that right-hand side and is reported) ...
+        if (t < kTile) {
+            const double pap = slots[S::ELEMS + t];
+            double al = 0.0;
+            if (s_colact[t]) {
+                if (pap > 0.0) {
+                    al = s_rr[t] / pap;
+                } else {
+                    s_flag[t] |= 2;
+                    s_colact[t] = 0;
+                }
+            }
+            s_al[t] = al;
+        }
+        __syncthreads();
+        // ... then the step of this iteration for every live sequence: zeta_{k+1}
+        // and a^c_k of each active shift; the base (zeta = 1) keeps stepping while
+        // any shift of its right-hand side is active
+        {
+            const int wpos = it - k0;
+            if (t < kTile * ns) {
+                const int c = t / kTile, j = t % kTile;
+                const double al = s_al[j];
+                if (!s_colact[j]) {
+                    s_act[c][j] = 0;
+                } else if (c == bs) {
+                    s_wz[c][wpos][j] = 1.0;
+                    s_wb[c][wpos][j] = s_btp[j];
+                    s_wa[c][wpos][j] = al;
+                    s_wn[c][j] = wpos + 1;
+                } else if (s_act[c][j]) {
+                    const double sig = sbase - a.shift[c];
+                    const double zk = s_z[c][j], zkm = s_zp[c][j];
+                    const double alp = s_alp[j], btp = s_btp[j];
+                    const double den = al * btp * (zkm - zk) + zkm * alp * (1.0 + sig * al);
+                    const double zn = (den != 0.0) ? zk * zkm * alp / den : 0.0;
+                    s_wz[c][wpos][j] = zk;
+                    s_wb[c][wpos][j] = s_bs[c][j];
+                    s_wa[c][wpos][j] = (zk != 0.0) ? al * zn / zk : 0.0;
+                    s_wn[c][j] = wpos + 1;
+                    s_zp[c][j] = zk;
+                    s_z[c][j] = zn;
+                }
+            }
+            __syncthreads();
+            // window full: apply it before pass 2 overwrites its oldest residual
+            if (wpos == WS - 1) {
+                flush(k0, WS);
+                k0 = it + 1;
+            }
+        }
+        PHASE_MARK(3);
+        // ---- pass 2: A p = y - Phi C; r_{k+1} = r_k - alpha A p (next ring slot); |r|^2
+        double rr_part = 0.0;
+        {
+            const double al = s_al[col];
+            double *rnext = Rs(it + 1);
+            for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
+                const int row0 = blk * 16;
+                const int R = row0 + 4 * q;
+                double w[NN];
+                gather<DIM>(pB, R, a.g, col, w);
+                double ro[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = R + e < ng ? R + e : ng - 1;
+                    ro[e] = rcur[row * kTile + col];
+                }
+                const d4 d = project_block<NB>(a.phi_cm, ng, slots, row0);
+                double y[4], pc[4];
+                stencil_from<DIM>(w, R, a.g, a.veff, sbase, y, pc);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double rn = ro[e] - al * (y[e] - d[e]);
+                    if (R + e < ng) {
+                        rnext[(R + e) * kTile + col] = rn;
+                        rr_part += rn * rn;
+                    }
+                }
+            }
+        }
+        PHASE_MARK(4);
+        column_partial(rr_part, red, group_mine(gs, tile));
+        if (!group_sum(gs, tile, s_tmp, kTile, a.abort_flag)) {
+            if (t == 0) s_abort = 1;
+            break;
+        }
+        if (t < kTile * ns) {
+            const int c = t / kTile, j = t % kTile;
+            const double rrn = s_tmp[j];
+            const double bt = (s_rr[j] > 0.0) ? rrn / s_rr[j] : 0.0;
+            const double thr = a.tol * s_bn[j];
+            if (c == bs) {
+                if (s_act[c][j]) {
+                    s_it[c][j] = it + 1;
+                    if (sqrt(rrn) <= thr) s_act[c][j] = 0;
+                }
+            } else if (s_act[c][j]) {
+                const double zr = s_z[c][j] / s_zp[c][j];
+                const double res = fabs(s_z[c][j]) * sqrt(rrn);
+                s_bs[c][j] = bt * zr * zr;
+                s_it[c][j] = it + 1;
+                if (res <= thr) {
+                    s_act[c][j] = 0;
+                    s_res[c][j] = res / s_bn[j];
+                }
+            }
+        }
+        __syncthreads();
+        if (t < kTile && s_colact[t]) {
+            s_alp[t] = s_al[t];
+            s_btp[t] = (s_rr[t] > 0.0) ? s_tmp[t] / s_rr[t] : 0.0;
+            s_rr[t] = s_tmp[t];
+        }
+        __syncthreads();
+        PHASE_MARK(5);
+        double *tmp = pA; pA = pB; pB = tmp;
+    }
+#ifdef ACP_PHASE_CLOCKS
+    if (prof)
+        for (int i = 0; i < 8; ++i) a.phase_clock[i] = prof_acc[i];
+#endif
+    if (s_abort) return;
+    // the partial last window
+    if (it > k0) flush(k0, it - k0);
+    if (kg == 0 && t < kTile * ns) {
+        const int c = t / kTile, j = t % kTile;
+        const long long gcol = ((long long)c * a.ntiles + tile) * kTile + j;
+        a.iters[gcol] = s_it[c][j];
+        double res;
+        if (c != bs && s_res[c][j] >= 0.0) res = s_res[c][j];   // converged shift
+        else {
+            const double zc = (c == bs) ? 1.0 : fabs(s_z[c][j]);
+            res = (s_bn[j] > 0.0) ? zc * sqrt(s_rr[j]) / s_bn[j] : 0.0;
+        }
+        a.resid[gcol] = res;
+        a.flags[gcol] = s_flag[j] | (s_act[c][j] ? 1 : 0);
+    }
+    if (kg == 0 && t == 0) a.tile_iters[tile] = it;
+}
+
+template <int DIM, int NB>
+hipError_t launch_ms(const MsArgs &a, hipStream_t s) {
+    MsArgs args = a;
+    void *kargs[] = {&args};
+    return hipLaunchCooperativeKernel((const void *)mscg_kernel<DIM, NB>,
+                                      dim3(a.ntiles * a.K), dim3(NT), kargs, 0, s);
+}
+
+template <int DIM, int NB>
+int max_groups_resident() {
+    int nb = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)mscg_kernel<DIM, NB>, NT, 0) !=
+        hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return nb * cus;
+}
+
+}  // namespace
+
+#define ACP_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+int mscg_resident_capacity(int dim, int ne) {
+    const int nb = (ne + 15) / 16;
+#define CASE(N)                                                                    \
+    if (nb == N) return dim == 1 ? max_groups_resident<1, N>() : max_groups_resident<2, N>();
+    ACP_NB_CASES(CASE)
+#undef CASE
+    return 0;
+}
+
+size_t mscg_group_slot(int ne) {
+    const int nb = (ne + 15) / 16;
+    return (size_t)nb * 16 * kTile + kTile;
+}
+
+hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.nshift > MAXSH || a.ne > 256) return hipErrorInvalidValue;
+    const int nb = (a.ne + 15) / 16;
+#define CASE(N)                                                                    \
+    if (nb == N) return a.g.dim == 1 ? launch_ms<1, N>(a, s) : launch_ms<2, N>(a, s);
+    ACP_NB_CASES(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace acp

@@ -301,9 +301,25 @@ __global__ void transpose_kernel(int m, int n, const double *A, int lda, double 
     }
 }
 
+__global__ void fill_u32_kernel(unsigned *p, size_t n, unsigned v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 inline unsigned nblk(long long tot, int b) { return (unsigned)((tot + b - 1) / b); }
 
 }  // namespace
+
+// Fills by kernel rather than hipMemsetAsync, so that they may be recorded in a graph.
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(nblk((long long)n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s) {
+    return launch_fill_u32((unsigned *)p, n, (unsigned)v, s);
+}
 
 hipError_t launch_transpose(int m, int n, const double *A, int lda, double *B, int ldb,
                             hipStream_t s) {

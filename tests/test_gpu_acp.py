@@ -67,7 +67,7 @@ def test_isdf_selection_and_interpolation(cid):
 
 
 @pytest.mark.parametrize("cid", [1, 11])
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 def test_compress_matches_oracle(cid, solver):
     cfg, m, gs, w, v, G, om, K = system(cid)
     ref_dec = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
