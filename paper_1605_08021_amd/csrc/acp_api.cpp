@@ -292,7 +292,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *us
         const int k = std::atoi(ov);
         if (k >= 1 && k * rhs_tiles <= cap) K = k;
     }
-    K = std::max(K, 1);
+    K = std::max(std::min(K, kMsMaxGroup), 1);
     const size_t vt = (size_t)ng * kTile;           // doubles per tile vector
     ENSURE(ctx->kx, (size_t)nc * rhs_tiles * vt * 8);
     ENSURE(ctx->msp, (size_t)nc * rhs_tiles * vt * 8);

@@ -143,6 +143,7 @@ struct MsArgs {
 // Iterations per window of the deferred solution updates of the multi-shift solver
 // (the residual ring holds this many residuals per tile).
 constexpr int kMsWindow = 8;
+constexpr int kMsMaxGroup = 16;   // workgroups per right-hand-side tile
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s);
 int mscg_resident_capacity(int dim, int ne);   // workgroups the device can hold at once
 size_t mscg_group_slot(int ne);                // doubles per group partial

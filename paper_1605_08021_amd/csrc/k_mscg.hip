@@ -36,6 +36,7 @@ using namespace kry;
 constexpr unsigned kSpinLimit = 1u << 22;   // ~seconds: a wait this long means a lost group
 constexpr int MAXSH = 16;                   // shifts per right-hand side
 constexpr int WS = kMsWindow;
+constexpr int KMAX = kMsMaxGroup;           // workgroups per tile
 
 struct GroupSync {
     unsigned *cnt;      // per-tile counter (monotonic)
@@ -44,7 +45,15 @@ struct GroupSync {
     int K;
     int kg;
     unsigned phase;     // number of completed group barriers
+    bool local;         // every workgroup of the group runs on this XCD (one L2)
 };
+
+// XCD (accelerator complex die) of the executing workgroup.
+__device__ __forceinline__ unsigned xcd_id() {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 0xfu;
+}
 
 // This workgroup's partial buffer for the next group barrier.
 __device__ __forceinline__ double *group_mine(const GroupSync &gs, int tile) {
@@ -57,22 +66,39 @@ __device__ __forceinline__ double *group_mine(const GroupSync &gs, int tile) {
 // Returns false if the wait expired (the launch is then abandoned).
 __device__ bool group_sum(GroupSync &gs, int tile, double *dst, int n, int *abort_flag) {
     const double *base = gs.buf + ((size_t)tile * 2 + (gs.phase & 1u)) * (size_t)gs.K * gs.slot;
-    // every wave's stores complete before the barrier; thread 0's release then
-    // publishes them (and the workgroup's halo rows) to the other workgroups
+    // every wave's stores complete before the barrier (explicitly in the local
+    // mode: the workgroup barrier alone does not wait for global stores); thread
+    // 0's release then publishes them (and the workgroup's halo rows)
+    if (gs.local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(gs.cnt + tile, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // A group on one XCD shares one L2, through which every store of the
+        // group passes (the vector L1 is write-through, and every wave waited
+        // for its stores to complete before the barrier above): the counter
+        // needs no L2 write-back on release, and acquiring needs only this
+        // compute unit's L1 invalidated.  Otherwise the agent-scope
+        // release/acquire pair.
+        if (gs.local)
+            __hip_atomic_fetch_add(gs.cnt + tile, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_fetch_add(gs.cnt + tile, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned target = (gs.phase + 1) * (unsigned)gs.K;
         unsigned spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(gs.cnt + tile, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        // spin on relaxed loads (an acquire per poll would invalidate caches every
+        // time), then one acquire fence once the group has arrived
+        while (__hip_atomic_load(gs.cnt + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > kSpinLimit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 ok = 0;
                 break;
             }
         }
+        if (gs.local)
+            asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");   // L1 only
+        else
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);   // agent scope (HIP's default for fences)
         if (!ok) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_ok = ok;
     }
@@ -80,10 +106,29 @@ __device__ bool group_sum(GroupSync &gs, int tile, double *dst, int n, int *abor
     __syncthreads();
     gs.phase += 1;
     if (!s_ok) return false;
-    for (int i = threadIdx.x; i < n; i += NT) {
-        double v = 0.0;
-        for (int k = 0; k < gs.K; ++k) v += base[(size_t)k * gs.slot + i];
-        dst[i] = v;
+    // the K partials of two elements are loaded together (up to 2 KMAX loads in
+    // flight per thread), then summed in group order
+    const int K = gs.K;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 2 * NT) {
+        const int i1 = i0 + NT < n ? i0 + NT : i0;
+        double v0[KMAX], v1[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < K) {
+                v0[k] = base[(size_t)k * gs.slot + i0];
+                v1[k] = base[(size_t)k * gs.slot + i1];
+            }
+        }
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < K) {
+                s0 += v0[k];
+                s1 += v1[k];
+            }
+        }
+        dst[i0] = s0;
+        if (i0 + NT < n) dst[i1] = s1;
     }
     __syncthreads();
     return true;
@@ -156,7 +201,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
     auto Ps = [&](int c) { return a.p + ((long long)c * a.ntiles + tile) * tstride; };
     auto Rs = [&](int k) { return a.r + ((long long)(k % WS) * a.ntiles + tile) * tstride; };
     const double sbase = a.shift[bs];
-    GroupSync gs{a.cnt, a.gbuf, S::ELEMS + kTile, K, kg, 0u};
+    GroupSync gs{a.cnt, a.gbuf, S::ELEMS + kTile, K, kg, 0u, false};
     const int nblk = (ng + 15) / 16;
     // rows of this workgroup in the flat walk of the deferred updates
     const int own_rows = ((nblk - kg + K - 1) / K) * 16;
@@ -273,8 +318,22 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
             }
         }
     }
-    column_partial(bb, red, group_mine(gs, tile));
+    // the first barrier (agent scope) also publishes each workgroup's XCD
+    __shared__ int s_local;
+    {
+        double *mine = group_mine(gs, tile);
+        if (t == 0) mine[kTile] = (double)xcd_id();
+        column_partial(bb, red, mine);
+    }
     if (!group_sum(gs, tile, s_tmp, kTile, a.abort_flag)) return;
+    if (t == 0) {
+        const double *first = a.gbuf + (size_t)tile * 2 * K * gs.slot;   // parity 0
+        int same = 1;
+        for (int k = 1; k < K; ++k) same &= first[(size_t)k * gs.slot + kTile] == first[kTile];
+        s_local = same;
+    }
+    __syncthreads();
+    gs.local = s_local != 0;
     if (t < kTile) {
         const double bn = sqrt(s_tmp[t]);
         s_bn[t] = bn;
@@ -567,7 +626,7 @@ size_t mscg_group_slot(int ne) {
 
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
-    if (a.nshift > MAXSH || a.ne > 256) return hipErrorInvalidValue;
+    if (a.nshift > MAXSH || a.ne > 256 || a.K < 1 || a.K > KMAX) return hipErrorInvalidValue;
     const int nb = (a.ne + 15) / 16;
 #define CASE(N)                                                                    \
     if (nb == N) return a.g.dim == 1 ? launch_ms<1, N>(a, s) : launch_ms<2, N>(a, s);
