@@ -116,7 +116,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--form", choices=["fast", "single", "plain"], default="fast")
+    ap.add_argument("--form", choices=["fast", "mixed", "single", "plain"], default="fast")
     ap.add_argument("--dyson-iters", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -156,10 +156,12 @@ def main():
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     phi, veff, G, om = T(inp.phi), T(inp.veff), T(inp.G), T(inp.omega)
-    solver = {"fast": acp.SOLVER_CG, "single": acp.SOLVER_CG_SINGLE,
+    solver = {"fast": acp.SOLVER_CG, "mixed": acp.SOLVER_CG, "single": acp.SOLVER_CG_SINGLE,
               "plain": acp.SOLVER_MINRES}[args.form]
+    mixed = args.form == "mixed"
     opts = dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol, max_iter=20000,
-                solver=solver, dyson_max_iter=args.dyson_iters)
+                solver=solver, dyson_max_iter=args.dyson_iters,
+                precision=acp.PREC_FP32_REFINE if mixed else acp.PREC_FP64, inner_tol=1e-5)
     ctx = acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0,
                            occ=cfg.f), opts, phi, inp.eps[: inp.n_e], veff)
     masses = np.ones(inp.R.shape[0])
@@ -196,10 +198,12 @@ def main():
     flops_per_launch = st["krylov_flops"] / launches
     ms_per_launch = st["ms_solve_kernel"] / launches
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
-    kname = {acp.SOLVER_CG: "mscg_kernel (multi-shift CG: fused stencil + projector, shifted updates)",
+    kname = {acp.SOLVER_CG: "mscg_kernel (multi-shift CG: fused stencil + projector, shifted updates)"
+             + (" FP32 storage, with per-system FP32 cg_kernel corrections" if mixed else ""),
              acp.SOLVER_MINRES: "minres_kernel (fused stencil + projector + MINRES)",
              acp.SOLVER_CG_SINGLE: "cg_kernel (fused stencil + projector + CG)"}[solver]
-    traffic = measured_traffic(f"config {args.config}") if solver == acp.SOLVER_CG else None
+    traffic = (measured_traffic(f"config {args.config}")
+               if solver == acp.SOLVER_CG and not mixed else None)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname,
@@ -219,17 +223,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
                                f"ground state, gap {inp.gap:.5f} Ha",
-                   "form": {acp.SOLVER_CG: "batched FP64 multi-shift CG",
+                   "form": "FP32-storage multi-shift CG + FP64 iterative refinement" if mixed else
+                           {acp.SOLVER_CG: "batched FP64 multi-shift CG",
                             acp.SOLVER_CG_SINGLE: "batched FP64 CG, one sequence per system",
                             acp.SOLVER_MINRES: "plain FP64 MINRES"}[solver],
                    "dyson_iterations": st["dyson_iters"], "n_g": ng, "n_e": ne,
                    "n_p": int(inp.G.shape[1]), "n_c": cfg.n_cheb, "n_mu": cfg.n_mu,
                    "tol": args.tol},
         "max_true_rel_residual": st["max_rel_residual"],
+        "refinements": st["refinements"],
         "iters_min_max_last_solve": [st["iters_min"], st["iters_max"]],
         "phase_ms_per_step": {k: round(st[k] / args.steps, 2) for k in
                               ("ms_isdf", "ms_rhs", "ms_solve", "ms_w", "ms_dyson_small",

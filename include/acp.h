@@ -54,7 +54,13 @@ typedef enum {
 
 typedef enum {
     ACP_PREC_FP64 = 0,         /* every Krylov step in FP64 */
-    ACP_PREC_FP32_REFINE = 1   /* FP32 inner solves, FP64 residual refinement */
+    ACP_PREC_FP32_REFINE = 1   /* FP32 inner solves, FP64 residual refinement: Phi, the
+                                  right-hand sides and the Krylov vectors are stored in FP32
+                                  (arithmetic in FP64, solutions accumulated in FP64); the
+                                  first solve (multi-shift with ACP_SOLVER_CG) runs to
+                                  inner_tol, then r = b - A x is recomputed in FP64 and FP32
+                                  per-system corrections run until every system meets tol
+                                  (at most 8 corrections, else ACP_ENOCONV).  CG only. */
 } acp_precision;
 
 typedef enum {
@@ -102,7 +108,7 @@ typedef struct {
     int iters_min, iters_max;    /* over systems of the last solve */
     double max_rel_residual;     /* max true FP64 relative residual of the last solve */
     int dyson_iters;             /* compressions done by the last acp_dyson */
-    int refinements;             /* outer FP64 refinement steps of the last solve */
+    int refinements;             /* FP64 refinement steps (corrections) since the last reset */
     double ms_isdf, ms_rhs, ms_solve, ms_w, ms_dyson_small, ms_dynmat;  /* accumulated */
     double ms_solve_kernel;      /* accumulated time inside the Krylov kernel launches */
     int64_t solve_kernel_launches;

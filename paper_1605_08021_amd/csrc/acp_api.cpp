@@ -63,6 +63,7 @@ struct acp_ctx {
     DevBuf gt, lchol, diag, isdf_scratch, l11, linv, c1, bc, tmp1, tmp2, tmp3, shifts_dev;
     DevBuf kx, kr, kpa, kpb, kw1, kw2, krhs, kiters, kresid, kflags, ktile;
     DevBuf msp, msgbuf, mscnt, msabort, msprof;
+    DevBuf phi_rm32, phi_cm32, krhs32, colmask;   // mixed-precision form
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     acp_stats stats{};
@@ -144,6 +145,10 @@ acp_status validate_opts(acp_ctx *ctx, const acp_opts *o) {
         return fail(ctx, ACP_EINVAL, "unknown solver");
     if (o->precision != ACP_PREC_FP64 && o->precision != ACP_PREC_FP32_REFINE)
         return fail(ctx, ACP_EINVAL, "unknown precision");
+    if (o->precision == ACP_PREC_FP32_REFINE && o->solver == ACP_SOLVER_MINRES)
+        return fail(ctx, ACP_EINVAL, "the mixed-precision form uses CG (MINRES runs in FP64)");
+    if (o->precision == ACP_PREC_FP32_REFINE && !(o->inner_tol > 0.0 && o->inner_tol < 1.0))
+        return fail(ctx, ACP_EINVAL, "inner_tol must lie in (0, 1)");
     if (o->dyson_max_iter < 1) return fail(ctx, ACP_EINVAL, "dyson_max_iter must be >= 1");
     if (o->node_mode != ACP_NODES_CHEBYSHEV && o->node_mode != ACP_NODES_OCCUPIED)
         return fail(ctx, ACP_EINVAL, "unknown node_mode");
@@ -199,51 +204,64 @@ acp_status vc_apply(acp_ctx *ctx, int n, const double *X, double *Y) {
     return ACP_OK;
 }
 
-// Batched projected shifted solve on tiled right-hand sides already in ctx->krhs.
+// Storage-typed inputs of the Krylov kernels: Phi (both orders) and the tiled
+// right-hand sides, in FP64 or in the FP32 copies of the mixed-precision form.
+template <typename T>
+struct KrylovInputs {
+    const T *phi_rm, *phi_cm, *rhs;
+};
+
+// Batched projected shifted solve of ntiles tiles (tile t uses right-hand-side
+// tile t % rhs_tiles) to relative residual tol; solutions (always FP64) land in
+// ctx->kx.  MINRES runs in FP64 only.
+template <typename T>
 acp_status solve_tiled(acp_ctx *ctx, int ntiles, int rhs_tiles, const double *shifts_dev,
-                       int *flags_or) {
+                       const KrylovInputs<T> &in, double tol, int *flags_or) {
     const int ng = ctx->ng;
-    const size_t vbytes = (size_t)ntiles * ng * kTile * 8;
-    ENSURE(ctx->kx, vbytes);
-    ENSURE(ctx->kr, vbytes);
-    ENSURE(ctx->kpa, vbytes);
-    ENSURE(ctx->kpb, vbytes);
-    if (ctx->opts.solver == ACP_SOLVER_MINRES) {
-        ENSURE(ctx->kw1, vbytes);
-        ENSURE(ctx->kw2, vbytes);
+    const size_t velems = (size_t)ntiles * ng * kTile;
+    const bool minres = ctx->opts.solver == ACP_SOLVER_MINRES;
+    if (minres && sizeof(T) != 8) return fail(ctx, ACP_EINVAL, "MINRES runs in FP64 only");
+    ENSURE(ctx->kx, velems * 8);
+    ENSURE(ctx->kr, velems * sizeof(T));
+    ENSURE(ctx->kpa, velems * sizeof(T));
+    ENSURE(ctx->kpb, velems * sizeof(T));
+    if (minres) {
+        ENSURE(ctx->kw1, velems * sizeof(T));
+        ENSURE(ctx->kw2, velems * sizeof(T));
     }
     const int ncols = ntiles * kTile;
     ENSURE(ctx->kiters, (size_t)ncols * 4);
     ENSURE(ctx->kresid, (size_t)ncols * 8);
     ENSURE(ctx->kflags, (size_t)ncols * 4);
     ENSURE(ctx->ktile, (size_t)ntiles * 4);
-    KrylovArgs a{};
+    KrylovArgsT<T> a{};
     a.g = ctx->gd;
     a.ne = ctx->nep;
     a.ntiles = ntiles;
     a.rhs_tiles = rhs_tiles;
-    a.phi_rm = dp<double>(ctx->phi_rm);
-    a.phi_cm = dp<double>(ctx->phi_cm);
+    a.phi_rm = in.phi_rm;
+    a.phi_cm = in.phi_cm;
     a.veff = dp<double>(ctx->veff);
     a.shift = shifts_dev;
-    a.rhs = dp<double>(ctx->krhs);
+    a.rhs = in.rhs;
     a.x = dp<double>(ctx->kx);
-    a.r = dp<double>(ctx->kr);
-    a.pa = dp<double>(ctx->kpa);
-    a.pb = dp<double>(ctx->kpb);
-    a.w1 = dp<double>(ctx->kw1);
-    a.w2 = dp<double>(ctx->kw2);
+    a.r = dp<T>(ctx->kr);
+    a.pa = dp<T>(ctx->kpa);
+    a.pb = dp<T>(ctx->kpb);
+    a.w1 = dp<T>(ctx->kw1);
+    a.w2 = dp<T>(ctx->kw2);
     a.iters = dp<int>(ctx->kiters);
     a.resid = dp<double>(ctx->kresid);
     a.flags = dp<int>(ctx->kflags);
-    a.tol = ctx->opts.tol;
+    a.tol = tol;
     a.max_iter = ctx->opts.max_iter;
     a.tile_iters = dp<int>(ctx->ktile);
     HIPCHK(hipEventRecord(ctx->ev[6], ctx->stream));
-    if (ctx->opts.solver == ACP_SOLVER_MINRES) {
-        HIPCHK(launch_minres_fp64(a, ctx->stream));
+    if constexpr (sizeof(T) == 8) {
+        if (minres) HIPCHK(launch_minres_fp64(a, ctx->stream));
+        else HIPCHK(launch_cg_fp64(a, ctx->stream));
     } else {
-        HIPCHK(launch_cg_fp64(a, ctx->stream));
+        HIPCHK(launch_cg_fp32(a, ctx->stream));
     }
     HIPCHK(hipEventRecord(ctx->ev[7], ctx->stream));
     std::vector<int> it(ncols), fl(ncols), ti(ntiles);
@@ -266,24 +284,29 @@ acp_status solve_tiled(acp_ctx *ctx, int ntiles, int rhs_tiles, const double *sh
     for (int t = 0; t < ntiles; ++t) tsum += ti[t];
     ctx->stats.system_iterations += sum;
     ctx->stats.tile_iterations += tsum;
-    const double vecs = (ctx->opts.solver == ACP_SOLVER_MINRES) ? 12.0 : 8.0;
-    ctx->stats.krylov_bytes += vecs * 8.0 * ng * (double)sum;
+    // per system-iteration: CG reads r, p_old, p, r and writes p, r in T and
+    // reads/writes x in FP64; MINRES streams 12 FP64 vectors
+    const double bytes_per_it = minres ? 12.0 * 8.0 : 6.0 * sizeof(T) + 16.0;
+    ctx->stats.krylov_bytes += bytes_per_it * ng * (double)sum;
     ctx->stats.krylov_flops += 4.0 * ng * (double)ctx->ne * (double)sum;
     ctx->stats.iters_min = imin;
     ctx->stats.iters_max = imax;
-    *flags_or = f;
+    *flags_or |= f;
     return ACP_OK;
 }
 
-// Multi-shift solve of every shift for the tiled right-hand sides in ctx->krhs
-// (rhs_tiles tiles); solutions land in ctx->kx with the per-system layout
-// (tile c * rhs_tiles + t holds shift c).  Returns false in *used when the
-// device cannot hold one workgroup per tile (the caller then solves per system).
-acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *used) {
+// Multi-shift solve of every shift for the rhs_tiles tiled right-hand sides to
+// relative residual tol; solutions (FP64) land in ctx->kx with the per-system
+// layout (tile c * rhs_tiles + t holds shift c).  Returns false in *used when
+// the device cannot hold one workgroup per tile (the caller then solves per
+// system).
+template <typename T>
+acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &in, double tol,
+                            int *flags_or, bool *used) {
     const int ng = ctx->ng, nc = (int)ctx->nodes.size();
     *used = false;
     if (nc > 16) return ACP_OK;
-    const int cap = mscg_resident_capacity(ctx->gd.dim, ctx->nep);
+    const int cap = mscg_resident_capacity(ctx->gd.dim, ctx->nep, sizeof(T) == 4);
     if (cap < rhs_tiles) return ACP_OK;
     const int nblk = (ng + 15) / 16;
     int K = cap / rhs_tiles;
@@ -293,12 +316,12 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *us
         if (k >= 1 && k * rhs_tiles <= cap) K = k;
     }
     K = std::max(std::min(K, kMsMaxGroup), 1);
-    const size_t vt = (size_t)ng * kTile;           // doubles per tile vector
+    const size_t vt = (size_t)ng * kTile;           // elements per tile vector
     ENSURE(ctx->kx, (size_t)nc * rhs_tiles * vt * 8);
-    ENSURE(ctx->msp, (size_t)nc * rhs_tiles * vt * 8);
-    ENSURE(ctx->kr, (size_t)kMsWindow * rhs_tiles * vt * 8);   // residual ring
-    ENSURE(ctx->kpa, (size_t)rhs_tiles * vt * 8);
-    ENSURE(ctx->kpb, (size_t)rhs_tiles * vt * 8);
+    ENSURE(ctx->msp, (size_t)nc * rhs_tiles * vt * sizeof(T));
+    ENSURE(ctx->kr, (size_t)kMsWindow * rhs_tiles * vt * sizeof(T));   // residual ring
+    ENSURE(ctx->kpa, (size_t)rhs_tiles * vt * sizeof(T));
+    ENSURE(ctx->kpb, (size_t)rhs_tiles * vt * sizeof(T));
     const size_t slot = mscg_group_slot(ctx->nep);
     ENSURE(ctx->msgbuf, (size_t)rhs_tiles * 2 * K * slot * 8);
     ENSURE(ctx->mscnt, (size_t)rhs_tiles * 4);
@@ -316,7 +339,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *us
     HIPCHK(hipMemcpyAsync(ctx->dy_s.p, ctx->nodes.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
     HIPCHK(launch_fill_u32(dp<unsigned>(ctx->mscnt), rhs_tiles, 0u, s));
     HIPCHK(launch_fill_i32(dp<int>(ctx->msabort), 1, 0, s));
-    MsArgs a{};
+    MsArgsT<T> a{};
     a.g = ctx->gd;
     a.ne = ctx->nep;
     a.ntiles = rhs_tiles;
@@ -324,15 +347,15 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *us
     a.nshift = nc;
     a.base = base;
     a.shift = dp<double>(ctx->dy_s);
-    a.phi_rm = dp<double>(ctx->phi_rm);
-    a.phi_cm = dp<double>(ctx->phi_cm);
+    a.phi_rm = in.phi_rm;
+    a.phi_cm = in.phi_cm;
     a.veff = dp<double>(ctx->veff);
-    a.rhs = dp<double>(ctx->krhs);
+    a.rhs = in.rhs;
     a.x = dp<double>(ctx->kx);
-    a.p = dp<double>(ctx->msp);
-    a.r = dp<double>(ctx->kr);
-    a.pa = dp<double>(ctx->kpa);
-    a.pb = dp<double>(ctx->kpb);
+    a.p = dp<T>(ctx->msp);
+    a.r = dp<T>(ctx->kr);
+    a.pa = dp<T>(ctx->kpa);
+    a.pb = dp<T>(ctx->kpb);
     a.gbuf = dp<double>(ctx->msgbuf);
     a.cnt = dp<unsigned>(ctx->mscnt);
     a.abort_flag = dp<int>(ctx->msabort);
@@ -340,7 +363,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *us
     a.resid = dp<double>(ctx->kresid);
     a.flags = dp<int>(ctx->kflags);
     a.tile_iters = dp<int>(ctx->ktile);
-    a.tol = ctx->opts.tol;
+    a.tol = tol;
     a.max_iter = ctx->opts.max_iter;
     const bool prof = std::getenv("ACP_MSCG_PHASES") != nullptr;   // with ACP_PHASE_CLOCKS builds
     if (prof) {
@@ -349,7 +372,8 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *us
         a.phase_clock = dp<unsigned long long>(ctx->msprof);
     }
     HIPCHK(hipEventRecord(ctx->ev[6], s));
-    HIPCHK(launch_mscg_fp64(a, s));
+    if constexpr (sizeof(T) == 8) HIPCHK(launch_mscg_fp64(a, s));
+    else HIPCHK(launch_mscg_fp32(a, s));
     HIPCHK(hipEventRecord(ctx->ev[7], s));
     std::vector<int> it(ncols), fl(ncols), ti(rhs_tiles);
     int abort_h = 0;
@@ -388,14 +412,14 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, int *flags_or, bool *us
     ctx->stats.iters_min = imin;
     ctx->stats.iters_max = imax;
     // base, per iteration: pass 1 reads r and p_old and writes p, pass 2 reads p
-    // and r and writes the next r, the window update reads r once more (7 sweeps);
-    // every sequence (base included) then reads and writes p_c and x_c once per
-    // window (4 sweeps per kMsWindow iterations)
-    const double per_window = 4.0 / kMsWindow;
-    ctx->stats.krylov_bytes += 8.0 * ng * ((7.0 + per_window) * (double)base_it +
-                                           per_window * (double)shifted_it);
+    // and r and writes the next r, the window update reads r once more (7 vectors
+    // in T); every sequence (base included) then reads and writes p_c (T) and x_c
+    // (FP64) once per window of kMsWindow iterations
+    const double per_window = (2.0 * sizeof(T) + 16.0) / kMsWindow;
+    ctx->stats.krylov_bytes += ng * ((7.0 * sizeof(T) + per_window) * (double)base_it +
+                                     per_window * (double)shifted_it);
     ctx->stats.krylov_flops += 4.0 * ng * (double)ctx->ne * (double)base_it;
-    *flags_or = f;
+    *flags_or |= f;
     return ACP_OK;
 }
 
@@ -434,6 +458,94 @@ acp_status true_residual(acp_ctx *ctx, int n, const double *shifts_dev, const do
     double m = 0.0;
     for (int j = 0; j < n; ++j)
         if (h[n + j] > 0.0) m = std::max(m, std::sqrt(h[j] / h[n + j]));
+    *max_rel = m;
+    return ACP_OK;
+}
+
+// FP32 copies of Phi (both orders) for the inner solves of the mixed form.
+acp_status ensure_phi32(acp_ctx *ctx) {
+    const size_t n = ctx->phi_rm.bytes / 8;
+    if (ctx->phi_rm32.p && ctx->phi_rm32.bytes >= n * 4) return ACP_OK;
+    ENSURE(ctx->phi_rm32, n * 4);
+    ENSURE(ctx->phi_cm32, n * 4);
+    HIPCHK(launch_to_f32(n, dp<double>(ctx->phi_rm), dp<float>(ctx->phi_rm32), ctx->stream));
+    HIPCHK(launch_to_f32(n, dp<double>(ctx->phi_cm), dp<float>(ctx->phi_cm32), ctx->stream));
+    return ACP_OK;
+}
+
+// Iterative refinement of the mixed-precision form: X (column-major FP64, n
+// columns, shifts per column in shifts_dev, padded to a multiple of 16) holds
+// the FP32 first solve.  Repeat: R = B - A X in FP64; stop once every column has
+// ||R_j|| <= tol ||B_j||; otherwise solve A D = R with FP32 storage to inner_tol
+// for the columns still above tol (the others get a zero right-hand side and
+// stop at once) and accumulate X += D in FP64.
+constexpr int kMaxRefine = 8;
+acp_status refine_fp32(acp_ctx *ctx, int n, const double *shifts_dev, const double *B, double *X,
+                       int *flags_or, double *max_rel) {
+    const int ng = ctx->ng;
+    const int ntiles = (n + kTile - 1) / kTile;
+    const int npad = ntiles * kTile;
+    hipStream_t s = ctx->stream;
+    CHECK(ensure_phi32(ctx));
+    ENSURE(ctx->tmp1, (size_t)ng * n * 8);
+    ENSURE(ctx->dy_norm, (size_t)2 * n * 8);
+    ENSURE(ctx->colmask, (size_t)npad * 8);
+    ENSURE(ctx->krhs32, (size_t)npad * ng * 4);
+    double *AX = dp<double>(ctx->tmp1);
+    double *rn = dp<double>(ctx->dy_norm), *bn = rn + n;
+    HIPCHK(launch_col_sqnorm(ng, n, B, ng, bn, s));
+    std::vector<double> h(2 * n), mask(npad, 0.0);
+    double m = 0.0;
+    for (int ref = 0;; ++ref) {
+        CHECK(apply_operator(ctx, n, shifts_dev, X, AX));
+        HIPCHK(launch_col_diff_sqnorm(ng, n, B, ng, AX, ng, rn, s));
+        HIPCHK(hipMemcpyAsync(h.data(), rn, 2 * n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        m = 0.0;
+        int open = 0;
+        for (int j = 0; j < n; ++j) {
+            const double rel = h[n + j] > 0.0 ? std::sqrt(h[j] / h[n + j]) : 0.0;
+            m = std::max(m, rel);
+            mask[j] = rel > ctx->opts.tol ? 1.0 : 0.0;
+            open += rel > ctx->opts.tol;
+        }
+        if (!open) break;
+        if (ref == kMaxRefine) {
+            *flags_or |= 1;
+            break;
+        }
+        HIPCHK(launch_axpby(ng, n, 1.0, B, ng, -1.0, AX, ng, s));   // AX <- B - A X
+        // back onto range(Q): the rounding of A X leaves an occupied component of
+        // order u ||A|| ||X||, which near the requested tolerance is no longer small
+        // against the residual itself, and the inner solve cannot remove it (the
+        // shifts lie inside the occupied band, so it would spoil p^T A p > 0)
+        {
+            ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+            const double *phi = dp<double>(ctx->phi_cm);
+            double *C = dp<double>(ctx->c1);
+            HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, AX, ng, 0, 0.0, C, ctx->ne, 0, 1, s));
+            HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, AX, ng, 0, 1, s));
+        }
+        HIPCHK(hipMemcpyAsync(ctx->colmask.p, mask.data(), (size_t)npad * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_to_tiled_f32(ng, n, npad, AX, ng, dp<double>(ctx->colmask),
+                                   dp<float>(ctx->krhs32), s));
+        KrylovInputs<float> in{dp<float>(ctx->phi_rm32), dp<float>(ctx->phi_cm32),
+                               dp<float>(ctx->krhs32)};
+        int f = 0;
+        CHECK(solve_tiled<float>(ctx, ntiles, ntiles, shifts_dev, in, ctx->opts.inner_tol, &f));
+        *flags_or |= f & ~1;   // an inner solve short of inner_tol is judged by the next residual
+        HIPCHK(launch_from_tiled_add(ng, n, dp<double>(ctx->kx), X, ng, s));
+        ctx->stats.refinements += 1;
+    }
+    // the solution of Eq. (3.6) lies in range(Q); the FP32 passes leave an occupied
+    // component of order u_32 ||X|| that no residual sees: remove it (A X unchanged)
+    {
+        ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+        const double *phi = dp<double>(ctx->phi_cm);
+        double *C = dp<double>(ctx->c1);
+        HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, X, ng, 0, 0.0, C, ctx->ne, 0, 1, s));
+        HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, X, ng, 0, 1, s));
+    }
     *max_rel = m;
     return ACP_OK;
 }
@@ -582,8 +694,29 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, sh.data(), sh.size() * 8, hipMemcpyHostToDevice, s));
     int flags = 0;
     bool ms_used = false;
-    if (ctx->opts.solver == ACP_SOLVER_CG) CHECK(solve_multishift(ctx, rhs_tiles, &flags, &ms_used));
-    if (!ms_used) CHECK(solve_tiled(ctx, ntiles, rhs_tiles, dp<double>(ctx->shifts_dev), &flags));
+    const bool mixed = ctx->opts.precision == ACP_PREC_FP32_REFINE;
+    if (!mixed) {
+        KrylovInputs<double> in{dp<double>(ctx->phi_rm), phi, dp<double>(ctx->krhs)};
+        if (ctx->opts.solver == ACP_SOLVER_CG)
+            CHECK(solve_multishift<double>(ctx, rhs_tiles, in, ctx->opts.tol, &flags, &ms_used));
+        if (!ms_used)
+            CHECK(solve_tiled<double>(ctx, ntiles, rhs_tiles, dp<double>(ctx->shifts_dev), in,
+                                      ctx->opts.tol, &flags));
+    } else {
+        // FP32 first solve (multi-shift when possible) to inner_tol, refined below
+        CHECK(ensure_phi32(ctx));
+        ENSURE(ctx->krhs32, (size_t)rhs_tiles * ng * kTile * 4);
+        HIPCHK(launch_to_f32((size_t)rhs_tiles * ng * kTile, dp<double>(ctx->krhs),
+                             dp<float>(ctx->krhs32), s));
+        KrylovInputs<float> in{dp<float>(ctx->phi_rm32), dp<float>(ctx->phi_cm32),
+                               dp<float>(ctx->krhs32)};
+        if (ctx->opts.solver == ACP_SOLVER_CG)
+            CHECK(solve_multishift<float>(ctx, rhs_tiles, in, ctx->opts.inner_tol, &flags, &ms_used));
+        if (!ms_used)
+            CHECK(solve_tiled<float>(ctx, ntiles, rhs_tiles, dp<double>(ctx->shifts_dev), in,
+                                     ctx->opts.inner_tol, &flags));
+        flags &= ~1;   // judged by the refined residual
+    }
     ctx->stats.systems_solved += (long long)nc * nmu;
     // Z (column-major, block c = shift c)
     ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
@@ -591,6 +724,23 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     for (int c = 0; c < nc; ++c)
         HIPCHK(launch_from_tiled(ng, nmu, dp<double>(ctx->kx) + (size_t)c * rhs_tiles * ng * kTile,
                                  Z + (size_t)c * nmu * ng, ng, s));
+    // every system's right-hand side and shift, column-major like Z
+    const int ncols = nc * nmu;
+    const int ncols_pad = (ncols + kTile - 1) / kTile * kTile;
+    ENSURE(ctx->tmp3, (size_t)ng * ncols * 8);
+    double *Bfull = dp<double>(ctx->tmp3);
+    std::vector<double> shc((size_t)ncols_pad, ctx->nodes[nc - 1]);
+    for (int c = 0; c < nc; ++c) {
+        HIPCHK(hipMemcpyAsync(Bfull + (size_t)c * nmu * ng, R, (size_t)ng * nmu * 8,
+                              hipMemcpyDeviceToDevice, s));
+        for (int j = 0; j < nmu; ++j) shc[(size_t)c * nmu + j] = ctx->nodes[c];
+    }
+    ENSURE(ctx->dy_s, shc.size() * 8);
+    HIPCHK(hipMemcpyAsync(ctx->dy_s.p, shc.data(), shc.size() * 8, hipMemcpyHostToDevice, s));
+    if (mixed) {
+        double mr = 0.0;
+        CHECK(refine_fp32(ctx, ncols, dp<double>(ctx->dy_s), Bfull, Z, &flags, &mr));
+    }
     HIPCHK(hipEventRecord(ctx->ev[3], s));
     // W = (2 f / h^d) sum_c Z_c o (Phi diag(L_c) Phi(Pi,:)^T)
     ENSURE(ctx->w, (size_t)ng * nmu * 8);
@@ -611,20 +761,8 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     ctx->stats.ms_w += event_ms(ctx->ev[3], ctx->ev[4]);
     // true residual of every system (FP64), reported in the statistics
     {
-        const int ncols = nc * nmu;
-        ENSURE(ctx->tmp3, (size_t)ng * ncols * 8);
-        double *Bfull = dp<double>(ctx->tmp3);
-        std::vector<double> shc((size_t)ncols);
-        for (int c = 0; c < nc; ++c) {
-            HIPCHK(hipMemcpyAsync(Bfull + (size_t)c * nmu * ng, R, (size_t)ng * nmu * 8,
-                                  hipMemcpyDeviceToDevice, s));
-            for (int j = 0; j < nmu; ++j) shc[(size_t)c * nmu + j] = ctx->nodes[c];
-        }
-        DevBuf &shb = ctx->dy_s;
-        ENSURE(shb, shc.size() * 8);
-        HIPCHK(hipMemcpyAsync(shb.p, shc.data(), shc.size() * 8, hipMemcpyHostToDevice, s));
         double mr = 0.0;
-        CHECK(true_residual(ctx, ncols, dp<double>(shb), Bfull, Z, &mr));
+        CHECK(true_residual(ctx, ncols, dp<double>(ctx->dy_s), Bfull, Z, &mr));
         ctx->stats.max_rel_residual = mr;
     }
     ctx->have_chi0 = true;
@@ -737,8 +875,25 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
     HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, sh.data(), (size_t)npad * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(ctx->ev[2], s));
     int flags = 0;
-    CHECK(solve_tiled(ctx, ntiles, ntiles, dp<double>(ctx->shifts_dev), &flags));
-    HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), X, ng, s));
+    if (ctx->opts.precision == ACP_PREC_FP32_REFINE) {
+        CHECK(ensure_phi32(ctx));
+        ENSURE(ctx->krhs32, (size_t)npad * ng * 4);
+        HIPCHK(launch_to_f32((size_t)npad * ng, dp<double>(ctx->krhs), dp<float>(ctx->krhs32), s));
+        KrylovInputs<float> in{dp<float>(ctx->phi_rm32), dp<float>(ctx->phi_cm32),
+                               dp<float>(ctx->krhs32)};
+        CHECK(solve_tiled<float>(ctx, ntiles, ntiles, dp<double>(ctx->shifts_dev), in,
+                                 ctx->opts.inner_tol, &flags));
+        flags &= ~1;
+        HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), X, ng, s));
+        double mr = 0.0;
+        CHECK(refine_fp32(ctx, n, dp<double>(ctx->shifts_dev), B, X, &flags, &mr));
+    } else {
+        KrylovInputs<double> in{dp<double>(ctx->phi_rm), dp<double>(ctx->phi_cm),
+                                dp<double>(ctx->krhs)};
+        CHECK(solve_tiled<double>(ctx, ntiles, ntiles, dp<double>(ctx->shifts_dev), in,
+                                  ctx->opts.tol, &flags));
+        HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), X, ng, s));
+    }
     HIPCHK(hipEventRecord(ctx->ev[3], s));
     if (iters) HIPCHK(hipMemcpyAsync(iters, ctx->kiters.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -933,7 +1088,8 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->kflags, &ctx->ktile, &ctx->dy_v, &ctx->dy_t, &ctx->dy_s, &ctx->dy_g,
                       &ctx->dy_gk, &ctx->dy_norm, &ctx->dm_phi, &ctx->dm_k, &ctx->dm_mass,
                       &ctx->dm_d, &ctx->dm_eig, &ctx->dm_work, &ctx->dm_asym, &ctx->splitk,
-                      &ctx->msp, &ctx->msgbuf, &ctx->mscnt, &ctx->msabort, &ctx->msprof};
+                      &ctx->msp, &ctx->msgbuf, &ctx->mscnt, &ctx->msabort, &ctx->msprof,
+                      &ctx->phi_rm32, &ctx->phi_cm32, &ctx->krhs32, &ctx->colmask};
     for (DevBuf *b : bufs) release(*b);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);

@@ -93,19 +93,31 @@ hipError_t launch_to_tiled(int ng, int ncols, int ncols_pad, const double *X, in
                            double *T, hipStream_t s);
 hipError_t launch_from_tiled(int ng, int ncols, const double *T, double *X, int ldx,
                              hipStream_t s);
+// FP32 tiles of X (each column scaled by colscale[j] when given), X += tiles,
+// and an elementwise FP64 -> FP32 copy: the mixed-precision form.
+hipError_t launch_to_tiled_f32(int ng, int ncols, int ncols_pad, const double *X, int ldx,
+                               const double *colscale, float *T, hipStream_t s);
+hipError_t launch_from_tiled_add(int ng, int ncols, const double *T, double *X, int ldx,
+                                 hipStream_t s);
+hipError_t launch_to_f32(size_t n, const double *X, float *Y, hipStream_t s);
 
-struct KrylovArgs {
+// T is the storage type of Phi, the right-hand sides and the Krylov vectors
+// (double, or float for the inner solves of the mixed-precision form); the
+// solution x is always accumulated in double, and all arithmetic is FP64.
+template <typename T>
+struct KrylovArgsT {
     GridDesc g;
     int ne;
     int ntiles;             // number of 16-column tiles to solve
     int rhs_tiles;          // tiles of the right-hand side; tile t uses rhs tile t % rhs_tiles
-    const double *phi_rm;   // N_g x N_e row-major (orbitals contiguous)
-    const double *phi_cm;   // N_g x N_e column-major
+    const T *phi_rm;        // N_g x N_e row-major (orbitals contiguous)
+    const T *phi_cm;        // N_g x N_e column-major
     const double *veff;     // N_g
     const double *shift;    // per column (ntiles * 16)
-    const double *rhs;      // tiled right-hand sides
-    double *x, *r, *pa, *pb;    // tiled state
-    double *w1, *w2, *w3;       // extra tiled vectors (MINRES)
+    const T *rhs;           // tiled right-hand sides
+    double *x;              // tiled solution
+    T *r, *pa, *pb;         // tiled state
+    T *w1, *w2, *w3;        // extra tiled vectors (MINRES)
     int *iters;             // per column
     double *resid;          // per column: final recurrence residual / ||b||
     int *flags;             // per column: bit0 not converged, bit1 non-positive curvature
@@ -113,22 +125,27 @@ struct KrylovArgs {
     int max_iter;
     int *tile_iters;        // per tile: iterations executed by its workgroup
 };
+using KrylovArgs = KrylovArgsT<double>;
 hipError_t launch_cg_fp64(const KrylovArgs &a, hipStream_t s);
+hipError_t launch_cg_fp32(const KrylovArgsT<float> &a, hipStream_t s);
 
 // Multi-shift CG: every tile of 16 right-hand sides solves all nshift shifts;
 // a group of K workgroups shares a tile (cooperative launch of ntiles * K).
-struct MsArgs {
+template <typename T>
+struct MsArgsT {
     GridDesc g;
     int ne;                 // padded orbital count (multiple of 16)
     int ntiles;             // right-hand-side tiles
     int K;                  // workgroups per tile
     int nshift, base;       // shifts; index of the base (largest) shift
     const double *shift;    // device, nshift
-    const double *phi_rm, *phi_cm, *veff;
-    const double *rhs;      // tiled right-hand sides, ntiles tiles
-    double *x, *p;          // [nshift][ntiles] tiles each
-    double *r;              // residual ring: [kMsWindow][ntiles] tiles
-    double *pa, *pb;        // ntiles tiles each
+    const T *phi_rm, *phi_cm;
+    const double *veff;
+    const T *rhs;           // tiled right-hand sides, ntiles tiles
+    double *x;              // [nshift][ntiles] tiles (always double)
+    T *p;                   // [nshift][ntiles] tiles
+    T *r;                   // residual ring: [kMsWindow][ntiles] tiles
+    T *pa, *pb;             // ntiles tiles each
     double *gbuf;           // ntiles * 2 * K * slot doubles
     unsigned *cnt;          // ntiles counters, zero at launch
     int *abort_flag;        // set if a group barrier wait expired
@@ -140,12 +157,14 @@ struct MsArgs {
     int max_iter;
     unsigned long long *phase_clock;   // 8 phase timers of workgroup 0 (ACP_PHASE_CLOCKS builds)
 };
+using MsArgs = MsArgsT<double>;
 // Iterations per window of the deferred solution updates of the multi-shift solver
 // (the residual ring holds this many residuals per tile).
 constexpr int kMsWindow = 8;
 constexpr int kMsMaxGroup = 16;   // workgroups per right-hand-side tile
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s);
-int mscg_resident_capacity(int dim, int ne);   // workgroups the device can hold at once
+hipError_t launch_mscg_fp32(const MsArgsT<float> &a, hipStream_t s);
+int mscg_resident_capacity(int dim, int ne, bool fp32);   // workgroups the device can hold at once
 size_t mscg_group_slot(int ne);                // doubles per group partial
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);

@@ -36,8 +36,8 @@ namespace {
 
 using namespace kry;
 
-template <int DIM, int NB>
-__global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
+template <int DIM, int NB, typename T>
+__global__ __launch_bounds__(NT) void cg_kernel(KrylovArgsT<T> a) {
     __shared__ double slots[Slots<NB>::N * Slots<NB>::ELEMS];
     __shared__ double red[NT];
     __shared__ double s_rr[kTile], s_alpha[kTile], s_beta[kTile], s_bn[kTile], s_tmp[kTile];
@@ -49,20 +49,20 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
     const int lane = t & 63;
     const int wave = t >> 6;
     const long long base = (long long)tile * a.g.ng * kTile;
-    const double *__restrict__ b = a.rhs + (long long)(tile % a.rhs_tiles) * a.g.ng * kTile;
+    const T *__restrict__ b = a.rhs + (long long)(tile % a.rhs_tiles) * a.g.ng * kTile;
     double *__restrict__ x = a.x + base;
-    double *__restrict__ r = a.r + base;
-    double *pA = a.pa + base;
-    double *pB = a.pb + base;
+    T *__restrict__ r = a.r + base;
+    T *pA = a.pa + base;
+    T *pB = a.pb + base;
     const double s = a.shift[tile * kTile + col];
 
     // init: x = 0, r = b, p_old = 0, rr = |b|^2
     double part = 0.0;
     for (int idx = t; idx < a.g.ng * kTile; idx += NT) {
-        const double bv = b[idx];
+        const double bv = (double)b[idx];
         x[idx] = 0.0;
-        r[idx] = bv;
-        pA[idx] = 0.0;
+        r[idx] = (T)bv;
+        pA[idx] = (T)0.0;
         part += bv * bv;   // idx % 16 == t % 16 == col since NT % 16 == 0
     }
     column_reduce(part, red, s_rr);
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
         if (!s_any) break;
         // ---- pass 1: p = r + beta p_old (into pB), y = (H - s) p, C = Phi^T y, p^T y
         const double beta = s_beta[col];
-        const double pty = apply_pass1<DIM, NB>(r, pA, beta, a, s, slots, pB);
+        const double pty = apply_pass1<DIM, NB, T>(r, pA, beta, a, s, slots, pB);
         column_reduce(pty, red, s_tmp);
         if (t < kTile) {
             double al = 0.0;
@@ -114,9 +114,9 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
             for (int e = 0; e < 4; ++e) {
                 const int row = R + e < a.g.ng ? R + e : a.g.ng - 1;
                 xo[e] = x[row * kTile + col];
-                ro[e] = r[row * kTile + col];
+                ro[e] = (double)r[row * kTile + col];
             }
-            const d4 d = project_block<NB>(a.phi_cm, a.g.ng, slots, row0);
+            const d4 d = project_block<NB, T>(a.phi_cm, a.g.ng, slots, row0);
             double y[4], pc[4];
             stencil_from<DIM>(w, R, a.g, a.veff, s, y, pc);
 #pragma unroll
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
                 const double rn = ro[e] - al * ap;
                 if (R + e < a.g.ng) {
                     x[(R + e) * kTile + col] = xn;
-                    r[(R + e) * kTile + col] = rn;
+                    r[(R + e) * kTile + col] = (T)rn;
                     rr_part += rn * rn;
                 }
             }
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(NT) void cg_kernel(KrylovArgs a) {
             }
         }
         __syncthreads();
-        double *tmp = pA; pA = pB; pB = tmp;
+        T *tmp = pA; pA = pB; pB = tmp;
     }
     if (t < kTile) {
         const int gc = tile * kTile + t;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
         __syncthreads();
         if (!s_any) break;
         // ---- pass 1: y = (H - s) v, C = Phi^T y, alpha = v^T y
-        const double vty = apply_pass1<DIM, NB>(v, nullptr, 0.0, a, s, slots, nullptr);
+        const double vty = apply_pass1<DIM, NB, double>(v, nullptr, 0.0, a, s, slots, nullptr);
         column_reduce(vty, red, s_alpha);
         // ---- pass 2: v_new = (y - Phi C) - alpha v - beta v_old  (into vo), |v_new|^2
         double nn = 0.0;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
                 const int row = R + e < a.g.ng ? R + e : a.g.ng - 1;
                 vold[e] = vo[row * kTile + col];
             }
-            const d4 d = project_block<NB>(a.phi_cm, a.g.ng, slots, row0);
+            const d4 d = project_block<NB, double>(a.phi_cm, a.g.ng, slots, row0);
             double y[4], pc[4];
             stencil_from<DIM>(w, R, a.g, a.veff, s, y, pc);
 #pragma unroll
@@ -311,13 +311,14 @@ __global__ __launch_bounds__(NT) void minres_kernel(KrylovArgs a) {
 
 #define ACP_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-hipError_t launch_cg_impl(const KrylovArgs &a, hipStream_t s) {
+template <typename T>
+hipError_t launch_cg_impl(const KrylovArgsT<T> &a, hipStream_t s) {
     const int nb = (a.ne + 15) / 16;
     dim3 grid(a.ntiles), block(NT);
 #define CASE(N)                                                                              \
     if (nb == N) {                                                                           \
-        if (a.g.dim == 1) hipLaunchKernelGGL((cg_kernel<1, N>), grid, block, 0, s, a);       \
-        else hipLaunchKernelGGL((cg_kernel<2, N>), grid, block, 0, s, a);                    \
+        if (a.g.dim == 1) hipLaunchKernelGGL((cg_kernel<1, N, T>), grid, block, 0, s, a);    \
+        else hipLaunchKernelGGL((cg_kernel<2, N, T>), grid, block, 0, s, a);                 \
         return hipGetLastError();                                                            \
     }
     ACP_NB_CASES(CASE)
@@ -342,6 +343,12 @@ hipError_t launch_minres_impl(const KrylovArgs &a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_cg_fp64(const KrylovArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ne > MAXNB * 16) return hipErrorInvalidValue;
+    return launch_cg_impl(a, s);
+}
+
+hipError_t launch_cg_fp32(const KrylovArgsT<float> &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     if (a.ne > MAXNB * 16) return hipErrorInvalidValue;
     return launch_cg_impl(a, s);

@@ -162,8 +162,8 @@ __device__ __forceinline__ void column_partial(double v, double *red, double *ou
 #define PHASE_MARK(i) do {} while (0)
 #endif
 
-template <int DIM, int NB>
-__global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
+template <int DIM, int NB, typename T>
+__global__ __launch_bounds__(NT) void mscg_kernel(MsArgsT<T> a) {
     using S = Slots<NB>;
     static_assert(S::N * S::ELEMS >= S::ELEMS + kTile, "slots hold C and p^T y");
     __shared__ double slots[S::N * S::ELEMS];
@@ -192,9 +192,9 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
     const int bs = a.base;
     const int ng = a.g.ng;
     const long long tstride = (long long)ng * kTile;
-    const double *__restrict__ b = a.rhs + (long long)tile * tstride;
-    double *pA = a.pa + (long long)tile * tstride;
-    double *pB = a.pb + (long long)tile * tstride;
+    const T *__restrict__ b = a.rhs + (long long)tile * tstride;
+    T *pA = a.pa + (long long)tile * tstride;
+    T *pB = a.pb + (long long)tile * tstride;
     // shift c of this tile: X[c] at a.x + (c * ntiles + tile) * tstride, same for P;
     // residual of iteration k at ring slot k % WS
     auto Xs = [&](int c) { return a.x + ((long long)c * a.ntiles + tile) * tstride; };
@@ -235,9 +235,9 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
 #pragma unroll
             for (int w = 0; w < WS; ++w) {
                 if (w < n_steps) {
-                    const double *rk = Rs(k0 + w);
+                    const T *rk = Rs(k0 + w);
 #pragma unroll
-                    for (int i = 0; i < RR; ++i) rw[w][i] = rk[id[i]];
+                    for (int i = 0; i < RR; ++i) rw[w][i] = (double)rk[id[i]];
                 }
             }
             double pn[RR] = {}, xn[RR] = {};
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
             if (nn > 0) {
 #pragma unroll
                 for (int i = 0; i < RR; ++i) {
-                    pn[i] = Ps(0)[id[i]];
+                    pn[i] = (double)Ps(0)[id[i]];
                     xn[i] = Xs(0)[id[i]];
                 }
             }
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
                     if (nn > 0) {
 #pragma unroll
                         for (int i = 0; i < RR; ++i) {
-                            pn[i] = Ps(c + 1)[id[i]];
+                            pn[i] = (double)Ps(c + 1)[id[i]];
                             xn[i] = Xs(c + 1)[id[i]];
                         }
                     }
@@ -279,11 +279,12 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
                             }
                         }
                     }
-                    double *pc = Ps(c), *xc = Xs(c);
+                    T *pc = Ps(c);
+                    double *xc = Xs(c);
 #pragma unroll
                     for (int i = 0; i < RR; ++i)
                         if (ok[i]) {
-                            pc[id[i]] = pv[i];
+                            pc[id[i]] = (T)pv[i];
                             xc[id[i]] = xv[i];
                         }
                 }
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
     // ---- init (own rows): r_0 = b, x_c = 0, p_c = 0, p_old = 0; |b|^2
     double bb = 0.0;
     {
-        double *r0 = Rs(0);
+        T *r0 = Rs(0);
         for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
             const int R = blk * 16 + 4 * q;
 #pragma unroll
@@ -306,12 +307,12 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
                 const int row = R + j;
                 if (row < ng) {
                     const int id = row * kTile + col;
-                    const double bv = b[id];
-                    r0[id] = bv;
-                    pA[id] = 0.0;
+                    const double bv = (double)b[id];
+                    r0[id] = (T)bv;
+                    pA[id] = (T)0.0;
                     for (int c = 0; c < ns; ++c) {
                         Xs(c)[id] = 0.0;
-                        Ps(c)[id] = 0.0;
+                        Ps(c)[id] = (T)0.0;
                     }
                     bb += bv * bv;
                 }
@@ -370,7 +371,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
         }
         __syncthreads();
         if (!s_any) break;
-        const double *rcur = Rs(it);
+        const T *rcur = Rs(it);
         // ---- pass 1: base p = r + beta p_old (-> pB), y = (H - s_base) p, C = Phi^T y, p^T y
         constexpr int nep = NB * 16;
         constexpr int NN = Nbr<DIM>::N;
@@ -384,16 +385,16 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
             const Nbr<DIM> nb(R, a.g);
             double w[NN], wp[NN];
 #pragma unroll
-            for (int k = 0; k < NN; ++k) w[k] = rcur[nb.idx[k] * kTile + col];
+            for (int k = 0; k < NN; ++k) w[k] = (double)rcur[nb.idx[k] * kTile + col];
 #pragma unroll
-            for (int k = 0; k < NN; ++k) wp[k] = pA[nb.idx[k] * kTile + col];
+            for (int k = 0; k < NN; ++k) wp[k] = (double)pA[nb.idx[k] * kTile + col];
             double av[4][NB];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int row = R + j < ng ? R + j : ng - 1;
-                const double *ph = a.phi_rm + (long long)row * nep + col;
+                const T *ph = a.phi_rm + (long long)row * nep + col;
 #pragma unroll
-                for (int mb = 0; mb < NB; ++mb) av[j][mb] = ph[mb * 16];
+                for (int mb = 0; mb < NB; ++mb) av[j][mb] = (double)ph[mb * 16];
             }
 #pragma unroll
             for (int k = 0; k < NN; ++k) w[k] += beta * wp[k];
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 pty += pc[j] * y[j];
-                if (R + j < ng) pB[(R + j) * kTile + col] = pc[j];
+                if (R + j < ng) pB[(R + j) * kTile + col] = (T)pc[j];
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
         double rr_part = 0.0;
         {
             const double al = s_al[col];
-            double *rnext = Rs(it + 1);
+            T *rnext = Rs(it + 1);
             for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
                 const int row0 = blk * 16;
                 const int R = row0 + 4 * q;
@@ -512,16 +513,16 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int row = R + e < ng ? R + e : ng - 1;
-                    ro[e] = rcur[row * kTile + col];
+                    ro[e] = (double)rcur[row * kTile + col];
                 }
-                const d4 d = project_block<NB>(a.phi_cm, ng, slots, row0);
+                const d4 d = project_block<NB, T>(a.phi_cm, ng, slots, row0);
                 double y[4], pc[4];
                 stencil_from<DIM>(w, R, a.g, a.veff, sbase, y, pc);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const double rn = ro[e] - al * (y[e] - d[e]);
                     if (R + e < ng) {
-                        rnext[(R + e) * kTile + col] = rn;
+                        rnext[(R + e) * kTile + col] = (T)rn;
                         rr_part += rn * rn;
                     }
                 }
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
         }
         __syncthreads();
         PHASE_MARK(5);
-        double *tmp = pA; pA = pB; pB = tmp;
+        T *tmp = pA; pA = pB; pB = tmp;
     }
 #ifdef ACP_PHASE_CLOCKS
     if (prof)
@@ -587,18 +588,18 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgs a) {
     if (kg == 0 && t == 0) a.tile_iters[tile] = it;
 }
 
-template <int DIM, int NB>
-hipError_t launch_ms(const MsArgs &a, hipStream_t s) {
-    MsArgs args = a;
+template <int DIM, int NB, typename T>
+hipError_t launch_ms(const MsArgsT<T> &a, hipStream_t s) {
+    MsArgsT<T> args = a;
     void *kargs[] = {&args};
-    return hipLaunchCooperativeKernel((const void *)mscg_kernel<DIM, NB>,
+    return hipLaunchCooperativeKernel((const void *)mscg_kernel<DIM, NB, T>,
                                       dim3(a.ntiles * a.K), dim3(NT), kargs, 0, s);
 }
 
-template <int DIM, int NB>
+template <int DIM, int NB, typename T>
 int max_groups_resident() {
     int nb = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)mscg_kernel<DIM, NB>, NT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)mscg_kernel<DIM, NB, T>, NT, 0) !=
         hipSuccess)
         return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -610,10 +611,13 @@ int max_groups_resident() {
 
 #define ACP_NB_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-int mscg_resident_capacity(int dim, int ne) {
+int mscg_resident_capacity(int dim, int ne, bool fp32) {
     const int nb = (ne + 15) / 16;
-#define CASE(N)                                                                    \
-    if (nb == N) return dim == 1 ? max_groups_resident<1, N>() : max_groups_resident<2, N>();
+#define CASE(N)                                                                            \
+    if (nb == N) {                                                                         \
+        if (fp32) return dim == 1 ? max_groups_resident<1, N, float>() : max_groups_resident<2, N, float>(); \
+        return dim == 1 ? max_groups_resident<1, N, double>() : max_groups_resident<2, N, double>(); \
+    }
     ACP_NB_CASES(CASE)
 #undef CASE
     return 0;
@@ -624,15 +628,19 @@ size_t mscg_group_slot(int ne) {
     return (size_t)nb * 16 * kTile + kTile;
 }
 
-hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s) {
+template <typename T>
+hipError_t launch_mscg(const MsArgsT<T> &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     if (a.nshift > MAXSH || a.ne > 256 || a.K < 1 || a.K > KMAX) return hipErrorInvalidValue;
     const int nb = (a.ne + 15) / 16;
 #define CASE(N)                                                                    \
-    if (nb == N) return a.g.dim == 1 ? launch_ms<1, N>(a, s) : launch_ms<2, N>(a, s);
+    if (nb == N) return a.g.dim == 1 ? launch_ms<1, N, T>(a, s) : launch_ms<2, N, T>(a, s);
     ACP_NB_CASES(CASE)
 #undef CASE
     return hipErrorInvalidValue;
 }
+
+hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s) { return launch_mscg(a, s); }
+hipError_t launch_mscg_fp32(const MsArgsT<float> &a, hipStream_t s) { return launch_mscg(a, s); }
 
 }  // namespace acp

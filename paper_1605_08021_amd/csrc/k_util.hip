@@ -188,8 +188,11 @@ __global__ void max_dev_identity_kernel(int n, const double *G, double *out) {
 
 // Column-major (ld = ldx) -> 16-column row-interleaved tiles; padded columns are zero.
 // Block: 16 columns x 64 rows through LDS.
+// Column-major -> 16-column tiles; TO = double, or float for the inner solves of
+// the mixed-precision form; colscale (optional) multiplies each column.
+template <typename TO>
 __global__ void to_tiled_kernel(int ng, int ncols, const double *__restrict__ X, int ldx,
-                                double *__restrict__ T) {
+                                const double *__restrict__ colscale, TO *__restrict__ T) {
     __shared__ double buf[kTile][65];
     const int tile = blockIdx.y;
     const int r0 = blockIdx.x * 64;
@@ -199,7 +202,7 @@ __global__ void to_tiled_kernel(int ng, int ncols, const double *__restrict__ X,
         int r = t & 63, c = (t >> 6) + 4 * q;
         int gr = r0 + r, gc = tile * kTile + c;
         double v = 0.0;
-        if (gr < ng && gc < ncols) v = X[gr + (long long)gc * ldx];
+        if (gr < ng && gc < ncols) v = X[gr + (long long)gc * ldx] * (colscale ? colscale[gc] : 1.0);
         buf[c][r] = v;
     }
     __syncthreads();
@@ -207,10 +210,12 @@ __global__ void to_tiled_kernel(int ng, int ncols, const double *__restrict__ X,
     for (int q = 0; q < 4; ++q) {
         int c = t & 15, r = (t >> 4) + 16 * q;
         int gr = r0 + r;
-        if (gr < ng) T[((long long)tile * ng + gr) * kTile + c] = buf[c][r];
+        if (gr < ng) T[((long long)tile * ng + gr) * kTile + c] = (TO)buf[c][r];
     }
 }
 
+// 16-column tiles -> column-major; ADD accumulates into X.
+template <bool ADD>
 __global__ void from_tiled_kernel(int ng, int ncols, const double *__restrict__ T,
                                   double *__restrict__ X, int ldx) {
     __shared__ double buf[kTile][65];
@@ -228,8 +233,16 @@ __global__ void from_tiled_kernel(int ng, int ncols, const double *__restrict__ 
     for (int q = 0; q < 4; ++q) {
         int r = t & 63, c = (t >> 6) + 4 * q;
         int gr = r0 + r, gc = tile * kTile + c;
-        if (gr < ng && gc < ncols) X[gr + (long long)gc * ldx] = buf[c][r];
+        if (gr < ng && gc < ncols) {
+            if (ADD) X[gr + (long long)gc * ldx] += buf[c][r];
+            else X[gr + (long long)gc * ldx] = buf[c][r];
+        }
     }
+}
+
+__global__ void to_f32_kernel(long long n, const double *__restrict__ X, float *__restrict__ Y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) Y[i] = (float)X[i];
 }
 
 // Real orthonormal Fourier basis of R^n: column 0 constant, columns 2k-1 / 2k
@@ -418,14 +431,34 @@ hipError_t launch_gram_check(int n, int /*unused*/, const double *G, double *max
 hipError_t launch_to_tiled(int ng, int ncols, int ncols_pad, const double *X, int ldx, double *T,
                            hipStream_t s) {
     dim3 grid(nblk(ng, 64), ncols_pad / kTile);
-    hipLaunchKernelGGL(to_tiled_kernel, grid, dim3(256), 0, s, ng, ncols, X, ldx, T);
+    hipLaunchKernelGGL(to_tiled_kernel<double>, grid, dim3(256), 0, s, ng, ncols, X, ldx,
+                       (const double *)nullptr, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_tiled_f32(int ng, int ncols, int ncols_pad, const double *X, int ldx,
+                               const double *colscale, float *T, hipStream_t s) {
+    dim3 grid(nblk(ng, 64), ncols_pad / kTile);
+    hipLaunchKernelGGL(to_tiled_kernel<float>, grid, dim3(256), 0, s, ng, ncols, X, ldx, colscale, T);
     return hipGetLastError();
 }
 
 hipError_t launch_from_tiled(int ng, int ncols, const double *T, double *X, int ldx,
                              hipStream_t s) {
     dim3 grid(nblk(ng, 64), (ncols + kTile - 1) / kTile);
-    hipLaunchKernelGGL(from_tiled_kernel, grid, dim3(256), 0, s, ng, ncols, T, X, ldx);
+    hipLaunchKernelGGL(from_tiled_kernel<false>, grid, dim3(256), 0, s, ng, ncols, T, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_tiled_add(int ng, int ncols, const double *T, double *X, int ldx,
+                                 hipStream_t s) {
+    dim3 grid(nblk(ng, 64), (ncols + kTile - 1) / kTile);
+    hipLaunchKernelGGL(from_tiled_kernel<true>, grid, dim3(256), 0, s, ng, ncols, T, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(size_t n, const double *X, float *Y, hipStream_t s) {
+    hipLaunchKernelGGL(to_f32_kernel, dim3(nblk((long long)n, 256)), dim3(256), 0, s, (long long)n, X, Y);
     return hipGetLastError();
 }
 

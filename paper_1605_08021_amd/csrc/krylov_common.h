@@ -114,10 +114,10 @@ struct Slots {
 // over rows, so any row order works as long as the A operand follows it).
 // C = Phi^T y is reduced across waves in LDS into slots[0] (orbital-major,
 // 16 systems per orbital).  Returns this thread's share of p^T y.
-template <int DIM, int NB>
-__device__ __forceinline__ double apply_pass1(const double *__restrict__ rv, const double *__restrict__ pv,
-                                              double beta, const KrylovArgs &a, double s,
-                                              double *slots, double *__restrict__ pstore) {
+template <int DIM, int NB, typename T>
+__device__ __forceinline__ double apply_pass1(const T *__restrict__ rv, const T *__restrict__ pv,
+                                              double beta, const KrylovArgsT<T> &a, double s,
+                                              double *slots, T *__restrict__ pstore) {
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -135,18 +135,18 @@ __device__ __forceinline__ double apply_pass1(const double *__restrict__ rv, con
         // issue every load of the block before any use
         double w[NN], wp[NN];
 #pragma unroll
-        for (int k = 0; k < NN; ++k) w[k] = rv[nb.idx[k] * kTile + col];
+        for (int k = 0; k < NN; ++k) w[k] = (double)rv[nb.idx[k] * kTile + col];
         if (pv) {
 #pragma unroll
-            for (int k = 0; k < NN; ++k) wp[k] = pv[nb.idx[k] * kTile + col];
+            for (int k = 0; k < NN; ++k) wp[k] = (double)pv[nb.idx[k] * kTile + col];
         }
         double av[4][NB];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int row = R + j < a.g.ng ? R + j : a.g.ng - 1;
-            const double *ph = a.phi_rm + (long long)row * nep + col;
+            const T *ph = a.phi_rm + (long long)row * nep + col;
 #pragma unroll
-            for (int mb = 0; mb < NB; ++mb) av[j][mb] = ph[mb * 16];
+            for (int mb = 0; mb < NB; ++mb) av[j][mb] = (double)ph[mb * 16];
         }
         if (pv) {
 #pragma unroll
@@ -157,7 +157,7 @@ __device__ __forceinline__ double apply_pass1(const double *__restrict__ rv, con
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             pty += pc[j] * y[j];
-            if (pstore && R + j < a.g.ng) pstore[(R + j) * kTile + col] = pc[j];
+            if (pstore && R + j < a.g.ng) pstore[(R + j) * kTile + col] = (T)pc[j];
         }
         // rows past the end contribute y = 0, so their (clamped) Phi rows are harmless
 #pragma unroll
@@ -196,18 +196,18 @@ __device__ __forceinline__ double apply_pass1(const double *__restrict__ rv, con
 // the matrix cores.  The f64 MFMA returns D[l/16 + 4 e][l%16] to lane l, so the
 // A operand feeds grid row 4 (m % 4) + m / 4 into MFMA row m: lane l then holds
 // the consecutive grid rows row0 + 4*(l/16) + e of system l % 16.
-template <int NB>
-__device__ __forceinline__ d4 project_block(const double *__restrict__ phi_cm, int ng,
+template <int NB, typename T>
+__device__ __forceinline__ d4 project_block(const T *__restrict__ phi_cm, int ng,
                                             const double *Cs, int row0) {
     const int lane = threadIdx.x & 63;
     constexpr int nep = NB * 16;
     const int m = lane & 15;
     int row = row0 + 4 * (m & 3) + (m >> 2);
     row = row < ng ? row : ng - 1;   // clamped rows feed outputs that are never stored
-    const double *ph = phi_cm + row + (long long)(lane >> 4) * ng;
+    const T *ph = phi_cm + row + (long long)(lane >> 4) * ng;
     double av[nep / 4];
 #pragma unroll
-    for (int k = 0; k < nep / 4; ++k) av[k] = ph[(long long)(4 * k) * ng];
+    for (int k = 0; k < nep / 4; ++k) av[k] = (double)ph[(long long)(4 * k) * ng];
     d4 d = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < nep / 4; ++k) {
@@ -218,12 +218,12 @@ __device__ __forceinline__ d4 project_block(const double *__restrict__ phi_cm, i
 }
 
 // Gather the stencil neighbourhood of rows R..R+3 of one system from v.
-template <int DIM>
-__device__ __forceinline__ void gather(const double *__restrict__ v, int R, const GridDesc &g,
+template <int DIM, typename T>
+__device__ __forceinline__ void gather(const T *__restrict__ v, int R, const GridDesc &g,
                                        int col, double (&w)[Nbr<DIM>::N]) {
     const Nbr<DIM> nb(R, g);
 #pragma unroll
-    for (int k = 0; k < Nbr<DIM>::N; ++k) w[k] = v[nb.idx[k] * kTile + col];
+    for (int k = 0; k < Nbr<DIM>::N; ++k) w[k] = (double)v[nb.idx[k] * kTile + col];
 }
 
 
