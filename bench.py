@@ -116,7 +116,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--form", choices=["fast", "mixed", "single", "plain"], default="fast")
+    ap.add_argument("--form", choices=["fast", "mixed", "learned", "single", "plain"], default="fast")
     ap.add_argument("--dyson-iters", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -157,7 +157,8 @@ def main():
 
     phi, veff, G, om = T(inp.phi), T(inp.veff), T(inp.G), T(inp.omega)
     solver = {"fast": acp.SOLVER_CG, "mixed": acp.SOLVER_CG, "single": acp.SOLVER_CG_SINGLE,
-              "plain": acp.SOLVER_MINRES}[args.form]
+              "plain": acp.SOLVER_MINRES, "learned": acp.SOLVER_CG_SINGLE}[args.form]
+    learned = args.form == "learned"
     mixed = args.form == "mixed"
     opts = dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol, max_iter=20000,
                 solver=solver, dyson_max_iter=args.dyson_iters,
@@ -165,6 +166,25 @@ def main():
     ctx = acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0,
                            occ=cfg.f), opts, phi, inp.eps[: inp.n_e], veff)
     masses = np.ones(inp.R.shape[0])
+    train_info = None
+    if learned:
+        # untimed: the network is trained once, on the method's own solves for 16
+        # right-hand sides at every shift of the first compression
+        from paper_1605_08021_amd import precond as PC
+        t0 = time.perf_counter()
+        ctx.compress(G, om)
+        Rfull = ctx.compress_get("rhs")
+        shifts = ctx.shifts()
+        cols = torch.arange(16, device=dev)
+        B = torch.cat([Rfull[:, cols]] * len(shifts), dim=1)
+        sh = np.repeat(shifts, 16)
+        hist = PC.train_preconditioner(ctx, sh, B, seed=1234)
+        ctx.set_opts(use_learned_precond=1)
+        train_info = {"pairs_systems": int(B.shape[1]), "steps": int(sum(len(h) for h in hist)),
+                      "loss_first": round(float(hist[0][:20].mean()), 4),
+                      "loss_last": round(float(hist[-1][-20:].mean()), 4),
+                      "seconds": round(time.perf_counter() - t0, 1)}
+        log(f"preconditioner trained: {train_info}")
 
     def step():
         U, iters, _ = ctx.dyson(G, om)
@@ -194,6 +214,8 @@ def main():
     ng = inp.phi.shape[0]
     ne = inp.n_e
     launches = max(st["solve_kernel_launches"], 1)
+    if st["ms_solve_kernel"] <= 0.0:
+        st["ms_solve_kernel"] = float("nan")
     bytes_per_launch = st["krylov_bytes"] / launches
     flops_per_launch = st["krylov_flops"] / launches
     ms_per_launch = st["ms_solve_kernel"] / launches
@@ -211,6 +233,8 @@ def main():
                 "mfma_fp64_tflops": round(flops_per_launch / (ms_per_launch * 1e-3) / 1e12, 2),
                 "ms_per_launch": round(ms_per_launch, 3),
                 "workgroups_per_tile": st["krylov_group"]}
+    if learned:
+        roofline = None   # no single fused kernel: the flexible CG is a host-driven loop
     log(f"stats: {json.dumps(st)}")
     out = {
         "metric": "Sternheimer RHS*shifts solved/s at 1e-8 residual",
@@ -227,7 +251,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
                                f"ground state, gap {inp.gap:.5f} Ha",
-                   "form": "FP32-storage multi-shift CG + FP64 iterative refinement" if mixed else
+                   "form": ("flexible CG with the learned BF16 conv preconditioner (FP64 vectors)"
+                            if learned else
+                            "FP32-storage multi-shift CG + FP64 iterative refinement") if (mixed or learned) else
                            {acp.SOLVER_CG: "batched FP64 multi-shift CG",
                             acp.SOLVER_CG_SINGLE: "batched FP64 CG, one sequence per system",
                             acp.SOLVER_MINRES: "plain FP64 MINRES"}[solver],
@@ -236,6 +262,7 @@ def main():
                    "tol": args.tol},
         "max_true_rel_residual": st["max_rel_residual"],
         "refinements": st["refinements"],
+        "preconditioner_training": train_info,
         "iters_min_max_last_solve": [st["iters_min"], st["iters_max"]],
         "phase_ms_per_step": {k: round(st[k] / args.steps, 2) for k in
                               ("ms_isdf", "ms_rhs", "ms_solve", "ms_w", "ms_dyson_small",

@@ -99,6 +99,12 @@ typedef struct {
     int dyson_max_iter;  /* k_max of Alg. 4 */
     double dyson_tol;    /* stop when ||U^k - U^{k-1}||_F <= dyson_tol ||U^k||_F (0: run k_max) */
     double inner_tol;    /* relative tolerance of each inner FP32 solve (ACP_PREC_FP32_REFINE) */
+    int use_learned_precond;  /* acp_sternheimer and acp_compress: 0 = the fused Krylov kernels;
+                                 1 = flexible CG preconditioned by the learned network
+                                 (d = Q N(r/rms(r), shift) rms(r)), plain FP64 MINRES
+                                 finishing any system it leaves unconverged;
+                                 2 = the same host-driven CG without the network (the
+                                 comparison the network is measured against) */
 } acp_opts;
 
 typedef struct {
@@ -203,6 +209,43 @@ acp_status acp_dyson(acp_ctx *ctx, const double *G, int n_p, const double *omega
 acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
                       const double *K_local, const double *mass, double *D,
                       double *omega2);
+
+/* acp_residual -- R = B - Q (H - shift[j]) Q X column by column, in FP64.
+ * shift host n; B, X, R dev N_g x n. */
+acp_status acp_residual(acp_ctx *ctx, const double *shift, int n, const double *B,
+                        const double *X, double *R);
+
+/* ---- Learned preconditioner (an addition to the paper's method) ----------
+ * Network N: four periodic convolutions of width 5 per grid axis (5 taps in
+ * 1D, 5 x 5 in 2D), channels 2 -> 32 -> 32 -> 32 -> 1, bias per channel, ReLU
+ * after the first three; BF16 operands on the matrix cores, FP32 accumulation.
+ * Input of a residual r at shift s: channel 0 = r / rms(r), channel 1 = the
+ * constant (s - (eps_1 + eps_Ne)/2) / ((eps_Ne - eps_1)/2 + 1e-12).
+ * Parameters theta (FP32): for each layer W [cout][cin][taps] then b [cout];
+ * acp_precond_n_params gives the count.  The context keeps FP32 master
+ * parameters, Adam moments and BF16 copies. */
+int acp_precond_n_params(int dim);
+/* Fan-in-scaled uniform initial weights from a 64-bit seed, zero biases. */
+acp_status acp_precond_init(acp_ctx *ctx, unsigned long long seed);
+/* theta host, n_params floats (set resets the Adam state). */
+acp_status acp_precond_set(acp_ctx *ctx, const float *theta, int n_params);
+acp_status acp_precond_get(acp_ctx *ctx, float *theta, int n_params);
+/* Raw network output for the residual columns R (dev N_g x n) at shifts
+ * (host n): out dev, n x N_g FP32 (sample-major). */
+acp_status acp_precond_forward(acp_ctx *ctx, const double *shift, int n, const double *R,
+                               float *out);
+/* Proposed corrections D = Q (N(r) rms(r)) (dev N_g x n, FP64). */
+acp_status acp_precond_apply(acp_ctx *ctx, const double *shift, int n, const double *R,
+                             double *D);
+/* One Adam step (learning rate lr; 0 computes the loss and gradient only) on
+ * the batch of pairs (R(:, j), E(:, j)) at shifts (host n), E = x* - x_k the
+ * error of an iterate whose residual is R = A E (dev N_g x n each, n <= 1024),
+ * minimising the mean energy-norm error of the corrections d = Q N(r) rms(r):
+ *   (d - e)^T A (d - e) / e^T A e = (d^T A d - 2 d^T r + e^T r) / e^T r.
+ * loss host (the batch loss before the step) or NULL; grad host n_params or
+ * NULL receives the gradient. */
+acp_status acp_precond_train_step(acp_ctx *ctx, const double *shift, int n, const double *R,
+                                  const double *E, double lr, double *loss, float *grad);
 
 acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out);
 void acp_reset_stats(acp_ctx *ctx);

@@ -16,9 +16,14 @@ A convolution is a cross-correlation over the periodic grid:
 Parameter vector theta (also the weight format of the C ABI): for each layer in
 order, W as [cout][cin][taps] then b as [cout].
 
-Training (Adam on theta) minimises the mean over samples of
-    ||N_theta(r) - e / rms(r)||^2 / ||e / rms(r)||^2,   e = x* - x_k,
-the error of a Krylov iterate x_k for the residual r_k = b - A x_k.
+Training (Adam on theta) minimises the mean over samples of the error of the
+proposed correction in the energy norm of A (the norm CG minimises),
+    (d - e)^T A (d - e) / e^T A e,   e = x* - x_k,  d = Q (N_theta(r) rms(r)),
+for iterates x_k with residuals r_k = b - A x_k.  Since A e = r, it is written
+    (d^T A d - 2 d^T r + e^T r) / e^T r,
+which needs A only on d.  (The plain l2 error ||N_theta(r) - e/rms(r)||^2 /
+||e/rms(r)||^2 is kept as `loss`/`loss_grad`; corrections trained on it keep
+high-frequency errors that A amplifies, so they make poor preconditioners.)
 
 Every function is the definition written out: the convolution as a sum of
 rolled copies, the backward pass by the chain rule layer by layer.
@@ -159,6 +164,21 @@ def loss_grad(out, T):
     d = out - T
     den = np.sum(T * T, axis=(1, 2))
     return 2.0 * d / (den[:, None, None] * out.shape[0])
+
+
+def energy_loss(out, rms, R, E, phi, apply_a):
+    """Energy-norm loss of the corrections d = Q (out rms) for pairs (R, E)
+    (columns; A E = R), and its gradient w.r.t. out ([B, 1, N]).
+    apply_a applies A column by column."""
+    B = out.shape[0]
+    D = out[:, 0, :].T * rms[None, :]
+    D = D - phi @ (phi.T @ D)
+    AD = apply_a(D)
+    er = np.sum(E * R, axis=0)
+    per = (np.sum(D * AD, axis=0) - 2.0 * np.sum(D * R, axis=0) + er) / er
+    G = 2.0 * (AD - R) / (er[None, :] * B)          # dL/dD (A symmetric)
+    G = G - phi @ (phi.T @ G)                       # through Q
+    return float(np.mean(per)), (G * rms[None, :]).T[:, None, :]
 
 
 def targets(E, rms):

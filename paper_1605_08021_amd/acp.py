@@ -46,7 +46,7 @@ class AcpOpts(C.Structure):
                 ("isdf_tol", C.c_double), ("node_mode", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("solver", C.c_int), ("precision", C.c_int),
                 ("dyson_max_iter", C.c_int), ("dyson_tol", C.c_double),
-                ("inner_tol", C.c_double)]
+                ("inner_tol", C.c_double), ("use_learned_precond", C.c_int)]
 
 
 class AcpStats(C.Structure):
@@ -92,6 +92,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_apply_chi0": (I, [P, P, I, P]),
         "acp_dyson": (I, [P, P, I, P, P, P, P, P]),
         "acp_dynmat": (I, [P, P, P, I, P, P, P, P]),
+        "acp_residual": (I, [P, P, I, P, P, P]),
+        "acp_precond_n_params": (I, [I]),
+        "acp_precond_init": (I, [P, C.c_ulonglong]),
+        "acp_precond_set": (I, [P, P, I]),
+        "acp_precond_get": (I, [P, P, I]),
+        "acp_precond_forward": (I, [P, P, I, P, P]),
+        "acp_precond_apply": (I, [P, P, I, P, P]),
+        "acp_precond_train_step": (I, [P, P, I, P, P, C.c_double, P, P]),
         "acp_get_stats": (I, [P, C.POINTER(AcpStats)]),
         "acp_reset_stats": (None, [P]),
         "acp_last_error": (C.c_char_p, [P]),
@@ -296,6 +304,56 @@ class Context:
                                         None if m is None else _hptr(m), D.ctypes.data,
                                         _hptr(w2)))
         return D, w2
+
+    def residual(self, shifts, B, X):
+        B, X = colmajor(B), colmajor(X)
+        sh = _hostd(shifts)
+        R = self._empty(*B.shape)
+        self._check(self.lib.acp_residual(self._ctx, _hptr(sh), B.shape[1], _dptr(B), _dptr(X),
+                                          _dptr(R)))
+        return R
+
+    # -- learned preconditioner (marshalling only) ----------------------------
+    def precond_n_params(self) -> int:
+        return self.lib.acp_precond_n_params(self.grid.dim)
+
+    def precond_init(self, seed: int):
+        self._check(self.lib.acp_precond_init(self._ctx, C.c_ulonglong(seed)))
+
+    def precond_set(self, theta):
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        self._check(self.lib.acp_precond_set(self._ctx, t.ctypes.data, t.size))
+
+    def precond_get(self) -> np.ndarray:
+        t = np.zeros(self.precond_n_params(), dtype=np.float32)
+        self._check(self.lib.acp_precond_get(self._ctx, t.ctypes.data, t.size))
+        return t
+
+    def precond_forward(self, shifts, R):
+        import torch
+        R = colmajor(R)
+        sh = _hostd(shifts)
+        out = torch.empty((R.shape[1], R.shape[0]), dtype=torch.float32, device=R.device)
+        self._check(self.lib.acp_precond_forward(self._ctx, _hptr(sh), R.shape[1], _dptr(R),
+                                                 out.data_ptr()))
+        return out
+
+    def precond_apply(self, shifts, R):
+        R = colmajor(R)
+        sh = _hostd(shifts)
+        D = self._empty(*R.shape)
+        self._check(self.lib.acp_precond_apply(self._ctx, _hptr(sh), R.shape[1], _dptr(R), _dptr(D)))
+        return D
+
+    def precond_train_step(self, shifts, R, E, lr: float, want_grad: bool = False):
+        R, E = colmajor(R), colmajor(E)
+        sh = _hostd(shifts)
+        loss = C.c_double(0.0)
+        g = np.zeros(self.precond_n_params(), dtype=np.float32) if want_grad else None
+        self._check(self.lib.acp_precond_train_step(self._ctx, _hptr(sh), R.shape[1], _dptr(R),
+                                                    _dptr(E), float(lr), C.byref(loss),
+                                                    None if g is None else g.ctypes.data))
+        return (loss.value, g) if want_grad else loss.value
 
     def stats(self) -> dict:
         s = AcpStats()

@@ -64,6 +64,15 @@ struct acp_ctx {
     DevBuf kx, kr, kpa, kpb, kw1, kw2, krhs, kiters, kresid, kflags, ktile;
     DevBuf msp, msgbuf, mscnt, msabort, msprof;
     DevBuf phi_rm32, phi_cm32, krhs32, colmask;   // mixed-precision form
+    // learned preconditioner
+    bool nn_ready = false;
+    int nn_np = 0, nn_step = 0, nn_cap = 0;
+    int nn_off[4] = {0, 0, 0, 0};
+    DevBuf nn_theta, nn_m, nn_v, nn_grad, nn_part, nn_bpart, nn_out, nn_rms, nn_shat, nn_tgt, nn_loss;
+    DevBuf nn_d, nn_ad;
+    std::vector<double> nn_shat_host;   // source of an asynchronous upload: lives with the context
+    DevBuf nn_wf[4], nn_wb[4], nn_act[4], nn_g[4];
+    DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc;           // flexible CG
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     acp_stats stats{};
@@ -153,6 +162,8 @@ acp_status validate_opts(acp_ctx *ctx, const acp_opts *o) {
     if (o->node_mode != ACP_NODES_CHEBYSHEV && o->node_mode != ACP_NODES_OCCUPIED)
         return fail(ctx, ACP_EINVAL, "unknown node_mode");
     if (o->isdf_tol < 0.0) return fail(ctx, ACP_EINVAL, "isdf_tol must be >= 0");
+    if (o->use_learned_precond < 0 || o->use_learned_precond > 2)
+        return fail(ctx, ACP_EINVAL, "use_learned_precond must be 0, 1 or 2");
     return ACP_OK;
 }
 
@@ -550,6 +561,276 @@ acp_status refine_fp32(acp_ctx *ctx, int n, const double *shifts_dev, const doub
     return ACP_OK;
 }
 
+// ------------------------------------------------------------ learned preconditioner
+
+int nn_param_count(int dim) {
+    const int T = nn_taps(dim);
+    int n = 0;
+    for (int l = 0; l < 4; ++l) n += kNnChannels[l + 1] * kNnChannels[l] * T + kNnChannels[l + 1];
+    return n;
+}
+
+// Parameter storage, Adam state and BF16 weight copies (once per context).
+acp_status nn_prepare(acp_ctx *ctx) {
+    const int dim = ctx->gd.dim, T = nn_taps(dim);
+    ctx->nn_np = nn_param_count(dim);
+    int off = 0;
+    for (int l = 0; l < 4; ++l) {
+        ctx->nn_off[l] = off;
+        off += kNnChannels[l + 1] * kNnChannels[l] * T + kNnChannels[l + 1];
+    }
+    const size_t np = ctx->nn_np;
+    ENSURE(ctx->nn_theta, np * 4);
+    ENSURE(ctx->nn_m, np * 4);
+    ENSURE(ctx->nn_v, np * 4);
+    ENSURE(ctx->nn_grad, np * 4);
+    for (int l = 0; l < 4; ++l) {
+        const int ci = kNnChannels[l], co = kNnChannels[l + 1];
+        ENSURE(ctx->nn_wf[l], (size_t)co * ((ci * T + 15) / 16 * 16) * 2);
+        ENSURE(ctx->nn_wb[l], (size_t)ci * ((co * T + 15) / 16 * 16) * 2);
+    }
+    return ACP_OK;
+}
+
+// Activation buffers for batches of up to B samples.
+constexpr int kNnGroups = 512;
+acp_status nn_batch(acp_ctx *ctx, int B) {
+    if (B <= ctx->nn_cap) return ACP_OK;
+    const size_t n = ctx->ng;
+    for (int l = 0; l < 4; ++l) {
+        ENSURE(ctx->nn_act[l], (size_t)B * kNnChannels[l] * n * 2);
+        ENSURE(ctx->nn_g[l], (size_t)B * kNnChannels[l + 1] * n * 2);
+    }
+    ENSURE(ctx->nn_out, (size_t)B * n * 4);
+    ENSURE(ctx->nn_tgt, (size_t)B * n * 4);
+    ENSURE(ctx->nn_rms, (size_t)B * 8);
+    ENSURE(ctx->nn_shat, (size_t)B * 8);
+    ENSURE(ctx->nn_loss, (size_t)B * 8);
+    const int T = nn_taps(ctx->gd.dim);
+    ENSURE(ctx->nn_part, (size_t)kNnGroups * 32 * 32 * T * 4);
+    ENSURE(ctx->nn_bpart, (size_t)kNnGroups * 32 * 4);
+    ctx->nn_cap = B;
+    return ACP_OK;
+}
+
+NnBuffers nn_buffers(acp_ctx *ctx) {
+    NnBuffers b{};
+    const int T = nn_taps(ctx->gd.dim);
+    float *theta = dp<float>(ctx->nn_theta);
+    for (int l = 0; l < 4; ++l) {
+        b.act[l] = dp<unsigned short>(ctx->nn_act[l]);
+        b.g[l] = dp<unsigned short>(ctx->nn_g[l]);
+        b.wf[l] = dp<unsigned short>(ctx->nn_wf[l]);
+        b.wb[l] = dp<unsigned short>(ctx->nn_wb[l]);
+        b.off[l] = ctx->nn_off[l];
+        b.bias[l] = theta + ctx->nn_off[l] + kNnChannels[l + 1] * kNnChannels[l] * T;
+    }
+    b.out = dp<float>(ctx->nn_out);
+    b.grad = dp<float>(ctx->nn_grad);
+    b.part = dp<float>(ctx->nn_part);
+    b.bpart = dp<float>(ctx->nn_bpart);
+    b.groups_max = kNnGroups;
+    return b;
+}
+
+NnShape nn_shape(acp_ctx *ctx) { return NnShape{ctx->gd.nx, ctx->gd.dim == 1 ? 1 : ctx->gd.ny}; }
+
+// Upload theta (host, FP32), reset Adam, refresh the BF16 copies.
+acp_status nn_upload(acp_ctx *ctx, const float *theta) {
+    CHECK(nn_prepare(ctx));
+    const size_t np = ctx->nn_np;
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipMemcpyAsync(ctx->nn_theta.p, theta, np * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(ctx->nn_m.p, 0, np * 4, s));
+    HIPCHK(hipMemsetAsync(ctx->nn_v.p, 0, np * 4, s));
+    HIPCHK(nn_pack_weights(ctx->gd.dim, dp<float>(ctx->nn_theta), nn_buffers(ctx), s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->nn_step = 0;
+    ctx->nn_ready = true;
+    return ACP_OK;
+}
+
+// Normalised shifts of the network input.
+std::vector<double> nn_shift_hat(const acp_ctx *ctx, const double *shift, int n) {
+    const double lo = ctx->eps.front(), hi = ctx->eps.back();
+    std::vector<double> h(n);
+    for (int j = 0; j < n; ++j) h[j] = (shift[j] - 0.5 * (lo + hi)) / (0.5 * (hi - lo) + 1e-12);
+    return h;
+}
+
+// Features and forward pass of n <= nn_cap columns of R (leading dimension ldr).
+acp_status nn_run_forward(acp_ctx *ctx, const double *shift, int n, const double *R, int ldr) {
+    if (!ctx->nn_ready) return fail(ctx, ACP_ESTATE, "no preconditioner weights (init or set first)");
+    CHECK(nn_batch(ctx, n));
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipStreamSynchronize(s));   // the previous upload from nn_shat_host has completed
+    ctx->nn_shat_host = nn_shift_hat(ctx, shift, n);
+    HIPCHK(hipMemcpyAsync(ctx->nn_shat.p, ctx->nn_shat_host.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    NnBuffers b = nn_buffers(ctx);
+    HIPCHK(nn_features(ctx->ng, n, R, ldr, dp<double>(ctx->nn_shat), b.act[0], dp<double>(ctx->nn_rms), s));
+    HIPCHK(nn_forward(ctx->gd.dim, nn_shape(ctx), n, b, s));
+    return ACP_OK;
+}
+
+// D = Q (N(R) rms(R)) for n columns, in chunks of the activation capacity.
+constexpr int kNnChunk = 1024;
+acp_status nn_apply(acp_ctx *ctx, const double *shift, int n, const double *R, int ldr, double *D,
+                    int ldd) {
+    const int ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    for (int j0 = 0; j0 < n; j0 += kNnChunk) {
+        const int m = std::min(kNnChunk, n - j0);
+        CHECK(nn_run_forward(ctx, shift + j0, m, R + (size_t)j0 * ldr, ldr));
+        HIPCHK(nn_scale_out(ng, m, dp<float>(ctx->nn_out), dp<double>(ctx->nn_rms), D + (size_t)j0 * ldd,
+                            ldd, s));
+    }
+    ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+    const double *phi = dp<double>(ctx->phi_cm);
+    double *C = dp<double>(ctx->c1);
+    HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, D, ldd, 0, 0.0, C, ctx->ne, 0, 1, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, D, ldd, 0, 1, s));
+    return ACP_OK;
+}
+
+// splitmix64 (Steele, Lea and Flood 2014) -> uniform in [0, 1).
+double splitmix_uniform(unsigned long long &state) {
+    unsigned long long z = (state += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Flexible CG (the preconditioner varies: Notay 2000) for n columns:
+//   z = M(r), p = z;  alpha = r.z / p.Ap;  x += alpha p;  r -= alpha Ap;
+//   z' = M(r);  beta = -alpha z'.Ap / r.z;  p = z' + beta p.
+// M is the network (mode 1) or the identity (mode 2, plain CG in the same form).
+// Columns that reach tol stop; the rest are finished by FP64 MINRES (mode 1).
+acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *shifts_dev,
+                     const double *B, double *X, int *iters, int *flags_or) {
+    const int ng = ctx->ng, mode = ctx->opts.use_learned_precond;
+    hipStream_t s = ctx->stream;
+    const size_t bytes = (size_t)ng * n * 8;
+    ENSURE(ctx->fc_r, bytes);
+    ENSURE(ctx->fc_z, bytes);
+    ENSURE(ctx->fc_p, bytes);
+    ENSURE(ctx->fc_q, bytes);
+    ENSURE(ctx->fc_sc, (size_t)3 * n * 8);
+    double *R = dp<double>(ctx->fc_r), *Z = dp<double>(ctx->fc_z), *P = dp<double>(ctx->fc_p),
+           *Q = dp<double>(ctx->fc_q);
+    double *d_a = dp<double>(ctx->fc_sc), *d_b = d_a + n, *d_t = d_b + n;
+    auto precond = [&](const double *Rin, double *Zout) -> acp_status {
+        if (mode == 1) return nn_apply(ctx, shift_h, n, Rin, ng, Zout, ng);
+        HIPCHK(hipMemcpyAsync(Zout, Rin, bytes, hipMemcpyDeviceToDevice, s));
+        return ACP_OK;
+    };
+    auto col = [&](hipError_t (*fn)(int, int, const double *, int, const double *, int, double *, hipStream_t),
+                   const double *A1, const double *A2, std::vector<double> &h) -> acp_status {
+        HIPCHK(fn(ng, n, A1, ng, A2, ng, d_t, s));
+        HIPCHK(hipMemcpyAsync(h.data(), d_t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return ACP_OK;
+    };
+    // host vectors handed to asynchronous copies are never modified before the
+    // next stream synchronisation
+    std::vector<double> bn(n), rz(n), pq(n), rr(n), zq(n), rzn(n), al(n), nal(n), be(n);
+    HIPCHK(hipMemsetAsync(X, 0, bytes, s));
+    HIPCHK(hipMemcpyAsync(R, B, bytes, hipMemcpyDeviceToDevice, s));
+    CHECK(col(launch_col_dot, B, B, bn));
+    std::vector<int> act(n);
+    for (int j = 0; j < n; ++j) {
+        bn[j] = std::sqrt(bn[j]);
+        act[j] = bn[j] > 0.0;
+        iters[j] = 0;
+    }
+    CHECK(precond(R, Z));
+    HIPCHK(hipMemcpyAsync(P, Z, bytes, hipMemcpyDeviceToDevice, s));
+    CHECK(col(launch_col_dot, R, Z, rz));
+    for (int k = 0; k < ctx->opts.max_iter; ++k) {
+        int open = 0;
+        for (int j = 0; j < n; ++j) open += act[j];
+        if (!open) break;
+        CHECK(apply_operator(ctx, n, shifts_dev, P, Q));
+        CHECK(col(launch_col_dot, P, Q, pq));
+        for (int j = 0; j < n; ++j) {
+            al[j] = 0.0;
+            if (!act[j]) continue;
+            if (!(pq[j] > 0.0)) {
+                *flags_or |= 2;
+                act[j] = 0;
+                continue;
+            }
+            al[j] = rz[j] / pq[j];
+        }
+        for (int j = 0; j < n; ++j) nal[j] = -al[j];
+        HIPCHK(hipMemcpyAsync(d_a, al.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_b, nal.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_col_axpby(ng, n, d_a, P, ng, nullptr, X, ng, s));   // x += alpha p
+        HIPCHK(launch_col_axpby(ng, n, d_b, Q, ng, nullptr, R, ng, s));   // r -= alpha Ap
+        CHECK(col(launch_col_dot, R, R, rr));
+        for (int j = 0; j < n; ++j)
+            if (act[j]) {
+                iters[j] += 1;
+                if (std::sqrt(rr[j]) <= ctx->opts.tol * bn[j]) act[j] = 0;
+            }
+        open = 0;
+        for (int j = 0; j < n; ++j) open += act[j];
+        if (!open) break;
+        CHECK(precond(R, Z));
+        CHECK(col(launch_col_dot, Z, Q, zq));
+        CHECK(col(launch_col_dot, R, Z, rzn));
+        for (int j = 0; j < n; ++j) {
+            // beta = -alpha z'.Ap / r.z  (= -z'.Ap / p.Ap)
+            be[j] = (act[j] && rz[j] != 0.0) ? -al[j] * zq[j] / rz[j] : 0.0;
+            rz[j] = rzn[j];
+        }
+        HIPCHK(hipMemcpyAsync(d_t, be.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_col_axpby(ng, n, nullptr, Z, ng, d_t, P, ng, s));   // p = z + beta p
+    }
+    int open = 0;
+    for (int j = 0; j < n; ++j) open += act[j];
+    if (open && mode == 1) {
+        // fallback: FP64 MINRES solves A d = r for the columns still open (the
+        // others get a zero right-hand side and stop at once); x += d
+        std::vector<double> mask(n);
+        for (int j = 0; j < n; ++j) mask[j] = act[j] ? 1.0 : 0.0;
+        HIPCHK(hipMemcpyAsync(d_a, mask.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(Z, 0, bytes, s));
+        HIPCHK(launch_col_axpby(ng, n, d_a, R, ng, nullptr, Z, ng, s));   // Z = mask r
+        const int ntiles = (n + kTile - 1) / kTile, npad = ntiles * kTile;
+        ENSURE(ctx->krhs, (size_t)npad * ng * 8);
+        HIPCHK(launch_to_tiled(ng, n, npad, Z, ng, dp<double>(ctx->krhs), s));
+        const int saved = ctx->opts.solver;
+        ctx->opts.solver = ACP_SOLVER_MINRES;
+        KrylovInputs<double> in{dp<double>(ctx->phi_rm), dp<double>(ctx->phi_cm), dp<double>(ctx->krhs)};
+        int f = 0;
+        acp_status st = solve_tiled<double>(ctx, ntiles, ntiles, shifts_dev, in, ctx->opts.tol, &f);
+        ctx->opts.solver = saved;
+        CHECK(st);
+        *flags_or |= f;
+        HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), Z, ng, s));
+        HIPCHK(launch_col_axpby(ng, n, nullptr, Z, ng, nullptr, X, ng, s));   // x += d
+        std::vector<int> it2(n);
+        HIPCHK(hipMemcpyAsync(it2.data(), ctx->kiters.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int j = 0; j < n; ++j) iters[j] += it2[j];
+        ctx->stats.refinements += 1;
+    } else if (open) {
+        *flags_or |= 1;
+    }
+    long long sum = 0;
+    int imin = 1 << 30, imax = 0;
+    for (int j = 0; j < n; ++j) {
+        sum += iters[j];
+        imin = std::min(imin, iters[j]);
+        imax = std::max(imax, iters[j]);
+    }
+    ctx->stats.system_iterations += sum;
+    ctx->stats.iters_min = imin;
+    ctx->stats.iters_max = imax;
+    return ACP_OK;
+}
+
 acp_status flags_status(acp_ctx *ctx, int f) {
     if (f & 2) return fail(ctx, ACP_ENOTSPD, "non-positive curvature in a shifted solve");
     if (f & 1) return fail(ctx, ACP_ENOCONV, "a shifted solve reached max_iter");
@@ -695,7 +976,27 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     int flags = 0;
     bool ms_used = false;
     const bool mixed = ctx->opts.precision == ACP_PREC_FP32_REFINE;
-    if (!mixed) {
+    const bool learned = ctx->opts.use_learned_precond != 0;
+    if (learned) {
+        // per-system flexible CG (the network, or none in mode 2) on every
+        // system, column-major like Z
+        const int ncols = nc * nmu;
+        const int ncols_pad = (ncols + kTile - 1) / kTile * kTile;
+        ENSURE(ctx->tmp3, (size_t)ng * ncols * 8);
+        ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
+        double *Bfull = dp<double>(ctx->tmp3);
+        std::vector<double> shc((size_t)ncols_pad, ctx->nodes[nc - 1]);
+        for (int c = 0; c < nc; ++c) {
+            HIPCHK(hipMemcpyAsync(Bfull + (size_t)c * nmu * ng, R, (size_t)ng * nmu * 8,
+                                  hipMemcpyDeviceToDevice, s));
+            for (int j = 0; j < nmu; ++j) shc[(size_t)c * nmu + j] = ctx->nodes[c];
+        }
+        ENSURE(ctx->shifts_dev, shc.size() * 8);
+        HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, shc.data(), shc.size() * 8, hipMemcpyHostToDevice, s));
+        std::vector<int> it(ncols);
+        CHECK(fcg_solve(ctx, ncols, shc.data(), dp<double>(ctx->shifts_dev), Bfull, dp<double>(ctx->z),
+                        it.data(), &flags));
+    } else if (!mixed) {
         KrylovInputs<double> in{dp<double>(ctx->phi_rm), phi, dp<double>(ctx->krhs)};
         if (ctx->opts.solver == ACP_SOLVER_CG)
             CHECK(solve_multishift<double>(ctx, rhs_tiles, in, ctx->opts.tol, &flags, &ms_used));
@@ -721,9 +1022,10 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     // Z (column-major, block c = shift c)
     ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
     double *Z = dp<double>(ctx->z);
-    for (int c = 0; c < nc; ++c)
-        HIPCHK(launch_from_tiled(ng, nmu, dp<double>(ctx->kx) + (size_t)c * rhs_tiles * ng * kTile,
-                                 Z + (size_t)c * nmu * ng, ng, s));
+    if (!learned)
+        for (int c = 0; c < nc; ++c)
+            HIPCHK(launch_from_tiled(ng, nmu, dp<double>(ctx->kx) + (size_t)c * rhs_tiles * ng * kTile,
+                                     Z + (size_t)c * nmu * ng, ng, s));
     // every system's right-hand side and shift, column-major like Z
     const int ncols = nc * nmu;
     const int ncols_pad = (ncols + kTile - 1) / kTile * kTile;
@@ -875,6 +1177,19 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
     HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, sh.data(), (size_t)npad * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(ctx->ev[2], s));
     int flags = 0;
+    if (ctx->opts.use_learned_precond) {
+        std::vector<int> it(n);
+        CHECK(fcg_solve(ctx, n, sh.data(), dp<double>(ctx->shifts_dev), B, X, it.data(), &flags));
+        HIPCHK(hipEventRecord(ctx->ev[3], s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (iters) std::memcpy(iters, it.data(), (size_t)n * 4);
+        ctx->stats.ms_solve += event_ms(ctx->ev[2], ctx->ev[3]);
+        ctx->stats.systems_solved += n;
+        double mr = 0.0;
+        CHECK(true_residual(ctx, n, dp<double>(ctx->shifts_dev), B, X, &mr));
+        ctx->stats.max_rel_residual = mr;
+        return flags_status(ctx, flags);
+    }
     if (ctx->opts.precision == ACP_PREC_FP32_REFINE) {
         CHECK(ensure_phi32(ctx));
         ENSURE(ctx->krhs32, (size_t)npad * ng * 4);
@@ -903,6 +1218,131 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
     CHECK(true_residual(ctx, n, dp<double>(ctx->shifts_dev), B, X, &mr));
     ctx->stats.max_rel_residual = mr;
     return flags_status(ctx, flags);
+}
+
+acp_status acp_residual(acp_ctx *ctx, const double *shift, int n, const double *B, const double *X,
+                        double *R) {
+    if (!ctx || !shift || !B || !X || !R || n < 0) return ACP_EINVAL;
+    if (n == 0) return ACP_OK;
+    ENSURE(ctx->dy_s, (size_t)n * 8);
+    HIPCHK(hipMemcpyAsync(ctx->dy_s.p, shift, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+    CHECK(apply_operator(ctx, n, dp<double>(ctx->dy_s), X, R));
+    HIPCHK(launch_axpby(ctx->ng, n, 1.0, B, ctx->ng, -1.0, R, ctx->ng, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+int acp_precond_n_params(int dim) { return (dim == 1 || dim == 2) ? nn_param_count(dim) : 0; }
+
+acp_status acp_precond_init(acp_ctx *ctx, unsigned long long seed) {
+    if (!ctx) return ACP_EINVAL;
+    const int dim = ctx->gd.dim, T = nn_taps(dim);
+    std::vector<float> th(nn_param_count(dim));
+    unsigned long long st = seed;
+    size_t k = 0;
+    for (int l = 0; l < 4; ++l) {
+        const int ci = kNnChannels[l], co = kNnChannels[l + 1];
+        const double lim = std::sqrt(6.0 / (ci * T));
+        for (int i = 0; i < co * ci * T; ++i) th[k++] = (float)((2.0 * splitmix_uniform(st) - 1.0) * lim);
+        for (int i = 0; i < co; ++i) th[k++] = 0.f;
+    }
+    return nn_upload(ctx, th.data());
+}
+
+acp_status acp_precond_set(acp_ctx *ctx, const float *theta, int n_params) {
+    if (!ctx || !theta) return ACP_EINVAL;
+    if (n_params != nn_param_count(ctx->gd.dim)) return fail(ctx, ACP_EINVAL, "wrong parameter count");
+    return nn_upload(ctx, theta);
+}
+
+acp_status acp_precond_get(acp_ctx *ctx, float *theta, int n_params) {
+    if (!ctx || !theta) return ACP_EINVAL;
+    if (!ctx->nn_ready) return fail(ctx, ACP_ESTATE, "no preconditioner weights");
+    if (n_params != ctx->nn_np) return fail(ctx, ACP_EINVAL, "wrong parameter count");
+    HIPCHK(hipMemcpyAsync(theta, ctx->nn_theta.p, (size_t)n_params * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_precond_forward(acp_ctx *ctx, const double *shift, int n, const double *R, float *out) {
+    if (!ctx || !shift || !R || !out || n < 1) return ACP_EINVAL;
+    for (int j0 = 0; j0 < n; j0 += kNnChunk) {
+        const int m = std::min(kNnChunk, n - j0);
+        CHECK(nn_run_forward(ctx, shift + j0, m, R + (size_t)j0 * ctx->ng, ctx->ng));
+        HIPCHK(hipMemcpyAsync(out + (size_t)j0 * ctx->ng, ctx->nn_out.p, (size_t)m * ctx->ng * 4,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_precond_apply(acp_ctx *ctx, const double *shift, int n, const double *R, double *D) {
+    if (!ctx || !shift || !R || !D || n < 1) return ACP_EINVAL;
+    CHECK(nn_apply(ctx, shift, n, R, ctx->ng, D, ctx->ng));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_precond_train_step(acp_ctx *ctx, const double *shift, int n, const double *R,
+                                  const double *E, double lr, double *loss, float *grad) {
+    if (!ctx || !shift || !R || !E || n < 1 || !(lr >= 0.0)) return ACP_EINVAL;
+    if (n > kNnChunk) return fail(ctx, ACP_EINVAL, "training batch larger than 1024");
+    const int ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    CHECK(nn_run_forward(ctx, shift, n, R, ng));
+    NnBuffers b = nn_buffers(ctx);
+    // corrections D = Q (out rms) and A D (FP64)
+    ENSURE(ctx->nn_d, (size_t)ng * n * 8);
+    ENSURE(ctx->nn_ad, (size_t)ng * n * 8);
+    ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+    ENSURE(ctx->dy_s, (size_t)n * 8);
+    ENSURE(ctx->dy_norm, (size_t)2 * n * 8);
+    double *D = dp<double>(ctx->nn_d), *AD = dp<double>(ctx->nn_ad), *C = dp<double>(ctx->c1);
+    const double *phi = dp<double>(ctx->phi_cm);
+    auto project = [&](double *X) -> acp_status {
+        HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, X, ng, 0, 0.0, C, ctx->ne, 0, 1, s));
+        HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, X, ng, 0, 1, s));
+        return ACP_OK;
+    };
+    HIPCHK(nn_scale_out(ng, n, b.out, dp<double>(ctx->nn_rms), D, ng, s));
+    CHECK(project(D));
+    HIPCHK(hipMemcpyAsync(ctx->dy_s.p, shift, (size_t)n * 8, hipMemcpyHostToDevice, s));
+    CHECK(apply_operator(ctx, n, dp<double>(ctx->dy_s), D, AD));
+    // energy-norm loss (d^T A d - 2 d^T r + e^T r) / e^T r  (A e = r)
+    double *t = dp<double>(ctx->dy_norm);
+    std::vector<double> dad(n), dr(n), er(n), rms(n);
+    HIPCHK(launch_col_dot(ng, n, D, ng, AD, ng, t, s));
+    HIPCHK(hipMemcpyAsync(dad.data(), t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(launch_col_dot(ng, n, D, ng, R, ng, t, s));
+    HIPCHK(hipMemcpyAsync(dr.data(), t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(launch_col_dot(ng, n, E, ng, R, ng, t, s));
+    HIPCHK(hipMemcpyAsync(er.data(), t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rms.data(), ctx->nn_rms.p, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double lsum = 0.0;
+    std::vector<double> scale(n);
+    for (int j = 0; j < n; ++j) {
+        const double den = er[j] > 0.0 ? er[j] : 1.0;
+        lsum += (dad[j] - 2.0 * dr[j] + er[j]) / den;
+        scale[j] = 2.0 * rms[j] / (den * n);
+    }
+    // dL/d(out) = rms Q (A D - R) 2 / (e^T r B), as BF16 samples
+    HIPCHK(launch_axpby(ng, n, -1.0, R, ng, 1.0, AD, ng, s));
+    CHECK(project(AD));
+    HIPCHK(hipMemcpyAsync(t, scale.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(nn_grad_out(ng, n, AD, ng, t, b.g[3], s));
+    HIPCHK(nn_backward(ctx->gd.dim, nn_shape(ctx), n, b, s));
+    if (grad)
+        HIPCHK(hipMemcpyAsync(grad, ctx->nn_grad.p, (size_t)ctx->nn_np * 4, hipMemcpyDeviceToHost, s));
+    if (lr > 0.0) {
+        ctx->nn_step += 1;
+        HIPCHK(nn_adam(ctx->nn_np, dp<float>(ctx->nn_theta), dp<float>(ctx->nn_m), dp<float>(ctx->nn_v),
+                       dp<float>(ctx->nn_grad), (float)lr, ctx->nn_step, s));
+        HIPCHK(nn_pack_weights(ctx->gd.dim, dp<float>(ctx->nn_theta), b, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (loss) *loss = lsum / n;
+    return ACP_OK;
 }
 
 acp_status acp_compress(acp_ctx *ctx, const double *G, int n_p, const double *omega,
@@ -1089,7 +1529,14 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->dy_gk, &ctx->dy_norm, &ctx->dm_phi, &ctx->dm_k, &ctx->dm_mass,
                       &ctx->dm_d, &ctx->dm_eig, &ctx->dm_work, &ctx->dm_asym, &ctx->splitk,
                       &ctx->msp, &ctx->msgbuf, &ctx->mscnt, &ctx->msabort, &ctx->msprof,
-                      &ctx->phi_rm32, &ctx->phi_cm32, &ctx->krhs32, &ctx->colmask};
+                      &ctx->phi_rm32, &ctx->phi_cm32, &ctx->krhs32, &ctx->colmask,
+                      &ctx->nn_theta, &ctx->nn_m, &ctx->nn_v, &ctx->nn_grad, &ctx->nn_part,
+                      &ctx->nn_bpart, &ctx->nn_out, &ctx->nn_rms, &ctx->nn_shat, &ctx->nn_tgt,
+                      &ctx->nn_loss, &ctx->nn_d, &ctx->nn_ad, &ctx->nn_wf[0], &ctx->nn_wf[1], &ctx->nn_wf[2], &ctx->nn_wf[3],
+                      &ctx->nn_wb[0], &ctx->nn_wb[1], &ctx->nn_wb[2], &ctx->nn_wb[3],
+                      &ctx->nn_act[0], &ctx->nn_act[1], &ctx->nn_act[2], &ctx->nn_act[3],
+                      &ctx->nn_g[0], &ctx->nn_g[1], &ctx->nn_g[2], &ctx->nn_g[3],
+                      &ctx->fc_r, &ctx->fc_z, &ctx->fc_p, &ctx->fc_q, &ctx->fc_sc};
     for (DevBuf *b : bufs) release(*b);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);

@@ -170,6 +170,42 @@ hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);
 hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s);
 
+// ---------------------------------------------------------------- learned preconditioner
+// Network of four periodic convolutions (channels kNnChannels), BF16 operands on
+// the matrix cores, FP32 accumulation (k_nn.hip).
+extern const int kNnChannels[5];
+int nn_taps(int dim);
+struct NnShape {
+    int nx, ny;                 // grid (ny = 1 in 1D)
+};
+struct NnBuffers {
+    unsigned short *act[4];     // act[0] = features [B][2][N]; act[1..3] = hidden [B][32][N]
+    float *out;                 // network output [B][N]
+    unsigned short *g[4];       // g[l] = dL/d(output of layer l) (g[3]: [B][1][N], others [B][32][N])
+    unsigned short *wf[4];      // forward weights [cout][KP]
+    unsigned short *wb[4];      // data-gradient weights [cin][KPb] (layers 1..3)
+    const float *bias[4];       // into theta
+    float *grad;                // [n_params], theta layout
+    int off[4];                 // offset of layer l in theta
+    float *part, *bpart;        // weight-gradient partials
+    int groups_max;
+};
+hipError_t nn_features(int n, int B, const double *R, int ldr, const double *shat, unsigned short *X,
+                       double *rms, hipStream_t s);
+hipError_t nn_scale_out(int n, int B, const float *out, const double *rms, double *D, int ldd,
+                        hipStream_t s);
+hipError_t nn_grad_out(int n, int B, const double *G, int ldg, const double *scale, unsigned short *g,
+                       hipStream_t s);
+hipError_t nn_pack_weights(int dim, const float *theta, const NnBuffers &nb, hipStream_t s);
+hipError_t nn_forward(int dim, const NnShape &sh, int B, const NnBuffers &nb, hipStream_t s);
+hipError_t nn_backward(int dim, const NnShape &sh, int B, const NnBuffers &nb, hipStream_t s);
+hipError_t nn_adam(int np, float *theta, float *m, float *v, const float *g, float lr, int step,
+                   hipStream_t s);
+hipError_t launch_col_dot(int m, int n, const double *X, int ldx, const double *Y, int ldy,
+                          double *out, hipStream_t s);                     // out[j] = X(:,j).Y(:,j)
+hipError_t launch_col_axpby(int m, int n, const double *a, const double *X, int ldx, const double *b,
+                            double *Y, int ldy, hipStream_t s);  // Y(:,j) = a[j] X(:,j) + b[j] Y(:,j)
+
 // ---------------------------------------------------------------- ISDF (K4)
 // Greedy pivoted Cholesky of the implicit Hadamard Gram matrix (row-major
 // inputs phi_rm N_g x nep, gt_rm N_g x r; factor L row-major N_g x ldl);

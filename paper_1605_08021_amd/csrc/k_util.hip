@@ -103,6 +103,33 @@ __global__ void col_sqnorm_kernel(int m, const double *X, int ldx, double *out) 
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// One block per column: out[j] = X(:,j) . Y(:,j) (deterministic).
+__global__ void col_dot_kernel(int m, const double *X, int ldx, const double *Y, int ldy, double *out) {
+    __shared__ double red[256];
+    const double *x = X + (long long)blockIdx.x * ldx;
+    const double *y = Y + (long long)blockIdx.x * ldy;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) s += x[i] * y[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// Y(:,j) = a[j] X(:,j) + b[j] Y(:,j); a null means 1, b null means 1.
+__global__ void col_axpby_kernel(int m, int n, const double *__restrict__ a, const double *X, int ldx,
+                                 const double *__restrict__ b, double *Y, int ldy) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)m * n) return;
+    const int j = (int)(i / m), r = (int)(i % m);
+    const double av = a ? a[j] : 1.0, bv = b ? b[j] : 1.0;
+    double *y = Y + (long long)j * ldy + r;
+    *y = av * X[(long long)j * ldx + r] + bv * *y;
+}
+
 // One block per column: out[j] = ||X(:,j) - Y(:,j)||^2 (deterministic).
 __global__ void col_diff_sqnorm_kernel(int m, const double *X, int ldx, const double *Y, int ldy,
                                        double *out) {
@@ -388,6 +415,21 @@ hipError_t launch_add_identity_neg(int n, double *T, int ld, hipStream_t s) {
 hipError_t launch_col_sqnorm(int m, int n, const double *X, int ldx, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(col_sqnorm_kernel, dim3(n), dim3(256), 0, s, m, X, ldx, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_dot(int m, int n, const double *X, int ldx, const double *Y, int ldy,
+                          double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_dot_kernel, dim3(n), dim3(256), 0, s, m, X, ldx, Y, ldy, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_axpby(int m, int n, const double *a, const double *X, int ldx, const double *b,
+                            double *Y, int ldy, hipStream_t s) {
+    const long long tot = (long long)m * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_axpby_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, a, X, ldx, b, Y, ldy);
     return hipGetLastError();
 }
 

@@ -121,3 +121,36 @@ def test_features_and_projected_apply():
 def test_parameter_count():
     assert P.n_params(1) == (2 * 32 * 5 + 32) + 2 * (32 * 32 * 5 + 32) + (32 * 5 + 1)
     assert P.n_params(2) == (2 * 32 * 25 + 32) + 2 * (32 * 32 * 25 + 32) + (32 * 25 + 1)
+
+
+def test_energy_loss_definition_and_gradient():
+    """With A E = R the loss equals the energy-norm error ratio written out
+    directly; its gradient w.r.t. the network output matches finite differences."""
+    rng = np.random.default_rng(9)
+    n, B = 15, 3
+    phi, _ = np.linalg.qr(rng.standard_normal((n, 2)))
+    Q = np.eye(n) - phi @ phi.T
+    M = rng.standard_normal((n, n))
+    A = Q @ (M @ M.T + n * np.eye(n)) @ Q          # SPD on range(Q)
+    E = Q @ rng.standard_normal((n, B))
+    R = A @ E
+    out = rng.standard_normal((B, 1, n))
+    rms = np.array([0.5, 2.0, 1.3])
+    L, g = P.energy_loss(out, rms, R, E, phi, lambda X: A @ X)
+    D = Q @ (out[:, 0, :].T * rms)
+    direct = np.mean([(D[:, b] - E[:, b]) @ A @ (D[:, b] - E[:, b]) / (E[:, b] @ A @ E[:, b])
+                      for b in range(B)])
+    assert abs(L - direct) < 1e-12 * max(1.0, direct)
+    h = 1e-6
+    for k in range(6):
+        i = np.unravel_index(rng.integers(out.size), out.shape)
+        op, om = out.copy(), out.copy()
+        op[i] += h
+        om[i] -= h
+        fd = (P.energy_loss(op, rms, R, E, phi, lambda X: A @ X)[0]
+              - P.energy_loss(om, rms, R, E, phi, lambda X: A @ X)[0]) / (2 * h)
+        assert abs(fd - g[i]) < 1e-7 * max(1.0, abs(fd))
+    # the exact correction d = e has zero loss
+    Lz, _ = P.energy_loss((np.linalg.pinv(np.diag(rms)) @ E.T)[:, None, :], rms, R, E, phi,
+                          lambda X: A @ X)
+    assert abs(Lz) < 1e-12
