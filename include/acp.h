@@ -247,6 +247,36 @@ acp_status acp_precond_apply(acp_ctx *ctx, const double *shift, int n, const dou
 acp_status acp_precond_train_step(acp_ctx *ctx, const double *shift, int n, const double *R,
                                   const double *E, double lr, double *loss, float *grad);
 
+/* ---- Ragged batch: many systems' shifted solves in one persistent launch ----
+ * A batch groups contexts of the same dimension (each set up for its own
+ * system: grid, orbitals, V_eff, options with the FP64 multi-shift CG).
+ * acp_batch_compress runs Alg. 3 for every system: point selection and
+ * right-hand sides per system, then ONE persistent launch in which workgroups
+ * take the right-hand-side tiles of all systems (every shift of a tile at
+ * once) from a work counter, then W per system; afterwards each context holds
+ * its chi0~ exactly as after acp_compress (apply_chi0, compress_get, stats).
+ * The first call autotunes the launch (grid of 64/128/256 workgroups, tiles in
+ * the given order or largest systems first, timed on the batch itself); with
+ * use_graph the launch sequence is captured once in a hipGraph and replayed
+ * (re-captured when buffers move).  The contexts must outlive the batch and
+ * must not be used concurrently with it. */
+typedef struct acp_batch acp_batch;
+typedef struct {
+    int n_systems, n_tiles;
+    int grid, order;          /* chosen launch: workgroups, 0 given order / 1 largest first */
+    int tuned;
+    long long graph_replays;
+    double ms_last;           /* the last batched solve (ms, HIP events) */
+    double tune_ms[6];        /* autotuning times: order 0 then 1, grids 64, 128, 256 */
+} acp_batch_info_t;
+acp_status acp_batch_create(acp_batch **batch, acp_ctx *const *systems, int n, int use_graph);
+/* G[i] dev N_g,i x n_p[i]; omega[i] dev n_p[i] x r_i; sel_in NULL or per system NULL/forced points. */
+acp_status acp_batch_compress(acp_batch *batch, const double *const *G, const int *n_p,
+                              const double *const *omega, const int *const *sel_in);
+acp_status acp_batch_info(const acp_batch *batch, acp_batch_info_t *out);
+const char *acp_batch_last_error(const acp_batch *batch);
+void acp_batch_destroy(acp_batch *batch);
+
 acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out);
 void acp_reset_stats(acp_ctx *ctx);
 const char *acp_last_error(const acp_ctx *ctx);

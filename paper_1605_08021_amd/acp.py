@@ -61,6 +61,12 @@ class AcpStats(C.Structure):
                 ("krylov_group", C.c_int)]
 
 
+class AcpBatchInfo(C.Structure):
+    _fields_ = [("n_systems", C.c_int), ("n_tiles", C.c_int), ("grid", C.c_int), ("order", C.c_int),
+                ("tuned", C.c_int), ("graph_replays", C.c_longlong), ("ms_last", C.c_double),
+                ("tune_ms", C.c_double * 6)]
+
+
 _lib = None
 
 
@@ -100,6 +106,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_precond_forward": (I, [P, P, I, P, P]),
         "acp_precond_apply": (I, [P, P, I, P, P]),
         "acp_precond_train_step": (I, [P, P, I, P, P, C.c_double, P, P]),
+        "acp_batch_create": (I, [C.POINTER(P), P, I, I]),
+        "acp_batch_compress": (I, [P, P, P, P, P]),
+        "acp_batch_info": (I, [P, C.POINTER(AcpBatchInfo)]),
+        "acp_batch_last_error": (C.c_char_p, [P]),
+        "acp_batch_destroy": (None, [P]),
         "acp_get_stats": (I, [P, C.POINTER(AcpStats)]),
         "acp_reset_stats": (None, [P]),
         "acp_last_error": (C.c_char_p, [P]),
@@ -367,6 +378,65 @@ class Context:
         if self._ctx:
             self.lib.acp_destroy(self._ctx)
             self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """acp_batch: the shifted solves of several contexts in one persistent launch."""
+
+    def __init__(self, contexts, use_graph: bool = False):
+        self.lib = load_library()
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c._ctx.value for c in self.contexts])
+        self._b = C.c_void_p()
+        st = self.lib.acp_batch_create(C.byref(self._b), arr, len(self.contexts), int(use_graph))
+        if st != ACP_OK:
+            msg = self.lib.acp_batch_last_error(self._b).decode() if self._b else ""
+            self.lib.acp_batch_destroy(self._b)
+            self._b = C.c_void_p()
+            raise ACPError(st, msg)
+
+    def compress(self, Gs, omegas, sel_in=None):
+        Gs = [colmajor(g) for g in Gs]
+        oms = [colmajor(o) for o in omegas]
+        n = len(self.contexts)
+        gp = (C.c_void_p * n)(*[_dptr(g) for g in Gs])
+        op = (C.c_void_p * n)(*[_dptr(o) for o in oms])
+        npv = (C.c_int * n)(*[g.shape[1] for g in Gs])
+        keep = []
+        sp = None
+        if sel_in is not None:
+            ptrs = []
+            for sel in sel_in:
+                if sel is None:
+                    ptrs.append(None)
+                else:
+                    a = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+                    keep.append(a)
+                    ptrs.append(a.ctypes.data)
+            sp = (C.c_void_p * n)(*ptrs)
+        st = self.lib.acp_batch_compress(self._b, gp, npv, op, sp)
+        if st != ACP_OK:
+            raise ACPError(st, self.lib.acp_batch_last_error(self._b).decode())
+
+    def info(self) -> dict:
+        i = AcpBatchInfo()
+        st = self.lib.acp_batch_info(self._b, C.byref(i))
+        if st != ACP_OK:
+            raise ACPError(st, "acp_batch_info")
+        d = {f: getattr(i, f) for f, _ in AcpBatchInfo._fields_ if f != "tune_ms"}
+        d["tune_ms"] = list(i.tune_ms)
+        return d
+
+    def close(self):
+        if self._b:
+            self.lib.acp_batch_destroy(self._b)
+            self._b = C.c_void_p()
 
     def __del__(self):
         try:

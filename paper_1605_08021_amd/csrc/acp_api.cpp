@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "acp_internal.h"
@@ -71,6 +72,10 @@ struct acp_ctx {
     DevBuf nn_theta, nn_m, nn_v, nn_grad, nn_part, nn_bpart, nn_out, nn_rms, nn_shat, nn_tgt, nn_loss;
     DevBuf nn_d, nn_ad;
     std::vector<double> nn_shat_host;   // source of an asynchronous upload: lives with the context
+    // autotuner: workgroups per tile of the multi-shift solver, per problem shape
+    std::map<long long, int> ms_tuned;
+    struct TuneEntry { long long key; int K; float ms; };
+    std::vector<TuneEntry> tune_log;
     DevBuf nn_wf[4], nn_wb[4], nn_act[4], nn_g[4];
     DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc;           // flexible CG
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm;
@@ -78,6 +83,30 @@ struct acp_ctx {
     acp_stats stats{};
     std::string err;
     hipEvent_t ev[8]{};
+};
+
+// A ragged batch of systems (contexts) whose shifted solves share one
+// persistent launch.
+struct acp_batch {
+    std::vector<acp_ctx *> sys;
+    int dim = 0, ne_pad = 0;
+    bool use_graph = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevBuf desc, wsys, wtile, queue, abort_flag;
+    std::vector<DevBuf> phi_rm_pad, phi_cm_pad;
+    std::vector<MsArgs> host_desc, graph_desc;
+    std::vector<int> host_wsys, host_wtile;
+    int grid = 0, order = 0;          // chosen by the autotuner
+    bool tuned = false;
+    std::vector<float> tune_ms;       // per candidate: grid {64,128,256} x order {given, largest first}
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_grid = -1, graph_order = -1;
+    long long replays = 0;
+    float ms_last = 0.f;
+    std::string err;
+    hipEvent_t ev[2]{};
 };
 
 namespace {
@@ -320,13 +349,24 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     const int cap = mscg_resident_capacity(ctx->gd.dim, ctx->nep, sizeof(T) == 4);
     if (cap < rhs_tiles) return ACP_OK;
     const int nblk = (ng + 15) / 16;
-    int K = cap / rhs_tiles;
-    K = std::min(K, std::max(1, nblk / 8));
-    if (const char *ov = std::getenv("ACP_MSCG_GROUP")) {   // tuning override
+    // workgroups per tile: autotuned once per problem shape (below), unless forced
+    const long long key = ((long long)ng * 4096 + ctx->nep) * 4096 + rhs_tiles * 32 + nc * 2 + (sizeof(T) == 4);
+    int K = 0;
+    auto tuned = ctx->ms_tuned.find(key);
+    if (tuned != ctx->ms_tuned.end()) K = tuned->second;
+    if (const char *ov = std::getenv("ACP_MSCG_GROUP")) {   // manual override
         const int k = std::atoi(ov);
-        if (k >= 1 && k * rhs_tiles <= cap) K = k;
+        if (k >= 1 && k * rhs_tiles <= cap && k <= kMsMaxGroup) K = k;
     }
-    K = std::max(std::min(K, kMsMaxGroup), 1);
+    std::vector<int> cands;
+    if (K == 0) {
+        for (int k = 1; k <= kMsMaxGroup; k *= 2)
+            if (k * rhs_tiles <= cap && k <= std::max(1, nblk / 4)) cands.push_back(k);
+        if (cands.empty()) cands.push_back(1);
+    } else {
+        cands.push_back(K);
+    }
+    const int Kmax = *std::max_element(cands.begin(), cands.end());
     const size_t vt = (size_t)ng * kTile;           // elements per tile vector
     ENSURE(ctx->kx, (size_t)nc * rhs_tiles * vt * 8);
     ENSURE(ctx->msp, (size_t)nc * rhs_tiles * vt * sizeof(T));
@@ -334,7 +374,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     ENSURE(ctx->kpa, (size_t)rhs_tiles * vt * sizeof(T));
     ENSURE(ctx->kpb, (size_t)rhs_tiles * vt * sizeof(T));
     const size_t slot = mscg_group_slot(ctx->nep);
-    ENSURE(ctx->msgbuf, (size_t)rhs_tiles * 2 * K * slot * 8);
+    ENSURE(ctx->msgbuf, (size_t)rhs_tiles * 2 * Kmax * slot * 8);
     ENSURE(ctx->mscnt, (size_t)rhs_tiles * 4);
     ENSURE(ctx->msabort, 4);
     const int ncols = nc * rhs_tiles * kTile;
@@ -348,13 +388,10 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
         if (ctx->nodes[c] > ctx->nodes[base]) base = c;
     hipStream_t s = ctx->stream;
     HIPCHK(hipMemcpyAsync(ctx->dy_s.p, ctx->nodes.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_fill_u32(dp<unsigned>(ctx->mscnt), rhs_tiles, 0u, s));
-    HIPCHK(launch_fill_i32(dp<int>(ctx->msabort), 1, 0, s));
     MsArgsT<T> a{};
     a.g = ctx->gd;
     a.ne = ctx->nep;
     a.ntiles = rhs_tiles;
-    a.K = K;
     a.nshift = nc;
     a.base = base;
     a.shift = dp<double>(ctx->dy_s);
@@ -382,10 +419,31 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
         HIPCHK(launch_fill_u32(dp<unsigned>(ctx->msprof), 16, 0u, s));
         a.phase_clock = dp<unsigned long long>(ctx->msprof);
     }
-    HIPCHK(hipEventRecord(ctx->ev[6], s));
-    if constexpr (sizeof(T) == 8) HIPCHK(launch_mscg_fp64(a, s));
-    else HIPCHK(launch_mscg_fp32(a, s));
-    HIPCHK(hipEventRecord(ctx->ev[7], s));
+    float best_ms = 0.f;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        K = cands[ci];
+        a.K = K;
+        HIPCHK(launch_fill_u32(dp<unsigned>(ctx->mscnt), rhs_tiles, 0u, s));
+        HIPCHK(launch_fill_i32(dp<int>(ctx->msabort), 1, 0, s));
+        HIPCHK(hipEventRecord(ctx->ev[6], s));
+        if constexpr (sizeof(T) == 8) HIPCHK(launch_mscg_fp64(a, s));
+        else HIPCHK(launch_mscg_fp32(a, s));
+        HIPCHK(hipEventRecord(ctx->ev[7], s));
+        if (cands.size() > 1) {
+            // autotuning run: keep the fastest group size for this shape; the
+            // results of the last run stand (every group size yields the same
+            // solution up to the order of the partial sums)
+            HIPCHK(hipStreamSynchronize(s));
+            int ab = 0;
+            HIPCHK(hipMemcpy(&ab, a.abort_flag, 4, hipMemcpyDeviceToHost));
+            const float ms = event_ms(ctx->ev[6], ctx->ev[7]);
+            ctx->tune_log.push_back({key, K, ab ? -1.f : ms});
+            if (!ab && (best_ms == 0.f || ms < best_ms)) {
+                best_ms = ms;
+                ctx->ms_tuned[key] = K;
+            }
+        }
+    }
     std::vector<int> it(ncols), fl(ncols), ti(rhs_tiles);
     int abort_h = 0;
     HIPCHK(hipMemcpyAsync(it.data(), a.iters, (size_t)ncols * 4, hipMemcpyDeviceToHost, s));
@@ -947,7 +1005,10 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
 
 // Alg. 3 steps 2-3 given ctx->xi: right-hand sides, the N_c N_mu shifted
 // solves, and W of Eq. (3.7).
-acp_status solve_and_assemble(acp_ctx *ctx) {
+// Alg. 3 after the point selection, part 1: right-hand sides -Q xi_mu (Eq. (3.6)),
+// their 16-column tiles (one copy shared by every shift) and the per-column
+// shifts.
+acp_status prepare_rhs(acp_ctx *ctx) {
     const int ng = ctx->ng, ne = ctx->ne, nmu = ctx->nmu, nmp = ctx->nmu_pad;
     const int nc = (int)ctx->nodes.size();
     hipStream_t s = ctx->stream;
@@ -973,6 +1034,23 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
         for (int j = 0; j < nmp; ++j) sh[(size_t)c * nmp + j] = ctx->nodes[c];
     ENSURE(ctx->shifts_dev, sh.size() * 8);
     HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, sh.data(), sh.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // sh is released on return
+    return ACP_OK;
+}
+
+acp_status finish_compress(acp_ctx *ctx, int flags, bool learned);
+
+// Alg. 3 after the point selection: right-hand sides, the N_c N_mu shifted
+// solves, W (Eq. (3.7)).
+acp_status solve_and_assemble(acp_ctx *ctx) {
+    CHECK(prepare_rhs(ctx));
+    const int ng = ctx->ng, nmu = ctx->nmu, nmp = ctx->nmu_pad;
+    const int nc = (int)ctx->nodes.size();
+    hipStream_t s = ctx->stream;
+    const int rhs_tiles = nmp / kTile;
+    const int ntiles = rhs_tiles * nc;
+    const double *R = dp<double>(ctx->rhs);
+    const double *phi = dp<double>(ctx->phi_cm);
     int flags = 0;
     bool ms_used = false;
     const bool mixed = ctx->opts.precision == ACP_PREC_FP32_REFINE;
@@ -1018,6 +1096,19 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
                                      ctx->opts.inner_tol, &flags));
         flags &= ~1;   // judged by the refined residual
     }
+    return finish_compress(ctx, flags, learned);
+}
+
+// Part 3: Z from the tiled solutions (unless the solver wrote Z), the mixed
+// form's refinement, W, timings, FP64 true residuals, status.
+acp_status finish_compress(acp_ctx *ctx, int flags, bool learned) {
+    const int ng = ctx->ng, ne = ctx->ne, nmu = ctx->nmu, nmp = ctx->nmu_pad;
+    const int nc = (int)ctx->nodes.size();
+    const int rhs_tiles = nmp / kTile;
+    const bool mixed = ctx->opts.precision == ACP_PREC_FP32_REFINE && !learned;
+    hipStream_t s = ctx->stream;
+    const double *R = dp<double>(ctx->rhs);
+    const double *phi = dp<double>(ctx->phi_cm);
     ctx->stats.systems_solved += (long long)nc * nmu;
     // Z (column-major, block c = shift c)
     ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
@@ -1069,6 +1160,230 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     }
     ctx->have_chi0 = true;
     return flags_status(ctx, flags);
+}
+
+// ------------------------------------------------------------ ragged batch
+
+constexpr int kBatchGrids[3] = {64, 128, 256};
+
+acp_status bfail(acp_batch *b, acp_status st, const std::string &msg) {
+    if (b) b->err = msg;
+    return st;
+}
+
+#define BHIP(x)                                                                               \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess)                                                                 \
+            return bfail(b, ACP_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+#define BENSURE(buf, bytes)                                                                   \
+    do {                                                                                      \
+        if (!ensure((buf), (bytes))) return bfail(b, ACP_ENOMEM, "device allocation failed");  \
+    } while (0)
+
+#define BCHECK(ctx_, st)                                                                      \
+    do {                                                                                      \
+        acp_status s_ = (st);                                                                 \
+        if (s_ != ACP_OK) return bfail(b, s_, (ctx_)->err);                                   \
+    } while (0)
+
+// Per system: the multi-shift buffers for K = 1, and its descriptor.
+acp_status batch_describe(acp_batch *b, size_t i, MsArgs &a) {
+    acp_ctx *ctx = b->sys[i];
+    const int ng = ctx->ng, nc = (int)ctx->nodes.size();
+    const int rhs_tiles = ctx->nmu_pad / kTile;
+    const size_t vt = (size_t)ng * kTile;
+    BENSURE(ctx->kx, (size_t)nc * rhs_tiles * vt * 8);
+    BENSURE(ctx->msp, (size_t)nc * rhs_tiles * vt * 8);
+    BENSURE(ctx->kr, (size_t)kMsWindow * rhs_tiles * vt * 8);
+    BENSURE(ctx->kpa, (size_t)rhs_tiles * vt * 8);
+    BENSURE(ctx->kpb, (size_t)rhs_tiles * vt * 8);
+    BENSURE(ctx->msgbuf, (size_t)rhs_tiles * 2 * mscg_group_slot(b->ne_pad) * 8);
+    BENSURE(ctx->mscnt, (size_t)rhs_tiles * 4);
+    const int ncols = nc * rhs_tiles * kTile;
+    BENSURE(ctx->kiters, (size_t)ncols * 4);
+    BENSURE(ctx->kresid, (size_t)ncols * 8);
+    BENSURE(ctx->kflags, (size_t)ncols * 4);
+    BENSURE(ctx->ktile, (size_t)rhs_tiles * 4);
+    BENSURE(ctx->dy_s, (size_t)nc * 8);
+    BHIP(hipMemcpy(ctx->dy_s.p, ctx->nodes.data(), (size_t)nc * 8, hipMemcpyHostToDevice));
+    int base = 0;
+    for (int c = 1; c < nc; ++c)
+        if (ctx->nodes[c] > ctx->nodes[base]) base = c;
+    a = MsArgs{};
+    a.g = ctx->gd;
+    a.ne = b->ne_pad;
+    a.ntiles = rhs_tiles;
+    a.K = 1;
+    a.nshift = nc;
+    a.base = base;
+    a.shift = dp<double>(ctx->dy_s);
+    const bool pad = ctx->nep != b->ne_pad;
+    a.phi_rm = pad ? dp<double>(b->phi_rm_pad[i]) : dp<double>(ctx->phi_rm);
+    a.phi_cm = pad ? dp<double>(b->phi_cm_pad[i]) : dp<double>(ctx->phi_cm);
+    a.veff = dp<double>(ctx->veff);
+    a.rhs = dp<double>(ctx->krhs);
+    a.x = dp<double>(ctx->kx);
+    a.p = dp<double>(ctx->msp);
+    a.r = dp<double>(ctx->kr);
+    a.pa = dp<double>(ctx->kpa);
+    a.pb = dp<double>(ctx->kpb);
+    a.gbuf = dp<double>(ctx->msgbuf);
+    a.cnt = dp<unsigned>(ctx->mscnt);
+    a.abort_flag = dp<int>(b->abort_flag);
+    a.iters = dp<int>(ctx->kiters);
+    a.resid = dp<double>(ctx->kresid);
+    a.flags = dp<int>(ctx->kflags);
+    a.tile_iters = dp<int>(ctx->ktile);
+    a.tol = ctx->opts.tol;
+    a.max_iter = ctx->opts.max_iter;
+    return ACP_OK;
+}
+
+// Work list: every right-hand-side tile of every system; order 1 puts the
+// systems with the most grid points first (their tiles run longest).
+void batch_order(acp_batch *b, int order) {
+    std::vector<size_t> idx(b->sys.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    if (order == 1)
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](size_t x, size_t y) { return b->sys[x]->ng > b->sys[y]->ng; });
+    b->host_wsys.clear();
+    b->host_wtile.clear();
+    for (size_t i : idx)
+        for (int t = 0; t < b->sys[i]->nmu_pad / kTile; ++t) {
+            b->host_wsys.push_back((int)i);
+            b->host_wtile.push_back(t);
+        }
+}
+
+// The launch sequence: zero the per-tile counters, the abort flag and the work
+// counter (fill kernels: the sequence may be captured), then the batch kernel.
+acp_status batch_enqueue(acp_batch *b, int grid) {
+    hipStream_t s = b->stream;
+    for (acp_ctx *ctx : b->sys) BHIP(launch_fill_u32(dp<unsigned>(ctx->mscnt), ctx->nmu_pad / kTile, 0u, s));
+    BHIP(launch_fill_i32(dp<int>(b->abort_flag), 1, 0, s));
+    BHIP(launch_fill_u32(dp<unsigned>(b->queue), 1, 0u, s));
+    BHIP(launch_mscg_batch_fp64(b->dim, b->ne_pad, dp<MsArgs>(b->desc), dp<int>(b->wsys), dp<int>(b->wtile),
+                                (int)b->host_wsys.size(), dp<unsigned>(b->queue), grid, s));
+    return ACP_OK;
+}
+
+acp_status batch_upload_work(acp_batch *b, int order) {
+    batch_order(b, order);
+    const size_t nw = b->host_wsys.size();
+    BENSURE(b->wsys, nw * 4);
+    BENSURE(b->wtile, nw * 4);
+    BHIP(hipMemcpy(b->wsys.p, b->host_wsys.data(), nw * 4, hipMemcpyHostToDevice));
+    BHIP(hipMemcpy(b->wtile.p, b->host_wtile.data(), nw * 4, hipMemcpyHostToDevice));
+    return ACP_OK;
+}
+
+// One batched solve: autotune (first call), then the chosen configuration,
+// replayed from a hipGraph when the batch was created with use_graph.
+acp_status batch_solve(acp_batch *b) {
+    hipStream_t s = b->stream;
+    b->host_desc.resize(b->sys.size());
+    for (size_t i = 0; i < b->sys.size(); ++i) CHECK(batch_describe(b, i, b->host_desc[i]));
+    BENSURE(b->desc, b->host_desc.size() * sizeof(MsArgs));
+    BHIP(hipMemcpy(b->desc.p, b->host_desc.data(), b->host_desc.size() * sizeof(MsArgs),
+                   hipMemcpyHostToDevice));
+    if (!b->tuned) {
+        // every configuration computes the same tiles in the same way, so the
+        // outputs do not depend on the choice: keep the fastest
+        b->tune_ms.clear();
+        float best = 0.f;
+        for (int order = 0; order < 2; ++order) {
+            CHECK(batch_upload_work(b, order));
+            for (int g : kBatchGrids) {
+                BHIP(hipEventRecord(b->ev[0], s));
+                CHECK(batch_enqueue(b, g));
+                BHIP(hipEventRecord(b->ev[1], s));
+                BHIP(hipStreamSynchronize(s));
+                const float ms = event_ms(b->ev[0], b->ev[1]);
+                b->tune_ms.push_back(ms);
+                if (best == 0.f || ms < best) {
+                    best = ms;
+                    b->grid = g;
+                    b->order = order;
+                }
+            }
+        }
+        b->tuned = true;
+        b->ms_last = best;
+        CHECK(batch_upload_work(b, b->order));
+        return ACP_OK;
+    }
+    if (b->use_graph) {
+        const bool same = b->exec && b->graph_grid == b->grid && b->graph_order == b->order &&
+                          b->graph_desc.size() == b->host_desc.size() &&
+                          std::memcmp(b->graph_desc.data(), b->host_desc.data(),
+                                      b->host_desc.size() * sizeof(MsArgs)) == 0;
+        if (!same) {
+            if (b->exec) BHIP(hipGraphExecDestroy(b->exec));
+            if (b->graph) BHIP(hipGraphDestroy(b->graph));
+            b->exec = nullptr;
+            b->graph = nullptr;
+            BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            acp_status st = batch_enqueue(b, b->grid);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &g);
+            CHECK(st);
+            BHIP(e);
+            b->graph = g;
+            BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->graph_desc = b->host_desc;
+            b->graph_grid = b->grid;
+            b->graph_order = b->order;
+        }
+        BHIP(hipEventRecord(b->ev[0], s));
+        BHIP(hipGraphLaunch(b->exec, s));
+        BHIP(hipEventRecord(b->ev[1], s));
+        b->replays += 1;
+    } else {
+        BHIP(hipEventRecord(b->ev[0], s));
+        CHECK(batch_enqueue(b, b->grid));
+        BHIP(hipEventRecord(b->ev[1], s));
+    }
+    BHIP(hipStreamSynchronize(s));
+    b->ms_last = event_ms(b->ev[0], b->ev[1]);
+    return ACP_OK;
+}
+
+// Per system after the batched solve: statistics of its tiles, then Z, W and
+// the FP64 true residuals as after a single-system solve.
+acp_status batch_finish(acp_batch *b, size_t i) {
+    acp_ctx *ctx = b->sys[i];
+    const int ng = ctx->ng, nc = (int)ctx->nodes.size(), rhs_tiles = ctx->nmu_pad / kTile;
+    const int ncols = nc * rhs_tiles * kTile;
+    std::vector<int> it(ncols), fl(ncols), ti(rhs_tiles);
+    BHIP(hipMemcpy(it.data(), ctx->kiters.p, (size_t)ncols * 4, hipMemcpyDeviceToHost));
+    BHIP(hipMemcpy(fl.data(), ctx->kflags.p, (size_t)ncols * 4, hipMemcpyDeviceToHost));
+    BHIP(hipMemcpy(ti.data(), ctx->ktile.p, (size_t)rhs_tiles * 4, hipMemcpyDeviceToHost));
+    int f = 0, imin = 1 << 30, imax = 0;
+    long long sum = 0, base_it = 0, shifted_it = 0, tsum = 0;
+    const int base = b->host_desc[i].base;
+    for (int c = 0; c < nc; ++c)
+        for (int j = 0; j < rhs_tiles * kTile; ++j) {
+            const int v = it[(size_t)c * rhs_tiles * kTile + j];
+            f |= fl[(size_t)c * rhs_tiles * kTile + j];
+            imin = std::min(imin, v);
+            imax = std::max(imax, v);
+            sum += v;
+            if (c == base) base_it += v; else shifted_it += v;
+        }
+    for (int t = 0; t < rhs_tiles; ++t) tsum += ti[t];
+    ctx->stats.system_iterations += sum;
+    ctx->stats.tile_iterations += tsum;
+    ctx->stats.iters_min = imin;
+    ctx->stats.iters_max = imax;
+    const double per_window = 32.0 / kMsWindow;
+    ctx->stats.krylov_bytes += ng * ((7.0 * 8 + per_window) * (double)base_it + per_window * (double)shifted_it);
+    ctx->stats.krylov_flops += 4.0 * ng * (double)ctx->ne * (double)base_it;
+    BCHECK(ctx, finish_compress(ctx, f, false));
+    return ACP_OK;
 }
 
 acp_status compress_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega,
@@ -1343,6 +1658,119 @@ acp_status acp_precond_train_step(acp_ctx *ctx, const double *shift, int n, cons
     HIPCHK(hipStreamSynchronize(s));
     if (loss) *loss = lsum / n;
     return ACP_OK;
+}
+
+acp_status acp_batch_create(acp_batch **out, acp_ctx *const *systems, int n, int use_graph) {
+    if (!out) return ACP_EINVAL;
+    *out = nullptr;
+    acp_batch *b = new (std::nothrow) acp_batch();
+    if (!b) return ACP_ENOMEM;
+    *out = b;
+    if (!systems || n < 1) return bfail(b, ACP_EINVAL, "no systems");
+    b->use_graph = use_graph != 0;
+    for (int i = 0; i < n; ++i) {
+        acp_ctx *c = systems[i];
+        if (!c) return bfail(b, ACP_EINVAL, "null system");
+        if (i > 0 && c->gd.dim != b->dim) return bfail(b, ACP_EINVAL, "systems of one dimension per batch");
+        if (c->opts.solver != ACP_SOLVER_CG || c->opts.precision != ACP_PREC_FP64 || c->opts.use_learned_precond)
+            return bfail(b, ACP_EINVAL, "batched systems use the FP64 multi-shift CG (solver CG, FP64)");
+        if (c->opts.n_cheb > 16) return bfail(b, ACP_EINVAL, "at most 16 shifts per system");
+        b->dim = c->gd.dim;
+        b->ne_pad = std::max(b->ne_pad, c->nep);
+        b->sys.push_back(c);
+    }
+    if (b->ne_pad > 256) return bfail(b, ACP_EINVAL, "at most 256 orbitals");
+    BHIP(hipSetDevice(b->sys[0]->device));
+    // its own stream (default priority): a graph cannot be captured on the null stream
+    BHIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->own_stream = true;
+    BHIP(hipEventCreate(&b->ev[0]));
+    BHIP(hipEventCreate(&b->ev[1]));
+    BENSURE(b->queue, 4);
+    BENSURE(b->abort_flag, 4);
+    // Phi padded with zero orbitals to the batch's common block count
+    b->phi_rm_pad.resize(n);
+    b->phi_cm_pad.resize(n);
+    for (int i = 0; i < n; ++i) {
+        acp_ctx *c = b->sys[i];
+        if (c->nep == b->ne_pad) continue;
+        const size_t ng = c->ng, np = b->ne_pad;
+        BENSURE(b->phi_rm_pad[i], ng * np * 8);
+        BENSURE(b->phi_cm_pad[i], ng * np * 8);
+        BHIP(hipMemset(b->phi_rm_pad[i].p, 0, ng * np * 8));
+        BHIP(hipMemset(b->phi_cm_pad[i].p, 0, ng * np * 8));
+        BHIP(hipMemcpy2D(b->phi_rm_pad[i].p, np * 8, c->phi_rm.p, (size_t)c->nep * 8, (size_t)c->nep * 8, ng,
+                         hipMemcpyDeviceToDevice));
+        BHIP(hipMemcpy(b->phi_cm_pad[i].p, c->phi_cm.p, ng * c->nep * 8, hipMemcpyDeviceToDevice));
+    }
+    return ACP_OK;
+}
+
+acp_status acp_batch_compress(acp_batch *b, const double *const *G, const int *n_p,
+                              const double *const *omega, const int *const *sel_in) {
+    if (!b || !G || !n_p || !omega) return ACP_EINVAL;
+    for (auto *c : b->sys) BHIP(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < b->sys.size(); ++i) {
+        acp_ctx *ctx = b->sys[i];
+        if (!G[i] || !omega[i] || n_p[i] < 1) return bfail(b, ACP_EINVAL, "G, omega, n_p");
+        hipStream_t s = ctx->stream;
+        BHIP(hipEventRecord(ctx->ev[0], s));
+        BCHECK(ctx, isdf_impl(ctx, G[i], n_p[i], omega[i], sel_in ? sel_in[i] : nullptr));
+        BHIP(hipEventRecord(ctx->ev[5], s));
+        BHIP(hipStreamSynchronize(s));
+        ctx->stats.ms_isdf += event_ms(ctx->ev[0], ctx->ev[5]);
+        if ((int)ctx->nodes.size() > 16) return bfail(b, ACP_EINVAL, "at most 16 shifts per system");
+        BCHECK(ctx, prepare_rhs(ctx));
+        BHIP(hipEventRecord(ctx->ev[2], s));
+        BHIP(hipStreamSynchronize(s));
+    }
+    CHECK(batch_solve(b));
+    int ab = 0;
+    BHIP(hipMemcpy(&ab, b->abort_flag.p, 4, hipMemcpyDeviceToHost));
+    if (ab) return bfail(b, ACP_EDEVICE, "batched solve: a barrier wait expired");
+    acp_status worst = ACP_OK;
+    for (size_t i = 0; i < b->sys.size(); ++i) {
+        acp_ctx *ctx = b->sys[i];
+        ctx->stats.ms_solve_kernel += b->ms_last / b->sys.size();
+        ctx->stats.solve_kernel_launches += 1;
+        ctx->stats.krylov_group = 1;
+        const acp_status st = batch_finish(b, i);
+        if (st != ACP_OK && worst == ACP_OK) worst = st;
+    }
+    return worst;
+}
+
+acp_status acp_batch_info(const acp_batch *b, acp_batch_info_t *out) {
+    if (!b || !out) return ACP_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->n_systems = (int)b->sys.size();
+    out->n_tiles = (int)b->host_wsys.size();
+    out->grid = b->grid;
+    out->order = b->order;
+    out->tuned = b->tuned;
+    out->graph_replays = b->replays;
+    out->ms_last = b->ms_last;
+    for (size_t k = 0; k < b->tune_ms.size() && k < 6; ++k) out->tune_ms[k] = b->tune_ms[k];
+    return ACP_OK;
+}
+
+const char *acp_batch_last_error(const acp_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+void acp_batch_destroy(acp_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    release(b->desc);
+    release(b->wsys);
+    release(b->wtile);
+    release(b->queue);
+    release(b->abort_flag);
+    for (auto &d : b->phi_rm_pad) release(d);
+    for (auto &d : b->phi_cm_pad) release(d);
+    delete b;
 }
 
 acp_status acp_compress(acp_ctx *ctx, const double *G, int n_p, const double *omega,

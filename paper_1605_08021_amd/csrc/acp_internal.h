@@ -164,6 +164,12 @@ constexpr int kMsWindow = 8;
 constexpr int kMsMaxGroup = 16;   // workgroups per right-hand-side tile
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s);
 hipError_t launch_mscg_fp32(const MsArgsT<float> &a, hipStream_t s);
+// Persistent ragged batch (K = 1 per tile): systems[] are device descriptors of
+// systems with the same dim whose orbital blocks are padded to ne_pad; the work
+// list (work_sys[w], work_tile[w]) is consumed through *queue (zero at launch).
+hipError_t launch_mscg_batch_fp64(int dim, int ne_pad, const MsArgs *systems, const int *work_sys,
+                                  const int *work_tile, int n_work, unsigned *queue, int grid,
+                                  hipStream_t s);
 int mscg_resident_capacity(int dim, int ne, bool fp32);   // workgroups the device can hold at once
 size_t mscg_group_slot(int ne);                // doubles per group partial
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);

@@ -162,8 +162,10 @@ __device__ __forceinline__ void column_partial(double v, double *red, double *ou
 #define PHASE_MARK(i) do {} while (0)
 #endif
 
+// The whole solve of one right-hand-side tile (all shifts) by workgroup kg of
+// its group.
 template <int DIM, int NB, typename T>
-__global__ __launch_bounds__(NT) void mscg_kernel(MsArgsT<T> a) {
+__device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     using S = Slots<NB>;
     static_assert(S::N * S::ELEMS >= S::ELEMS + kTile, "slots hold C and p^T y");
     __shared__ double slots[S::N * S::ELEMS];
@@ -178,11 +180,6 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgsT<T> a) {
         s_colact[kTile], s_any, s_abort;
 
     const int K = a.K;
-    // group members blockIdx = tile + ntiles * k: with workgroups dealt round-robin
-    // to the XCDs, a group whose ntiles is a multiple of the XCD count stays on one
-    // XCD (one L2) for its barriers and halo exchange
-    const int tile = blockIdx.x % a.ntiles;
-    const int kg = blockIdx.x / a.ntiles;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -588,6 +585,35 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgsT<T> a) {
     if (kg == 0 && t == 0) a.tile_iters[tile] = it;
 }
 
+// Group members blockIdx = tile + ntiles * k: with workgroups dealt round-robin
+// to the XCDs, a group whose ntiles is a multiple of the XCD count stays on one
+// XCD (one L2) for its barriers and halo exchange.
+template <int DIM, int NB, typename T>
+__global__ __launch_bounds__(NT) void mscg_kernel(MsArgsT<T> a) {
+    mscg_tile<DIM, NB, T>(a, blockIdx.x % a.ntiles, blockIdx.x / a.ntiles);
+}
+
+// Persistent batch: every workgroup takes the next entry of a work list (one
+// right-hand-side tile of one system, K = 1) from a global counter until the
+// list is exhausted; systems of different sizes share the launch.
+template <int DIM, int NB, typename T>
+__global__ __launch_bounds__(NT) void mscg_batch_kernel(const MsArgsT<T> *__restrict__ systems,
+                                                        const int *__restrict__ work_sys,
+                                                        const int *__restrict__ work_tile, int n_work,
+                                                        unsigned *queue) {
+    __shared__ int s_w;
+    for (;;) {
+        __syncthreads();   // the previous entry is finished with s_w and the LDS state
+        if (threadIdx.x == 0)
+            s_w = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int w = s_w;
+        if (w >= n_work) break;
+        const MsArgsT<T> a = systems[work_sys[w]];
+        mscg_tile<DIM, NB, T>(a, work_tile[w], 0);
+    }
+}
+
 template <int DIM, int NB, typename T>
 hipError_t launch_ms(const MsArgsT<T> &a, hipStream_t s) {
     MsArgsT<T> args = a;
@@ -641,6 +667,27 @@ hipError_t launch_mscg(const MsArgsT<T> &a, hipStream_t s) {
 }
 
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s) { return launch_mscg(a, s); }
+
+hipError_t launch_mscg_batch_fp64(int dim, int ne_pad, const MsArgs *systems, const int *work_sys,
+                                  const int *work_tile, int n_work, unsigned *queue, int grid,
+                                  hipStream_t s) {
+    if (n_work <= 0) return hipSuccess;
+    if (grid < 1 || ne_pad > 256) return hipErrorInvalidValue;
+    const int nb = (ne_pad + 15) / 16;
+#define CASE(N)                                                                                      \
+    if (nb == N) {                                                                                   \
+        if (dim == 1)                                                                                \
+            hipLaunchKernelGGL((mscg_batch_kernel<1, N, double>), dim3(grid), dim3(NT), 0, s, systems, \
+                               work_sys, work_tile, n_work, queue);                                  \
+        else                                                                                         \
+            hipLaunchKernelGGL((mscg_batch_kernel<2, N, double>), dim3(grid), dim3(NT), 0, s, systems, \
+                               work_sys, work_tile, n_work, queue);                                  \
+        return hipGetLastError();                                                                    \
+    }
+    ACP_NB_CASES(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
+}
 hipError_t launch_mscg_fp32(const MsArgsT<float> &a, hipStream_t s) { return launch_mscg(a, s); }
 
 }  // namespace acp

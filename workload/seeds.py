@@ -170,3 +170,21 @@ def draw_sketch(cfg: Config, n_p: int, seed_stream: int = 3) -> np.ndarray:
 def draw_ragged_sizes(cid: int, count: int, lo: int, hi: int) -> np.ndarray:
     """Integer sizes drawn uniformly from [lo, hi] (inclusive)."""
     return _rng(cid, 4).integers(lo, hi + 1, size=count)
+
+
+def ragged_batch_configs(count: int = 16, lo: int = 16, hi: int = 128, *, pts_per_site: int = 40,
+                         n_cheb: int = 8, vacancy_frac: float = 0.05, cid_base: int = 400,
+                         size_seed: int = 4):
+    """The 1D half of the uneven batch: `count` chains with N_A drawn uniformly
+    from [lo, hi], spacing 10, Z = 2, sigma = 1, 40 grid points per site, 5%
+    vacancies (at least one), N_c = 8, N_mu = 4 N_e (N_e after the vacancies),
+    r = 8.  Each system has its own seed streams (cid_base + index)."""
+    sizes = draw_ragged_sizes(size_seed, count, lo, hi)
+    out = []
+    for i, n_a in enumerate(sizes):
+        cfg = small_config(cid_base + i, 1, int(n_a), pts_per_site, jitter=0.0, n_cheb=n_cheb,
+                           vacancy_frac=vacancy_frac)
+        n_e = draw_sites(cfg)[2]
+        out.append(dataclasses.replace(cfg, n_mu=4 * n_e,
+                                       name=f"ragged 1D chain {i}: {n_a} sites, {n_e} occupied"))
+    return out
