@@ -78,7 +78,7 @@ struct acp_ctx {
     std::vector<TuneEntry> tune_log;
     DevBuf nn_wf[4], nn_wb[4], nn_act[4], nn_g[4];
     DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc;           // flexible CG
-    DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm;
+    DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     acp_stats stats{};
     std::string err;
@@ -1840,34 +1840,55 @@ acp_status acp_dyson(acp_ctx *ctx, const double *G, int n_p, const double *omega
                         (size_t)ctx->nmu * 4);
         const int nmu = ctx->nmu;
         HIPCHK(hipEventRecord(ctx->ev[0], s));
-        // V = v_c W
+        // T = I - (v_c W)(Pi, :).  v_c is translation invariant on the periodic grid,
+        // so its rows Pi are shifts of its first column g = v_c e_0: (v_c W)(Pi, :)
+        // = K_Pi W with K_Pi(mu, a) = g(r_{Pi_mu} - r_a) -- N_mu rows instead of
+        // applying v_c to all N_mu columns of W.
+        if (!ctx->vc_g.p) {
+            ENSURE(ctx->vc_g, (size_t)ng * 8);
+            ENSURE(ctx->tmp2, (size_t)ng * 8);
+            HIPCHK(hipMemsetAsync(ctx->tmp2.p, 0, (size_t)ng * 8, s));
+            const double one = 1.0;
+            HIPCHK(hipMemcpyAsync(ctx->tmp2.p, &one, 8, hipMemcpyHostToDevice, s));
+            CHECK(vc_apply(ctx, 1, dp<double>(ctx->tmp2), dp<double>(ctx->vc_g)));
+            HIPCHK(hipStreamSynchronize(s));
+        }
         ENSURE(ctx->dy_v, (size_t)ng * nmu * 8);
-        double *V = dp<double>(ctx->dy_v);
-        CHECK(vc_apply(ctx, nmu, dp<double>(ctx->w), V));
-        // T = I - V(Pi, :),  S = G(Pi, :)
+        double *Kp = dp<double>(ctx->dy_v);
+        HIPCHK(launch_circulant_rows(nmu, dp<int>(ctx->sel_dev), ctx->gd.nx, ctx->gd.dim == 1 ? 1 : ctx->gd.ny,
+                                     dp<double>(ctx->vc_g), Kp, s));
         ENSURE(ctx->dy_t, (size_t)nmu * nmu * 8);
         ENSURE(ctx->dy_g, (size_t)nmu * n_p * 8);
         double *T = dp<double>(ctx->dy_t), *S = dp<double>(ctx->dy_g);
-        HIPCHK(launch_gather_rows(nmu, nmu, dp<int>(ctx->sel_dev), V, ng, T, nmu, s));
+        HIPCHK(gemm(Op::N, Op::N, nmu, nmu, ng, 1.0, Kp, nmu, 0, dp<double>(ctx->w), ng, 0, 0.0, T, nmu, 0, 1, s));
         HIPCHK(launch_add_identity_neg(nmu, T, nmu, s));
         HIPCHK(launch_gather_rows(nmu, n_p, dp<int>(ctx->sel_dev), G, ng, S, nmu, s));
-        HIPCHK(gauss_jordan_solve(nmu, n_p, T, nmu, S, nmu, nullptr, s));
-        // U^{k+1} = W S (into tmp1), G^{k+1} = G + V S
+        ENSURE(ctx->dy_piv, (size_t)nmu * 4);
+        HIPCHK(lu_solve(nmu, n_p, T, nmu, S, nmu, dp<int>(ctx->dy_piv), s));
+        // U^{k+1} = W S (into tmp1), G^{k+1} = G + v_c W S = G + v_c U^{k+1}
         ENSURE(ctx->tmp1, (size_t)ng * n_p * 8);
         double *Un = dp<double>(ctx->tmp1);
         HIPCHK(gemm(Op::N, Op::N, ng, n_p, nmu, 1.0, dp<double>(ctx->w), ng, 0, S, nmu, 0, 0.0, Un,
                     ng, 0, 1, s));
-        HIPCHK(hipMemcpyAsync(Gk, G, (size_t)ng * n_p * 8, hipMemcpyDeviceToDevice, s));
-        HIPCHK(gemm(Op::N, Op::N, ng, n_p, nmu, 1.0, V, ng, 0, S, nmu, 0, 1.0, Gk, ng, 0, 1, s));
+        CHECK(vc_apply(ctx, n_p, Un, Gk));
+        HIPCHK(launch_axpby(ng, n_p, 1.0, G, ng, 1.0, Gk, ng, s));
         // relative change ||U^{k+1} - U^k|| / ||U^{k+1}||
-        ENSURE(ctx->dy_norm, 16);
-        HIPCHK(launch_diff_sqnorm(ng, n_p, Un, Uprev, ng, dp<double>(ctx->dy_norm), s));
+        // column sums (one block per column), added on the host in column order
+        ENSURE(ctx->dy_norm, (size_t)2 * n_p * 8);
+        double *cn = dp<double>(ctx->dy_norm);
+        HIPCHK(launch_col_diff_sqnorm(ng, n_p, Un, ng, Uprev, ng, cn, s));
+        HIPCHK(launch_col_sqnorm(ng, n_p, Un, ng, cn + n_p, s));
         HIPCHK(hipMemcpyAsync(Uprev, Un, (size_t)ng * n_p * 8, hipMemcpyDeviceToDevice, s));
-        double nrm[2];
-        HIPCHK(hipMemcpyAsync(nrm, ctx->dy_norm.p, 16, hipMemcpyDeviceToHost, s));
+        std::vector<double> cnh((size_t)2 * n_p);
+        HIPCHK(hipMemcpyAsync(cnh.data(), cn, (size_t)2 * n_p * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ctx->ev[1], s));
         HIPCHK(hipStreamSynchronize(s));
         ctx->stats.ms_dyson_small += event_ms(ctx->ev[0], ctx->ev[1]);
+        double nrm[2] = {0.0, 0.0};
+        for (int j = 0; j < n_p; ++j) {
+            nrm[0] += cnh[j];
+            nrm[1] += cnh[n_p + j];
+        }
         const double change = nrm[1] > 0 ? std::sqrt(nrm[0] / nrm[1]) : 0.0;
         if (ctx->opts.dyson_tol > 0.0 && change <= ctx->opts.dyson_tol) {
             ++it;
@@ -1920,7 +1941,7 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
     HIPCHK(launch_dynmat_assemble(n_p, ctx->grid.dim, dp<double>(ctx->dm_phi), Kd, Md,
                                   dp<double>(ctx->dm_d), dp<double>(ctx->dm_asym), s));
     HIPCHK(hipMemcpyAsync(D, ctx->dm_d.p, nn * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(jacobi_eigvals(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig),
+    HIPCHK(sym_eigvals(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig),
                           dp<double>(ctx->dm_work), s));
     HIPCHK(hipMemcpyAsync(omega2, ctx->dm_eig.p, (size_t)n_p * 8, hipMemcpyDeviceToHost, s));
     double asym[2];
@@ -1964,7 +1985,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->nn_wb[0], &ctx->nn_wb[1], &ctx->nn_wb[2], &ctx->nn_wb[3],
                       &ctx->nn_act[0], &ctx->nn_act[1], &ctx->nn_act[2], &ctx->nn_act[3],
                       &ctx->nn_g[0], &ctx->nn_g[1], &ctx->nn_g[2], &ctx->nn_g[3],
-                      &ctx->fc_r, &ctx->fc_z, &ctx->fc_p, &ctx->fc_q, &ctx->fc_sc};
+                      &ctx->fc_r, &ctx->fc_z, &ctx->fc_p, &ctx->fc_q, &ctx->fc_sc, &ctx->dy_piv, &ctx->vc_g};
     for (DevBuf *b : bufs) release(*b);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);

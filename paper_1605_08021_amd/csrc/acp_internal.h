@@ -100,6 +100,10 @@ hipError_t launch_to_tiled_f32(int ng, int ncols, int ncols_pad, const double *X
 hipError_t launch_from_tiled_add(int ng, int ncols, const double *T, double *X, int ldx,
                                  hipStream_t s);
 hipError_t launch_to_f32(size_t n, const double *X, float *Y, hipStream_t s);
+// K(mu, a) = g((x, y)(sel[mu]) - (x, y)(a)) on the periodic nx x ny grid: the rows
+// sel of the translation-invariant operator whose first column is g.
+hipError_t launch_circulant_rows(int nsel, const int *sel, int nx, int ny, const double *g, double *K,
+                                 hipStream_t s);
 
 // T is the storage type of Phi, the right-hand sides and the Krylov vectors
 // (double, or float for the inner solves of the mixed-precision form); the
@@ -231,9 +235,13 @@ hipError_t launch_gather_lower(int n, const int *sel, const double *L, int ldl, 
 // Solve A X = B in place (A n x n, B n x nrhs) by Gauss-Jordan with partial pivoting.
 hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, int ldb,
                               int *piv_scratch, hipStream_t s);
+// A X = B (A n x n, B n x nrhs, column-major, both overwritten: B <- X) by a
+// blocked LU with partial pivoting; piv: device scratch of n ints.  Falls back
+// to Gauss-Jordan above 576 unknowns.
+hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *piv, hipStream_t s);
 // Symmetric eigenvalues (cyclic Jacobi), A overwritten; eig sorted ascending;
 // work holds n + 2 doubles + n + 2 ints.
-hipError_t jacobi_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s);
+hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s);
 hipError_t launch_dynmat_assemble(int np, int dim, const double *Phi_el, const double *K_local,
                                   const double *mass, double *D, double *asym2,
                                   hipStream_t s);

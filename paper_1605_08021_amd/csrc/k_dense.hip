@@ -358,88 +358,6 @@ __global__ void jacobi_kernel(int n, double *A, int lda, double *eig, double *wo
     }
 }
 
-// Same cyclic Jacobi with the whole matrix resident in LDS (n <= 128): one
-// workgroup, row stride n + 1 to spread the column accesses over the banks.
-constexpr int JAC_LDS_MAX = 128;
-__global__ __launch_bounds__(1024) void jacobi_lds_kernel(int n, const double *Ain, int lda,
-                                                          double *eig, int max_sweeps, double tol) {
-    __shared__ double A[JAC_LDS_MAX * (JAC_LDS_MAX + 1)];
-    __shared__ double cs[JAC_LDS_MAX / 2 + 1], sn[JAC_LDS_MAX / 2 + 1];
-    __shared__ int pp[JAC_LDS_MAX / 2 + 1], qq[JAC_LDS_MAX / 2 + 1];
-    __shared__ int s_rot;
-    const int t = threadIdx.x;
-    const int ld = n + 1;
-    const int N = n + (n & 1);
-    const int half = N / 2;
-    for (int idx = t; idx < n * n; idx += 1024) {
-        const int i = idx % n, j = idx / n;
-        A[i + j * ld] = Ain[i + (long long)j * lda];
-    }
-    __syncthreads();
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (t == 0) s_rot = 0;
-        __syncthreads();
-        for (int round = 0; round < N - 1; ++round) {
-            if (t < half) {
-                const int k = t;
-                const int a = (k == 0) ? 0 : 1 + (k - 1 + round) % (N - 1);
-                const int b = 1 + (N - 2 - k + round) % (N - 1);
-                const int p = a < b ? a : b;
-                int q = a < b ? b : a;
-                double c = 1.0, sv = 0.0;
-                if (q < n) {
-                    const double apq = A[p + q * ld];
-                    if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(A[p + p * ld] * A[q + q * ld]))) {
-                        atomicAdd(&s_rot, 1);
-                        const double theta = (A[q + q * ld] - A[p + p * ld]) / (2.0 * apq);
-                        const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(tt * tt + 1.0);
-                        sv = tt * c;
-                    }
-                } else {
-                    q = -1;
-                }
-                pp[k] = p;
-                qq[k] = q;
-                cs[k] = c;
-                sn[k] = sv;
-            }
-            __syncthreads();
-            for (int idx = t; idx < half * n; idx += 1024) {
-                const int k = idx / n, i = idx % n;
-                const int p = pp[k], q = qq[k];
-                if (q < 0) continue;
-                const double c = cs[k], sv = sn[k];
-                const double aip = A[i + p * ld], aiq = A[i + q * ld];
-                A[i + p * ld] = c * aip - sv * aiq;
-                A[i + q * ld] = sv * aip + c * aiq;
-            }
-            __syncthreads();
-            for (int idx = t; idx < half * n; idx += 1024) {
-                const int k = idx / n, j = idx % n;
-                const int p = pp[k], q = qq[k];
-                if (q < 0) continue;
-                const double c = cs[k], sv = sn[k];
-                const double apj = A[p + j * ld], aqj = A[q + j * ld];
-                A[p + j * ld] = c * apj - sv * aqj;
-                A[q + j * ld] = sv * apj + c * aqj;
-            }
-            __syncthreads();
-        }
-        if (s_rot == 0) break;
-        __syncthreads();
-    }
-    for (int i = t; i < n; i += 1024) {
-        const double v = A[i + i * ld];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double u = A[j + j * ld];
-            if (u < v || (u == v && j < i)) ++rank;
-        }
-        eig[rank] = v;
-    }
-}
-
 // D = M^{-1/2} ((Phi + Phi^T)/2 + K) M^{-1/2}; asym2 = {||Phi - Phi^T||^2, ||Phi||^2}.
 __global__ void dynmat_assemble_kernel(int np, int dim, const double *Phi, const double *K,
                                        const double *mass, double *D, int ldd, double *asym2) {
@@ -518,6 +436,200 @@ hipError_t launch_gather_lower(int n, const int *sel, const double *L, int ldl, 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ blocked LU solve
+// A X = B by a right-looking blocked LU with partial pivoting applied to the
+// augmented [A | B] (A n x n, B n x nrhs, column-major, in place): panels of
+// LU_NB columns are factored by one workgroup with the panel in LDS; their row
+// interchanges are applied to the other columns, the block row is solved with
+// the unit lower triangle, and the trailing matrix (and B) is updated by a GEMM
+// on the matrix cores.  Back substitution then proceeds by blocks.
+constexpr int LU_NB = 32;
+constexpr int LU_MAXM = 576;      // panel rows held in LDS (LU_MAXM x LU_NB doubles)
+constexpr int LU_NT = 1024;
+
+__global__ __launch_bounds__(LU_NT) void lu_panel_kernel(int m, int nb, double *A, int lda, int *piv) {
+    __shared__ double P[LU_MAXM * LU_NB];    // P[c * m + r]
+    __shared__ double wv[LU_NT / 64];
+    __shared__ int wi[LU_NT / 64];
+    __shared__ int s_p;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int i = t; i < m * nb; i += LU_NT) {
+        const int c = i / m, r = i % m;
+        P[i] = A[r + (long long)c * lda];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        // pivot: largest |P[r][j]|, r >= j, ties to the smallest row (m <= LU_NT:
+        // one row per thread, wave shuffles, then the 16 wave results)
+        double bv = -1.0;
+        int bi = 0x7fffffff;
+        if (t >= j && t < m) {
+            bv = fabs(P[j * m + t]);
+            bi = t;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            wv[wave] = bv;
+            wi[wave] = bi;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double b = wv[0];
+            int bi0 = wi[0];
+            for (int w = 1; w < LU_NT / 64; ++w)
+                if (wv[w] > b || (wv[w] == b && wi[w] < bi0)) {
+                    b = wv[w];
+                    bi0 = wi[w];
+                }
+            s_p = bi0;
+            piv[j] = bi0;
+        }
+        __syncthreads();
+        const int p = s_p;
+        // the pivot row's entries (after the swap) and the multipliers, from
+        // values read before any thread writes
+        const double piv_jj = P[j * m + p];
+        double lr = 0.0;
+        int r = -1;
+        if (t > j && t < m) {
+            r = t;
+            const int src = (r == p) ? j : r;           // row r after the swap
+            lr = P[j * m + src] / piv_jj;
+        }
+        __syncthreads();
+        if (t < nb && p != j) {
+            const double a = P[t * m + j];
+            P[t * m + j] = P[t * m + p];
+            P[t * m + p] = a;
+        }
+        __syncthreads();
+        if (r >= 0) {
+            P[j * m + r] = lr;
+            for (int c = j + 1; c < nb; ++c) P[c * m + r] -= lr * P[c * m + j];
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < m * nb; i += LU_NT) {
+        const int c = i / m, r = i % m;
+        A[r + (long long)c * lda] = P[i];
+    }
+}
+
+// Row interchanges of panel k0 (rows k0 + j <-> k0 + piv[j], in order) on every
+// column outside the panel, and on B.  One thread per column.
+__global__ void lu_swap_kernel(int n, int nrhs, int k0, int nb, const int *piv, double *A, int lda,
+                               double *B, int ldb) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n + nrhs) return;
+    if (c >= k0 && c < k0 + nb) return;
+    double *col = c < n ? A + (long long)c * lda : B + (long long)(c - n) * ldb;
+    for (int j = 0; j < nb; ++j) {
+        const int p = piv[j];
+        if (p != j) {
+            const double a = col[k0 + j];
+            col[k0 + j] = col[k0 + p];
+            col[k0 + p] = a;
+        }
+    }
+}
+
+// Block row k0: X = L11^{-1} X for the columns right of the panel and for B
+// (L11 unit lower, nb x nb, staged in LDS).  One thread per column.
+__global__ __launch_bounds__(64) void lu_trsm_lower_kernel(int n, int nrhs, int k0, int nb, const double *A,
+                                                           int lda, double *Aw, double *B, int ldb) {
+    __shared__ double L[LU_NB * LU_NB];
+    for (int i = threadIdx.x; i < LU_NB * LU_NB; i += 64) {
+        const int r = i % LU_NB, c = i / LU_NB;
+        L[r * LU_NB + c] = (r < nb && c < nb) ? A[(k0 + r) + (long long)(k0 + c) * lda] : 0.0;
+    }
+    __syncthreads();
+    const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncols = (n - k0 - nb) + nrhs;
+    if (c0 >= ncols) return;
+    double *col = c0 < n - k0 - nb ? Aw + (long long)(k0 + nb + c0) * lda : B + (long long)(c0 - (n - k0 - nb)) * ldb;
+    double x[LU_NB];
+#pragma unroll
+    for (int i = 0; i < LU_NB; ++i) x[i] = i < nb ? col[k0 + i] : 0.0;
+#pragma unroll
+    for (int i = 1; i < LU_NB; ++i) {
+        double sacc = x[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) sacc -= L[i * LU_NB + j] * x[j];
+        x[i] = sacc;
+    }
+    for (int i = 0; i < nb; ++i) col[k0 + i] = x[i];
+}
+
+// Back substitution on block rows r0..r0+nb-1: X = U11^{-1} X for every column
+// of B (U11 staged in LDS).  One thread per column.
+__global__ __launch_bounds__(64) void lu_trsm_upper_kernel(int nrhs, int r0, int nb, const double *A, int lda,
+                                                           double *B, int ldb) {
+    __shared__ double U[LU_NB * LU_NB];
+    for (int i = threadIdx.x; i < LU_NB * LU_NB; i += 64) {
+        const int r = i % LU_NB, c = i / LU_NB;
+        U[r * LU_NB + c] = (r < nb && c < nb) ? A[(r0 + r) + (long long)(r0 + c) * lda] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    double *col = B + (long long)c * ldb;
+    double x[LU_NB];
+#pragma unroll
+    for (int i = 0; i < LU_NB; ++i) x[i] = i < nb ? col[r0 + i] : 0.0;
+#pragma unroll
+    for (int i = LU_NB - 1; i >= 0; --i) {
+        double sacc = x[i];
+#pragma unroll
+        for (int j = i + 1; j < LU_NB; ++j) sacc -= U[i * LU_NB + j] * x[j];
+        x[i] = sacc / U[i * LU_NB + i];
+    }
+    for (int i = 0; i < nb; ++i) col[r0 + i] = x[i];
+}
+
+hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *piv, hipStream_t s) {
+    if (n > LU_MAXM) return gauss_jordan_solve(n, nrhs, A, lda, B, ldb, nullptr, s);
+    hipError_t e;
+    for (int k0 = 0; k0 < n; k0 += LU_NB) {
+        const int nb = std::min(LU_NB, n - k0), m = n - k0;
+        hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(LU_NT), 0, s, m, nb,
+                           A + k0 + (long long)k0 * lda, lda, piv + k0);
+        hipLaunchKernelGGL(lu_swap_kernel, dim3(nblk(n + nrhs, 256)), dim3(256), 0, s, n, nrhs, k0, nb,
+                           (const int *)(piv + k0), A, lda, B, ldb);
+        const int ncols = (n - k0 - nb) + nrhs;
+        hipLaunchKernelGGL(lu_trsm_lower_kernel, dim3(nblk(ncols, 64)), dim3(64), 0, s, n, nrhs, k0, nb,
+                           (const double *)A, lda, A, B, ldb);
+        const int mr = n - k0 - nb;
+        if (mr > 0) {
+            if ((e = gemm(Op::N, Op::N, mr, mr, nb, -1.0, A + (k0 + nb) + (long long)k0 * lda, lda, 0,
+                          A + k0 + (long long)(k0 + nb) * lda, lda, 0, 1.0,
+                          A + (k0 + nb) + (long long)(k0 + nb) * lda, lda, 0, 1, s)) != hipSuccess)
+                return e;
+            if ((e = gemm(Op::N, Op::N, mr, nrhs, nb, -1.0, A + (k0 + nb) + (long long)k0 * lda, lda, 0,
+                          B + k0, ldb, 0, 1.0, B + (k0 + nb), ldb, 0, 1, s)) != hipSuccess)
+                return e;
+        }
+    }
+    const int nblocks = (n + LU_NB - 1) / LU_NB;
+    for (int kb = nblocks - 1; kb >= 0; --kb) {
+        const int r0 = kb * LU_NB, nb = std::min(LU_NB, n - r0);
+        hipLaunchKernelGGL(lu_trsm_upper_kernel, dim3(nblk(nrhs, 64)), dim3(64), 0, s, nrhs, r0, nb,
+                           (const double *)A, lda, B, ldb);
+        if (r0 > 0 &&
+            (e = gemm(Op::N, Op::N, r0, nrhs, nb, -1.0, A + (long long)r0 * lda, lda, 0, B + r0, ldb, 0, 1.0,
+                      B, ldb, 0, 1, s)) != hipSuccess)
+            return e;
+    }
+    return hipGetLastError();
+}
+
 hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, int ldb,
                               int * /*piv_scratch*/, hipStream_t s) {
     for (int k = 0; k < n; ++k) {
@@ -533,9 +645,124 @@ hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, in
     return hipGetLastError();
 }
 
-hipError_t jacobi_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s) {
+// Largest matrix whose eigenvalues are computed in one workgroup's LDS.
+constexpr int JAC_LDS_MAX = 128;
+
+// Eigenvalues of a symmetric n x n matrix (n <= JAC_LDS_MAX), one workgroup:
+// Householder reduction to tridiagonal form in LDS (lower triangle, textbook
+// two-sided update A <- A - v w^T - w v^T with w = p - (beta/2)(v^T p) v,
+// p = beta A v, beta = 2 / v^T v), then every eigenvalue by bisection on the
+// Sturm sequence count (one thread per eigenvalue, Gershgorin bracket).
+__global__ __launch_bounds__(1024) void tridiag_bisect_kernel(int n, const double *Ain, int lda, double *eig) {
+    __shared__ double A[JAC_LDS_MAX * (JAC_LDS_MAX + 1)];
+    __shared__ double v[JAC_LDS_MAX], p[JAC_LDS_MAX], dd[JAC_LDS_MAX], ee[JAC_LDS_MAX];
+    __shared__ double red[1024];
+    __shared__ double s_beta, s_alpha, s_k;
+    const int t = threadIdx.x;
+    const int ld = n + 1;
+    for (int idx = t; idx < n * n; idx += 1024) {
+        const int i = idx % n, j = idx / n;
+        A[i + j * ld] = Ain[i + (long long)j * lda];
+    }
+    __syncthreads();
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;        // rows k+1 .. n-1
+        // ||x||^2, x = A[k+1:, k]
+        double sq = 0.0;
+        for (int i = t; i < m; i += 1024) { const double x = A[(k + 1 + i) + k * ld]; sq += x * x; }
+        red[t] = sq;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        if (t == 0) {
+            const double x0 = A[(k + 1) + k * ld];
+            const double nrm = sqrt(red[0]);
+            const double alpha = x0 >= 0.0 ? -nrm : nrm;
+            const double vtv = red[0] - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+            s_alpha = alpha;
+            s_beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+            dd[k] = A[k + k * ld];
+            ee[k] = alpha;
+        }
+        __syncthreads();
+        for (int i = t; i < m; i += 1024) v[i] = A[(k + 1 + i) + k * ld] - (i == 0 ? s_alpha : 0.0);
+        __syncthreads();
+        const double beta = s_beta;
+        // p = beta A22 v: 8 threads per row, then the partial sums
+        for (int idx = t; idx < m * 8; idx += 1024) {
+            const int i = idx >> 3, part = idx & 7;
+            double acc = 0.0;
+            for (int j = part; j < m; j += 8) acc += A[(k + 1 + i) + (k + 1 + j) * ld] * v[j];
+            red[idx] = acc;
+        }
+        __syncthreads();
+        for (int i = t; i < m; i += 1024) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += red[i * 8 + q];
+            p[i] = beta * acc;
+        }
+        __syncthreads();
+        double vp = 0.0;
+        for (int i = t; i < m; i += 1024) vp += v[i] * p[i];
+        red[t] = vp;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        if (t == 0) s_k = 0.5 * beta * red[0];
+        __syncthreads();
+        for (int i = t; i < m; i += 1024) p[i] -= s_k * v[i];      // p <- w
+        __syncthreads();
+        for (int idx = t; idx < m * m; idx += 1024) {
+            const int i = idx % m, j = idx / m;
+            A[(k + 1 + i) + (k + 1 + j) * ld] -= v[i] * p[j] + p[i] * v[j];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (n >= 2) {
+            dd[n - 2] = A[(n - 2) + (n - 2) * ld];
+            ee[n - 2] = A[(n - 1) + (n - 2) * ld];
+        }
+        dd[n - 1] = A[(n - 1) + (n - 1) * ld];
+    }
+    __syncthreads();
+    // Gershgorin bracket
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+        lo = i == 0 ? dd[i] - r : fmin(lo, dd[i] - r);
+        hi = i == 0 ? dd[i] + r : fmax(hi, dd[i] + r);
+    }
+    const double scale = fmax(fabs(lo), fabs(hi));
+    const double tiny = 1e-300 + 1e-30 * scale;
+    for (int idx = t; idx < n; idx += 1024) {
+        // the idx-th smallest: count(x) = #{eigenvalues < x}
+        double a = lo, b = hi;
+        for (int it = 0; it < 200 && b - a > 4e-16 * scale; ++it) {
+            const double x = 0.5 * (a + b);
+            int cnt = 0;
+            double q = dd[0] - x;
+            if (q == 0.0) q = -tiny;
+            cnt += q < 0.0;
+            for (int i = 1; i < n; ++i) {
+                q = dd[i] - x - ee[i - 1] * ee[i - 1] / q;
+                if (q == 0.0) q = -tiny;
+                cnt += q < 0.0;
+            }
+            if (cnt > idx) b = x; else a = x;
+        }
+        eig[idx] = 0.5 * (a + b);
+    }
+}
+
+hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s) {
     if (n <= JAC_LDS_MAX) {
-        hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(1024), 0, s, n, A, lda, eig, 40, 1e-16);
+        hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(1), dim3(1024), 0, s, n, (const double *)A, lda, eig);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, n, A, lda, eig, work, 40, 1e-16);

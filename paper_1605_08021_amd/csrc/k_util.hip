@@ -267,6 +267,25 @@ __global__ void from_tiled_kernel(int ng, int ncols, const double *__restrict__ 
     }
 }
 
+// Rows Pi of a translation-invariant (periodic) operator with first column g:
+// K(mu, a) = g(x(Pi_mu) - x(a), y(Pi_mu) - y(a)) (indices mod the grid),
+// K column-major with leading dimension nsel.
+__global__ void circulant_rows_kernel(int nsel, const int *__restrict__ sel, int nx, int ny,
+                                      const double *__restrict__ g, double *__restrict__ K) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long ng = (long long)nx * ny;
+    if (i >= (long long)nsel * ng) return;
+    const int mu = (int)(i % nsel);
+    const long long a = i / nsel;
+    const int p = sel[mu];
+    const int ax = (int)(a % nx), ay = (int)(a / nx);
+    const int px = p % nx, py = p / nx;
+    int dx = px - ax, dy = py - ay;
+    if (dx < 0) dx += nx;
+    if (dy < 0) dy += ny;
+    K[i] = g[(long long)dy * nx + dx];
+}
+
 __global__ void to_f32_kernel(long long n, const double *__restrict__ X, float *__restrict__ Y) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) Y[i] = (float)X[i];
@@ -496,6 +515,13 @@ hipError_t launch_from_tiled_add(int ng, int ncols, const double *T, double *X, 
                                  hipStream_t s) {
     dim3 grid(nblk(ng, 64), (ncols + kTile - 1) / kTile);
     hipLaunchKernelGGL(from_tiled_kernel<true>, grid, dim3(256), 0, s, ng, ncols, T, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_circulant_rows(int nsel, const int *sel, int nx, int ny, const double *g, double *K,
+                                 hipStream_t s) {
+    const long long tot = (long long)nsel * nx * ny;
+    hipLaunchKernelGGL(circulant_rows_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, nsel, sel, nx, ny, g, K);
     return hipGetLastError();
 }
 
