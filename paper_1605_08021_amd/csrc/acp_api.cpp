@@ -959,10 +959,10 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
     const int rank_bound = std::min(r * ctx->ne, ng);
     if (nmu < 1 || nmu > rank_bound)
         return fail(ctx, ACP_EINVAL, "n_mu must satisfy 1 <= n_mu <= min(r n_e, N_g)");
-    // G~ = G Omega, stored row-major (r x N_g column-major): G~^T = Omega^T G^T
+    // G~ = G Omega (N_g x r, column-major)
     ENSURE(ctx->gt, (size_t)ng * r * 8);
-    HIPCHK(gemm(Op::T, Op::T, r, ng, n_p, 1.0, omega, n_p, 0, G, ng, 0, 0.0, dp<double>(ctx->gt),
-                r, 0, 1, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, r, n_p, 1.0, G, ng, 0, omega, n_p, 0, 0.0, dp<double>(ctx->gt), ng, 0,
+                1, s));
     ENSURE(ctx->lchol, (size_t)ng * nmu * 8);
     ENSURE(ctx->diag, (size_t)ng * 8);
     ENSURE(ctx->isdf_scratch, isdf_scratch_bytes(ng));
@@ -976,9 +976,8 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
         forced = dp<int>(ctx->forced_dev);
     }
     int got = 0;
-    const int ldl = nmu;
-    HIPCHK(isdf_pivoted_cholesky(ng, ctx->nep, r, dp<double>(ctx->phi_rm), dp<double>(ctx->gt), nmu,
-                                 sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol), ldl,
+    HIPCHK(isdf_pivoted_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), dp<double>(ctx->gt), nmu,
+                                 sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol),
                                  dp<double>(ctx->diag), dp<int>(ctx->sel_dev), forced, &got,
                                  ctx->isdf_scratch.p, s));
     if (got < 1) return fail(ctx, ACP_EINVAL, "interpolative decomposition found no pivot");
@@ -991,13 +990,14 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
     HIPCHK(hipMemcpyAsync(ctx->sel_host.data(), ctx->sel_dev.p, (size_t)nmu * 4,
                           hipMemcpyDeviceToHost, s));
     // Xi = L L11^{-1}, Xi(Pi, :) = I
-    ENSURE(ctx->linv, (size_t)nmu * nmu * 8);
-    HIPCHK(launch_tri_inverse_rows(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->lchol), ldl,
-                                   dp<double>(ctx->linv), s));
+    const int n2 = tri_inverse_order(nmu);
+    ENSURE(ctx->linv, (size_t)n2 * n2 * 8);
+    ENSURE(ctx->l11, (size_t)n2 * n2 / 4 * 8);
+    HIPCHK(launch_isdf_l11_inverse(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->lchol), ng,
+                                   dp<double>(ctx->linv), dp<double>(ctx->l11), s));
     ENSURE(ctx->xi, (size_t)ng * nmu * 8);
-    // Xi = L L11^{-1} with L row-major (= L^T column-major, leading dimension ldl)
-    HIPCHK(gemm(Op::T, Op::N, ng, nmu, nmu, 1.0, dp<double>(ctx->lchol), ldl, 0,
-                dp<double>(ctx->linv), nmu, 0, 0.0, dp<double>(ctx->xi), ng, 0, 1, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, nmu, nmu, 1.0, dp<double>(ctx->lchol), ng, 0, dp<double>(ctx->linv), n2,
+                0, 0.0, dp<double>(ctx->xi), ng, 0, 1, s));
     HIPCHK(launch_scatter_identity(nmu, dp<int>(ctx->sel_dev), dp<double>(ctx->xi), ng, s));
     HIPCHK(hipStreamSynchronize(s));
     return ACP_OK;
@@ -1857,13 +1857,13 @@ acp_status acp_dyson(acp_ctx *ctx, const double *G, int n_p, const double *omega
         double *Kp = dp<double>(ctx->dy_v);
         HIPCHK(launch_circulant_rows(nmu, dp<int>(ctx->sel_dev), ctx->gd.nx, ctx->gd.dim == 1 ? 1 : ctx->gd.ny,
                                      dp<double>(ctx->vc_g), Kp, s));
-        ENSURE(ctx->dy_t, (size_t)nmu * nmu * 8);
-        ENSURE(ctx->dy_g, (size_t)nmu * n_p * 8);
-        double *T = dp<double>(ctx->dy_t), *S = dp<double>(ctx->dy_g);
+        // [T | S] side by side (one leading dimension) for the blocked LU
+        ENSURE(ctx->dy_t, (size_t)nmu * (nmu + n_p) * 8);
+        double *T = dp<double>(ctx->dy_t), *S = T + (size_t)nmu * nmu;
         HIPCHK(gemm(Op::N, Op::N, nmu, nmu, ng, 1.0, Kp, nmu, 0, dp<double>(ctx->w), ng, 0, 0.0, T, nmu, 0, 1, s));
         HIPCHK(launch_add_identity_neg(nmu, T, nmu, s));
         HIPCHK(launch_gather_rows(nmu, n_p, dp<int>(ctx->sel_dev), G, ng, S, nmu, s));
-        ENSURE(ctx->dy_piv, (size_t)nmu * 4);
+        ENSURE(ctx->dy_piv, lu_pinfo_ints(nmu) * 4);
         HIPCHK(lu_solve(nmu, n_p, T, nmu, S, nmu, dp<int>(ctx->dy_piv), s));
         // U^{k+1} = W S (into tmp1), G^{k+1} = G + v_c W S = G + v_c U^{k+1}
         ENSURE(ctx->tmp1, (size_t)ng * n_p * 8);

@@ -217,28 +217,31 @@ hipError_t launch_col_axpby(int m, int n, const double *a, const double *X, int 
                             double *Y, int ldy, hipStream_t s);  // Y(:,j) = a[j] X(:,j) + b[j] Y(:,j)
 
 // ---------------------------------------------------------------- ISDF (K4)
-// Greedy pivoted Cholesky of the implicit Hadamard Gram matrix (row-major
-// inputs phi_rm N_g x nep, gt_rm N_g x r; factor L row-major N_g x ldl);
-// forced (dev, nmu_max entries) replaces the argmax by the given pivots.
-hipError_t isdf_pivoted_cholesky(int ng, int nep, int r, const double *phi_rm, const double *gt_rm,
-                                 int nmu_max, double tol, double *L, int ldl, double *diag,
-                                 int *sel_dev, const int *forced, int *nmu_out_host,
-                                 void *scratch, hipStream_t s);
+// Greedy pivoted Cholesky of the implicit Hadamard Gram matrix (column-major
+// inputs phi N_g x n_e and gt N_g x r, leading dimension N_g; factor L
+// column-major N_g x nmu_max, leading dimension N_g); forced (dev, nmu_max
+// entries) replaces the argmax by the given pivots.
+hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const double *gt,
+                                 int nmu_max, double tol, double *L, double *diag, int *sel_dev,
+                                 const int *forced, int *nmu_out_host, void *scratch, hipStream_t s);
 size_t isdf_scratch_bytes(int ng);
-// Linv = L11^{-1} for L11(i, :) = L_rm(sel[i], 0..i) (row-major factor, leading dimension ldl).
-hipError_t launch_tri_inverse_rows(int n, const int *sel, const double *L, int ldl, double *Linv,
-                                  hipStream_t s);
-hipError_t launch_gather_lower(int n, const int *sel, const double *L, int ldl, double *L11,
-                               hipStream_t s);
+// Order n2 >= n (32 times a power of two) of the padded inverse below.
+int tri_inverse_order(int n);
+// X (n2 x n2, leading dimension n2) = [L11 0; 0 I]^{-1} for L11(i, j) = L(sel[i], j),
+// j <= i (L column-major, leading dimension ng); T: n2 * n2 / 4 doubles of scratch.
+hipError_t launch_isdf_l11_inverse(int n, const int *sel, const double *L, int ng, double *X, double *T,
+                                   hipStream_t s);
 
 // ---------------------------------------------------------------- dense FP64
 // Solve A X = B in place (A n x n, B n x nrhs) by Gauss-Jordan with partial pivoting.
 hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, int ldb,
                               int *piv_scratch, hipStream_t s);
 // A X = B (A n x n, B n x nrhs, column-major, both overwritten: B <- X) by a
-// blocked LU with partial pivoting; piv: device scratch of n ints.  Falls back
-// to Gauss-Jordan above 576 unknowns.
-hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *piv, hipStream_t s);
+// blocked LU with partial pivoting; pinfo: device scratch of lu_pinfo_ints(n)
+// ints.  B = A + n lda with ldb = lda lets one GEMM update both.  Falls back to
+// Gauss-Jordan above 1024 unknowns.
+size_t lu_pinfo_ints(int n);
+hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *pinfo, hipStream_t s);
 // Symmetric eigenvalues (cyclic Jacobi), A overwritten; eig sorted ascending;
 // work holds n + 2 doubles + n + 2 ints.
 hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s);

@@ -26,15 +26,21 @@ namespace {
 
 inline unsigned nblk(long long tot, int b) { return (unsigned)((tot + b - 1) / b); }
 
-// The ISDF kernels work on row-major data: phi_rm (N_g x nep), gt_rm (N_g x r)
-// and L_rm (N_g x ldl), so that one grid row is contiguous.  A wave handles 4
-// rows with 16 lanes per row; dot products over orbitals, sketch columns and
-// previous pivots are split over the 16 lanes and reduced by shuffles in a
-// fixed order.  Each block leaves its best remaining diagonal entry as a
-// candidate (value, row); every block of the next step reduces the candidates
-// itself, so one launch per pivot suffices.
-constexpr int ISDF_NT = 256;
-constexpr int ISDF_ROWS = ISDF_NT / 16;   // rows per block
+// The ISDF kernels read column-major data with leading dimension N_g: Phi
+// (N_g x n_e), G~ (N_g x r) and the factor L (N_g x N_mu; step k writes column
+// k), so that 16 consecutive grid rows of one column form one 128-byte segment.
+// A block owns 16 grid rows; its 512 threads form 32 streams of 16 lanes, and
+// stream s takes the columns s, s + 32, ... of each of the three dot products
+// of a step, summed over the streams afterwards in a fixed order.  The pivot
+// row's entries are staged in LDS.  Each block leaves its best remaining
+// diagonal entry as a candidate (value, row); every block of the next step
+// reduces the candidates itself, so one launch per pivot suffices.  Block b
+// owns the same rows at every step, so it re-reads its slice of Phi, G~ and L
+// on the same XCD.
+constexpr int ISDF_NT = 512;
+constexpr int ISDF_ROWS = 16;
+constexpr int ISDF_NS = ISDF_NT / ISDF_ROWS;   // column streams per block
+constexpr int ISDF_VCH = 4096;                 // pivot-row entries staged per pass
 
 struct Cand {
     double v;
@@ -42,50 +48,92 @@ struct Cand {
     int pad;
 };
 
-__device__ __forceinline__ double sum16(double v) {
-#pragma unroll
-    for (int m = 8; m > 0; m >>= 1) v += __shfl_xor(v, m, 16);
-    return v;
-}
-
 __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
     return v > bv || (v == bv && i < bi);
 }
 
-// Block-level candidate of the rows owned by this block (LDS reduction).
-__device__ void block_candidate(double v, int i, Cand *out) {
-    __shared__ double sv[ISDF_ROWS];
-    __shared__ int si[ISDF_ROWS];
-    const int t = threadIdx.x;
-    if ((t & 15) == 0) { sv[t >> 4] = v; si[t >> 4] = i; }
-    __syncthreads();
-    if (t == 0) {
-        double bv = sv[0];
-        int bi = si[0];
-        for (int k = 1; k < ISDF_ROWS; ++k)
-            if (better(sv[k], si[k], bv, bi)) { bv = sv[k]; bi = si[k]; }
-        out[blockIdx.x].v = bv;
-        out[blockIdx.x].i = bi;
+// Best (value, row) over threads 0..15 (the block's rows); thread 0 writes it.
+__device__ __forceinline__ void block_candidate16(double v, int i, Cand *out) {
+    if (threadIdx.x < 64) {
+#pragma unroll
+        for (int m = 8; m > 0; m >>= 1) {
+            const double ov = __shfl_xor(v, m, 16);
+            const int oi = __shfl_xor(i, m, 16);
+            if (better(ov, oi, v, i)) {
+                v = ov;
+                i = oi;
+            }
+        }
+        if (threadIdx.x == 0) {
+            out[blockIdx.x].v = v;
+            out[blockIdx.x].i = i;
+        }
     }
 }
 
-// diag(alpha) = |phi(alpha,:)|^2 |G~(alpha,:)|^2 and the first candidates.
-__global__ __launch_bounds__(ISDF_NT) void isdf_init_kernel(int ng, int nep, int r,
-                                                            const double *phi_rm, const double *gt_rm,
-                                                            double *diag, Cand *cand) {
-    const int t = threadIdx.x;
-    const int l16 = t & 15;
-    const int a = blockIdx.x * ISDF_ROWS + (t >> 4);
-    double s1 = 0.0, s2 = 0.0;
-    if (a < ng) {
-        for (int i = l16; i < nep; i += 16) { const double v = phi_rm[(long long)a * nep + i]; s1 += v * v; }
-        for (int j = l16; j < r; j += 16) { const double v = gt_rm[(long long)a * r + j]; s2 += v * v; }
+// sum_j col0[j ng] v[j] over this stream's columns j = st, st + 32, ... < n
+// (four independent accumulators, combined in a fixed order).
+__device__ __forceinline__ double stream_dot(const double *col0, int ng, const double *v, int n, int st) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = st;
+    for (; j + 3 * ISDF_NS < n; j += 4 * ISDF_NS) {
+        a0 += col0[(long long)j * ng] * v[j];
+        a1 += col0[(long long)(j + ISDF_NS) * ng] * v[j + ISDF_NS];
+        a2 += col0[(long long)(j + 2 * ISDF_NS) * ng] * v[j + 2 * ISDF_NS];
+        a3 += col0[(long long)(j + 3 * ISDF_NS) * ng] * v[j + 3 * ISDF_NS];
     }
-    s1 = sum16(s1);
-    s2 = sum16(s2);
-    const double d = s1 * s2;
-    if (a < ng && l16 == 0) diag[a] = d;
-    block_candidate(a < ng ? d : -2.0, a < ng ? a : 0x7fffffff, cand);
+    for (; j < n; j += ISDF_NS) a0 += col0[(long long)j * ng] * v[j];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// Row a's dot product with row p over the n columns of M (column-major, ld ng),
+// this stream's share: the pivot row is staged in LDS ISDF_VCH entries at a time.
+__device__ double stream_row_dot(const double *M, int ng, int n, int p, long long a, int st, double *vp) {
+    double acc = 0.0;
+    for (int c0 = 0; c0 < n; c0 += ISDF_VCH) {
+        const int cn = min(ISDF_VCH, n - c0);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cn; j += ISDF_NT) vp[j] = M[p + (long long)(c0 + j) * ng];
+        __syncthreads();
+        acc += stream_dot(M + a + (long long)c0 * ng, ng, vp, cn, st);
+    }
+    return acc;
+}
+
+// diag(alpha) = |phi(alpha,:)|^2 |G~(alpha,:)|^2 and the first candidates.
+__global__ __launch_bounds__(ISDF_NT) void isdf_init_kernel(int ng, int ne, int r, const double *phi,
+                                                            const double *gt, double *diag, Cand *cand) {
+    __shared__ double red[2][ISDF_NT];
+    const int t = threadIdx.x, st = t / ISDF_ROWS;
+    const int a = blockIdx.x * ISDF_ROWS + t % ISDF_ROWS;
+    const long long ac = a < ng ? a : ng - 1;
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = st; i < ne; i += ISDF_NS) {
+        const double v = phi[ac + (long long)i * ng];
+        s1 += v * v;
+    }
+    for (int j = st; j < r; j += ISDF_NS) {
+        const double v = gt[ac + (long long)j * ng];
+        s2 += v * v;
+    }
+    red[0][t] = s1;
+    red[1][t] = s2;
+    __syncthreads();
+    double d = -2.0;
+    int idx = 0x7fffffff;
+    if (t < ISDF_ROWS) {
+        double a1 = 0.0, a2 = 0.0;
+        for (int k = 0; k < ISDF_NS; ++k) {
+            a1 += red[0][k * ISDF_ROWS + t];
+            a2 += red[1][k * ISDF_ROWS + t];
+        }
+        if (a < ng) {
+            d = a1 * a2;
+            diag[a] = d;
+            idx = a;
+        }
+    }
+    block_candidate16(d, idx, cand);
 }
 
 // Step k of the greedy pivoted Cholesky of K = (Phi Phi^T) o (G~ G~^T):
@@ -93,13 +141,15 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_init_kernel(int ng, int nep, int
 //   L(a,k) = (K(a,p) - sum_{j<k} L(a,j) L(p,j)) / sqrt(diag(p)), diag(a) -= L(a,k)^2.
 // state[0] = accepted pivots, state[1] = stopped; dvals[0] = first pivot value.
 __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
-    int ng, int nep, int r, int k, int nblk, const double *phi_rm, const double *gt_rm, double *L,
-    int ldl, double *diag, int *sel, const int *forced, double tol2, int *state, double *dvals,
+    int ng, int ne, int r, int k, int nblk, const double *phi, const double *gt, double *L,
+    double *diag, int *sel, const int *forced, double tol2, int *state, double *dvals,
     const Cand *cand_in, Cand *cand_out) {
-    __shared__ double s_piv;
-    __shared__ int s_p, s_stop;
+    __shared__ double vp[ISDF_VCH];
+    __shared__ double red[3][ISDF_NT];
     __shared__ double rv[ISDF_NT];
     __shared__ int ri[ISDF_NT];
+    __shared__ double s_piv;
+    __shared__ int s_p, s_stop;
     const int t = threadIdx.x;
     const int stopped = state[1];
     if (!forced && !stopped) {
@@ -107,12 +157,18 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
         double bv = -2.0;
         int bi = 0x7fffffff;
         for (int b = t; b < nblk; b += ISDF_NT)
-            if (better(cand_in[b].v, cand_in[b].i, bv, bi)) { bv = cand_in[b].v; bi = cand_in[b].i; }
+            if (better(cand_in[b].v, cand_in[b].i, bv, bi)) {
+                bv = cand_in[b].v;
+                bi = cand_in[b].i;
+            }
         rv[t] = bv;
         ri[t] = bi;
         __syncthreads();
         for (int w = ISDF_NT / 2; w > 0; w >>= 1) {
-            if (t < w && better(rv[t + w], ri[t + w], rv[t], ri[t])) { rv[t] = rv[t + w]; ri[t] = ri[t + w]; }
+            if (t < w && better(rv[t + w], ri[t + w], rv[t], ri[t])) {
+                rv[t] = rv[t + w];
+                ri[t] = ri[t + w];
+            }
             __syncthreads();
         }
     }
@@ -147,63 +203,63 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
     __syncthreads();
     if (s_stop) return;
     const int p = s_p;
-    const double rsq = 1.0 / sqrt(s_piv);
-    const int l16 = t & 15;
-    const int a = blockIdx.x * ISDF_ROWS + (t >> 4);
-    const int ac = a < ng ? a : ng - 1;
-    double s1 = 0.0, s2 = 0.0, y = 0.0;
-    for (int i = l16; i < nep; i += 16) s1 += phi_rm[(long long)ac * nep + i] * phi_rm[(long long)p * nep + i];
-    for (int j = l16; j < r; j += 16) s2 += gt_rm[(long long)ac * r + j] * gt_rm[(long long)p * r + j];
-    for (int j = l16; j < k; j += 16) y += L[(long long)ac * ldl + j] * L[(long long)p * ldl + j];
-    s1 = sum16(s1);
-    s2 = sum16(s2);
-    y = sum16(y);
+    const int st = t / ISDF_ROWS;
+    const int a = blockIdx.x * ISDF_ROWS + t % ISDF_ROWS;
+    const long long ac = a < ng ? a : ng - 1;
+    red[0][t] = stream_row_dot(phi, ng, ne, p, ac, st, vp);
+    red[1][t] = stream_row_dot(gt, ng, r, p, ac, st, vp);
+    red[2][t] = stream_row_dot(L, ng, k, p, ac, st, vp);
+    __syncthreads();
     double dnew = -2.0;
-    if (a < ng) {
-        const double lk = (s1 * s2 - y) * rsq;
-        dnew = (a == p) ? -1.0 : diag[a] - lk * lk;
-        if (l16 == 0) {
-            L[(long long)a * ldl + k] = lk;
-            diag[a] = dnew;
+    int idx = 0x7fffffff;
+    if (t < ISDF_ROWS && a < ng) {
+        double s1 = 0.0, s2 = 0.0, y = 0.0;
+        for (int q = 0; q < ISDF_NS; ++q) {
+            s1 += red[0][q * ISDF_ROWS + t];
+            s2 += red[1][q * ISDF_ROWS + t];
+            y += red[2][q * ISDF_ROWS + t];
         }
+        const double lk = (s1 * s2 - y) / sqrt(s_piv);
+        dnew = (a == p) ? -1.0 : diag[a] - lk * lk;
+        L[a + (long long)k * ng] = lk;
+        diag[a] = dnew;
+        idx = a;
     }
-    block_candidate(dnew, a < ng ? a : 0x7fffffff, cand_out);
+    block_candidate16(dnew, idx, cand_out);
 }
 
-// L11(i, j) = L(sel[i], j) for j <= i, 0 above the diagonal (L row-major, ld ldl).
-__global__ void gather_lower_kernel(int n, const int *sel, const double *L, int ldl, double *L11) {
-    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)n * n) return;
-    int i = (int)(idx % n);
-    int j = (int)(idx / n);
-    L11[idx] = (j <= i) ? L[(long long)sel[i] * ldl + j] : 0.0;
+// X (n2 x n2, column-major) = [L11 0; 0 I] with L11(i, j) = L(sel[i], j) for
+// j <= i and 0 above the diagonal (L column-major, leading dimension ng).
+__global__ void gather_l11_kernel(int n, int n2, const int *sel, const double *L, int ng, double *X) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)n2 * n2) return;
+    const int i = (int)(idx % n2);
+    const int j = (int)(idx / n2);
+    double v;
+    if (i < n && j < n) v = (j <= i) ? L[sel[i] + (long long)j * ng] : 0.0;
+    else v = (i == j) ? 1.0 : 0.0;
+    X[idx] = v;
 }
 
-// Inverse of the lower-triangular L11 (row i = L_rm(sel[i], 0..i)), one wave per
-// column j:  x_j = 1 / L_jj,  x_i = -(sum_{l=j}^{i-1} L_il x_l) / L_ii.  Each dot
-// product is split over the 64 lanes (contiguous row of L) and reduced by
-// shuffles in a fixed order; x lives in LDS.
-constexpr int TRI_MAX = 4096;
-__global__ __launch_bounds__(64) void tri_inverse_rows_kernel(int n, const int *sel, const double *L,
-                                                              int ldl, double *X) {
-    __shared__ double x[TRI_MAX];
-    const int j = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int i = lane; i < n; i += 64) x[i] = 0.0;
+// In place inverse of every 32 x 32 lower-triangular diagonal block of X
+// (one workgroup per block, one thread per column, forward substitution in LDS).
+constexpr int TRI_B = 32;
+__global__ __launch_bounds__(TRI_B) void tri_diag_inverse_kernel(int n2, double *X) {
+    __shared__ double A[TRI_B][TRI_B + 1];
+    const int c = threadIdx.x;
+    double *blk = X + (long long)blockIdx.x * TRI_B * (n2 + 1);
+    for (int i = 0; i < TRI_B; ++i) A[i][c] = blk[i + (long long)c * n2];
     __syncthreads();
-    const double *Lj = L + (long long)sel[j] * ldl;
-    if (lane == 0) x[j] = 1.0 / Lj[j];
-    __syncthreads();
-    for (int i = j + 1; i < n; ++i) {
-        const double *Li = L + (long long)sel[i] * ldl;
-        double sacc = 0.0;
-        for (int l = j + lane; l < i; l += 64) sacc += Li[l] * x[l];
+    double x[TRI_B];
 #pragma unroll
-        for (int m = 32; m > 0; m >>= 1) sacc += __shfl_xor(sacc, m, 64);
-        if (lane == 0) x[i] = -sacc / Li[i];
-        __syncthreads();
+    for (int i = 0; i < TRI_B; ++i) {
+        double sacc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = 0; l < i; ++l) sacc -= A[i][l] * x[l];
+        x[i] = (i < c) ? 0.0 : sacc / A[i][i];
     }
-    for (int i = lane; i < n; i += 64) X[i + (long long)j * n] = x[i];
+#pragma unroll
+    for (int i = 0; i < TRI_B; ++i) blk[i + (long long)c * n2] = x[i];
 }
 
 // ------------------------------------------------------------ Gauss-Jordan
@@ -385,10 +441,9 @@ __global__ void dynmat_assemble_kernel(int np, int dim, const double *Phi, const
 
 }  // namespace
 
-hipError_t isdf_pivoted_cholesky(int ng, int nep, int r, const double *phi_rm, const double *gt_rm,
-                                 int nmu_max, double tol, double *L, int ldl, double *diag,
-                                 int *sel_dev, const int *forced, int *nmu_out_host, void *scratch,
-                                 hipStream_t s) {
+hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const double *gt,
+                                 int nmu_max, double tol, double *L, double *diag, int *sel_dev,
+                                 const int *forced, int *nmu_out_host, void *scratch, hipStream_t s) {
     // scratch: int state[2] | pad | double dvals[2] | Cand[2][nblk]
     const int nblk = (ng + ISDF_ROWS - 1) / ISDF_ROWS;
     int *state = (int *)scratch;
@@ -397,13 +452,12 @@ hipError_t isdf_pivoted_cholesky(int ng, int nep, int r, const double *phi_rm, c
     Cand *c1 = c0 + nblk;
     hipError_t e = hipMemsetAsync(state, 0, 2 * sizeof(int), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(isdf_init_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, nep, r, phi_rm, gt_rm,
-                       diag, c0);
+    hipLaunchKernelGGL(isdf_init_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, phi, gt, diag, c0);
     const double tol2 = tol * tol;
     for (int k = 0; k < nmu_max; ++k) {
-        hipLaunchKernelGGL(isdf_step_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, nep, r, k, nblk,
-                           phi_rm, gt_rm, L, ldl, diag, sel_dev, forced, tol2, state, dvals,
-                           (k & 1) ? c1 : c0, (k & 1) ? c0 : c1);
+        hipLaunchKernelGGL(isdf_step_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, k, nblk, phi,
+                           gt, L, diag, sel_dev, forced, tol2, state, dvals, (k & 1) ? c1 : c0,
+                           (k & 1) ? c0 : c1);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -421,199 +475,268 @@ size_t isdf_scratch_bytes(int ng) {
     return 32 + 2 * (size_t)nblk * sizeof(Cand);
 }
 
-hipError_t launch_tri_inverse_rows(int n, const int *sel, const double *L, int ldl, double *Linv,
-                                  hipStream_t s) {
-    if (n > TRI_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tri_inverse_rows_kernel, dim3(n), dim3(64), 0, s, n, sel, L, ldl, Linv);
-    return hipGetLastError();
+int tri_inverse_order(int n) {
+    int n2 = TRI_B;
+    while (n2 < n) n2 *= 2;
+    return n2;
 }
 
-hipError_t launch_gather_lower(int n, const int *sel, const double *L, int ldl, double *L11,
-                               hipStream_t s) {
-    long long tot = (long long)n * n;
-    hipLaunchKernelGGL(gather_lower_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, n, sel, L, ldl,
-                       L11);
-    return hipGetLastError();
+// Inverse of a lower-triangular matrix by blocks: the 32 x 32 diagonal blocks
+// are inverted directly, then pairs of inverted blocks are joined level by level,
+//     [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1}  C^{-1}],
+// two batched GEMMs per level (T = B A^{-1}, then B <- -C^{-1} T).
+hipError_t launch_isdf_l11_inverse(int n, const int *sel, const double *L, int ng, double *X, double *T,
+                                   hipStream_t s) {
+    const int n2 = tri_inverse_order(n);
+    const long long tot = (long long)n2 * n2;
+    hipLaunchKernelGGL(gather_l11_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, n, n2, sel, L, ng, X);
+    hipLaunchKernelGGL(tri_diag_inverse_kernel, dim3(n2 / TRI_B), dim3(TRI_B), 0, s, n2, X);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int sz = 2 * TRI_B; sz <= n2; sz *= 2) {
+        const int h = sz / 2, np = n2 / sz;
+        const long long sd = (long long)sz * (n2 + 1), st = (long long)h * h;
+        if ((e = gemm(Op::N, Op::N, h, h, h, 1.0, X + h, n2, sd, X, n2, sd, 0.0, T, h, st, np, s)) !=
+            hipSuccess)
+            return e;
+        if ((e = gemm(Op::N, Op::N, h, h, h, -1.0, X + h + (long long)h * n2, n2, sd, T, h, st, 0.0, X + h,
+                      n2, sd, np, s)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------ blocked LU solve
 // A X = B by a right-looking blocked LU with partial pivoting applied to the
 // augmented [A | B] (A n x n, B n x nrhs, column-major, in place): panels of
-// LU_NB columns are factored by one workgroup with the panel in LDS; their row
-// interchanges are applied to the other columns, the block row is solved with
-// the unit lower triangle, and the trailing matrix (and B) is updated by a GEMM
-// on the matrix cores.  Back substitution then proceeds by blocks.
+// LU_NB columns are factored by one workgroup that keeps one panel row per
+// thread in registers; the panel's row permutation is applied to the columns
+// right of it (and to B) together with the solve by its unit lower triangle,
+// and the trailing matrix and B are updated by a GEMM on the matrix cores.
+// Columns left of a panel are not permuted: B is eliminated along with A, so
+// the multipliers of earlier panels are never used again.  Back substitution
+// then proceeds by blocks.
 constexpr int LU_NB = 32;
-constexpr int LU_MAXM = 576;      // panel rows held in LDS (LU_MAXM x LU_NB doubles)
+constexpr int LU_MAXM = 1024;     // panel rows, one per thread
 constexpr int LU_NT = 1024;
+// Per-panel permutation record: position i < LU_NB of the permuted panel rows
+// holds original row top[i]; ndisp rows at or below LU_NB receive another row:
+// row dst[e] <- original row src[e] (panel-relative indices).
+constexpr int LU_PI_TOP = 0, LU_PI_ND = LU_NB, LU_PI_DST = LU_NB + 1, LU_PI_SRC = 2 * LU_NB + 1;
+constexpr int LU_PINFO = 4 * LU_NB;
 
-__global__ __launch_bounds__(LU_NT) void lu_panel_kernel(int m, int nb, double *A, int lda, int *piv) {
-    __shared__ double P[LU_MAXM * LU_NB];    // P[c * m + r]
-    __shared__ double wv[LU_NT / 64];
-    __shared__ int wi[LU_NT / 64];
-    __shared__ int s_p;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int i = t; i < m * nb; i += LU_NT) {
-        const int c = i / m, r = i % m;
-        P[i] = A[r + (long long)c * lda];
-    }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        // pivot: largest |P[r][j]|, r >= j, ties to the smallest row (m <= LU_NT:
-        // one row per thread, wave shuffles, then the 16 wave results)
-        double bv = -1.0;
-        int bi = 0x7fffffff;
-        if (t >= j && t < m) {
-            bv = fabs(P[j * m + t]);
-            bi = t;
-        }
+struct LuPanelShared {
+    double rows[2][2][LU_NB];   // [parity][row j | pivot row]
+    double wv[2][LU_NT / 64];
+    int wi[2][LU_NT / 64];
+    int idx[LU_MAXM];           // original row at each position of the permuted panel
+    int nd;
+};
+
+// Column J of the panel (static J, so the row stays in registers).
+template <int J>
+__device__ __forceinline__ void lu_panel_column(double (&P)[LU_NB], LuPanelShared &sh, int nb, bool own) {
+    if constexpr (J < LU_NB) {
+        const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+        if (J < nb) {
+            constexpr int par = J & 1;
+            // pivot: largest |P[r][J]|, r >= J, ties to the smallest row
+            double bv = -1.0;
+            int bi = 0x7fffffff;
+            if (own && t >= J) {
+                bv = fabs(P[J]);
+                bi = t;
+            }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(bv, o, 64);
-            const int oi = __shfl_xor(bi, o, 64);
-            if (ov > bv || (ov == bv && oi < bi)) {
-                bv = ov;
-                bi = oi;
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                sh.wv[par][wave] = bv;
+                sh.wi[par][wave] = bi;
+            }
+            __syncthreads();
+            double b = sh.wv[par][0];
+            int p = sh.wi[par][0];
+#pragma unroll
+            for (int w = 1; w < LU_NT / 64; ++w)
+                if (sh.wv[par][w] > b || (sh.wv[par][w] == b && sh.wi[par][w] < p)) {
+                    b = sh.wv[par][w];
+                    p = sh.wi[par][w];
+                }
+            if (t == J) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) sh.rows[par][0][c] = P[c];
+            }
+            if (t == p) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) sh.rows[par][1][c] = P[c];
+            }
+            if (t == 0) {
+                const int a = sh.idx[J];
+                sh.idx[J] = sh.idx[p];
+                sh.idx[p] = a;
+            }
+            __syncthreads();
+            if (p != J) {
+                if (t == J) {
+#pragma unroll
+                    for (int c = 0; c < LU_NB; ++c) P[c] = sh.rows[par][1][c];
+                } else if (t == p) {
+#pragma unroll
+                    for (int c = 0; c < LU_NB; ++c) P[c] = sh.rows[par][0][c];
+                }
+            }
+            if (own && t > J) {
+                const double l = P[J] / sh.rows[par][1][J];
+                P[J] = l;
+#pragma unroll
+                for (int c = J + 1; c < LU_NB; ++c) P[c] -= l * sh.rows[par][1][c];
             }
         }
-        if (lane == 0) {
-            wv[wave] = bv;
-            wi[wave] = bi;
-        }
-        __syncthreads();
-        if (t == 0) {
-            double b = wv[0];
-            int bi0 = wi[0];
-            for (int w = 1; w < LU_NT / 64; ++w)
-                if (wv[w] > b || (wv[w] == b && wi[w] < bi0)) {
-                    b = wv[w];
-                    bi0 = wi[w];
-                }
-            s_p = bi0;
-            piv[j] = bi0;
-        }
-        __syncthreads();
-        const int p = s_p;
-        // the pivot row's entries (after the swap) and the multipliers, from
-        // values read before any thread writes
-        const double piv_jj = P[j * m + p];
-        double lr = 0.0;
-        int r = -1;
-        if (t > j && t < m) {
-            r = t;
-            const int src = (r == p) ? j : r;           // row r after the swap
-            lr = P[j * m + src] / piv_jj;
-        }
-        __syncthreads();
-        if (t < nb && p != j) {
-            const double a = P[t * m + j];
-            P[t * m + j] = P[t * m + p];
-            P[t * m + p] = a;
-        }
-        __syncthreads();
-        if (r >= 0) {
-            P[j * m + r] = lr;
-            for (int c = j + 1; c < nb; ++c) P[c * m + r] -= lr * P[c * m + j];
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < m * nb; i += LU_NT) {
-        const int c = i / m, r = i % m;
-        A[r + (long long)c * lda] = P[i];
+        lu_panel_column<J + 1>(P, sh, nb, own);
     }
 }
 
-// Row interchanges of panel k0 (rows k0 + j <-> k0 + piv[j], in order) on every
-// column outside the panel, and on B.  One thread per column.
-__global__ void lu_swap_kernel(int n, int nrhs, int k0, int nb, const int *piv, double *A, int lda,
-                               double *B, int ldb) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n + nrhs) return;
-    if (c >= k0 && c < k0 + nb) return;
-    double *col = c < n ? A + (long long)c * lda : B + (long long)(c - n) * ldb;
-    for (int j = 0; j < nb; ++j) {
-        const int p = piv[j];
-        if (p != j) {
-            const double a = col[k0 + j];
-            col[k0 + j] = col[k0 + p];
-            col[k0 + p] = a;
-        }
-    }
-}
-
-// Block row k0: X = L11^{-1} X for the columns right of the panel and for B
-// (L11 unit lower, nb x nb, staged in LDS).  One thread per column.
-__global__ __launch_bounds__(64) void lu_trsm_lower_kernel(int n, int nrhs, int k0, int nb, const double *A,
-                                                           int lda, double *Aw, double *B, int ldb) {
-    __shared__ double L[LU_NB * LU_NB];
-    for (int i = threadIdx.x; i < LU_NB * LU_NB; i += 64) {
-        const int r = i % LU_NB, c = i / LU_NB;
-        L[r * LU_NB + c] = (r < nb && c < nb) ? A[(k0 + r) + (long long)(k0 + c) * lda] : 0.0;
+__global__ __launch_bounds__(LU_NT) void lu_panel_kernel(int m, int nb, double *A, int lda, int *pinfo) {
+    __shared__ LuPanelShared sh;
+    const int t = threadIdx.x;
+    const bool own = t < m;
+    double P[LU_NB];
+#pragma unroll
+    for (int c = 0; c < LU_NB; ++c) P[c] = (own && c < nb) ? A[t + (long long)c * lda] : 0.0;
+    if (own) sh.idx[t] = t;
+    if (t == 0) sh.nd = 0;
+    __syncthreads();
+    lu_panel_column<0>(P, sh, nb, own);
+#pragma unroll
+    for (int c = 0; c < LU_NB; ++c)
+        if (own && c < nb) A[t + (long long)c * lda] = P[c];
+    __syncthreads();
+    if (t < nb) pinfo[LU_PI_TOP + t] = sh.idx[t];
+    if (own && t >= nb && sh.idx[t] != t) {
+        const int e = atomicAdd(&sh.nd, 1);   // at most nb displaced rows
+        pinfo[LU_PI_DST + e] = t;
+        pinfo[LU_PI_SRC + e] = sh.idx[t];
     }
     __syncthreads();
+    if (t == 0) pinfo[LU_PI_ND] = sh.nd;
+}
+
+// col[0..nb) = x[0..nb) for nb <= LU_NB; a partial block goes through the
+// caller's LDS staging area (one column per thread).
+__device__ __forceinline__ void store_block(double *col, const double (&x)[LU_NB], int nb,
+                                            double (*stage)[64]) {
+    if (nb == LU_NB) {
+#pragma unroll
+        for (int i = 0; i < LU_NB; ++i) col[i] = x[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < LU_NB; ++i) stage[i][threadIdx.x] = x[i];
+        for (int i = 0; i < nb; ++i) col[i] = stage[i][threadIdx.x];
+    }
+}
+
+// Block row k0 for every column right of the panel and for B: the panel's row
+// permutation, then X = L11^{-1} X (L11 unit lower, staged in LDS).  One thread
+// per column; every read of a column precedes every write to it (displaced
+// rows pass through LDS).
+__global__ __launch_bounds__(64) void lu_rowblock_kernel(int n, int nrhs, int k0, int nb, double *A, int lda,
+                                                         double *B, int ldb, const int *pinfo) {
+    __shared__ double L[LU_NB][LU_NB + 1];
+    __shared__ double dv[LU_NB][64];
+    __shared__ int pi[LU_PINFO];
+    for (int i = threadIdx.x; i < LU_NB * LU_NB; i += 64) {
+        const int r = i % LU_NB, c = i / LU_NB;
+        L[r][c] = (r < nb && c < r) ? A[(k0 + r) + (long long)(k0 + c) * lda] : 0.0;
+    }
+    for (int i = threadIdx.x; i < LU_PINFO; i += 64) pi[i] = pinfo[i];
+    __syncthreads();
     const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncols = (n - k0 - nb) + nrhs;
-    if (c0 >= ncols) return;
-    double *col = c0 < n - k0 - nb ? Aw + (long long)(k0 + nb + c0) * lda : B + (long long)(c0 - (n - k0 - nb)) * ldb;
+    const int nright = n - k0 - nb;
+    if (c0 >= nright + nrhs) return;
+    double *col = c0 < nright ? A + (long long)(k0 + nb + c0) * lda : B + (long long)(c0 - nright) * ldb;
+    col += k0;
+    const int nd = pi[LU_PI_ND];
+    // (loads and stores of x without branches on nb: per-element branches make
+    // the register allocator spill x)
     double x[LU_NB];
 #pragma unroll
-    for (int i = 0; i < LU_NB; ++i) x[i] = i < nb ? col[k0 + i] : 0.0;
+    for (int i = 0; i < LU_NB; ++i) {
+        const double v = col[pi[LU_PI_TOP + (i < nb ? i : 0)]];
+        x[i] = i < nb ? v : 0.0;
+    }
+    for (int e = 0; e < nd; ++e) dv[e][threadIdx.x] = col[pi[LU_PI_SRC + e]];
+    for (int e = 0; e < nd; ++e) col[pi[LU_PI_DST + e]] = dv[e][threadIdx.x];
 #pragma unroll
     for (int i = 1; i < LU_NB; ++i) {
         double sacc = x[i];
 #pragma unroll
-        for (int j = 0; j < i; ++j) sacc -= L[i * LU_NB + j] * x[j];
+        for (int j = 0; j < i; ++j) sacc -= L[i][j] * x[j];
         x[i] = sacc;
     }
-    for (int i = 0; i < nb; ++i) col[k0 + i] = x[i];
+    store_block(col, x, nb, dv);
 }
 
 // Back substitution on block rows r0..r0+nb-1: X = U11^{-1} X for every column
 // of B (U11 staged in LDS).  One thread per column.
 __global__ __launch_bounds__(64) void lu_trsm_upper_kernel(int nrhs, int r0, int nb, const double *A, int lda,
                                                            double *B, int ldb) {
-    __shared__ double U[LU_NB * LU_NB];
+    __shared__ double U[LU_NB][LU_NB + 1];
+    __shared__ double stage[LU_NB][64];
     for (int i = threadIdx.x; i < LU_NB * LU_NB; i += 64) {
         const int r = i % LU_NB, c = i / LU_NB;
-        U[r * LU_NB + c] = (r < nb && c < nb) ? A[(r0 + r) + (long long)(r0 + c) * lda] : (r == c ? 1.0 : 0.0);
+        U[r][c] = (r < nb && c < nb) ? A[(r0 + r) + (long long)(r0 + c) * lda] : (r == c ? 1.0 : 0.0);
     }
     __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nrhs) return;
-    double *col = B + (long long)c * ldb;
+    double *col = B + (long long)c * ldb + r0;
     double x[LU_NB];
 #pragma unroll
-    for (int i = 0; i < LU_NB; ++i) x[i] = i < nb ? col[r0 + i] : 0.0;
+    for (int i = 0; i < LU_NB; ++i) {
+        const double v = col[i < nb ? i : 0];
+        x[i] = i < nb ? v : 0.0;
+    }
 #pragma unroll
     for (int i = LU_NB - 1; i >= 0; --i) {
         double sacc = x[i];
 #pragma unroll
-        for (int j = i + 1; j < LU_NB; ++j) sacc -= U[i * LU_NB + j] * x[j];
-        x[i] = sacc / U[i * LU_NB + i];
+        for (int j = i + 1; j < LU_NB; ++j) sacc -= U[i][j] * x[j];
+        x[i] = sacc / U[i][i];
     }
-    for (int i = 0; i < nb; ++i) col[r0 + i] = x[i];
+    store_block(col, x, nb, stage);
 }
 
-hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *piv, hipStream_t s) {
+size_t lu_pinfo_ints(int n) { return (size_t)((n + LU_NB - 1) / LU_NB) * LU_PINFO; }
+
+hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *pinfo, hipStream_t s) {
     if (n > LU_MAXM) return gauss_jordan_solve(n, nrhs, A, lda, B, ldb, nullptr, s);
     hipError_t e;
+    // B stored right after A with the same leading dimension: one GEMM updates both
+    const bool joint = B == A + (long long)n * lda && ldb == lda;
     for (int k0 = 0; k0 < n; k0 += LU_NB) {
         const int nb = std::min(LU_NB, n - k0), m = n - k0;
-        hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(LU_NT), 0, s, m, nb,
-                           A + k0 + (long long)k0 * lda, lda, piv + k0);
-        hipLaunchKernelGGL(lu_swap_kernel, dim3(nblk(n + nrhs, 256)), dim3(256), 0, s, n, nrhs, k0, nb,
-                           (const int *)(piv + k0), A, lda, B, ldb);
+        int *pi = pinfo + (size_t)(k0 / LU_NB) * LU_PINFO;
+        hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(LU_NT), 0, s, m, nb, A + k0 + (long long)k0 * lda,
+                           lda, pi);
         const int ncols = (n - k0 - nb) + nrhs;
-        hipLaunchKernelGGL(lu_trsm_lower_kernel, dim3(nblk(ncols, 64)), dim3(64), 0, s, n, nrhs, k0, nb,
-                           (const double *)A, lda, A, B, ldb);
+        hipLaunchKernelGGL(lu_rowblock_kernel, dim3(nblk(ncols, 64)), dim3(64), 0, s, n, nrhs, k0, nb, A, lda,
+                           B, ldb, (const int *)pi);
         const int mr = n - k0 - nb;
         if (mr > 0) {
-            if ((e = gemm(Op::N, Op::N, mr, mr, nb, -1.0, A + (k0 + nb) + (long long)k0 * lda, lda, 0,
+            const double *L21 = A + (k0 + nb) + (long long)k0 * lda;
+            if ((e = gemm(Op::N, Op::N, mr, joint ? mr + nrhs : mr, nb, -1.0, L21, lda, 0,
                           A + k0 + (long long)(k0 + nb) * lda, lda, 0, 1.0,
                           A + (k0 + nb) + (long long)(k0 + nb) * lda, lda, 0, 1, s)) != hipSuccess)
                 return e;
-            if ((e = gemm(Op::N, Op::N, mr, nrhs, nb, -1.0, A + (k0 + nb) + (long long)k0 * lda, lda, 0,
-                          B + k0, ldb, 0, 1.0, B + (k0 + nb), ldb, 0, 1, s)) != hipSuccess)
+            if (!joint && (e = gemm(Op::N, Op::N, mr, nrhs, nb, -1.0, L21, lda, 0, B + k0, ldb, 0, 1.0,
+                                    B + (k0 + nb), ldb, 0, 1, s)) != hipSuccess)
                 return e;
         }
     }
