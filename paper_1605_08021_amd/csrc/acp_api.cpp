@@ -231,7 +231,10 @@ acp_status vc_apply(acp_ctx *ctx, int n, const double *X, double *Y) {
     double *T = dp<double>(ctx->tmp3);
     const double *Fx = dp<double>(ctx->fx);
     // T = Fx^T X   (X viewed as nx x (ny n))
-    HIPCHK(gemm(Op::T, Op::N, nx, ny * n, nx, 1.0, Fx, nx, 0, X, nx, 0, 0.0, T, nx, 0, 1, s));
+    ENSURE(ctx->splitk, (size_t)4 * ng * n * 8);
+    double *wk = dp<double>(ctx->splitk);
+    const size_t wn = ctx->splitk.bytes / 8;
+    HIPCHK(gemm_splitk(Op::T, Op::N, nx, ny * n, nx, 1.0, Fx, nx, X, nx, 0.0, T, nx, wk, wn, s));
     if (ny > 1) {
         const double *Fy = dp<double>(ctx->fy);
         HIPCHK(gemm(Op::N, Op::N, nx, ny, ny, 1.0, T, nx, ng, Fy, ny, 0, 0.0, Y, nx, ng, n, s));
@@ -240,7 +243,7 @@ acp_status vc_apply(acp_ctx *ctx, int n, const double *X, double *Y) {
     } else {
         HIPCHK(launch_mul_symbol(ng, n, dp<double>(ctx->svc), T, s));
     }
-    HIPCHK(gemm(Op::N, Op::N, nx, ny * n, nx, 1.0, Fx, nx, 0, T, nx, 0, 0.0, Y, nx, 0, 1, s));
+    HIPCHK(gemm_splitk(Op::N, Op::N, nx, ny * n, nx, 1.0, Fx, nx, T, nx, 0.0, Y, nx, wk, wn, s));
     return ACP_OK;
 }
 
@@ -1860,7 +1863,9 @@ acp_status acp_dyson(acp_ctx *ctx, const double *G, int n_p, const double *omega
         // [T | S] side by side (one leading dimension) for the blocked LU
         ENSURE(ctx->dy_t, (size_t)nmu * (nmu + n_p) * 8);
         double *T = dp<double>(ctx->dy_t), *S = T + (size_t)nmu * nmu;
-        HIPCHK(gemm(Op::N, Op::N, nmu, nmu, ng, 1.0, Kp, nmu, 0, dp<double>(ctx->w), ng, 0, 0.0, T, nmu, 0, 1, s));
+        ENSURE(ctx->splitk, std::max((size_t)8 * nmu * nmu, (size_t)4 * ng * n_p) * 8);
+        HIPCHK(gemm_splitk(Op::N, Op::N, nmu, nmu, ng, 1.0, Kp, nmu, dp<double>(ctx->w), ng, 0.0, T, nmu,
+                           dp<double>(ctx->splitk), ctx->splitk.bytes / 8, s));
         HIPCHK(launch_add_identity_neg(nmu, T, nmu, s));
         HIPCHK(launch_gather_rows(nmu, n_p, dp<int>(ctx->sel_dev), G, ng, S, nmu, s));
         ENSURE(ctx->dy_piv, lu_pinfo_ints(nmu) * 4);
@@ -1868,8 +1873,8 @@ acp_status acp_dyson(acp_ctx *ctx, const double *G, int n_p, const double *omega
         // U^{k+1} = W S (into tmp1), G^{k+1} = G + v_c W S = G + v_c U^{k+1}
         ENSURE(ctx->tmp1, (size_t)ng * n_p * 8);
         double *Un = dp<double>(ctx->tmp1);
-        HIPCHK(gemm(Op::N, Op::N, ng, n_p, nmu, 1.0, dp<double>(ctx->w), ng, 0, S, nmu, 0, 0.0, Un,
-                    ng, 0, 1, s));
+        HIPCHK(gemm_splitk(Op::N, Op::N, ng, n_p, nmu, 1.0, dp<double>(ctx->w), ng, S, nmu, 0.0, Un, ng,
+                           dp<double>(ctx->splitk), ctx->splitk.bytes / 8, s));
         CHECK(vc_apply(ctx, n_p, Un, Gk));
         HIPCHK(launch_axpby(ng, n_p, 1.0, G, ng, 1.0, Gk, ng, s));
         // relative change ||U^{k+1} - U^k|| / ||U^{k+1}||

@@ -26,6 +26,39 @@ namespace {
 
 inline unsigned nblk(long long tot, int b) { return (unsigned)((tot + b - 1) / b); }
 
+// One step of a wave-wide argmax (largest value, ties to the smallest index)
+// with the partner lane chosen by a DPP control; lanes outside row_mask keep
+// their own pair.
+template <int CTRL, int ROWM>
+__device__ __forceinline__ void argmax_dpp_step(double &v, int &i) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROWM, 0xf, false);
+    const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWM, 0xf, false);
+    const double ov = __hiloint2double(hi, lo);
+    if (ov > v || (ov == v && oi < i)) {
+        v = ov;
+        i = oi;
+    }
+}
+
+// Wave argmax, valid in lane 63: pairs within quads (quad_perm 1,0,3,2 and
+// 2,3,0,1), half rows (row_half_mirror), rows (row_mirror), then rows 0-1 and
+// 2-3 (row_bcast:15) and all four (row_bcast:31).
+__device__ __forceinline__ void wave_argmax(double &v, int &i) {
+    argmax_dpp_step<0xB1, 0xf>(v, i);
+    argmax_dpp_step<0x4E, 0xf>(v, i);
+    argmax_dpp_step<0x141, 0xf>(v, i);
+    argmax_dpp_step<0x140, 0xf>(v, i);
+    argmax_dpp_step<0x142, 0xa>(v, i);
+    argmax_dpp_step<0x143, 0xc>(v, i);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+
 // The ISDF kernels read column-major data with leading dimension N_g: Phi
 // (N_g x n_e), G~ (N_g x r) and the factor L (N_g x N_mu; step k writes column
 // k), so that 16 consecutive grid rows of one column form one 128-byte segment.
@@ -146,69 +179,59 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
     const Cand *cand_in, Cand *cand_out) {
     __shared__ double vp[ISDF_VCH];
     __shared__ double red[3][ISDF_NT];
-    __shared__ double rv[ISDF_NT];
-    __shared__ int ri[ISDF_NT];
-    __shared__ double s_piv;
-    __shared__ int s_p, s_stop;
     const int t = threadIdx.x;
-    const int stopped = state[1];
-    if (!forced && !stopped) {
-        // every block reduces the previous step's candidates (fixed tree order)
-        double bv = -2.0;
-        int bi = 0x7fffffff;
-        for (int b = t; b < nblk; b += ISDF_NT)
-            if (better(cand_in[b].v, cand_in[b].i, bv, bi)) {
-                bv = cand_in[b].v;
-                bi = cand_in[b].i;
+    if (state[1]) return;   // stopped at an earlier step
+    // the pivot: every wave reduces the previous step's candidates itself
+    // (same order in every wave, so every thread holds the same pivot)
+    double bv = -2.0;
+    int bi = 0x7fffffff;
+    if (forced) {
+        bi = forced[k];
+        bv = diag[bi];
+    } else {
+        for (int b = t & 63; b < nblk; b += 64) {
+            const Cand c = cand_in[b];
+            if (better(c.v, c.i, bv, bi)) {
+                bv = c.v;
+                bi = c.i;
             }
-        rv[t] = bv;
-        ri[t] = bi;
-        __syncthreads();
-        for (int w = ISDF_NT / 2; w > 0; w >>= 1) {
-            if (t < w && better(rv[t + w], ri[t + w], rv[t], ri[t])) {
-                rv[t] = rv[t + w];
-                ri[t] = ri[t + w];
-            }
-            __syncthreads();
+        }
+        wave_argmax(bv, bi);
+        bv = readlane_f64(bv, 63);
+        bi = __builtin_amdgcn_readlane(bi, 63);
+    }
+    const bool stop = !(bv > 0.0) || (!forced && tol2 > 0.0 && k > 0 && bv < tol2 * dvals[0]);
+    if (blockIdx.x == 0 && t == 0) {
+        if (stop) {
+            state[1] = 1;
+        } else {
+            sel[k] = bi;
+            state[0] = k + 1;
+            if (k == 0) dvals[0] = bv;
         }
     }
-    if (t == 0) {
-        int stop = stopped;
-        double bv = -2.0;
-        int bi = 0x7fffffff;
-        if (!stop) {
-            if (forced) {
-                bi = forced[k];
-                bv = diag[bi];
-            } else {
-                bv = rv[0];
-                bi = ri[0];
-            }
-            if (!(bv > 0.0)) stop = 1;
-            if (!forced && tol2 > 0.0 && k > 0 && bv < tol2 * dvals[0]) stop = 1;
-        }
-        s_piv = bv;
-        s_p = bi;
-        s_stop = stop;
-        if (blockIdx.x == 0) {
-            if (stop) {
-                state[1] = 1;
-            } else {
-                sel[k] = bi;
-                state[0] = k + 1;
-                if (k == 0) dvals[0] = bv;
-            }
-        }
-    }
-    __syncthreads();
-    if (s_stop) return;
-    const int p = s_p;
+    if (stop) return;
+    const int p = bi;
     const int st = t / ISDF_ROWS;
     const int a = blockIdx.x * ISDF_ROWS + t % ISDF_ROWS;
     const long long ac = a < ng ? a : ng - 1;
-    red[0][t] = stream_row_dot(phi, ng, ne, p, ac, st, vp);
-    red[1][t] = stream_row_dot(gt, ng, r, p, ac, st, vp);
-    red[2][t] = stream_row_dot(L, ng, k, p, ac, st, vp);
+    if (ne + r + k <= ISDF_VCH) {
+        // one staging pass: vp = [phi(p,:) | G~(p,:) | L(p, 0..k-1)]
+        for (int j = t; j < ne + r + k; j += ISDF_NT) {
+            const double *src = j < ne ? phi + (long long)j * ng
+                                : j < ne + r ? gt + (long long)(j - ne) * ng
+                                             : L + (long long)(j - ne - r) * ng;
+            vp[j] = src[p];
+        }
+        __syncthreads();
+        red[0][t] = stream_dot(phi + ac, ng, vp, ne, st);
+        red[1][t] = stream_dot(gt + ac, ng, vp + ne, r, st);
+        red[2][t] = stream_dot(L + ac, ng, vp + ne + r, k, st);
+    } else {
+        red[0][t] = stream_row_dot(phi, ng, ne, p, ac, st, vp);
+        red[1][t] = stream_row_dot(gt, ng, r, p, ac, st, vp);
+        red[2][t] = stream_row_dot(L, ng, k, p, ac, st, vp);
+    }
     __syncthreads();
     double dnew = -2.0;
     int idx = 0x7fffffff;
@@ -219,7 +242,7 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
             s2 += red[1][q * ISDF_ROWS + t];
             y += red[2][q * ISDF_ROWS + t];
         }
-        const double lk = (s1 * s2 - y) / sqrt(s_piv);
+        const double lk = (s1 * s2 - y) / sqrt(bv);
         dnew = (a == p) ? -1.0 : diag[a] - lk * lk;
         L[a + (long long)k * ng] = lk;
         diag[a] = dnew;
@@ -533,9 +556,10 @@ struct LuPanelShared {
     int nd;
 };
 
-// Column J of the panel (static J, so the row stays in registers).
+// Column J of the panel (static J, so the row stays in registers); the block
+// has nw waves.
 template <int J>
-__device__ __forceinline__ void lu_panel_column(double (&P)[LU_NB], LuPanelShared &sh, int nb, bool own) {
+__device__ __forceinline__ void lu_panel_column(double (&P)[LU_NB], LuPanelShared &sh, int nb, bool own, int nw) {
     if constexpr (J < LU_NB) {
         const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
         if (J < nb) {
@@ -547,24 +571,15 @@ __device__ __forceinline__ void lu_panel_column(double (&P)[LU_NB], LuPanelShare
                 bv = fabs(P[J]);
                 bi = t;
             }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(bv, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ov > bv || (ov == bv && oi < bi)) {
-                    bv = ov;
-                    bi = oi;
-                }
-            }
-            if (lane == 0) {
+            wave_argmax(bv, bi);
+            if (lane == 63) {
                 sh.wv[par][wave] = bv;
                 sh.wi[par][wave] = bi;
             }
             __syncthreads();
             double b = sh.wv[par][0];
             int p = sh.wi[par][0];
-#pragma unroll
-            for (int w = 1; w < LU_NT / 64; ++w)
+            for (int w = 1; w < nw; ++w)
                 if (sh.wv[par][w] > b || (sh.wv[par][w] == b && sh.wi[par][w] < p)) {
                     b = sh.wv[par][w];
                     p = sh.wi[par][w];
@@ -599,7 +614,7 @@ __device__ __forceinline__ void lu_panel_column(double (&P)[LU_NB], LuPanelShare
                 for (int c = J + 1; c < LU_NB; ++c) P[c] -= l * sh.rows[par][1][c];
             }
         }
-        lu_panel_column<J + 1>(P, sh, nb, own);
+        lu_panel_column<J + 1>(P, sh, nb, own, nw);
     }
 }
 
@@ -613,7 +628,7 @@ __global__ __launch_bounds__(LU_NT) void lu_panel_kernel(int m, int nb, double *
     if (own) sh.idx[t] = t;
     if (t == 0) sh.nd = 0;
     __syncthreads();
-    lu_panel_column<0>(P, sh, nb, own);
+    lu_panel_column<0>(P, sh, nb, own, (int)(blockDim.x >> 6));
 #pragma unroll
     for (int c = 0; c < LU_NB; ++c)
         if (own && c < nb) A[t + (long long)c * lda] = P[c];
@@ -723,7 +738,7 @@ hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int
     for (int k0 = 0; k0 < n; k0 += LU_NB) {
         const int nb = std::min(LU_NB, n - k0), m = n - k0;
         int *pi = pinfo + (size_t)(k0 / LU_NB) * LU_PINFO;
-        hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(LU_NT), 0, s, m, nb, A + k0 + (long long)k0 * lda,
+        hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3((m + 63) / 64 * 64), 0, s, m, nb, A + k0 + (long long)k0 * lda,
                            lda, pi);
         const int ncols = (n - k0 - nb) + nrhs;
         hipLaunchKernelGGL(lu_rowblock_kernel, dim3(nblk(ncols, 64)), dim3(64), 0, s, n, nrhs, k0, nb, A, lda,

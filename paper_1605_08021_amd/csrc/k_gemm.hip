@@ -190,24 +190,28 @@ __global__ void splitk_reduce_kernel(int m, int n, int nsplit, const double *W, 
 hipError_t gemm_splitk(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
                        const double *B, int ldb, double beta, double *C, int ldc, double *work,
                        size_t work_elems, hipStream_t s) {
-    // split so that the grid has >= ~256 workgroups; each slice handles a multiple of 64 of K
+    // split so that the grid has >= ~512 workgroups; each slice handles a multiple
+    // of 64 of K.  The slices of equal length run as one batched launch (batch
+    // index = slice), a shorter last slice as a second launch.
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
-    int nsplit = (256 + tiles - 1) / tiles;
+    int nsplit = (512 + tiles - 1) / tiles;
     const int kmax_split = (k + 63) / 64;
     if (nsplit > kmax_split) nsplit = kmax_split;
     while (nsplit > 1 && (size_t)nsplit * m * n > work_elems) --nsplit;
     if (nsplit <= 1)
         return gemm(ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, s);
     const int kc = ((k + nsplit - 1) / nsplit + 63) / 64 * 64;
-    nsplit = (k + kc - 1) / kc;
-    hipError_t e;
-    for (int sidx = 0; sidx < nsplit; ++sidx) {
-        const int k0 = sidx * kc;
-        const int kk = (k - k0) < kc ? (k - k0) : kc;
-        const double *As = (ta == Op::N) ? A + (long long)k0 * lda : A + k0;
-        const double *Bs = (tb == Op::N) ? B + k0 : B + (long long)k0 * ldb;
-        e = gemm(ta, tb, m, n, kk, 1.0, As, lda, 0, Bs, ldb, 0, 0.0, work + (size_t)sidx * m * n, m,
-                 0, 1, s);
+    const int nfull = k / kc;
+    const int rem = k - nfull * kc;
+    nsplit = nfull + (rem > 0 ? 1 : 0);
+    const long long sa = (ta == Op::N) ? (long long)kc * lda : kc;
+    const long long sb = (tb == Op::N) ? kc : (long long)kc * ldb;
+    const long long sc = (long long)m * n;
+    hipError_t e = gemm(ta, tb, m, n, kc, 1.0, A, lda, sa, B, ldb, sb, 0.0, work, m, sc, nfull, s);
+    if (e != hipSuccess) return e;
+    if (rem > 0) {
+        e = gemm(ta, tb, m, n, rem, 1.0, A + nfull * sa, lda, 0, B + nfull * sb, ldb, 0, 0.0,
+                 work + (size_t)nfull * m * n, m, 0, 1, s);
         if (e != hipSuccess) return e;
     }
     long long tot = (long long)m * n;
