@@ -152,6 +152,8 @@ struct MsArgsT {
     T *pa, *pb;             // ntiles tiles each
     double *gbuf;           // ntiles * 2 * K * slot doubles
     unsigned *cnt;          // ntiles counters, zero at launch
+    int sg;                 // lockstep: tiles t, t + ntiles/sg, ... share one barrier (<= 1: off)
+    int *active;            // lockstep: per super-group tiles not yet done, sg at launch
     int *abort_flag;        // set if a group barrier wait expired
     int *iters;             // [nshift][ntiles * 16]
     double *resid;

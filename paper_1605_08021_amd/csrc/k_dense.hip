@@ -478,9 +478,8 @@ hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const
     hipLaunchKernelGGL(isdf_init_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, phi, gt, diag, c0);
     const double tol2 = tol * tol;
     for (int k = 0; k < nmu_max; ++k) {
-        hipLaunchKernelGGL(isdf_step_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, k, nblk, phi,
-                           gt, L, diag, sel_dev, forced, tol2, state, dvals, (k & 1) ? c1 : c0,
-                           (k & 1) ? c0 : c1);
+        hipLaunchKernelGGL(isdf_step_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, k, nblk, phi, gt, L,
+                           diag, sel_dev, forced, tol2, state, dvals, (k & 1) ? c1 : c0, (k & 1) ? c0 : c1);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -39,11 +39,12 @@ constexpr int WS = kMsWindow;
 constexpr int KMAX = kMsMaxGroup;           // workgroups per tile
 
 struct GroupSync {
-    unsigned *cnt;      // per-tile counter (monotonic)
+    unsigned *cnt;      // barrier counter of this workgroup's (super-)group (monotonic)
     double *buf;        // per tile: [2 parities][K][slot]
     int slot;           // doubles per partial
     int K;
     int kg;
+    unsigned members;   // workgroups that arrive at every barrier (K, or K SG in lockstep)
     unsigned phase;     // number of completed group barriers
     bool local;         // every workgroup of the group runs on this XCD (one L2)
 };
@@ -80,15 +81,15 @@ __device__ bool group_sum(GroupSync &gs, int tile, double *dst, int n, int *abor
         // compute unit's L1 invalidated.  Otherwise the agent-scope
         // release/acquire pair.
         if (gs.local)
-            __hip_atomic_fetch_add(gs.cnt + tile, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gs.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         else
-            __hip_atomic_fetch_add(gs.cnt + tile, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = (gs.phase + 1) * (unsigned)gs.K;
+            __hip_atomic_fetch_add(gs.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (gs.phase + 1) * gs.members;
         unsigned spins = 0;
         int ok = 1;
         // spin on relaxed loads (an acquire per poll would invalidate caches every
         // time), then one acquire fence once the group has arrived
-        while (__hip_atomic_load(gs.cnt + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(gs.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > kSpinLimit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 ok = 0;
@@ -198,7 +199,14 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     auto Ps = [&](int c) { return a.p + ((long long)c * a.ntiles + tile) * tstride; };
     auto Rs = [&](int k) { return a.r + ((long long)(k % WS) * a.ntiles + tile) * tstride; };
     const double sbase = a.shift[bs];
-    GroupSync gs{a.cnt, a.gbuf, S::ELEMS + kTile, K, kg, 0u, false};
+    // lockstep: the SG tiles tile mod (ntiles / SG) share one barrier counter
+    // (and then one XCD, which makes them read the same rows of Phi at about
+    // the same time); every other use of the group stays per tile
+    const int SG = a.sg > 1 ? a.sg : 1;
+    const int nsg = a.ntiles / SG;
+    const int sgid = tile % nsg;
+    GroupSync gs{a.cnt + (SG > 1 ? sgid : tile), a.gbuf, S::ELEMS + kTile, K, kg,
+                 (unsigned)(K * SG), 0u, false};
     const int nblk = (ng + 15) / 16;
     // rows of this workgroup in the flat walk of the deferred updates
     const int own_rows = ((nblk - kg + K - 1) / K) * 16;
@@ -325,9 +333,13 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     }
     if (!group_sum(gs, tile, s_tmp, kTile, a.abort_flag)) return;
     if (t == 0) {
-        const double *first = a.gbuf + (size_t)tile * 2 * K * gs.slot;   // parity 0
+        // every workgroup that shares the barrier counter on this XCD?
+        const double me = (double)xcd_id();
         int same = 1;
-        for (int k = 1; k < K; ++k) same &= first[(size_t)k * gs.slot + kTile] == first[kTile];
+        for (int j = 0; j < SG; ++j) {
+            const double *first = a.gbuf + (size_t)(sgid + j * nsg) * 2 * K * gs.slot;   // parity 0
+            for (int k = 0; k < K; ++k) same &= first[(size_t)k * gs.slot + kTile] == me;
+        }
         s_local = same;
     }
     __syncthreads();
@@ -583,6 +595,23 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
         a.flags[gcol] = s_flag[j] | (s_act[c][j] ? 1 : 0);
     }
     if (kg == 0 && t == 0) a.tile_iters[tile] = it;
+    if (SG > 1) {
+        // lockstep: keep arriving at the shared barrier until every tile of the
+        // super-group is done (the last one to finish brings the count to zero
+        // before its next arrival, so all leave after the same barrier)
+        if (t == 0 && kg == 0) {
+            __hip_atomic_fetch_add(a.active + sgid, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+        for (;;) {
+            if (!group_sum(gs, tile, s_tmp, 0, a.abort_flag)) return;
+            if (t == 0) s_any = __hip_atomic_load(a.active + sgid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int left = s_any;
+            __syncthreads();
+            if (left == 0) break;
+        }
+    }
 }
 
 // Group members blockIdx = tile + ntiles * k: with workgroups dealt round-robin
