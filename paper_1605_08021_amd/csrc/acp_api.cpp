@@ -63,7 +63,7 @@ struct acp_ctx {
     int u_np = 0;
     DevBuf gt, lchol, diag, isdf_scratch, l11, linv, c1, bc, tmp1, tmp2, tmp3, shifts_dev;
     DevBuf kx, kr, kpa, kpb, kw1, kw2, krhs, kiters, kresid, kflags, ktile;
-    DevBuf msp, msgbuf, mscnt, msactive, msabort, msprof;
+    DevBuf msp, msgbuf, mscnt, msactive, mshalo, msabort, msprof;
     DevBuf phi_rm32, phi_cm32, krhs32, colmask;   // mixed-precision form
     // learned preconditioner
     bool nn_ready = false;
@@ -390,6 +390,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     ENSURE(ctx->msgbuf, (size_t)rhs_tiles * 2 * Kmax * slot * 8);
     ENSURE(ctx->mscnt, (size_t)rhs_tiles * 4);
     ENSURE(ctx->msactive, (size_t)rhs_tiles * 4);
+    ENSURE(ctx->mshalo, (size_t)rhs_tiles * Kmax * 4);
     ENSURE(ctx->msabort, 4);
     const int ncols = nc * rhs_tiles * kTile;
     ENSURE(ctx->kiters, (size_t)ncols * 4);
@@ -421,6 +422,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     a.gbuf = dp<double>(ctx->msgbuf);
     a.cnt = dp<unsigned>(ctx->mscnt);
     a.active = dp<int>(ctx->msactive);
+    a.hflag = dp<int>(ctx->mshalo);
     a.abort_flag = dp<int>(ctx->msabort);
     a.iters = dp<int>(ctx->kiters);
     a.resid = dp<double>(ctx->kresid);
@@ -442,6 +444,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
         a.sg = SG;
         HIPCHK(launch_fill_u32(dp<unsigned>(ctx->mscnt), rhs_tiles, 0u, s));
         HIPCHK(launch_fill_i32(dp<int>(ctx->msactive), rhs_tiles, SG, s));
+        HIPCHK(launch_fill_i32(dp<int>(ctx->mshalo), (size_t)rhs_tiles * K, 0, s));
         HIPCHK(launch_fill_i32(dp<int>(ctx->msabort), 1, 0, s));
         HIPCHK(hipEventRecord(ctx->ev[6], s));
         if constexpr (sizeof(T) == 8) HIPCHK(launch_mscg_fp64(a, s));
@@ -1255,6 +1258,7 @@ acp_status batch_describe(acp_batch *b, size_t i, MsArgs &a) {
     a.gbuf = dp<double>(ctx->msgbuf);
     a.cnt = dp<unsigned>(ctx->mscnt);
     a.active = dp<int>(ctx->msactive);
+    a.hflag = dp<int>(ctx->mshalo);
     a.abort_flag = dp<int>(b->abort_flag);
     a.iters = dp<int>(ctx->kiters);
     a.resid = dp<double>(ctx->kresid);
@@ -2002,7 +2006,8 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->kflags, &ctx->ktile, &ctx->dy_v, &ctx->dy_t, &ctx->dy_s, &ctx->dy_g,
                       &ctx->dy_gk, &ctx->dy_norm, &ctx->dm_phi, &ctx->dm_k, &ctx->dm_mass,
                       &ctx->dm_d, &ctx->dm_eig, &ctx->dm_work, &ctx->dm_asym, &ctx->splitk,
-                      &ctx->msp, &ctx->msgbuf, &ctx->mscnt, &ctx->msactive, &ctx->msabort, &ctx->msprof,
+                      &ctx->msp, &ctx->msgbuf, &ctx->mscnt, &ctx->msactive, &ctx->mshalo, &ctx->msabort,
+                      &ctx->msprof,
                       &ctx->phi_rm32, &ctx->phi_cm32, &ctx->krhs32, &ctx->colmask,
                       &ctx->nn_theta, &ctx->nn_m, &ctx->nn_v, &ctx->nn_grad, &ctx->nn_part,
                       &ctx->nn_bpart, &ctx->nn_out, &ctx->nn_rms, &ctx->nn_shat, &ctx->nn_tgt,

@@ -149,11 +149,12 @@ struct MsArgsT {
     double *x;              // [nshift][ntiles] tiles (always double)
     T *p;                   // [nshift][ntiles] tiles
     T *r;                   // residual ring: [kMsWindow][ntiles] tiles
-    T *pa, *pb;             // ntiles tiles each
+    T *pa, *pb;             // ntiles tiles each (pa: s = A p of the base sequence)
     double *gbuf;           // ntiles * 2 * K * slot doubles
     unsigned *cnt;          // ntiles counters, zero at launch
     int sg;                 // lockstep: tiles t, t + ntiles/sg, ... share one barrier (<= 1: off)
     int *active;            // lockstep: per super-group tiles not yet done, sg at launch
+    int *hflag;             // halo flags: [ntiles][K], zero at launch (K > 1)
     int *abort_flag;        // set if a group barrier wait expired
     int *iters;             // [nshift][ntiles * 16]
     double *resid;

@@ -18,13 +18,15 @@
 // iteration by (4 per shift + the window's residuals) per window.
 //
 // Work decomposition (gfx950): a tile of 16 right-hand sides is shared by a
-// group of K workgroups (8 waves each); workgroup k owns the 16-row blocks
-// blk = k (mod K).  The two reductions of every iteration (Phi^T y with p^T y,
-// and |r|^2) are reduced inside each workgroup in LDS, then across the group
-// through global memory behind a counter barrier; every workgroup sums the K
-// partials in the same order, so all of them hold identical scalars.  The
-// kernel is launched cooperatively, which guarantees that all workgroups of a
-// group are resident; every barrier wait is bounded and aborts the launch on
+// group of K workgroups (8 waves each); workgroup k owns a contiguous range of
+// 16-row blocks.  The base sequence runs CG in the Chronopoulos-Gear
+// arrangement, so each iteration has a single reduction (Phi^T y, r.r, r.y):
+// reduced inside each workgroup in LDS, then across the group through global
+// memory behind a counter barrier; every workgroup sums the K partials in the
+// same order, so all of them hold identical scalars.  The stencil's halo rows
+// are exchanged through per-workgroup flags that only the neighbours wait for.
+// The kernel is launched cooperatively, which guarantees that all workgroups
+// of a group are resident; every wait is bounded and aborts the launch on
 // expiry.
 #include "krylov_common.h"
 
@@ -67,10 +69,10 @@ __device__ __forceinline__ double *group_mine(const GroupSync &gs, int tile) {
 // Returns false if the wait expired (the launch is then abandoned).
 __device__ bool group_sum(GroupSync &gs, int tile, double *dst, int n, int *abort_flag) {
     const double *base = gs.buf + ((size_t)tile * 2 + (gs.phase & 1u)) * (size_t)gs.K * gs.slot;
-    // every wave's stores complete before the barrier (explicitly in the local
-    // mode: the workgroup barrier alone does not wait for global stores); thread
-    // 0's release then publishes them (and the workgroup's halo rows)
-    if (gs.local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // every wave's stores complete before the barrier (the workgroup barrier
+    // alone does not wait for global stores); thread 0's release then publishes
+    // them
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
@@ -149,6 +151,70 @@ __device__ __forceinline__ void column_partial(double v, double *red, double *ou
     __syncthreads();
 }
 
+// Halo exchange inside one tile's group: after writing its rows of a residual,
+// a workgroup raises its flag to that residual's iteration number; before reading
+// rows of the workgroups within D positions of it (cyclically) it waits until
+// their flags reach that number.  Every wave first waits for its own stores, so
+// the flag covers them; thread 0 then also refreshes this compute unit's L1,
+// since the waves read each other's rows next.
+__device__ __forceinline__ void halo_publish(const GroupSync &gs, int *flags, int k) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (gs.K > 1) {
+            if (gs.local)
+                __hip_atomic_store(flags + gs.kg, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __hip_atomic_store(flags + gs.kg, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __syncthreads();
+}
+
+__device__ bool halo_wait(const GroupSync &gs, const int *flags, int D, int k, int *abort_flag) {
+    __shared__ int s_hok;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        for (int d = -D; d <= D && ok; ++d) {
+            if (d == 0) continue;
+            const int other = ((gs.kg + d) % gs.K + gs.K) % gs.K;
+            unsigned spins = 0;
+            while (__hip_atomic_load(flags + other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit ||
+                    __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        if (gs.local)
+            asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        else
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        if (!ok) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_hok = ok;
+    }
+    __syncthreads();
+    return s_hok != 0;
+}
+
+// Column sums of two per-thread values (fixed order), to out[0..15] and out[16..31].
+__device__ __forceinline__ void column_partial2(double v0, double v1, double *red, double *out) {
+    red[threadIdx.x] = v0;
+    red[NT + threadIdx.x] = v1;
+    __syncthreads();
+    if (threadIdx.x < 2 * kTile) {
+        const int h = threadIdx.x / kTile, c = threadIdx.x % kTile;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT / kTile; ++k) s += red[h * NT + c + kTile * k];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 #ifdef ACP_PHASE_CLOCKS
 // Per-phase timers of workgroup 0, thread 0 (tuning builds only).
 #define PHASE_MARK(i)                                                          \
@@ -164,13 +230,23 @@ __device__ __forceinline__ void column_partial(double v, double *red, double *ou
 #endif
 
 // The whole solve of one right-hand-side tile (all shifts) by workgroup kg of
-// its group.
+// its group.  The base sequence is CG in the Chronopoulos-Gear arrangement,
+//   r_{k+1} = r_k - a_k s_k,   w = A r_{k+1},
+//   g_{k+1} = r.r,  d_{k+1} = r.w,  b_k = g_{k+1} / g_k,
+//   a_{k+1} = g_{k+1} / (d_{k+1} - b_k g_{k+1} / a_k),   s_{k+1} = w + b_k s_k,
+// which yields the scalars of textbook CG (a_k, b_k, with p_k^T A p_k =
+// d_k - b_{k-1} g_k / a_{k-1}) from one reduction per iteration: C = Phi^T y,
+// r.r and r.y (= r.w, as r lies in range(Q)) travel together.  Workgroup kg owns
+// a contiguous range of 16-row blocks; between the sweep that writes r_{k+1} and
+// the sweep that applies the stencil to it, only the stencil neighbours' rows
+// are awaited (per-workgroup flags), and the blocks away from the range ends
+// are processed first.
 template <int DIM, int NB, typename T>
 __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     using S = Slots<NB>;
-    static_assert(S::N * S::ELEMS >= S::ELEMS + kTile, "slots hold C and p^T y");
+    static_assert(S::N * S::ELEMS >= S::ELEMS + 2 * kTile, "slots hold C, r.r and r.y");
     __shared__ double slots[S::N * S::ELEMS];
-    __shared__ double red[NT];
+    __shared__ double red[2 * NT];
     __shared__ double s_rr[kTile], s_bn[kTile], s_al[kTile], s_btp[kTile], s_alp[kTile],
         s_tmp[kTile];
     __shared__ double s_z[MAXSH][kTile], s_zp[MAXSH][kTile], s_bs[MAXSH][kTile],
@@ -191,8 +267,8 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     const int ng = a.g.ng;
     const long long tstride = (long long)ng * kTile;
     const T *__restrict__ b = a.rhs + (long long)tile * tstride;
-    T *pA = a.pa + (long long)tile * tstride;
-    T *pB = a.pb + (long long)tile * tstride;
+    T *sv = a.pa + (long long)tile * tstride;   // s = A p of the base sequence (own rows)
+    int *hflags = a.hflag ? a.hflag + (size_t)tile * K : nullptr;
     // shift c of this tile: X[c] at a.x + (c * ntiles + tile) * tstride, same for P;
     // residual of iteration k at ring slot k % WS
     auto Xs = [&](int c) { return a.x + ((long long)c * a.ntiles + tile) * tstride; };
@@ -205,11 +281,21 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     const int SG = a.sg > 1 ? a.sg : 1;
     const int nsg = a.ntiles / SG;
     const int sgid = tile % nsg;
-    GroupSync gs{a.cnt + (SG > 1 ? sgid : tile), a.gbuf, S::ELEMS + kTile, K, kg,
+    GroupSync gs{a.cnt + (SG > 1 ? sgid : tile), a.gbuf, S::ELEMS + 2 * kTile, K, kg,
                  (unsigned)(K * SG), 0u, false};
     const int nblk = (ng + 15) / 16;
-    // rows of this workgroup in the flat walk of the deferred updates
-    const int own_rows = ((nblk - kg + K - 1) / K) * 16;
+    // this workgroup's blocks [kb0, kb1) and rows [r0, r1)
+    const int kb0 = (int)((long long)kg * nblk / K), kb1 = (int)((long long)(kg + 1) * nblk / K);
+    const int r0 = kb0 * 16, r1 = kb1 * 16 < ng ? kb1 * 16 : ng;
+    const int own_rows = (kb1 - kb0) * 16;
+    // stencil reach in grid rows, the neighbours within it, and the blocks whose
+    // stencil leaves the range
+    const int reach = DIM == 1 ? 4 : 4 * a.g.nx;
+    const int min_chunk = (nblk / K) * 16;
+    const int D = K == 1 ? 0 : (min_chunk > 0 ? min((reach + min_chunk - 1) / min_chunk, K - 1) : K - 1);
+    auto boundary = [&](int blk) {
+        return K > 1 && (blk * 16 - reach < r0 || blk * 16 + 16 + reach > r1);
+    };
 
 #ifdef ACP_PHASE_CLOCKS
     const bool prof = a.phase_clock && blockIdx.x == 0 && t == 0;
@@ -232,7 +318,7 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
 #pragma unroll
             for (int i = 0; i < RR; ++i) {
                 const int rl = rl0 + i * RSTEP;
-                const int row = (kg + K * (rl >> 4)) * 16 + (rl & 15);
+                const int row = r0 + rl;
                 ok[i] = rl < own_rows && row < ng;
                 id[i] = (long long)(ok[i] ? row : 0) * kTile + j;   // row 0 always exists
             }
@@ -301,11 +387,11 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     };
 
     if (t == 0) s_abort = 0;
-    // ---- init (own rows): r_0 = b, x_c = 0, p_c = 0, p_old = 0; |b|^2
+    // ---- init (own rows): r_0 = b, s = 0, x_c = 0, p_c = 0; |b|^2
     double bb = 0.0;
     {
-        T *r0 = Rs(0);
-        for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
+        T *rz = Rs(0);
+        for (int blk = kb0 + wave; blk < kb1; blk += NW) {
             const int R = blk * 16 + 4 * q;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -313,8 +399,8 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
                 if (row < ng) {
                     const int id = row * kTile + col;
                     const double bv = (double)b[id];
-                    r0[id] = (T)bv;
-                    pA[id] = (T)0.0;
+                    rz[id] = (T)bv;
+                    sv[id] = (T)0.0;
                     for (int c = 0; c < ns; ++c) {
                         Xs(c)[id] = 0.0;
                         Ps(c)[id] = (T)0.0;
@@ -324,7 +410,9 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
             }
         }
     }
-    // the first barrier (agent scope) also publishes each workgroup's XCD
+    // the first barrier (agent scope) also publishes each workgroup's XCD and
+    // makes r_0 visible to the whole group
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __shared__ int s_local;
     {
         double *mine = group_mine(gs, tile);
@@ -341,6 +429,7 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
             for (int k = 0; k < K; ++k) same &= first[(size_t)k * gs.slot + kTile] == me;
         }
         s_local = same;
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
     }
     __syncthreads();
     gs.local = s_local != 0;
@@ -363,66 +452,56 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     if (t < kTile * MAXSH) s_wn[t / kTile][t % kTile] = 0;
     __syncthreads();
 
+    constexpr int nep = NB * 16;
+    constexpr int NN = Nbr<DIM>::N;
     int it = 0, k0 = 0;
-    for (; it < a.max_iter; ++it) {
-        // a right-hand side whose shifts have all converged stops its base sequence too
-        if (t < kTile) {
-            int ca = 0;
-            for (int c = 0; c < ns; ++c) ca |= s_act[c][t];
-            s_colact[t] = ca;
-            if (!ca) s_btp[t] = 0.0;
-        }
-        __syncthreads();
-        if (t == 0) {
-            int any = 0;
-            for (int j = 0; j < kTile; ++j) any |= s_colact[j];
-            s_any = any;
-        }
-        __syncthreads();
-        if (!s_any) break;
+    for (;;) {
         const T *rcur = Rs(it);
-        // ---- pass 1: base p = r + beta p_old (-> pB), y = (H - s_base) p, C = Phi^T y, p^T y
-        constexpr int nep = NB * 16;
-        constexpr int NN = Nbr<DIM>::N;
-        const double beta = s_btp[col];
+        // ---- sweep B: y = (H - s_base) r_it, C = Phi^T y, r.r, r.y; blocks away
+        // from the range ends first, then (neighbours' rows of r_it awaited) the rest
         d4 acc[NB];
 #pragma unroll
         for (int mb = 0; mb < NB; ++mb) acc[mb] = d4{0.0, 0.0, 0.0, 0.0};
-        double pty = 0.0;
-        for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
-            const int R = blk * 16 + 4 * q;
-            const Nbr<DIM> nb(R, a.g);
-            double w[NN], wp[NN];
+        double gam = 0.0, del = 0.0;
+        auto sweep_b = [&](bool ends) {
+            for (int blk = kb0 + wave; blk < kb1; blk += NW) {
+                if (boundary(blk) != ends) continue;
+                const int R = blk * 16 + 4 * q;
+                const Nbr<DIM> nb(R, a.g);
+                double w[NN];
 #pragma unroll
-            for (int k = 0; k < NN; ++k) w[k] = (double)rcur[nb.idx[k] * kTile + col];
+                for (int k = 0; k < NN; ++k) w[k] = (double)rcur[nb.idx[k] * kTile + col];
+                double av[4][NB];
 #pragma unroll
-            for (int k = 0; k < NN; ++k) wp[k] = (double)pA[nb.idx[k] * kTile + col];
-            double av[4][NB];
+                for (int j = 0; j < 4; ++j) {
+                    const int row = R + j < ng ? R + j : ng - 1;
+                    const T *ph = a.phi_rm + (long long)row * nep + col;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = R + j < ng ? R + j : ng - 1;
-                const T *ph = a.phi_rm + (long long)row * nep + col;
+                    for (int mb = 0; mb < NB; ++mb) av[j][mb] = (double)ph[mb * 16];
+                }
+                double y[4], rc[4];
+                stencil_from<DIM>(w, R, a.g, a.veff, sbase, y, rc);
 #pragma unroll
-                for (int mb = 0; mb < NB; ++mb) av[j][mb] = (double)ph[mb * 16];
+                for (int j = 0; j < 4; ++j) {
+                    gam += rc[j] * rc[j];
+                    del += rc[j] * y[j];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int mb = 0; mb < NB; ++mb)
+                        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][mb], y[j], acc[mb], 0, 0, 0);
             }
-#pragma unroll
-            for (int k = 0; k < NN; ++k) w[k] += beta * wp[k];
-            double y[4], pc[4];
-            stencil_from<DIM>(w, R, a.g, a.veff, sbase, y, pc);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                pty += pc[j] * y[j];
-                if (R + j < ng) pB[(R + j) * kTile + col] = (T)pc[j];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int mb = 0; mb < NB; ++mb)
-                    acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j][mb], y[j], acc[mb], 0, 0, 0);
+        };
+        sweep_b(false);
+        if (K > 1 && it > 0 && !halo_wait(gs, hflags, D, it, a.abort_flag)) {
+            if (t == 0) s_abort = 1;
+            break;
         }
+        sweep_b(true);
         PHASE_MARK(0);
         // workgroup reduction of C through the LDS slots (fixed order), published
-        // with p^T y as this workgroup's partial
+        // with r.r and r.y as this workgroup's partial
 #pragma unroll 1
         for (int ph = 0; ph < NW / S::N; ++ph) {
             if (wave / S::N == ph) {
@@ -446,23 +525,69 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
                 for (int k = 1; k < S::N; ++k) v += slots[k * S::ELEMS + idx];
                 mine[idx] = v;
             }
-            column_partial(pty, red, mine + S::ELEMS);
+            column_partial2(gam, del, red, mine + S::ELEMS);
         }
         PHASE_MARK(1);
-        // group reduction: slots[0..ELEMS) = C, slots[ELEMS..) = p^T y
-        if (!group_sum(gs, tile, slots, S::ELEMS + kTile, a.abort_flag)) {
+        // group reduction: slots[0..ELEMS) = C, then r.r, then r.y
+        if (!group_sum(gs, tile, slots, S::ELEMS + 2 * kTile, a.abort_flag)) {
             if (t == 0) s_abort = 1;
             break;
         }
         PHASE_MARK(2);
-        // scalars: base alpha per right-hand side (a non-positive curvature stops
-        // that right-hand side and is reported) ...
+        const double *g_rr = slots + S::ELEMS, *g_ry = slots + S::ELEMS + kTile;
+        if (it > 0) {
+            // convergence of r_it and the shifted b^c_{it-1}
+            if (t < kTile * ns) {
+                const int c = t / kTile, j = t % kTile;
+                const double rrn = g_rr[j];
+                const double bt = (s_rr[j] > 0.0) ? rrn / s_rr[j] : 0.0;
+                const double thr = a.tol * s_bn[j];
+                if (c == bs) {
+                    if (s_act[c][j]) {
+                        s_it[c][j] = it;
+                        if (sqrt(rrn) <= thr) s_act[c][j] = 0;
+                    }
+                } else if (s_act[c][j]) {
+                    const double zr = s_z[c][j] / s_zp[c][j];
+                    const double res = fabs(s_z[c][j]) * sqrt(rrn);
+                    s_bs[c][j] = bt * zr * zr;
+                    s_it[c][j] = it;
+                    if (res <= thr) {
+                        s_act[c][j] = 0;
+                        s_res[c][j] = res / s_bn[j];
+                    }
+                }
+            }
+            __syncthreads();
+            if (t < kTile && s_colact[t]) {
+                s_btp[t] = (s_rr[t] > 0.0) ? g_rr[t] / s_rr[t] : 0.0;
+                s_rr[t] = g_rr[t];
+            }
+        }
+        // a right-hand side whose shifts have all converged stops its base sequence too
         if (t < kTile) {
-            const double pap = slots[S::ELEMS + t];
+            int ca = 0;
+            for (int c = 0; c < ns; ++c) ca |= s_act[c][t];
+            s_colact[t] = ca;
+            if (!ca) s_btp[t] = 0.0;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int any = 0;
+            for (int j = 0; j < kTile; ++j) any |= s_colact[j];
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any || it >= a.max_iter) break;
+        // base step a_it = g / (p^T A p), p^T A p = d - b_{it-1} g / a_{it-1}; a
+        // non-positive curvature stops that right-hand side and is reported
+        if (t < kTile) {
             double al = 0.0;
             if (s_colact[t]) {
+                const double gg = s_rr[t];
+                const double pap = it == 0 ? g_ry[t] : g_ry[t] - s_btp[t] * gg / s_alp[t];
                 if (pap > 0.0) {
-                    al = s_rr[t] / pap;
+                    al = gg / pap;
                 } else {
                     s_flag[t] |= 2;
                     s_colact[t] = 0;
@@ -471,9 +596,9 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
             s_al[t] = al;
         }
         __syncthreads();
-        // ... then the step of this iteration for every live sequence: zeta_{k+1}
-        // and a^c_k of each active shift; the base (zeta = 1) keeps stepping while
-        // any shift of its right-hand side is active
+        // the step of this iteration for every live sequence: zeta_{k+1} and a^c_k
+        // of each active shift; the base (zeta = 1) keeps stepping while any shift
+        // of its right-hand side is active
         {
             const int wpos = it - k0;
             if (t < kTile * ns) {
@@ -501,78 +626,49 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
                 }
             }
             __syncthreads();
-            // window full: apply it before pass 2 overwrites its oldest residual
+            // window full: apply it before the sweep below overwrites its oldest residual
             if (wpos == WS - 1) {
                 flush(k0, WS);
                 k0 = it + 1;
             }
         }
         PHASE_MARK(3);
-        // ---- pass 2: A p = y - Phi C; r_{k+1} = r_k - alpha A p (next ring slot); |r|^2
-        double rr_part = 0.0;
+        // ---- sweep CA: w = y - Phi C (= A r_it), s = w + b_{it-1} s,
+        // r_{it+1} = r_it - a_it s (next ring slot)
         {
-            const double al = s_al[col];
+            const double al = s_al[col], beta = s_btp[col];
             T *rnext = Rs(it + 1);
-            for (int blk = kg + K * wave; blk < nblk; blk += K * NW) {
+            for (int blk = kb0 + wave; blk < kb1; blk += NW) {
                 const int row0 = blk * 16;
                 const int R = row0 + 4 * q;
                 double w[NN];
-                gather<DIM>(pB, R, a.g, col, w);
-                double ro[4];
+                gather<DIM>(rcur, R, a.g, col, w);
+                double so[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int row = R + e < ng ? R + e : ng - 1;
-                    ro[e] = (double)rcur[row * kTile + col];
+                    so[e] = (double)sv[row * kTile + col];
                 }
                 const d4 d = project_block<NB, T>(a.phi_cm, ng, slots, row0);
-                double y[4], pc[4];
-                stencil_from<DIM>(w, R, a.g, a.veff, sbase, y, pc);
+                double y[4], rc[4];
+                stencil_from<DIM>(w, R, a.g, a.veff, sbase, y, rc);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const double rn = ro[e] - al * (y[e] - d[e]);
+                    const double sn = (y[e] - d[e]) + beta * so[e];
+                    const double rn = rc[e] - al * sn;
                     if (R + e < ng) {
+                        sv[(R + e) * kTile + col] = (T)sn;
                         rnext[(R + e) * kTile + col] = (T)rn;
-                        rr_part += rn * rn;
                     }
                 }
             }
         }
         PHASE_MARK(4);
-        column_partial(rr_part, red, group_mine(gs, tile));
-        if (!group_sum(gs, tile, s_tmp, kTile, a.abort_flag)) {
-            if (t == 0) s_abort = 1;
-            break;
-        }
-        if (t < kTile * ns) {
-            const int c = t / kTile, j = t % kTile;
-            const double rrn = s_tmp[j];
-            const double bt = (s_rr[j] > 0.0) ? rrn / s_rr[j] : 0.0;
-            const double thr = a.tol * s_bn[j];
-            if (c == bs) {
-                if (s_act[c][j]) {
-                    s_it[c][j] = it + 1;
-                    if (sqrt(rrn) <= thr) s_act[c][j] = 0;
-                }
-            } else if (s_act[c][j]) {
-                const double zr = s_z[c][j] / s_zp[c][j];
-                const double res = fabs(s_z[c][j]) * sqrt(rrn);
-                s_bs[c][j] = bt * zr * zr;
-                s_it[c][j] = it + 1;
-                if (res <= thr) {
-                    s_act[c][j] = 0;
-                    s_res[c][j] = res / s_bn[j];
-                }
-            }
-        }
-        __syncthreads();
-        if (t < kTile && s_colact[t]) {
-            s_alp[t] = s_al[t];
-            s_btp[t] = (s_rr[t] > 0.0) ? s_tmp[t] / s_rr[t] : 0.0;
-            s_rr[t] = s_tmp[t];
-        }
+        halo_publish(gs, hflags, it + 1);
+        if (t < kTile && s_colact[t]) s_alp[t] = s_al[t];
         __syncthreads();
         PHASE_MARK(5);
-        T *tmp = pA; pA = pB; pB = tmp;
+        ++it;
     }
 #ifdef ACP_PHASE_CLOCKS
     if (prof)
@@ -680,7 +776,7 @@ int mscg_resident_capacity(int dim, int ne, bool fp32) {
 
 size_t mscg_group_slot(int ne) {
     const int nb = (ne + 15) / 16;
-    return (size_t)nb * 16 * kTile + kTile;
+    return (size_t)nb * 16 * kTile + 2 * kTile;
 }
 
 template <typename T>
