@@ -505,12 +505,12 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     ctx->stats.tile_iterations += tsum;
     ctx->stats.iters_min = imin;
     ctx->stats.iters_max = imax;
-    // base, per iteration: pass 1 reads r and p_old and writes p, pass 2 reads p
-    // and r and writes the next r, the window update reads r once more (7 vectors
-    // in T); every sequence (base included) then reads and writes p_c (T) and x_c
-    // (FP64) once per window of kMsWindow iterations
-    const double per_window = (2.0 * sizeof(T) + 16.0) / kMsWindow;
-    ctx->stats.krylov_bytes += ng * ((7.0 * sizeof(T) + per_window) * (double)base_it +
+    // base, per iteration: the stencil sweep reads r, the update sweep reads r
+    // and s and writes s and the next r, the window update reads r once more (6
+    // vectors in T); every sequence (base included) then reads and writes p_c (T)
+    // and x_c (FP64) once per window (16 iterations for at most 8 shifts, else 8)
+    const double per_window = (2.0 * sizeof(T) + 16.0) / (nc <= 8 ? 16 : 8);
+    ctx->stats.krylov_bytes += ng * ((6.0 * sizeof(T) + per_window) * (double)base_it +
                                      per_window * (double)shifted_it);
     ctx->stats.krylov_flops += 4.0 * ng * (double)ctx->ne * (double)base_it;
     *flags_or |= f;
@@ -1406,8 +1406,8 @@ acp_status batch_finish(acp_batch *b, size_t i) {
     ctx->stats.tile_iterations += tsum;
     ctx->stats.iters_min = imin;
     ctx->stats.iters_max = imax;
-    const double per_window = 32.0 / kMsWindow;
-    ctx->stats.krylov_bytes += ng * ((7.0 * 8 + per_window) * (double)base_it + per_window * (double)shifted_it);
+    const double per_window = 32.0 / (nc <= 8 ? 16 : 8);
+    ctx->stats.krylov_bytes += ng * ((6.0 * 8 + per_window) * (double)base_it + per_window * (double)shifted_it);
     ctx->stats.krylov_flops += 4.0 * ng * (double)ctx->ne * (double)base_it;
     BCHECK(ctx, finish_compress(ctx, f, false));
     return ACP_OK;

@@ -165,9 +165,10 @@ struct MsArgsT {
     unsigned long long *phase_clock;   // 8 phase timers of workgroup 0 (ACP_PHASE_CLOCKS builds)
 };
 using MsArgs = MsArgsT<double>;
-// Iterations per window of the deferred solution updates of the multi-shift solver
-// (the residual ring holds this many residuals per tile).
-constexpr int kMsWindow = 8;
+// Longest window of the deferred solution updates of the multi-shift solver (16
+// iterations with at most 8 shifts, else 8); the residual ring holds this many
+// residuals per tile.
+constexpr int kMsWindow = 16;
 constexpr int kMsMaxGroup = 16;   // workgroups per right-hand-side tile
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s);
 hipError_t launch_mscg_fp32(const MsArgsT<float> &a, hipStream_t s);

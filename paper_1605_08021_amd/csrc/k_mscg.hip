@@ -37,7 +37,8 @@ using namespace kry;
 
 constexpr unsigned kSpinLimit = 1u << 22;   // ~seconds: a wait this long means a lost group
 constexpr int MAXSH = 16;                   // shifts per right-hand side
-constexpr int WS = kMsWindow;
+constexpr int WS = kMsWindow;              // residual ring slots (longest window)
+constexpr int WSLOTS = 8 * MAXSH;           // window step records per column: shifts x window
 constexpr int KMAX = kMsMaxGroup;           // workgroups per tile
 
 struct GroupSync {
@@ -252,7 +253,9 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     __shared__ double s_z[MAXSH][kTile], s_zp[MAXSH][kTile], s_bs[MAXSH][kTile],
         s_res[MAXSH][kTile];
     // step scalars of the current window: p = wz r + wb p, x += wa p
-    __shared__ double s_wz[MAXSH][WS][kTile], s_wb[MAXSH][WS][kTile], s_wa[MAXSH][WS][kTile];
+    // (record of shift c, step w at c * wl + w; windows of wl = 16 steps when
+    // there are at most 8 shifts, else 8)
+    __shared__ double s_wz[WSLOTS][kTile], s_wb[WSLOTS][kTile], s_wa[WSLOTS][kTile];
     __shared__ int s_act[MAXSH][kTile], s_it[MAXSH][kTile], s_wn[MAXSH][kTile], s_flag[kTile],
         s_colact[kTile], s_any, s_abort;
 
@@ -264,6 +267,7 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     const int q = lane >> 4;
     const int ns = a.nshift;
     const int bs = a.base;
+    const int wl = ns <= 8 ? 16 : 8;   // window length (wl * ns <= WSLOTS)
     const int ng = a.g.ng;
     const long long tstride = (long long)ng * kTile;
     const T *__restrict__ b = a.rhs + (long long)tile * tstride;
@@ -310,7 +314,7 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     // The next shift's loads are issued before the current shift's arithmetic.
     auto flush = [&](int k0, int n_steps) {
         const int j = t & 15;
-        constexpr int RR = 4;
+        constexpr int RR = 2;
         constexpr int RSTEP = NT / kTile;
         for (int rl0 = t >> 4; rl0 < own_rows; rl0 += RR * RSTEP) {
             long long id[RR];
@@ -362,7 +366,8 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
 #pragma unroll
                     for (int w = 0; w < WS; ++w) {
                         if (w < n) {
-                            const double wz = s_wz[c][w][j], wb = s_wb[c][w][j], wa = s_wa[c][w][j];
+                            const int wi = c * wl + w;
+                            const double wz = s_wz[wi][j], wb = s_wb[wi][j], wa = s_wa[wi][j];
 #pragma unroll
                             for (int i = 0; i < RR; ++i) {
                                 pv[i] = wb * pv[i] + wz * rw[w][i];
@@ -607,9 +612,9 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
                 if (!s_colact[j]) {
                     s_act[c][j] = 0;
                 } else if (c == bs) {
-                    s_wz[c][wpos][j] = 1.0;
-                    s_wb[c][wpos][j] = s_btp[j];
-                    s_wa[c][wpos][j] = al;
+                    s_wz[c * wl + wpos][j] = 1.0;
+                    s_wb[c * wl + wpos][j] = s_btp[j];
+                    s_wa[c * wl + wpos][j] = al;
                     s_wn[c][j] = wpos + 1;
                 } else if (s_act[c][j]) {
                     const double sig = sbase - a.shift[c];
@@ -617,9 +622,9 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
                     const double alp = s_alp[j], btp = s_btp[j];
                     const double den = al * btp * (zkm - zk) + zkm * alp * (1.0 + sig * al);
                     const double zn = (den != 0.0) ? zk * zkm * alp / den : 0.0;
-                    s_wz[c][wpos][j] = zk;
-                    s_wb[c][wpos][j] = s_bs[c][j];
-                    s_wa[c][wpos][j] = (zk != 0.0) ? al * zn / zk : 0.0;
+                    s_wz[c * wl + wpos][j] = zk;
+                    s_wb[c * wl + wpos][j] = s_bs[c][j];
+                    s_wa[c * wl + wpos][j] = (zk != 0.0) ? al * zn / zk : 0.0;
                     s_wn[c][j] = wpos + 1;
                     s_zp[c][j] = zk;
                     s_z[c][j] = zn;
@@ -627,8 +632,8 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
             }
             __syncthreads();
             // window full: apply it before the sweep below overwrites its oldest residual
-            if (wpos == WS - 1) {
-                flush(k0, WS);
+            if (wpos == wl - 1) {
+                flush(k0, wl);
                 k0 = it + 1;
             }
         }
