@@ -62,6 +62,8 @@ struct acp_ctx {
     DevBuf u_last;
     int u_np = 0;
     DevBuf gt, lchol, diag, isdf_scratch, l11, linv, c1, bc, tmp1, tmp2, tmp3, shifts_dev;
+    DevBuf pgram;              // Phi Phi^T (N_g x N_g) for the point selection, when it fits
+    bool pgram_ready = false;
     DevBuf kx, kr, kpa, kpb, kw1, kw2, krhs, kiters, kresid, kflags, ktile;
     DevBuf msp, msgbuf, mscnt, msactive, mshalo, msabort, msprof;
     DevBuf phi_rm32, phi_cm32, krhs32, colmask;   // mixed-precision form
@@ -975,6 +977,9 @@ acp_status setup_impl(acp_ctx *ctx, const acp_grid *grid, const acp_opts *opts, 
     return ACP_OK;
 }
 
+// Largest Phi Phi^T kept for the point selection (4 GiB: N_g up to 23170).
+constexpr double kGramBudgetBytes = 4.0 * 1024 * 1024 * 1024;
+
 // Alg. 2 (sketched) for the columns of G: fills ctx->sel_dev / sel_host, ctx->xi.
 acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega,
                      const int *sel_in) {
@@ -1000,8 +1005,22 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
         HIPCHK(hipMemcpyAsync(ctx->forced_dev.p, sel_in, (size_t)nmu * 4, hipMemcpyHostToDevice, s));
         forced = dp<int>(ctx->forced_dev);
     }
+    // Phi Phi^T once per context (Phi does not change) when it fits a modest budget:
+    // each greedy pivot step then reads one of its columns instead of all of Phi.
+    // A forced selection keeps the direct products (its pivots may lie past the
+    // numerical rank, where the sign of the rounding decides acceptance).
+    const double *pgram = nullptr;
+    if (!sel_in && (double)ng * ng * 8.0 <= kGramBudgetBytes) {
+        if (!ctx->pgram_ready) {
+            ENSURE(ctx->pgram, (size_t)ng * ng * 8);
+            HIPCHK(gemm(Op::N, Op::T, ng, ng, ctx->ne, 1.0, dp<double>(ctx->phi_cm), ng, 0,
+                        dp<double>(ctx->phi_cm), ng, 0, 0.0, dp<double>(ctx->pgram), ng, 0, 1, s));
+            ctx->pgram_ready = true;
+        }
+        pgram = dp<double>(ctx->pgram);
+    }
     int got = 0;
-    HIPCHK(isdf_pivoted_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), dp<double>(ctx->gt), nmu,
+    HIPCHK(isdf_pivoted_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), pgram, dp<double>(ctx->gt), nmu,
                                  sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol),
                                  dp<double>(ctx->diag), dp<int>(ctx->sel_dev), forced, &got,
                                  ctx->isdf_scratch.p, s));
@@ -2000,7 +2019,7 @@ void acp_destroy(acp_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->phi_cm, &ctx->phi_rm, &ctx->veff, &ctx->lw_dev, &ctx->fx, &ctx->fy,
                       &ctx->svc, &ctx->sel_dev, &ctx->forced_dev, &ctx->xi, &ctx->rhs, &ctx->z,
                       &ctx->w, &ctx->u_last, &ctx->gt, &ctx->lchol, &ctx->diag,
-                      &ctx->isdf_scratch, &ctx->l11, &ctx->linv, &ctx->c1, &ctx->bc, &ctx->tmp1,
+                      &ctx->isdf_scratch, &ctx->pgram, &ctx->l11, &ctx->linv, &ctx->c1, &ctx->bc, &ctx->tmp1,
                       &ctx->tmp2, &ctx->tmp3, &ctx->shifts_dev, &ctx->kx, &ctx->kr, &ctx->kpa,
                       &ctx->kpb, &ctx->kw1, &ctx->kw2, &ctx->krhs, &ctx->kiters, &ctx->kresid,
                       &ctx->kflags, &ctx->ktile, &ctx->dy_v, &ctx->dy_t, &ctx->dy_s, &ctx->dy_g,

@@ -222,12 +222,13 @@ hipError_t launch_col_axpby(int m, int n, const double *a, const double *X, int 
 
 // ---------------------------------------------------------------- ISDF (K4)
 // Greedy pivoted Cholesky of the implicit Hadamard Gram matrix (column-major
-// inputs phi N_g x n_e and gt N_g x r, leading dimension N_g; factor L
-// column-major N_g x nmu_max, leading dimension N_g); forced (dev, nmu_max
-// entries) replaces the argmax by the given pivots.
-hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const double *gt,
-                                 int nmu_max, double tol, double *L, double *diag, int *sel_dev,
-                                 const int *forced, int *nmu_out_host, void *scratch, hipStream_t s);
+// inputs phi N_g x n_e and gt N_g x r, leading dimension N_g; pgram: Phi Phi^T
+// (N_g x N_g) or null; factor L column-major N_g x nmu_max, leading dimension
+// N_g); forced (dev, nmu_max entries) replaces the argmax by the given pivots.
+hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const double *pgram,
+                                 const double *gt, int nmu_max, double tol, double *L, double *diag,
+                                 int *sel_dev, const int *forced, int *nmu_out_host, void *scratch,
+                                 hipStream_t s);
 size_t isdf_scratch_bytes(int ng);
 // Order n2 >= n (32 times a power of two) of the padded inverse below.
 int tri_inverse_order(int n);

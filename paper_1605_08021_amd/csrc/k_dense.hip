@@ -174,8 +174,8 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_init_kernel(int ng, int ne, int 
 //   L(a,k) = (K(a,p) - sum_{j<k} L(a,j) L(p,j)) / sqrt(diag(p)), diag(a) -= L(a,k)^2.
 // state[0] = accepted pivots, state[1] = stopped; dvals[0] = first pivot value.
 __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
-    int ng, int ne, int r, int k, int nblk, const double *phi, const double *gt, double *L,
-    double *diag, int *sel, const int *forced, double tol2, int *state, double *dvals,
+    int ng, int ne, int r, int k, int nblk, const double *phi, const double *pgram, const double *gt,
+    double *L, double *diag, int *sel, const int *forced, double tol2, int *state, double *dvals,
     const Cand *cand_in, Cand *cand_out) {
     __shared__ double vp[ISDF_VCH];
     __shared__ double red[3][ISDF_NT];
@@ -215,6 +215,8 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
     const int st = t / ISDF_ROWS;
     const int a = blockIdx.x * ISDF_ROWS + t % ISDF_ROWS;
     const long long ac = a < ng ? a : ng - 1;
+    // with the Gram matrix Phi Phi^T at hand, phi(a,:).phi(p,:) is one entry of its column p
+    if (pgram) ne = 0;
     if (ne + r + k <= ISDF_VCH) {
         // one staging pass: vp = [phi(p,:) | G~(p,:) | L(p, 0..k-1)]
         for (int j = t; j < ne + r + k; j += ISDF_NT) {
@@ -242,8 +244,91 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
             s2 += red[1][q * ISDF_ROWS + t];
             y += red[2][q * ISDF_ROWS + t];
         }
+        if (pgram) s1 = pgram[a + (long long)p * ng];
         const double lk = (s1 * s2 - y) / sqrt(bv);
         dnew = (a == p) ? -1.0 : diag[a] - lk * lk;
+        L[a + (long long)k * ng] = lk;
+        diag[a] = dnew;
+        idx = a;
+    }
+    block_candidate16(dnew, idx, cand_out);
+}
+
+// The greedy step with Phi Phi^T at hand and this thread's share of its row in
+// registers.  The loads are ordered by need: the previous step's candidates
+// first, then the virtual columns v = st + 32 i (i < MAXR) of [G~ | L(:, 0..k-1)]
+// (independent of the pivot, in flight during the candidate reduction), then,
+// once the pivot p is known, its row (staged in LDS) and Phi Phi^T(a, p).  The
+// launch picks the smallest MAXR with r + k <= 32 MAXR.
+template <int MAXR>
+__global__ __launch_bounds__(ISDF_NT) void isdf_step_gram_kernel(
+    int ng, int r, int k, int nblk, const double *pgram, const double *gt, double *L, double *diag,
+    int *sel, double tol2, int *state, double *dvals, const Cand *cand_in, Cand *cand_out) {
+    constexpr int NV = ISDF_NS * MAXR;
+    __shared__ double vp[NV];
+    __shared__ double red[2][ISDF_NT];
+    const int t = threadIdx.x;
+    const int st = t / ISDF_ROWS;
+    const int a = blockIdx.x * ISDF_ROWS + t % ISDF_ROWS;
+    const long long ac = a < ng ? a : ng - 1;
+    const int ntot = r + k;
+    const int stopped = state[1];
+    double bv = -2.0;
+    int bi = 0x7fffffff;
+    for (int b = t & 63; b < nblk; b += 64) {
+        const Cand c = cand_in[b];
+        if (better(c.v, c.i, bv, bi)) {
+            bv = c.v;
+            bi = c.i;
+        }
+    }
+    auto column = [&](int v) -> const double * {
+        return v < r ? gt + (long long)v * ng : v < ntot ? L + (long long)(v - r) * ng : gt;
+    };
+    double x[MAXR];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) x[i] = column(st + ISDF_NS * i)[ac];
+    const double dold = diag[ac];
+    if (stopped) return;
+    wave_argmax(bv, bi);
+    bv = readlane_f64(bv, 63);
+    bi = __builtin_amdgcn_readlane(bi, 63);
+    const bool stop = !(bv > 0.0) || (tol2 > 0.0 && k > 0 && bv < tol2 * dvals[0]);
+    if (blockIdx.x == 0 && t == 0) {
+        if (stop) {
+            state[1] = 1;
+        } else {
+            sel[k] = bi;
+            state[0] = k + 1;
+            if (k == 0) dvals[0] = bv;
+        }
+    }
+    if (stop) return;
+    const int p = bi;
+    const double kp = pgram[ac + (long long)p * ng];
+    for (int v = t; v < NV; v += ISDF_NT) vp[v] = v < ntot ? column(v)[p] : 0.0;
+    __syncthreads();
+    double s2 = 0.0, y = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+        const int v = st + ISDF_NS * i;
+        const double pr = x[i] * vp[v];
+        s2 += v < r ? pr : 0.0;
+        y += v >= r ? pr : 0.0;
+    }
+    red[0][t] = s2;
+    red[1][t] = y;
+    __syncthreads();
+    double dnew = -2.0;
+    int idx = 0x7fffffff;
+    if (t < ISDF_ROWS && a < ng) {
+        double a2 = 0.0, a3 = 0.0;
+        for (int q = 0; q < ISDF_NS; ++q) {
+            a2 += red[0][q * ISDF_ROWS + t];
+            a3 += red[1][q * ISDF_ROWS + t];
+        }
+        const double lk = (kp * a2 - a3) / sqrt(bv);
+        dnew = (a == p) ? -1.0 : dold - lk * lk;
         L[a + (long long)k * ng] = lk;
         diag[a] = dnew;
         idx = a;
@@ -464,9 +549,10 @@ __global__ void dynmat_assemble_kernel(int np, int dim, const double *Phi, const
 
 }  // namespace
 
-hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const double *gt,
-                                 int nmu_max, double tol, double *L, double *diag, int *sel_dev,
-                                 const int *forced, int *nmu_out_host, void *scratch, hipStream_t s) {
+hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const double *pgram,
+                                 const double *gt, int nmu_max, double tol, double *L, double *diag,
+                                 int *sel_dev, const int *forced, int *nmu_out_host, void *scratch,
+                                 hipStream_t s) {
     // scratch: int state[2] | pad | double dvals[2] | Cand[2][nblk]
     const int nblk = (ng + ISDF_ROWS - 1) / ISDF_ROWS;
     int *state = (int *)scratch;
@@ -478,8 +564,22 @@ hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const
     hipLaunchKernelGGL(isdf_init_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, phi, gt, diag, c0);
     const double tol2 = tol * tol;
     for (int k = 0; k < nmu_max; ++k) {
-        hipLaunchKernelGGL(isdf_step_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, k, nblk, phi, gt, L,
-                           diag, sel_dev, forced, tol2, state, dvals, (k & 1) ? c1 : c0, (k & 1) ? c0 : c1);
+        const Cand *cin = (k & 1) ? c1 : c0;
+        Cand *cout = (k & 1) ? c0 : c1;
+        if (pgram && !forced) {
+            const int nreg = (r + k + ISDF_NS - 1) / ISDF_NS;
+#define ISDF_GRAM(M)                                                                                     \
+    if (nreg <= M) {                                                                                     \
+        hipLaunchKernelGGL(isdf_step_gram_kernel<M>, dim3(nblk), dim3(ISDF_NT), 0, s, ng, r, k, nblk, pgram, \
+                           gt, L, diag, sel_dev, tol2, state, dvals, cin, cout);                         \
+        continue;                                                                                        \
+    }
+            ISDF_GRAM(2) ISDF_GRAM(4) ISDF_GRAM(6) ISDF_GRAM(8) ISDF_GRAM(10) ISDF_GRAM(12) ISDF_GRAM(14)
+            ISDF_GRAM(16) ISDF_GRAM(18) ISDF_GRAM(20) ISDF_GRAM(24) ISDF_GRAM(28) ISDF_GRAM(32)
+#undef ISDF_GRAM
+        }
+        hipLaunchKernelGGL(isdf_step_kernel, dim3(nblk), dim3(ISDF_NT), 0, s, ng, ne, r, k, nblk, phi,
+                           forced ? nullptr : pgram, gt, L, diag, sel_dev, forced, tol2, state, dvals, cin, cout);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
