@@ -99,12 +99,15 @@ __device__ __forceinline__ void column_reduce(double v, double *red, double *red
     __syncthreads();
 }
 
-// LDS slots for the cross-wave reduction of C = Phi^T y (64 KB in total).
+// LDS slots for the cross-wave reduction of C = Phi^T y (at most 64 KB): the
+// waves write their partial C in NW / N phases of N slots, so N divides NW.
 template <int NB>
 struct Slots {
     static constexpr int NEP = NB * 16;
-    static constexpr int N = (512 / NEP) < NW ? (512 / NEP) : NW;
+    static constexpr int FIT = 512 / NEP;   // partials of NEP x 16 doubles in 64 KB
+    static constexpr int N = FIT >= 8 ? 8 : FIT >= 4 ? 4 : FIT >= 2 ? 2 : 1;
     static constexpr int ELEMS = NEP * kTile;
+    static_assert(NW % N == 0, "every wave has a slot in some phase");
 };
 
 // Pass 1 of the projected apply.  Each wave owns the 16-row blocks b = wave,

@@ -104,3 +104,24 @@ def test_lockstep_is_bitwise_neutral(monkeypatch):
     print(f"[mscg] workload 2: K = 4 vs K = 8, max rel diff {rel:.2e}", flush=True)
     assert rel < 1e-6   # two solves to relative residual 1e-8 with different sum orders
     ctx.close()
+
+
+@pytest.mark.parametrize("ne", [70, 86, 140])
+def test_orbital_blocks_with_partial_reduction_phases(ne):
+    """N_e padded to 80, 96 or 144 orbitals: the cross-wave reduction of Phi^T y
+    then uses 4 or 2 LDS slots per phase (not a divisor-free count that would
+    drop waves).  The multi-shift and the per-system solvers must reach the
+    requested true residual (recomputed in FP64 by the library)."""
+    ctx, G, om = _context_2d(ne=ne, n_mu=48)
+    print(f"[mscg] 2D, N_e = {ne}: multi-shift", flush=True)
+    ctx.compress(to_dev(G), to_dev(om))
+    assert ctx.stats()["max_rel_residual"] <= 1e-11
+    print(f"[mscg] 2D, N_e = {ne}: per-system CG", flush=True)
+    R = ctx.compress_get("rhs")
+    shifts = np.repeat(ctx.shifts()[:2], 8)
+    import torch
+    B = torch.cat([R[:, :8], R[:, 8:16]], dim=1)
+    ctx.reset_stats()
+    X, it, _ = ctx.sternheimer(shifts, B)
+    assert ctx.stats()["max_rel_residual"] <= 1e-11
+    ctx.close()
