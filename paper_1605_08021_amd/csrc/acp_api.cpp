@@ -520,6 +520,16 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
 }
 
 // A X = Q (H - s_j) Q X for column-major X (n columns); result in Y.
+// C = Phi^T X (N_e x n, leading dimension N_e) for column-major X (leading
+// dimension ldx): split-K over the grid when the output has few tiles.
+acp_status phi_t_times(acp_ctx *ctx, int n, const double *X, int ldx, double *C) {
+    const int ng = ctx->ng, ne = ctx->ne;
+    ENSURE(ctx->splitk, (size_t)8 * ne * n * 8);
+    HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, dp<double>(ctx->phi_cm), ng, X, ldx, 0.0, C, ne,
+                       dp<double>(ctx->splitk), ctx->splitk.bytes / 8, ctx->stream));
+    return ACP_OK;
+}
+
 acp_status apply_operator(acp_ctx *ctx, int n, const double *shifts_dev, const double *X,
                           double *Y) {
     const int ng = ctx->ng, ne = ctx->ne;
@@ -528,12 +538,12 @@ acp_status apply_operator(acp_ctx *ctx, int n, const double *shifts_dev, const d
     ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
     double *QX = dp<double>(ctx->tmp2), *C = dp<double>(ctx->c1);
     const double *phi = dp<double>(ctx->phi_cm);
-    HIPCHK(gemm(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, 0, X, ng, 0, 0.0, C, ne, 0, 1, s));
+    CHECK(phi_t_times(ctx, n, X, ng, C));
     HIPCHK(launch_scale_copy(ng, n, 1.0, X, ng, QX, ng, s));
     HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, QX, ng, 0, 1, s));
     HIPCHK(launch_stencil(ctx->gd, n, QX, ng, Y, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
                           shifts_dev, s));
-    HIPCHK(gemm(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, 0, Y, ng, 0, 0.0, C, ne, 0, 1, s));
+    CHECK(phi_t_times(ctx, n, Y, ng, C));
     HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, Y, ng, 0, 1, s));
     return ACP_OK;
 }
@@ -619,7 +629,7 @@ acp_status refine_fp32(acp_ctx *ctx, int n, const double *shifts_dev, const doub
             ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
             const double *phi = dp<double>(ctx->phi_cm);
             double *C = dp<double>(ctx->c1);
-            HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, AX, ng, 0, 0.0, C, ctx->ne, 0, 1, s));
+            CHECK(phi_t_times(ctx, n, AX, ng, C));
             HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, AX, ng, 0, 1, s));
         }
         HIPCHK(hipMemcpyAsync(ctx->colmask.p, mask.data(), (size_t)npad * 8, hipMemcpyHostToDevice, s));
@@ -639,7 +649,7 @@ acp_status refine_fp32(acp_ctx *ctx, int n, const double *shifts_dev, const doub
         ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
         const double *phi = dp<double>(ctx->phi_cm);
         double *C = dp<double>(ctx->c1);
-        HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, X, ng, 0, 0.0, C, ctx->ne, 0, 1, s));
+        CHECK(phi_t_times(ctx, n, X, ng, C));
         HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, X, ng, 0, 1, s));
     }
     *max_rel = m;
@@ -772,7 +782,7 @@ acp_status nn_apply(acp_ctx *ctx, const double *shift, int n, const double *R, i
     ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
     const double *phi = dp<double>(ctx->phi_cm);
     double *C = dp<double>(ctx->c1);
-    HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, D, ldd, 0, 0.0, C, ctx->ne, 0, 1, s));
+    CHECK(phi_t_times(ctx, n, D, ldd, C));
     HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, D, ldd, 0, 1, s));
     return ACP_OK;
 }
@@ -1661,7 +1671,7 @@ acp_status acp_precond_train_step(acp_ctx *ctx, const double *shift, int n, cons
     double *D = dp<double>(ctx->nn_d), *AD = dp<double>(ctx->nn_ad), *C = dp<double>(ctx->c1);
     const double *phi = dp<double>(ctx->phi_cm);
     auto project = [&](double *X) -> acp_status {
-        HIPCHK(gemm(Op::T, Op::N, ctx->ne, n, ng, 1.0, phi, ng, 0, X, ng, 0, 0.0, C, ctx->ne, 0, 1, s));
+        CHECK(phi_t_times(ctx, n, X, ng, C));
         HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, X, ng, 0, 1, s));
         return ACP_OK;
     };
