@@ -594,7 +594,10 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
                 if (pap > 0.0) {
                     al = gg / pap;
                 } else {
-                    s_flag[t] |= 2;
+                    // with FP32 storage the rearranged curvature can lose its sign
+                    // to storage rounding late in the solve: the column stops
+                    // unconverged and the FP64 refinement finishes it
+                    s_flag[t] |= sizeof(T) == 4 ? 1 : 2;
                     s_colact[t] = 0;
                 }
             }
