@@ -247,7 +247,8 @@ hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, in
 // Gauss-Jordan above 1024 unknowns.
 size_t lu_pinfo_ints(int n);
 hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *pinfo, hipStream_t s);
-// Symmetric eigenvalues (cyclic Jacobi), A overwritten; eig sorted ascending;
+// Symmetric eigenvalues (Householder + bisection up to n = 128, cyclic Jacobi
+// beyond), A overwritten; eig sorted ascending;
 // work holds n + 2 doubles + n + 2 ints.
 hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s);
 hipError_t launch_dynmat_assemble(int np, int dim, const double *Phi_el, const double *K_local,

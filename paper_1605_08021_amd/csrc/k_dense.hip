@@ -15,10 +15,12 @@
 // M~ is never formed: each step costs one column of K (N_g (N_e + r)) and one
 // update with the previous columns of L (N_g k).
 //
-// Dense algebra: Gauss-Jordan elimination with partial pivoting for the
-// N_mu x N_mu system of the Sherman-Morrison-Woodbury update (Eq. (3.13)),
-// triangular inversion, cyclic Jacobi for the eigenvalues of the dynamical
-// matrix, and the assembly D = M^{-1/2} (sym(h^d G^T U) + K_local) M^{-1/2}.
+// Dense algebra: a blocked LU with partial pivoting for the N_mu x N_mu system
+// of the Sherman-Morrison-Woodbury update (Eq. (3.13); Gauss-Jordan above 1024
+// unknowns), the blocked inverse of the triangular factor L11, Householder
+// tridiagonalisation with Sturm bisection for the eigenvalues of the dynamical
+// matrix (cyclic Jacobi above 128), and the assembly
+// D = M^{-1/2} (sym(h^d G^T U) + K_local) M^{-1/2}.
 #include "acp_internal.h"
 
 namespace acp {
