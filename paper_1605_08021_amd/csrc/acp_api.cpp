@@ -1244,18 +1244,27 @@ acp_status bfail(acp_batch *b, acp_status st, const std::string &msg) {
     } while (0)
 
 // Per system: the multi-shift buffers for K = 1, and its descriptor.
+// Workgroups per tile of a system in the batch: about 40 16-row blocks each
+// (640 grid rows), at most 8.
+int batch_group_size(const acp_ctx *ctx) {
+    const int nblk = (ctx->ng + 15) / 16;
+    return std::max(1, std::min(8, nblk / 40));
+}
+
 acp_status batch_describe(acp_batch *b, size_t i, MsArgs &a) {
     acp_ctx *ctx = b->sys[i];
     const int ng = ctx->ng, nc = (int)ctx->nodes.size();
     const int rhs_tiles = ctx->nmu_pad / kTile;
+    const int K = batch_group_size(ctx);
     const size_t vt = (size_t)ng * kTile;
     BENSURE(ctx->kx, (size_t)nc * rhs_tiles * vt * 8);
     BENSURE(ctx->msp, (size_t)nc * rhs_tiles * vt * 8);
     BENSURE(ctx->kr, (size_t)kMsWindow * rhs_tiles * vt * 8);
     BENSURE(ctx->kpa, (size_t)rhs_tiles * vt * 8);
     BENSURE(ctx->kpb, (size_t)rhs_tiles * vt * 8);
-    BENSURE(ctx->msgbuf, (size_t)rhs_tiles * 2 * mscg_group_slot(b->ne_pad) * 8);
+    BENSURE(ctx->msgbuf, (size_t)rhs_tiles * 2 * K * mscg_group_slot(b->ne_pad) * 8);
     BENSURE(ctx->mscnt, (size_t)rhs_tiles * 4);
+    BENSURE(ctx->mshalo, (size_t)rhs_tiles * K * 4);
     const int ncols = nc * rhs_tiles * kTile;
     BENSURE(ctx->kiters, (size_t)ncols * 4);
     BENSURE(ctx->kresid, (size_t)ncols * 8);
@@ -1270,7 +1279,7 @@ acp_status batch_describe(acp_batch *b, size_t i, MsArgs &a) {
     a.g = ctx->gd;
     a.ne = b->ne_pad;
     a.ntiles = rhs_tiles;
-    a.K = 1;
+    a.K = K;
     a.nshift = nc;
     a.base = base;
     a.shift = dp<double>(ctx->dy_s);
@@ -1286,7 +1295,7 @@ acp_status batch_describe(acp_batch *b, size_t i, MsArgs &a) {
     a.pb = dp<double>(ctx->kpb);
     a.gbuf = dp<double>(ctx->msgbuf);
     a.cnt = dp<unsigned>(ctx->mscnt);
-    a.active = dp<int>(ctx->msactive);
+    a.active = nullptr;   // no lockstep in the batch
     a.hflag = dp<int>(ctx->mshalo);
     a.abort_flag = dp<int>(b->abort_flag);
     a.iters = dp<int>(ctx->kiters);
@@ -1298,8 +1307,9 @@ acp_status batch_describe(acp_batch *b, size_t i, MsArgs &a) {
     return ACP_OK;
 }
 
-// Work list: every right-hand-side tile of every system; order 1 puts the
-// systems with the most grid points first (their tiles run longest).
+// Work list: the group members of every right-hand-side tile of every system
+// (consecutive); order 1 puts the systems with the most grid points first
+// (their tiles run longest).
 void batch_order(acp_batch *b, int order) {
     std::vector<size_t> idx(b->sys.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
@@ -1308,18 +1318,25 @@ void batch_order(acp_batch *b, int order) {
                          [&](size_t x, size_t y) { return b->sys[x]->ng > b->sys[y]->ng; });
     b->host_wsys.clear();
     b->host_wtile.clear();
-    for (size_t i : idx)
-        for (int t = 0; t < b->sys[i]->nmu_pad / kTile; ++t) {
-            b->host_wsys.push_back((int)i);
-            b->host_wtile.push_back(t);
-        }
+    for (size_t i : idx) {
+        const int K = batch_group_size(b->sys[i]);
+        for (int t = 0; t < b->sys[i]->nmu_pad / kTile; ++t)
+            for (int k = 0; k < K; ++k) {   // a group's members are consecutive entries
+                b->host_wsys.push_back((int)i);
+                b->host_wtile.push_back(t * kMsMaxGroup + k);
+            }
+    }
 }
 
 // The launch sequence: zero the per-tile counters, the abort flag and the work
 // counter (fill kernels: the sequence may be captured), then the batch kernel.
 acp_status batch_enqueue(acp_batch *b, int grid) {
     hipStream_t s = b->stream;
-    for (acp_ctx *ctx : b->sys) BHIP(launch_fill_u32(dp<unsigned>(ctx->mscnt), ctx->nmu_pad / kTile, 0u, s));
+    for (acp_ctx *ctx : b->sys) {
+        const int tiles = ctx->nmu_pad / kTile;
+        BHIP(launch_fill_u32(dp<unsigned>(ctx->mscnt), tiles, 0u, s));
+        BHIP(launch_fill_i32(dp<int>(ctx->mshalo), (size_t)tiles * batch_group_size(ctx), 0, s));
+    }
     BHIP(launch_fill_i32(dp<int>(b->abort_flag), 1, 0, s));
     BHIP(launch_fill_u32(dp<unsigned>(b->queue), 1, 0u, s));
     BHIP(launch_mscg_batch_fp64(b->dim, b->ne_pad, dp<MsArgs>(b->desc), dp<int>(b->wsys), dp<int>(b->wtile),
@@ -1789,7 +1806,7 @@ acp_status acp_batch_compress(acp_batch *b, const double *const *G, const int *n
         acp_ctx *ctx = b->sys[i];
         ctx->stats.ms_solve_kernel += b->ms_last / b->sys.size();
         ctx->stats.solve_kernel_launches += 1;
-        ctx->stats.krylov_group = 1;
+        ctx->stats.krylov_group = batch_group_size(ctx);
         const acp_status st = batch_finish(b, i);
         if (st != ACP_OK && worst == ACP_OK) worst = st;
     }

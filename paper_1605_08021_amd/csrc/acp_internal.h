@@ -172,9 +172,11 @@ constexpr int kMsWindow = 16;
 constexpr int kMsMaxGroup = 16;   // workgroups per right-hand-side tile
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s);
 hipError_t launch_mscg_fp32(const MsArgsT<float> &a, hipStream_t s);
-// Persistent ragged batch (K = 1 per tile): systems[] are device descriptors of
-// systems with the same dim whose orbital blocks are padded to ne_pad; the work
-// list (work_sys[w], work_tile[w]) is consumed through *queue (zero at launch).
+// Persistent ragged batch: systems[] are device descriptors of systems with the
+// same dim whose orbital blocks are padded to ne_pad (each with its own group
+// size K); the work list (work_sys[w], work_tile[w] = tile * kMsMaxGroup + kg,
+// the K members of a tile consecutive) is consumed in order through *queue
+// (zero at launch); grid >= the largest K.
 hipError_t launch_mscg_batch_fp64(int dim, int ne_pad, const MsArgs *systems, const int *work_sys,
                                   const int *work_tile, int n_work, unsigned *queue, int grid,
                                   hipStream_t s);

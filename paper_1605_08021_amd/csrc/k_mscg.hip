@@ -727,8 +727,13 @@ __global__ __launch_bounds__(NT) void mscg_kernel(MsArgsT<T> a) {
 }
 
 // Persistent batch: every workgroup takes the next entry of a work list (one
-// right-hand-side tile of one system, K = 1) from a global counter until the
-// list is exhausted; systems of different sizes share the launch.
+// member kg of the group of one right-hand-side tile of one system, coded as
+// tile * KMAX + kg) from a global counter until the list is exhausted; systems
+// of different sizes (and group sizes, systems[s].K) share the launch.  The K
+// members of a group are consecutive entries and the counter hands entries out
+// in order, so at most one group is ever incomplete, and its missing members
+// are the next entries taken by workgroups that finish complete groups: with a
+// grid of at least K resident workgroups every group barrier is reached.
 template <int DIM, int NB, typename T>
 __global__ __launch_bounds__(NT) void mscg_batch_kernel(const MsArgsT<T> *__restrict__ systems,
                                                         const int *__restrict__ work_sys,
@@ -743,7 +748,7 @@ __global__ __launch_bounds__(NT) void mscg_batch_kernel(const MsArgsT<T> *__rest
         const int w = s_w;
         if (w >= n_work) break;
         const MsArgsT<T> a = systems[work_sys[w]];
-        mscg_tile<DIM, NB, T>(a, work_tile[w], 0);
+        mscg_tile<DIM, NB, T>(a, work_tile[w] / KMAX, work_tile[w] % KMAX);
     }
 }
 
