@@ -79,7 +79,7 @@ struct acp_ctx {
     struct TuneEntry { long long key; int K, sg; float ms; };
     std::vector<TuneEntry> tune_log;
     DevBuf nn_wf[4], nn_wb[4], nn_act[4], nn_g[4];
-    DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc;           // flexible CG
+    DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc, fc_idx;   // flexible CG
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     acp_stats stats{};
@@ -810,19 +810,29 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
     ENSURE(ctx->fc_z, bytes);
     ENSURE(ctx->fc_p, bytes);
     ENSURE(ctx->fc_q, bytes);
-    ENSURE(ctx->fc_sc, (size_t)3 * n * 8);
+    ENSURE(ctx->fc_sc, (size_t)4 * n * 8);
+    ENSURE(ctx->fc_idx, (size_t)2 * n * 4);
     double *R = dp<double>(ctx->fc_r), *Z = dp<double>(ctx->fc_z), *P = dp<double>(ctx->fc_p),
            *Q = dp<double>(ctx->fc_q);
-    double *d_a = dp<double>(ctx->fc_sc), *d_b = d_a + n, *d_t = d_b + n;
+    double *d_a = dp<double>(ctx->fc_sc), *d_b = d_a + n, *d_t = d_b + n, *d_sh = d_t + n;
+    int *d_cols = dp<int>(ctx->fc_idx), *d_ord = d_cols + n;
+    // The open systems occupy the first w columns of R, Z, P, Q (compact index i
+    // is system cols[i]); X stays in system order.  When fewer than 3/4 of the w
+    // columns are still open, the open ones are gathered to the front, so the
+    // network and the operator are applied to open systems only.
+    int w = n;
+    std::vector<int> cols(n);
+    std::vector<double> shc(shift_h, shift_h + n);
+    for (int j = 0; j < n; ++j) cols[j] = j;
     auto precond = [&](const double *Rin, double *Zout) -> acp_status {
-        if (mode == 1) return nn_apply(ctx, shift_h, n, Rin, ng, Zout, ng);
-        HIPCHK(hipMemcpyAsync(Zout, Rin, bytes, hipMemcpyDeviceToDevice, s));
+        if (mode == 1) return nn_apply(ctx, shc.data(), w, Rin, ng, Zout, ng);
+        HIPCHK(hipMemcpyAsync(Zout, Rin, (size_t)ng * w * 8, hipMemcpyDeviceToDevice, s));
         return ACP_OK;
     };
     auto col = [&](hipError_t (*fn)(int, int, const double *, int, const double *, int, double *, hipStream_t),
                    const double *A1, const double *A2, std::vector<double> &h) -> acp_status {
-        HIPCHK(fn(ng, n, A1, ng, A2, ng, d_t, s));
-        HIPCHK(hipMemcpyAsync(h.data(), d_t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(fn(ng, w, A1, ng, A2, ng, d_t, s));
+        HIPCHK(hipMemcpyAsync(h.data(), d_t, (size_t)w * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         return ACP_OK;
     };
@@ -831,6 +841,8 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
     std::vector<double> bn(n), rz(n), pq(n), rr(n), zq(n), rzn(n), al(n), nal(n), be(n);
     HIPCHK(hipMemsetAsync(X, 0, bytes, s));
     HIPCHK(hipMemcpyAsync(R, B, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_cols, cols.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_sh, shc.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     CHECK(col(launch_col_dot, B, B, bn));
     std::vector<int> act(n);
     for (int j = 0; j < n; ++j) {
@@ -841,57 +853,88 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
     CHECK(precond(R, Z));
     HIPCHK(hipMemcpyAsync(P, Z, bytes, hipMemcpyDeviceToDevice, s));
     CHECK(col(launch_col_dot, R, Z, rz));
+    std::vector<int> ord;
     for (int k = 0; k < ctx->opts.max_iter; ++k) {
         int open = 0;
-        for (int j = 0; j < n; ++j) open += act[j];
+        for (int i = 0; i < w; ++i) open += act[i];
         if (!open) break;
-        CHECK(apply_operator(ctx, n, shifts_dev, P, Q));
+        if (4 * open < 3 * w && w > kTile) {
+            // gather the open columns of R and P to the front (through Q)
+            ord.clear();
+            for (int i = 0; i < w; ++i)
+                if (act[i]) ord.push_back(i);
+            HIPCHK(hipMemcpyAsync(d_ord, ord.data(), (size_t)open * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_col_gather(ng, open, R, ng, d_ord, Q, ng, s));
+            HIPCHK(hipMemcpyAsync(R, Q, (size_t)ng * open * 8, hipMemcpyDeviceToDevice, s));
+            HIPCHK(launch_col_gather(ng, open, P, ng, d_ord, Q, ng, s));
+            HIPCHK(hipMemcpyAsync(P, Q, (size_t)ng * open * 8, hipMemcpyDeviceToDevice, s));
+            for (int i = 0; i < open; ++i) {
+                const int o = ord[i];
+                cols[i] = cols[o];
+                bn[i] = bn[o];
+                rz[i] = rz[o];
+                shc[i] = shc[o];
+                act[i] = 1;
+            }
+            w = open;
+            HIPCHK(hipMemcpyAsync(d_cols, cols.data(), (size_t)w * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_sh, shc.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));   // ord, cols, shc reused below
+        }
+        CHECK(apply_operator(ctx, w, d_sh, P, Q));
         CHECK(col(launch_col_dot, P, Q, pq));
-        for (int j = 0; j < n; ++j) {
-            al[j] = 0.0;
-            if (!act[j]) continue;
-            if (!(pq[j] > 0.0)) {
+        for (int i = 0; i < w; ++i) {
+            al[i] = 0.0;
+            if (!act[i]) continue;
+            if (!(pq[i] > 0.0)) {
                 *flags_or |= 2;
-                act[j] = 0;
+                act[i] = 0;
                 continue;
             }
-            al[j] = rz[j] / pq[j];
+            al[i] = rz[i] / pq[i];
         }
-        for (int j = 0; j < n; ++j) nal[j] = -al[j];
-        HIPCHK(hipMemcpyAsync(d_a, al.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d_b, nal.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_col_axpby(ng, n, d_a, P, ng, nullptr, X, ng, s));   // x += alpha p
-        HIPCHK(launch_col_axpby(ng, n, d_b, Q, ng, nullptr, R, ng, s));   // r -= alpha Ap
+        for (int i = 0; i < w; ++i) nal[i] = -al[i];
+        HIPCHK(hipMemcpyAsync(d_a, al.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_b, nal.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_col_axpy_scatter(ng, w, d_a, P, ng, d_cols, X, ng, s));   // x += alpha p
+        HIPCHK(launch_col_axpby(ng, w, d_b, Q, ng, nullptr, R, ng, s));          // r -= alpha Ap
         CHECK(col(launch_col_dot, R, R, rr));
-        for (int j = 0; j < n; ++j)
-            if (act[j]) {
-                iters[j] += 1;
-                if (std::sqrt(rr[j]) <= ctx->opts.tol * bn[j]) act[j] = 0;
+        for (int i = 0; i < w; ++i)
+            if (act[i]) {
+                iters[cols[i]] += 1;
+                if (std::sqrt(rr[i]) <= ctx->opts.tol * bn[i]) act[i] = 0;
             }
         open = 0;
-        for (int j = 0; j < n; ++j) open += act[j];
+        for (int i = 0; i < w; ++i) open += act[i];
         if (!open) break;
         CHECK(precond(R, Z));
         CHECK(col(launch_col_dot, Z, Q, zq));
         CHECK(col(launch_col_dot, R, Z, rzn));
-        for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < w; ++i) {
             // beta = -alpha z'.Ap / r.z  (= -z'.Ap / p.Ap)
-            be[j] = (act[j] && rz[j] != 0.0) ? -al[j] * zq[j] / rz[j] : 0.0;
-            rz[j] = rzn[j];
+            be[i] = (act[i] && rz[i] != 0.0) ? -al[i] * zq[i] / rz[i] : 0.0;
+            rz[i] = rzn[i];
         }
-        HIPCHK(hipMemcpyAsync(d_t, be.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_col_axpby(ng, n, nullptr, Z, ng, d_t, P, ng, s));   // p = z + beta p
+        HIPCHK(hipMemcpyAsync(d_t, be.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_col_axpby(ng, w, nullptr, Z, ng, d_t, P, ng, s));   // p = z + beta p
     }
-    int open = 0;
-    for (int j = 0; j < n; ++j) open += act[j];
-    if (open && mode == 1) {
-        // fallback: FP64 MINRES solves A d = r for the columns still open (the
-        // others get a zero right-hand side and stop at once); x += d
-        std::vector<double> mask(n);
-        for (int j = 0; j < n; ++j) mask[j] = act[j] ? 1.0 : 0.0;
-        HIPCHK(hipMemcpyAsync(d_a, mask.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    // the still-open systems, back in system order: R(:, i) -> Z(:, cols[i])
+    {
+        std::vector<double> mask(w);
+        for (int i = 0; i < w; ++i) mask[i] = act[i] ? 1.0 : 0.0;
+        HIPCHK(hipMemcpyAsync(d_a, mask.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemsetAsync(Z, 0, bytes, s));
-        HIPCHK(launch_col_axpby(ng, n, d_a, R, ng, nullptr, Z, ng, s));   // Z = mask r
+        HIPCHK(launch_col_axpy_scatter(ng, w, d_a, R, ng, d_cols, Z, ng, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    std::vector<int> act_sys(n, 0);
+    for (int i = 0; i < w; ++i) act_sys[cols[i]] = act[i];
+    int open = 0;
+    for (int j = 0; j < n; ++j) open += act_sys[j];
+    if (open && mode == 1) {
+        // fallback: FP64 MINRES solves A d = r for the columns still open (Z holds
+        // their residuals; the others get a zero right-hand side and stop at
+        // once); x += d
         const int ntiles = (n + kTile - 1) / kTile, npad = ntiles * kTile;
         ENSURE(ctx->krhs, (size_t)npad * ng * 8);
         HIPCHK(launch_to_tiled(ng, n, npad, Z, ng, dp<double>(ctx->krhs), s));
@@ -2061,7 +2104,8 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->nn_wb[0], &ctx->nn_wb[1], &ctx->nn_wb[2], &ctx->nn_wb[3],
                       &ctx->nn_act[0], &ctx->nn_act[1], &ctx->nn_act[2], &ctx->nn_act[3],
                       &ctx->nn_g[0], &ctx->nn_g[1], &ctx->nn_g[2], &ctx->nn_g[3],
-                      &ctx->fc_r, &ctx->fc_z, &ctx->fc_p, &ctx->fc_q, &ctx->fc_sc, &ctx->dy_piv, &ctx->vc_g};
+                      &ctx->fc_r, &ctx->fc_z, &ctx->fc_p, &ctx->fc_q, &ctx->fc_sc, &ctx->fc_idx, &ctx->dy_piv,
+                      &ctx->vc_g};
     for (DevBuf *b : bufs) release(*b);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);

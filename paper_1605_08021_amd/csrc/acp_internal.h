@@ -219,6 +219,11 @@ hipError_t nn_adam(int np, float *theta, float *m, float *v, const float *g, flo
                    hipStream_t s);
 hipError_t launch_col_dot(int m, int n, const double *X, int ldx, const double *Y, int ldy,
                           double *out, hipStream_t s);                     // out[j] = X(:,j).Y(:,j)
+// dst(:, i) = src(:, idx[i]) and Y(:, idx[i]) += a[i] X(:, i) for i < n (idx on the device).
+hipError_t launch_col_gather(int m, int n, const double *src, int lds, const int *idx, double *dst, int ldd,
+                             hipStream_t s);
+hipError_t launch_col_axpy_scatter(int m, int n, const double *a, const double *X, int ldx, const int *idx,
+                                   double *Y, int ldy, hipStream_t s);
 hipError_t launch_col_axpby(int m, int n, const double *a, const double *X, int ldx, const double *b,
                             double *Y, int ldy, hipStream_t s);  // Y(:,j) = a[j] X(:,j) + b[j] Y(:,j)
 

@@ -130,6 +130,24 @@ __global__ void col_axpby_kernel(int m, int n, const double *__restrict__ a, con
     *y = av * X[(long long)j * ldx + r] + bv * *y;
 }
 
+// dst(:, i) = src(:, idx[i]), i < n.
+__global__ void col_gather_kernel(int m, int n, const double *__restrict__ src, int lds,
+                                  const int *__restrict__ idx, double *dst, int ldd) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)m * n) return;
+    const int j = (int)(i / m), r = (int)(i % m);
+    dst[(long long)j * ldd + r] = src[(long long)idx[j] * lds + r];
+}
+
+// Y(:, idx[i]) += a[i] X(:, i), i < n (the idx[i] distinct).
+__global__ void col_axpy_scatter_kernel(int m, int n, const double *__restrict__ a, const double *X, int ldx,
+                                        const int *__restrict__ idx, double *Y, int ldy) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)m * n) return;
+    const int j = (int)(i / m), r = (int)(i % m);
+    Y[(long long)idx[j] * ldy + r] += a[j] * X[(long long)j * ldx + r];
+}
+
 // One block per column: out[j] = ||X(:,j) - Y(:,j)||^2 (deterministic).
 __global__ void col_diff_sqnorm_kernel(int m, const double *X, int ldx, const double *Y, int ldy,
                                        double *out) {
@@ -449,6 +467,23 @@ hipError_t launch_col_axpby(int m, int n, const double *a, const double *X, int 
     const long long tot = (long long)m * n;
     if (tot <= 0) return hipSuccess;
     hipLaunchKernelGGL(col_axpby_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, a, X, ldx, b, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_gather(int m, int n, const double *src, int lds, const int *idx, double *dst, int ldd,
+                             hipStream_t s) {
+    const long long tot = (long long)m * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_gather_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, src, lds, idx, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_axpy_scatter(int m, int n, const double *a, const double *X, int ldx, const int *idx,
+                                   double *Y, int ldy, hipStream_t s) {
+    const long long tot = (long long)m * n;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_axpy_scatter_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, a, X, ldx, idx, Y,
+                       ldy);
     return hipGetLastError();
 }
 
