@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--form", choices=["fast", "mixed", "learned", "single", "plain", "batch"],
+    ap.add_argument("--form", choices=["fast", "mixed", "learned", "single", "plain", "batch", "compress"],
                     default="fast")
     ap.add_argument("--batch-systems", type=int, default=16)
     ap.add_argument("--dyson-iters", type=int, default=4)
@@ -168,7 +168,9 @@ def main():
 
     phi, veff, G, om = T(inp.phi), T(inp.veff), T(inp.G), T(inp.omega)
     solver = {"fast": acp.SOLVER_CG, "mixed": acp.SOLVER_CG, "single": acp.SOLVER_CG_SINGLE,
-              "plain": acp.SOLVER_MINRES, "learned": acp.SOLVER_CG_SINGLE}[args.form]
+              "plain": acp.SOLVER_MINRES, "learned": acp.SOLVER_CG_SINGLE,
+              "compress": acp.SOLVER_CG}[args.form]
+    compress_only = args.form == "compress"
     learned = args.form == "learned"
     mixed = args.form == "mixed"
     opts = dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol, max_iter=20000,
@@ -198,6 +200,9 @@ def main():
         log(f"preconditioner trained: {train_info}")
 
     def step():
+        if compress_only:
+            ctx.compress(G, om)
+            return 1, None
         U, iters, _ = ctx.dyson(G, om)
         D, w2 = ctx.dynmat(G, U, inp.K_local, masses)
         return iters, w2
@@ -262,9 +267,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
                                f"ground state, gap {inp.gap:.5f} Ha",
-                   "form": ("flexible CG with the learned BF16 conv preconditioner (FP64 vectors)"
+                   "form": ("one compression per step (point selection, right-hand sides, "
+                            "batched FP64 multi-shift CG, W); no Dyson update or dynamical matrix"
+                            if compress_only else
+                            "flexible CG with the learned BF16 conv preconditioner (FP64 vectors)"
                             if learned else
-                            "FP32-storage multi-shift CG + FP64 iterative refinement") if (mixed or learned) else
+                            "FP32-storage multi-shift CG + FP64 iterative refinement") if (mixed or learned or compress_only) else
                            {acp.SOLVER_CG: "batched FP64 multi-shift CG",
                             acp.SOLVER_CG_SINGLE: "batched FP64 CG, one sequence per system",
                             acp.SOLVER_MINRES: "plain FP64 MINRES"}[solver],

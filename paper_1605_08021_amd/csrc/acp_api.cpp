@@ -1030,8 +1030,9 @@ acp_status setup_impl(acp_ctx *ctx, const acp_grid *grid, const acp_opts *opts, 
     return ACP_OK;
 }
 
-// Largest Phi Phi^T kept for the point selection (4 GiB: N_g up to 23170).
-constexpr double kGramBudgetBytes = 4.0 * 1024 * 1024 * 1024;
+// Largest Phi Phi^T kept for the point selection (16 GiB of the 288 GiB of
+// HBM: N_g up to 46340).
+constexpr double kGramBudgetBytes = 16.0 * 1024 * 1024 * 1024;
 
 // Alg. 2 (sketched) for the columns of G: fills ctx->sel_dev / sel_host, ctx->xi.
 acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega,

@@ -112,6 +112,58 @@ def _lowest(H, k):
     return sla.eigh(H, subset_by_index=[0, k - 1], driver="evr")
 
 
+# Grids above this size are diagonalised iteratively (a dense matrix would not fit).
+_DENSE_MAX = 8000
+
+
+def _kinetic_sparse(grid: "_Grid"):
+    """-1/2 Delta_h as a sparse matrix (same stencil as kinetic_dense)."""
+    import scipy.sparse as sp
+
+    def d2(n, h):
+        rows, cols, vals = [], [], []
+        for i in range(n):
+            for k in range(-4, 5):
+                rows.append(i)
+                cols.append((i + k) % n)
+                vals.append(_C[abs(k)] / h ** 2)
+        return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+    Dx = d2(grid.n[0], grid.h)
+    if grid.d == 1:
+        return (-0.5 * Dx).tocsr()
+    Dy = d2(grid.n[1], grid.h)
+    return (-0.5 * (sp.kron(sp.eye(grid.n[1]), Dx) + sp.kron(Dy, sp.eye(grid.n[0])))).tocsr()
+
+
+def _lowest_sparse(T, V, k):
+    """The k lowest eigenpairs of T + diag(V) by shift-invert Lanczos with the
+    shift below the spectrum (T is positive semidefinite)."""
+    import sys
+    import time
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    H = (T + sp.diags(V)).tocsc()
+    sigma = float(V.min()) - 1.0
+    t0 = time.perf_counter()
+    lu = spla.splu((H - sigma * sp.eye(H.shape[0])).tocsc())
+    print(f"[inputs] factorised H - sigma I ({H.shape[0]} points) in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    solves = [0]
+
+    def inv(x):
+        solves[0] += 1
+        if solves[0] % 200 == 0:
+            print(f"[inputs] {solves[0]} shift-invert solves, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+        return lu.solve(x)
+
+    op = spla.LinearOperator(H.shape, matvec=inv, dtype=np.float64)
+    w, v = spla.eigsh(H, k=k, sigma=sigma, OPinv=op, which="LM", tol=1e-13)
+    o = np.argsort(w)
+    return w[o], v[:, o]
+
+
 def _kerker(grid: _Grid, q0: float = 0.3) -> np.ndarray:
     q2 = np.zeros(grid.shape)
     for ax, k in enumerate(reversed(grid.n)):
@@ -185,8 +237,14 @@ def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
         rho += (Z[I] / z_ref) * np.interp(dist[:, I], r_tab, rho_tab, right=0.0)
     # exact neutrality of the start
     rho *= (cfg.f * n_e) / (rho.sum() * grid.dv)
-    T = grid.kinetic_dense()
-    rho, V, w, v, sc = _scf(grid, T, m, rho, n_e, cfg.f, max(scf_iters, 0) + 1, 1e-8)
+    if grid.ng <= _DENSE_MAX:
+        T = grid.kinetic_dense()
+        rho, V, w, v, sc = _scf(grid, T, m, rho, n_e, cfg.f, max(scf_iters, 0) + 1, 1e-8)
+    else:
+        # large grids: the Harris potential only, diagonalised iteratively
+        V = grid.vc(rho + m)
+        w, v = _lowest_sparse(_kinetic_sparse(grid), V, n_e + 1)
+        sc = False
     phi = np.ascontiguousarray(v[:, :n_e])
     rho_gs = (cfg.f / grid.dv) * (phi ** 2).sum(axis=1)
     # perturbations g_{I,a} = v_c d m_I / d R_{I,a} and the local Hessian terms
