@@ -797,8 +797,13 @@ hipError_t launch_mscg(const MsArgsT<T> &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     if (a.nshift > MAXSH || a.ne > 256 || a.K < 1 || a.K > KMAX) return hipErrorInvalidValue;
     const int nb = (a.ne + 15) / 16;
+    // 2D grids whose lines hold a multiple of 4 points take the compact stencil
+    // gather (the 4 rows of a group share one line)
+    const bool compact2d = a.g.dim == 2 && a.g.nx % 4 == 0;
 #define CASE(N)                                                                    \
-    if (nb == N) return a.g.dim == 1 ? launch_ms<1, N, T>(a, s) : launch_ms<2, N, T>(a, s);
+    if (nb == N)                                                                   \
+        return a.g.dim == 1 ? launch_ms<1, N, T>(a, s)                             \
+                            : compact2d ? launch_ms<3, N, T>(a, s) : launch_ms<2, N, T>(a, s);
     ACP_NB_CASES(CASE)
 #undef CASE
     return hipErrorInvalidValue;

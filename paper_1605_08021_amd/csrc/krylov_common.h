@@ -20,15 +20,31 @@ __device__ __forceinline__ int wrap(int i, int n) {
 
 // Neighbour rows of the 4-row group R..R+3 of one system, for the 8th-order
 // stencil.  1D: rows R-4 .. R+7 (12 rows, periodic).  2D: for each of the 4 rows
-// its 8 x-neighbours and 8 y-neighbours.  Every index is clamped into [0, ng)
-// so that all loads can be issued unconditionally (rows past the end of the grid
-// in the last block are computed but never stored).
+// its 8 x-neighbours and 8 y-neighbours.  DIM = 3 is the 2D grid with n_x a
+// multiple of 4, where the 4 rows of a group share one grid line: the x-window
+// x-4 .. x+7 of that line (12 values) and the 8 y-neighbours of each row (32).
+// Every index is clamped into [0, ng) so that all loads can be issued
+// unconditionally (rows past the end of the grid in the last block are
+// computed but never stored).
 template <int DIM>
 struct Nbr {
-    static constexpr int N = DIM == 1 ? 12 : 4 * 17;
+    static constexpr int N = DIM == 1 ? 12 : DIM == 3 ? 12 + 32 : 4 * 17;
     int idx[N];
     __device__ __forceinline__ Nbr(int R, const GridDesc &g) {
-        if (DIM == 1) {
+        if (DIM == 3) {
+            const int r0 = R + 3 < g.ng ? R : g.ng - 4;   // whole group inside the grid
+            const int ix = r0 % g.nx, iy = r0 / g.nx;
+            const int line = iy * g.nx;
+#pragma unroll
+            for (int o = -4; o < 8; ++o) idx[4 + o] = line + wrap(ix + o, g.nx);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int k = 1; k <= 4; ++k) {
+                    idx[12 + 8 * j + (k - 1)] = wrap(iy + k, g.ny) * g.nx + ix + j;
+                    idx[12 + 8 * j + 4 + (k - 1)] = wrap(iy - k, g.ny) * g.nx + ix + j;
+                }
+        } else if (DIM == 1) {
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
                 int rr = R - 4 + q;
@@ -73,6 +89,12 @@ __device__ __forceinline__ void stencil_from(const double (&w)[Nbr<DIM>::N], int
             lap = fd8(0) * c;
 #pragma unroll
             for (int k = 1; k <= 4; ++k) lap += fd8(k) * (w[4 + j + k] + w[4 + j - k]);
+        } else if (DIM == 3) {
+            c = w[4 + j];
+            lap = 2.0 * fd8(0) * c;
+#pragma unroll
+            for (int k = 1; k <= 4; ++k)
+                lap += fd8(k) * (w[4 + j + k] + w[4 + j - k] + w[12 + 8 * j + (k - 1)] + w[12 + 8 * j + 4 + (k - 1)]);
         } else {
             c = w[17 * j];
             lap = 2.0 * fd8(0) * c;
