@@ -80,8 +80,6 @@ hipError_t launch_col_diff_sqnorm(int m, int n, const double *X, int ldx, const 
                                   int ldy, double *out, hipStream_t s);  // ||X(:,j)-Y(:,j)||^2
 hipError_t launch_axpby(int m, int n, double a, const double *X, int ldx, double b, double *Y,
                         int ldy, hipStream_t s);                           // Y = a X + b Y
-hipError_t launch_diff_sqnorm(int m, int n, const double *X, const double *Y, int ld,
-                              double *out2, hipStream_t s);  // out2[0]=||X-Y||^2, out2[1]=||X||^2
 hipError_t launch_weighted_rows(int ne, int nmu, const double *L, const int *sel,
                                 const double *phi, int ldphi, double *Bc, hipStream_t s);
 hipError_t launch_gram_check(int n, int unused, const double *G, double *maxdev, hipStream_t s);

@@ -177,31 +177,6 @@ __global__ void axpby_kernel(int m, int n, double a, const double *X, int ldx, d
     Y[i + j * ldy] = a * X[i + j * ldx] + b * Y[i + j * ldy];
 }
 
-// Single block: out[0] = ||X - Y||_F^2, out[1] = ||X||_F^2 (deterministic).
-__global__ void diff_sqnorm_kernel(long long tot, int m, int ld, const double *X, const double *Y,
-                                   double *out) {
-    __shared__ double r0[1024], r1[1024];
-    double a = 0.0, b = 0.0;
-    for (long long idx = threadIdx.x; idx < tot; idx += 1024) {
-        int i = (int)(idx % m);
-        long long j = idx / m;
-        double x = X[i + j * ld], y = Y[i + j * ld];
-        a += (x - y) * (x - y);
-        b += x * x;
-    }
-    r0[threadIdx.x] = a;
-    r1[threadIdx.x] = b;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            r0[threadIdx.x] += r0[threadIdx.x + w];
-            r1[threadIdx.x] += r1[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) { out[0] = r0[0]; out[1] = r1[0]; }
-}
-
 // Bc(i, mu) = L(i) * phi(sel[mu], i): the N_e x N_mu factor diag(L_c) Phi(Pi,:)^T of Eq. (3.7).
 __global__ void weighted_rows_kernel(int ne, int nmu, const double *L, const int *sel,
                                      const double *phi, int ldphi, double *Bc) {
@@ -500,13 +475,6 @@ hipError_t launch_axpby(int m, int n, double a, const double *X, int ldx, double
     if (tot <= 0) return hipSuccess;
     hipLaunchKernelGGL(axpby_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, a, X, ldx, b, Y,
                        ldy);
-    return hipGetLastError();
-}
-
-hipError_t launch_diff_sqnorm(int m, int n, const double *X, const double *Y, int ld, double *out2,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(diff_sqnorm_kernel, dim3(1), dim3(1024), 0, s, (long long)m * n, m, ld, X,
-                       Y, out2);
     return hipGetLastError();
 }
 
