@@ -161,8 +161,21 @@ struct MsArgsT {
     double tol;
     int max_iter;
     unsigned long long *phase_clock;   // 8 phase timers of workgroup 0 (ACP_PHASE_CLOCKS builds)
+    // Suspend and resume at window boundaries (both multiples of the window
+    // length): it0 > 0 resumes every tile at iteration it0 from the vectors in
+    // x, p, pa and ring slot it0 of r and from the scalars in state; stop_at > 0
+    // suspends a tile still running at the top of iteration stop_at, leaving
+    // its scalars in state.  state: [ntiles][kMsStateFields][16] doubles, then
+    // [ntiles][16] carry flags (1: suspended and still live).
+    int it0, stop_at;
+    double *state;
 };
 using MsArgs = MsArgsT<double>;
+// Scalar state of one right-hand side of a tile: its base-sequence scalars
+// (fields 0-7: r.r, |b|, b_{k-1}, a_{k-1}, flags, live, suspended, unused),
+// then six per shift (zeta_k, zeta_{k-1}, b^c, converged residual, live,
+// iterations).
+constexpr int kMsStateFields = 8 + 6 * 16;
 // Longest window of the deferred solution updates of the multi-shift solver (16
 // iterations with at most 8 shifts, else 8); the residual ring holds this many
 // residuals per tile.
@@ -218,6 +231,13 @@ hipError_t nn_adam(int np, float *theta, float *m, float *v, const float *g, flo
 hipError_t launch_col_dot(int m, int n, const double *X, int ldx, const double *Y, int ldy,
                           double *out, hipStream_t s);                     // out[j] = X(:,j).Y(:,j)
 // dst(:, i) = src(:, idx[i]) and Y(:, idx[i]) += a[i] X(:, i) for i < n (idx on the device).
+// Columns of tile-interleaved vectors ([tile][row][16]): destination column m
+// of each of nvec vectors (strides svs, dvs elements) takes source column map[m];
+// map[m] < 0 writes zero (zero_missing) or skips the column.  ncols = 16 x tiles.
+hipError_t launch_tilecol_gather(int rows, int ncols, const int *map, const double *src, long long svs,
+                                 double *dst, long long dvs, int nvec, bool zero_missing, hipStream_t s);
+hipError_t launch_tilecol_gather(int rows, int ncols, const int *map, const float *src, long long svs,
+                                 float *dst, long long dvs, int nvec, bool zero_missing, hipStream_t s);
 hipError_t launch_col_gather(int m, int n, const double *src, int lds, const int *idx, double *dst, int ldd,
                              hipStream_t s);
 hipError_t launch_col_axpy_scatter(int m, int n, const double *a, const double *X, int ldx, const int *idx,

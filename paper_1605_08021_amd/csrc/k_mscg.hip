@@ -392,9 +392,11 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     };
 
     if (t == 0) s_abort = 0;
-    // ---- init (own rows): r_0 = b, s = 0, x_c = 0, p_c = 0; |b|^2
+    // ---- init (own rows): r_0 = b, s = 0, x_c = 0, p_c = 0; |b|^2 (a resumed
+    // tile finds its vectors in place)
+    const bool resume = a.it0 > 0;
     double bb = 0.0;
-    {
+    if (!resume) {
         T *rz = Rs(0);
         for (int blk = kb0 + wave; blk < kb1; blk += NW) {
             const int R = blk * 16 + 4 * q;
@@ -438,7 +440,26 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
     }
     __syncthreads();
     gs.local = s_local != 0;
-    if (t < kTile) {
+    // scalar state of a resumed tile, as the suspending launch left it
+    auto st_at = [&](int f) -> double & {
+        return a.state[((size_t)tile * kMsStateFields + f) * kTile + t];
+    };
+    if (resume && t < kTile) {
+        s_rr[t] = st_at(0);
+        s_bn[t] = st_at(1);
+        s_btp[t] = st_at(2);
+        s_alp[t] = st_at(3);
+        s_flag[t] = (int)st_at(4);
+        s_colact[t] = (int)st_at(5);
+        for (int c = 0; c < ns; ++c) {
+            s_z[c][t] = st_at(8 + 6 * c);
+            s_zp[c][t] = st_at(9 + 6 * c);
+            s_bs[c][t] = st_at(10 + 6 * c);
+            s_res[c][t] = st_at(11 + 6 * c);
+            s_act[c][t] = (int)st_at(12 + 6 * c);
+            s_it[c][t] = (int)st_at(13 + 6 * c);
+        }
+    } else if (t < kTile) {
         const double bn = sqrt(s_tmp[t]);
         s_bn[t] = bn;
         s_rr[t] = s_tmp[t];
@@ -459,8 +480,14 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
 
     constexpr int nep = NB * 16;
     constexpr int NN = Nbr<DIM>::N;
-    int it = 0, k0 = 0;
+    int it = a.it0, k0 = a.it0;
+    bool suspended = false;
     for (;;) {
+        // suspension at a window boundary (k0 == it: no deferred steps pending)
+        if (it == a.stop_at && it > a.it0) {
+            suspended = true;
+            break;
+        }
         const T *rcur = Rs(it);
         // ---- sweep B: y = (H - s_base) r_it, C = Phi^T y, r.r, r.y; blocks away
         // from the range ends first, then (neighbours' rows of r_it awaited) the rest
@@ -699,6 +726,28 @@ __device__ void mscg_tile(const MsArgsT<T> &a, const int tile, const int kg) {
         a.flags[gcol] = s_flag[j] | (s_act[c][j] ? 1 : 0);
     }
     if (kg == 0 && t == 0) a.tile_iters[tile] = it;
+    if (a.state && kg == 0 && t < kTile) {
+        st_at(6) = suspended ? 1.0 : 0.0;
+        // right-hand sides to carry into the next launch, after every tile's state
+        a.state[((size_t)a.ntiles * kMsStateFields + tile) * kTile + t] =
+            suspended && s_colact[t] ? 1.0 : 0.0;
+        if (suspended) {
+            st_at(0) = s_rr[t];
+            st_at(1) = s_bn[t];
+            st_at(2) = s_btp[t];
+            st_at(3) = s_alp[t];
+            st_at(4) = (double)s_flag[t];
+            st_at(5) = (double)s_colact[t];
+            for (int c = 0; c < ns; ++c) {
+                st_at(8 + 6 * c) = s_z[c][t];
+                st_at(9 + 6 * c) = s_zp[c][t];
+                st_at(10 + 6 * c) = s_bs[c][t];
+                st_at(11 + 6 * c) = s_res[c][t];
+                st_at(12 + 6 * c) = (double)s_act[c][t];
+                st_at(13 + 6 * c) = (double)s_it[c][t];
+            }
+        }
+    }
     if (SG > 1) {
         // lockstep: keep arriving at the shared barrier until every tile of the
         // super-group is done (the last one to finish brings the count to zero

@@ -360,6 +360,31 @@ __global__ void fill_u32_kernel(unsigned *p, size_t n, unsigned v) {
 
 inline unsigned nblk(long long tot, int b) { return (unsigned)((tot + b - 1) / b); }
 
+
+// Columns of tile-interleaved vectors (tile-major, then row, then the 16
+// columns of the tile): destination column m (tile m / 16, position m % 16) of
+// each of the gridDim.y vectors takes source column map[m]; a negative entry
+// writes zero (zero_missing) or leaves the destination column as it is.
+template <typename T>
+__global__ void tilecol_gather_kernel(int rows, int ncols, const int *map, const T *src,
+                                      long long src_vstride, T *dst, long long dst_vstride,
+                                      int zero_missing) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)rows * ncols) return;
+    const int pos = (int)(idx & 15);
+    const long long rest = idx >> 4;
+    const int row = (int)(rest % rows);
+    const long long tile = rest / rows;
+    const long long ts = (long long)rows * 16;
+    const int sm = map[tile * 16 + pos];
+    T *d = dst + (long long)blockIdx.y * dst_vstride + tile * ts + (long long)row * 16 + pos;
+    if (sm < 0) {
+        if (zero_missing) *d = (T)0;
+        return;
+    }
+    *d = src[(long long)blockIdx.y * src_vstride + (long long)(sm >> 4) * ts + (long long)row * 16 + (sm & 15)];
+}
+
 }  // namespace
 
 // Fills by kernel rather than hipMemsetAsync, so that they may be recorded in a graph.
@@ -443,6 +468,26 @@ hipError_t launch_col_axpby(int m, int n, const double *a, const double *X, int 
     if (tot <= 0) return hipSuccess;
     hipLaunchKernelGGL(col_axpby_kernel, dim3(nblk(tot, 256)), dim3(256), 0, s, m, n, a, X, ldx, b, Y, ldy);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t tilecol_gather(int rows, int ncols, const int *map, const T *src, long long svs, T *dst,
+                                 long long dvs, int nvec, bool zero_missing, hipStream_t s) {
+    const long long tot = (long long)rows * ncols;
+    if (tot <= 0 || nvec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tilecol_gather_kernel<T>, dim3(nblk(tot, 256), nvec), dim3(256), 0, s, rows, ncols, map,
+                       src, svs, dst, dvs, zero_missing ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_tilecol_gather(int rows, int ncols, const int *map, const double *src, long long svs,
+                                 double *dst, long long dvs, int nvec, bool zero_missing, hipStream_t s) {
+    return tilecol_gather(rows, ncols, map, src, svs, dst, dvs, nvec, zero_missing, s);
+}
+
+hipError_t launch_tilecol_gather(int rows, int ncols, const int *map, const float *src, long long svs,
+                                 float *dst, long long dvs, int nvec, bool zero_missing, hipStream_t s) {
+    return tilecol_gather(rows, ncols, map, src, svs, dst, dvs, nvec, zero_missing, s);
 }
 
 hipError_t launch_col_gather(int m, int n, const double *src, int lds, const int *idx, double *dst, int ldd,

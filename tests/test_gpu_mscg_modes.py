@@ -48,6 +48,7 @@ def _context_2d(nx=32, ny=16, ne=16, n_mu=48, seed=7):
 @pytest.mark.parametrize("K", [2, 4, 8])
 def test_group_sizes_agree_2d(K, monkeypatch):
     ctx, G, om = _context_2d()
+    monkeypatch.setenv("ACP_MSCG_COMPACT", "0")   # one launch per solve
     monkeypatch.setenv("ACP_MSCG_GROUP", "1")
     print("[mscg] 2D, K = 1", flush=True)
     sel1 = ctx.compress(to_dev(G), to_dev(om))
@@ -86,6 +87,7 @@ def test_lockstep_is_bitwise_neutral(monkeypatch):
                       dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=1e-8, max_iter=5000,
                            solver=0),
                       T(inp.phi), inp.eps[:inp.n_e], T(inp.veff))
+    monkeypatch.setenv("ACP_MSCG_COMPACT", "0")   # one launch per solve
     out = {}
     for K, ls in ((8, 0), (8, 1), (4, 0)):
         monkeypatch.setenv("ACP_MSCG_GROUP", str(K))
@@ -156,3 +158,77 @@ def test_batch_groups_match_single_system_solves():
     batch.close()
     for c in ctxs:
         c.close()
+
+
+def test_suspend_and_compact_2d(monkeypatch):
+    """Suspension at forced window boundaries, with the live right-hand sides
+    gathered into fewer tiles and resumed with more workgroups per tile, yields
+    the single launch's solutions to the solve tolerance."""
+    ctx, G, om = _context_2d(n_mu=48)
+    monkeypatch.setenv("ACP_MSCG_COMPACT", "0")
+    print("[mscg] 2D, one launch", flush=True)
+    sel0 = ctx.compress(to_dev(G), to_dev(om))
+    Z0 = to_host(ctx.compress_get("z"))
+    monkeypatch.delenv("ACP_MSCG_COMPACT")
+    monkeypatch.setenv("ACP_MSCG_STOPS", "32,48,80")
+    ctx.reset_stats()
+    print("[mscg] 2D, suspended at 32, 48, 80", flush=True)
+    sel1 = ctx.compress(to_dev(G), to_dev(om))
+    st = ctx.stats()
+    assert st["max_rel_residual"] <= 1e-11
+    assert st["solve_kernel_launches"] >= 2, st["solve_kernel_launches"]
+    assert np.array_equal(np.asarray(sel0), np.asarray(sel1))
+    Z1 = to_host(ctx.compress_get("z"))
+    rel = np.abs(Z1 - Z0).max() / np.abs(Z0).max()
+    print(f"[mscg] 2D phased: {st['solve_kernel_launches']} launches, max rel diff {rel:.2e}", flush=True)
+    assert rel < 1e-9
+    ctx.close()
+
+
+def test_suspend_and_compact_workload2(monkeypatch):
+    """The bench workload with suspensions where a third of the right-hand
+    sides are done (tiles padded with empty columns): every shifted system
+    reaches the requested true residual (recomputed in FP64 by the library),
+    the iteration counts match the single launch's to within a few iterations,
+    and the solutions agree to the solve tolerance."""
+    import torch
+    from paper_1605_08021_amd import acp
+    from paper_1605_08021_amd.workload_model import build_inputs
+    from workload.seeds import get_config
+    cfg = get_config(2)
+    inp = build_inputs(cfg)
+    dev = torch.device("cuda:0")
+
+    def T(a):
+        a = np.asarray(a)
+        if a.ndim == 2:
+            return torch.from_numpy(np.ascontiguousarray(a.T)).to(dev).t()
+        return torch.from_numpy(a).to(dev)
+
+    ctx = acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0, occ=cfg.f),
+                      dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=1e-8, max_iter=5000,
+                           solver=0),
+                      T(inp.phi), inp.eps[:inp.n_e], T(inp.veff))
+    monkeypatch.setenv("ACP_MSCG_COMPACT", "0")
+    print("[mscg] workload 2, one launch", flush=True)
+    ctx.compress(T(inp.G), T(inp.omega))
+    st0 = ctx.stats()
+    Z0 = to_host(ctx.compress_get("z"))
+    monkeypatch.delenv("ACP_MSCG_COMPACT")
+    monkeypatch.setenv("ACP_MSCG_STOPS", "128,176,224")
+    ctx.reset_stats()
+    print("[mscg] workload 2, suspended at 128, 176, 224", flush=True)
+    ctx.compress(T(inp.G), T(inp.omega))
+    st = ctx.stats()
+    print(f"[mscg] workload 2 phased: {st['solve_kernel_launches']} launches, K of the last phase "
+          f"{st['krylov_group']}, iterations {st['iters_min']}-{st['iters_max']} "
+          f"(one launch: {st0['iters_min']}-{st0['iters_max']}), true residual {st['max_rel_residual']:.3e}",
+          flush=True)
+    assert st["solve_kernel_launches"] == 4
+    assert st["max_rel_residual"] <= 1e-8 * (1 + 1e-6)
+    assert abs(st["iters_max"] - st0["iters_max"]) <= 4
+    Z1 = to_host(ctx.compress_get("z"))
+    rel = np.abs(Z1 - Z0).max() / np.abs(Z0).max()
+    print(f"[mscg] workload 2 phased vs one launch: max rel diff {rel:.2e}", flush=True)
+    assert rel < 1e-6
+    ctx.close()
