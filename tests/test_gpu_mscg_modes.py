@@ -11,6 +11,9 @@ and the XCD lockstep yield the same shifted solutions.
 * The bench workload (1D, N_g = 5120, 32 right-hand-side tiles): the lockstep
   only changes which workgroups share a barrier counter, not one operation of
   the arithmetic, so Z and W are bitwise identical with and without it.
+* Suspension at window boundaries with compaction of the live right-hand sides
+  into fewer tiles (more workgroups each) continues the same recurrences: the
+  solutions agree with the single launch's to the solve tolerance.
 """
 import numpy as np
 import pytest
