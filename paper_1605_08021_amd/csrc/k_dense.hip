@@ -87,6 +87,44 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
     return v > bv || (v == bv && i < bi);
 }
 
+// Candidates of the previous step, 8 per lane and pass: a pass issues all its
+// loads before any comparison (one memory round trip), and the comparisons can
+// wait until other independent loads are in flight.  The order of comparisons
+// does not matter: better() is a total order.
+struct CandPass {
+    static constexpr int CPL = 8;
+    double v[CPL];
+    int ix[CPL];
+    __device__ __forceinline__ void load(const Cand *cand, int n, int b0) {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            const int b = b0 + lane + 64 * i;
+            const Cand c = cand[b < n ? b : n - 1];
+            v[i] = c.v;
+            ix[i] = c.i;
+        }
+    }
+    __device__ __forceinline__ void reduce(int n, int b0, double &bv, int &bi) const {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int i = 0; i < CPL; ++i)
+            if (b0 + lane + 64 * i < n && better(v[i], ix[i], bv, bi)) {
+                bv = v[i];
+                bi = ix[i];
+            }
+    }
+};
+
+// This lane's best (value, row) over cand[0..n); the caller reduces across the wave.
+__device__ __forceinline__ void lane_best_candidate(const Cand *cand, int n, double &bv, int &bi) {
+    CandPass cp;
+    for (int b0 = 0; b0 < n; b0 += 64 * CandPass::CPL) {
+        cp.load(cand, n, b0);
+        cp.reduce(n, b0, bv, bi);
+    }
+}
+
 // Best (value, row) over threads 0..15 (the block's rows); thread 0 writes it.
 __device__ __forceinline__ void block_candidate16(double v, int i, Cand *out) {
     if (threadIdx.x < 64) {
@@ -191,13 +229,7 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_kernel(
         bi = forced[k];
         bv = diag[bi];
     } else {
-        for (int b = t & 63; b < nblk; b += 64) {
-            const Cand c = cand_in[b];
-            if (better(c.v, c.i, bv, bi)) {
-                bv = c.v;
-                bi = c.i;
-            }
-        }
+        lane_best_candidate(cand_in, nblk, bv, bi);
         wave_argmax(bv, bi);
         bv = readlane_f64(bv, 63);
         bi = __builtin_amdgcn_readlane(bi, 63);
@@ -277,13 +309,8 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_gram_kernel(
     const int stopped = state[1];
     double bv = -2.0;
     int bi = 0x7fffffff;
-    for (int b = t & 63; b < nblk; b += 64) {
-        const Cand c = cand_in[b];
-        if (better(c.v, c.i, bv, bi)) {
-            bv = c.v;
-            bi = c.i;
-        }
-    }
+    CandPass cp;
+    cp.load(cand_in, nblk, 0);
     auto column = [&](int v) -> const double * {
         return v < r ? gt + (long long)v * ng : v < ntot ? L + (long long)(v - r) * ng : gt;
     };
@@ -291,6 +318,11 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_gram_kernel(
 #pragma unroll
     for (int i = 0; i < MAXR; ++i) x[i] = column(st + ISDF_NS * i)[ac];
     const double dold = diag[ac];
+    cp.reduce(nblk, 0, bv, bi);
+    for (int b0 = 64 * CandPass::CPL; b0 < nblk; b0 += 64 * CandPass::CPL) {
+        cp.load(cand_in, nblk, b0);
+        cp.reduce(nblk, b0, bv, bi);
+    }
     if (stopped) return;
     wave_argmax(bv, bi);
     bv = readlane_f64(bv, 63);
