@@ -710,13 +710,11 @@ __device__ __forceinline__ void lu_panel_column(double (&P)[LU_NB], LuPanelShare
                 sh.wi[par][wave] = bi;
             }
             __syncthreads();
-            double b = sh.wv[par][0];
-            int p = sh.wi[par][0];
-            for (int w = 1; w < nw; ++w)
-                if (sh.wv[par][w] > b || (sh.wv[par][w] == b && sh.wi[par][w] < p)) {
-                    b = sh.wv[par][w];
-                    p = sh.wi[par][w];
-                }
+            // every wave reduces the per-wave winners itself, one per lane
+            double b = lane < nw ? sh.wv[par][lane] : -2.0;
+            int p = lane < nw ? sh.wi[par][lane] : 0x7fffffff;
+            wave_argmax(b, p);
+            p = __builtin_amdgcn_readlane(p, 63);
             if (t == J) {
 #pragma unroll
                 for (int c = 0; c < LU_NB; ++c) sh.rows[par][0][c] = P[c];
