@@ -28,7 +28,7 @@ def _gpu():
     require_gpu()
 
 
-def _context_2d(nx=32, ny=16, ne=16, n_mu=48, seed=7):
+def _context_2d(nx=32, ny=16, ne=16, n_mu=48, seed=7, **extra_opts):
     from paper_1605_08021_amd import acp
     rng = np.random.default_rng(seed)
     ng = nx * ny
@@ -40,7 +40,7 @@ def _context_2d(nx=32, ny=16, ne=16, n_mu=48, seed=7):
     # the spectrum of H
     eps = np.linspace(-3.0, -1.5, ne)
     grid = dict(dim=2, n=(nx, ny), h=h, kappa=0.5, eps0=1.0, occ=2.0)
-    opts = dict(n_cheb=4, n_mu=n_mu, sketch_r=4, tol=1e-12, max_iter=4000, solver=0)
+    opts = dict(n_cheb=4, n_mu=n_mu, sketch_r=4, tol=1e-12, max_iter=4000, solver=0, **extra_opts)
     ctx = acp.Context(grid, opts, to_dev(phi), eps, to_dev(veff))
     n_p = 12
     G = rng.standard_normal((ng, n_p))
@@ -234,4 +234,30 @@ def test_suspend_and_compact_workload2(monkeypatch):
     rel = np.abs(Z1 - Z0).max() / np.abs(Z0).max()
     print(f"[mscg] workload 2 phased vs one launch: max rel diff {rel:.2e}", flush=True)
     assert rel < 1e-6
+    ctx.close()
+
+
+def test_suspend_and_compact_fp32_storage(monkeypatch):
+    """The FP32-storage multi-shift pass (mixed precision) suspended and
+    compacted at forced stops, followed by the FP64 refinement: every system
+    reaches the FP64 tolerance and the solutions agree with the FP64 solve in
+    one launch."""
+    ctx0, G, om = _context_2d(n_mu=48)
+    monkeypatch.setenv("ACP_MSCG_COMPACT", "0")
+    print("[mscg] 2D FP64, one launch", flush=True)
+    ctx0.compress(to_dev(G), to_dev(om))
+    Z0 = to_host(ctx0.compress_get("z"))
+    ctx0.close()
+    ctx, G, om = _context_2d(n_mu=48, precision=1, inner_tol=1e-5)
+    monkeypatch.delenv("ACP_MSCG_COMPACT")
+    monkeypatch.setenv("ACP_MSCG_STOPS", "16,32")
+    print("[mscg] 2D FP32 storage, suspended at 16, 32", flush=True)
+    ctx.compress(to_dev(G), to_dev(om))
+    st = ctx.stats()
+    assert st["max_rel_residual"] <= 1e-11
+    Z1 = to_host(ctx.compress_get("z"))
+    rel = np.abs(Z1 - Z0).max() / np.abs(Z0).max()
+    print(f"[mscg] 2D FP32 phased + refinement vs FP64: max rel diff {rel:.2e}, "
+          f"{st['refinements']} refinements", flush=True)
+    assert rel < 1e-9
     ctx.close()
