@@ -87,29 +87,28 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
     return v > bv || (v == bv && i < bi);
 }
 
-// Candidates of the previous step, 8 per lane and pass: a pass issues all its
-// loads before any comparison (one memory round trip), and the comparisons can
-// wait until other independent loads are in flight.  The order of comparisons
-// does not matter: better() is a total order.
+// Candidates of the previous step, 8 per thread and pass (thread pos of
+// `stride` threads takes b0 + pos + stride i): a pass issues all its loads
+// before any comparison (one memory round trip), and the comparisons can wait
+// until other independent loads are in flight.  The order of comparisons does
+// not matter: better() is a total order.
 struct CandPass {
     static constexpr int CPL = 8;
     double v[CPL];
     int ix[CPL];
-    __device__ __forceinline__ void load(const Cand *cand, int n, int b0) {
-        const int lane = threadIdx.x & 63;
+    __device__ __forceinline__ void load(const Cand *cand, int n, int b0, int pos, int stride) {
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
-            const int b = b0 + lane + 64 * i;
+            const int b = b0 + pos + stride * i;
             const Cand c = cand[b < n ? b : n - 1];
             v[i] = c.v;
             ix[i] = c.i;
         }
     }
-    __device__ __forceinline__ void reduce(int n, int b0, double &bv, int &bi) const {
-        const int lane = threadIdx.x & 63;
+    __device__ __forceinline__ void reduce(int n, int b0, int pos, int stride, double &bv, int &bi) const {
 #pragma unroll
         for (int i = 0; i < CPL; ++i)
-            if (b0 + lane + 64 * i < n && better(v[i], ix[i], bv, bi)) {
+            if (b0 + pos + stride * i < n && better(v[i], ix[i], bv, bi)) {
                 bv = v[i];
                 bi = ix[i];
             }
@@ -119,9 +118,10 @@ struct CandPass {
 // This lane's best (value, row) over cand[0..n); the caller reduces across the wave.
 __device__ __forceinline__ void lane_best_candidate(const Cand *cand, int n, double &bv, int &bi) {
     CandPass cp;
+    const int lane = threadIdx.x & 63;
     for (int b0 = 0; b0 < n; b0 += 64 * CandPass::CPL) {
-        cp.load(cand, n, b0);
-        cp.reduce(n, b0, bv, bi);
+        cp.load(cand, n, b0, lane, 64);
+        cp.reduce(n, b0, lane, 64, bv, bi);
     }
 }
 
@@ -307,10 +307,18 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_gram_kernel(
     const long long ac = a < ng ? a : ng - 1;
     const int ntot = r + k;
     const int stopped = state[1];
+    __shared__ double s_cv[ISDF_NT / 64];
+    __shared__ int s_ci[ISDF_NT / 64];
     double bv = -2.0;
     int bi = 0x7fffffff;
+    // up to 512 candidates every wave reads them all in one pass (no barrier);
+    // beyond, the block shares them out (thread t takes t, t + 512, ...: one
+    // pass up to 4096, each read once per block) and the waves' winners meet
+    // in LDS
+    const bool shared = nblk > 64 * CandPass::CPL;   // uniform over the launch
+    const int pos = shared ? t : (t & 63), stride = shared ? ISDF_NT : 64;
     CandPass cp;
-    cp.load(cand_in, nblk, 0);
+    cp.load(cand_in, nblk, 0, pos, stride);
     auto column = [&](int v) -> const double * {
         return v < r ? gt + (long long)v * ng : v < ntot ? L + (long long)(v - r) * ng : gt;
     };
@@ -318,13 +326,23 @@ __global__ __launch_bounds__(ISDF_NT) void isdf_step_gram_kernel(
 #pragma unroll
     for (int i = 0; i < MAXR; ++i) x[i] = column(st + ISDF_NS * i)[ac];
     const double dold = diag[ac];
-    cp.reduce(nblk, 0, bv, bi);
-    for (int b0 = 64 * CandPass::CPL; b0 < nblk; b0 += 64 * CandPass::CPL) {
-        cp.load(cand_in, nblk, b0);
-        cp.reduce(nblk, b0, bv, bi);
+    cp.reduce(nblk, 0, pos, stride, bv, bi);
+    for (int b0 = stride * CandPass::CPL; b0 < nblk; b0 += stride * CandPass::CPL) {
+        cp.load(cand_in, nblk, b0, pos, stride);
+        cp.reduce(nblk, b0, pos, stride, bv, bi);
     }
     if (stopped) return;
     wave_argmax(bv, bi);
+    if (shared) {
+        if ((t & 63) == 63) {
+            s_cv[t >> 6] = bv;
+            s_ci[t >> 6] = bi;
+        }
+        __syncthreads();
+        bv = (t & 63) < ISDF_NT / 64 ? s_cv[t & 63] : -2.0;
+        bi = (t & 63) < ISDF_NT / 64 ? s_ci[t & 63] : 0x7fffffff;
+        wave_argmax(bv, bi);
+    }
     bv = readlane_f64(bv, 63);
     bi = __builtin_amdgcn_readlane(bi, 63);
     const bool stop = !(bv > 0.0) || (tol2 > 0.0 && k > 0 && bv < tol2 * dvals[0]);
