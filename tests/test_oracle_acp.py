@@ -190,3 +190,53 @@ def test_krylov_solvers_match_exact(sys_, solver):
     dense = A.DenseShiftedSolver(m.hamiltonian_dense(gs.veff), gs.phi)
     ex2 = np.concatenate([dense(s, R) for s in nodes], axis=1)
     assert np.abs(ex2 - ex).max() < 1e-9 * np.abs(ex).max()
+
+
+def test_isdf_rank_rule_on_prescribed_pivots():
+    """Alg. 2 step 3: the rank is the number of pivots whose |R_kk| is at least
+    tol |R_11|.  Pin: with one orbital equal to 1 everywhere and Omega = I, the
+    sketched matrix M~ is G itself; G has nonzero rows only at five grid points,
+    each a multiple of a different unit vector, so the pivoted QR takes those
+    rows in decreasing size with |R_kk| equal to the sizes (orthogonal rows).
+    An off-by-one in the rule, or a rule on the wrong end of the threshold,
+    changes the rank or the selected points."""
+    n_g, n_p = 48, 6
+    pts = np.array([17, 3, 40, 8, 25])
+    size = np.array([1e-2, 1.0, 1e-4, 1e-1, 1e-3])
+    G = np.zeros((n_g, n_p))
+    G[pts, np.arange(5)] = size
+    phi = np.ones((n_g, 1))
+    om = np.eye(n_p)
+    order = pts[np.argsort(-size)]              # 3, 8, 17, 25, 40
+    for tol, rank in ((5e-3, 3), (5e-2, 2), (0.5, 1), (5e-4, 4), (5e-5, 5)):
+        dec = A.isdf_qrcp(phi, G, om, 5, tol=tol)
+        assert len(dec.sel) == rank, (tol, len(dec.sel))
+        assert np.array_equal(dec.sel, order[:rank])
+        assert np.allclose(dec.rdiag[:5], np.sort(size)[::-1], rtol=1e-12, atol=0)
+    # the fixed rank caps the rule
+    dec = A.isdf_qrcp(phi, G, om, 2, tol=5e-4)
+    assert np.array_equal(dec.sel, order[:2])
+    # tol = 0 keeps the fixed rank even past the numerical rank of the sketch
+    assert len(A.isdf_qrcp(phi, G, om, 5).sel) == 5
+
+
+def test_dyson_stop_rule(sys_):
+    """Alg. 4 stops after the first compression whose relative change
+    ||U^k - U^{k-1}||_F / ||U^k||_F is at most delta.  Pin: with every grid
+    point selected and the occupied eigenvalues as nodes the compression is
+    exact, so U^1 is already chi G (the change of the first iteration, from
+    U^0 = 0, is exactly 1) and U^2 repeats it to rounding.  Hence delta = 1e-9
+    stops after exactly 2 compressions, delta >= 1 after 1, and delta = 0 runs
+    k_max."""
+    cfg, m, gs, w, v, G, om = sys_
+    n_g = m.grid.n_grid
+    solver = A.ExactShiftedSolver(w, v, gs.n_e)
+    sel = np.arange(n_g)
+    common = dict(vc=m.vc, vc_inv=m.vc_inv, f=m.f, dv=m.grid.dv, sel_hist=[sel] * 3,
+                  node_mode="occupied")
+    args = (gs.phi, gs.eps[:gs.n_e], G, om, cfg.n_cheb, n_g, solver)
+    r = A.acp_dyson(*args, k_max=3, delta=1e-9, **common)
+    assert r.iters == 2 and len(r.changes) == 2
+    assert r.changes[0] == 1.0 and r.changes[1] < 1e-9
+    assert A.acp_dyson(*args, k_max=3, delta=1.0, **common).iters == 1
+    assert A.acp_dyson(*args, k_max=3, delta=0.0, **common).iters == 3

@@ -154,3 +154,27 @@ def test_energy_loss_definition_and_gradient():
     Lz, _ = P.energy_loss((np.linalg.pinv(np.diag(rms)) @ E.T)[:, None, :], rms, R, E, phi,
                           lambda X: A @ X)
     assert abs(Lz) < 1e-12
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments equal g and g^2 at
+    every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so after t steps
+    theta = theta_0 - t lr g / (|g| + eps) exactly (up to rounding); a wrong
+    bias-correction power or moment update breaks it after the first step."""
+    rng = np.random.default_rng(11)
+    th0 = rng.standard_normal(6)
+    g = rng.standard_normal(6)
+    th, m, v = th0.copy(), np.zeros(6), np.zeros(6)
+    lr = 3e-3
+    for t in range(1, 41):
+        th, m, v = P.adam(th, g, m, v, t, lr=lr)
+        assert np.allclose(th, th0 - t * lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+
+
+def test_adam_minimises_a_quadratic():
+    """Adam on f(theta) = |theta - c|^2 / 2 (gradient theta - c) reaches c."""
+    c = np.array([0.3, -1.2, 2.0])
+    th, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 4001):
+        th, m, v = P.adam(th, th - c, m, v, t, lr=1e-2)
+    assert np.abs(th - c).max() < 1e-3
