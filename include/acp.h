@@ -122,6 +122,8 @@ typedef struct {
     double krylov_bytes;         /* algorithmic HBM bytes of the Krylov kernels (accumulated) */
     double krylov_flops;         /* algorithmic FP64 flops of their projector products */
     int krylov_group;            /* workgroups per 16-system tile in the last multi-shift solve */
+    int n_mu;                    /* rank N_mu of the last compression (below opts.n_mu when the
+                                    rank rule of isdf_tol stopped the point selection early) */
 } acp_stats;
 
 typedef struct acp_ctx acp_ctx;

@@ -222,6 +222,7 @@ class DysonResult:
     sel_hist: List[np.ndarray]
     W_hist: List[np.ndarray]
     changes: List[float]
+    last: Optional[Compressed] = None   # the last compression (Z, W, selection)
 
 
 def acp_dyson(phi, eps_occ, G, omega, n_c, n_mu, solver, *, vc: Callable, vc_inv: Callable,
@@ -242,6 +243,7 @@ def acp_dyson(phi, eps_occ, G, omega, n_c, n_mu, solver, *, vc: Callable, vc_inv
     U_prev = np.zeros_like(G)
     sels, Ws, changes = [], [], []
     it = 0
+    last = None
     for it in range(1, k_max + 1):
         forced = None if sel_hist is None else sel_hist[it - 1]
         comp = compress(phi, eps_occ, Gk, omega, n_c, n_mu, solver, f, dv, sel=forced,
@@ -256,9 +258,10 @@ def acp_dyson(phi, eps_occ, G, omega, n_c, n_mu, solver, *, vc: Callable, vc_inv
         Ws.append(comp.W)
         changes.append(float(ch))
         U_prev = U
+        last = comp
         if delta > 0 and ch <= delta:
             break
-    return DysonResult(U=U_prev, iters=it, sel_hist=sels, W_hist=Ws, changes=changes)
+    return DysonResult(U=U_prev, iters=it, sel_hist=sels, W_hist=Ws, changes=changes, last=last)
 
 
 def smw_dense_reference(W, sel, Vc_dense, B) -> np.ndarray:

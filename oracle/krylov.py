@@ -14,8 +14,9 @@ from __future__ import annotations
 import numpy as np
 
 
-def make_operator(model, veff, phi, shifts):
-    """Column-wise A_j x = Q (H - s_j) Q x."""
+def make_operator(model, veff, phi, shifts, H=None):
+    """Column-wise A_j x = Q (H - s_j) Q x.  H: optionally the same Hamiltonian
+    as a sparse matrix (model.hamiltonian_sparse(veff)), faster on large grids."""
     shifts = np.asarray(shifts, dtype=np.float64)
 
     def q(x):
@@ -23,7 +24,8 @@ def make_operator(model, veff, phi, shifts):
 
     def apply(x):
         y = q(x)
-        y = model.hamiltonian_apply(veff, y) - y * shifts[None, :]
+        hy = model.hamiltonian_apply(veff, y) if H is None else H @ y
+        y = hy - y * shifts[None, :]
         return q(y)
 
     return apply

@@ -289,6 +289,62 @@ class Model:
         return GroundState(phi=phi, eps=w, veff=veff, rho=self.density(phi), n_e=n_e,
                            scf_iters=it, scf_residual=float(res))
 
+    # -- non-self-consistent inputs for large grids --------------------------
+    def superposed_atoms_potential(self, width_factor: float = 1.5) -> np.ndarray:
+        """A neutral potential without self-consistency (a Harris-type input):
+        V = v_c (rho_at + m), where rho_at puts on every site a Gaussian electron
+        cloud of charge Z_I and width width_factor * sigma, so that each
+        pseudocharge of Eq. (4.2) is screened by a wider cloud of the same charge.
+        The shifted equations of Eq. (3.6) only need some V_eff and its occupied
+        eigenpairs; this one has a positive gap for the lattices used here."""
+        d = self.grid.dim
+        s = width_factor * self.sigma
+        D = min_image(self.grid, self.R)
+        r2 = np.sum(D * D, axis=2)
+        rho_at = (self.Z[None, :] * (2.0 * np.pi * s ** 2) ** (-d / 2.0)
+                  * np.exp(-r2 / (2.0 * s ** 2))).sum(axis=1)
+        return self.vc(rho_at + self.m)
+
+    def hamiltonian_sparse(self, veff: np.ndarray):
+        """H = -1/2 Delta_h + diag(V_eff) as a scipy sparse matrix (CSR)."""
+        import scipy.sparse as sp
+        mats = []
+        for k in self.grid.n:          # periodic 1D second difference, 9 points
+            rows, cols, vals = [], [], []
+            for sft in range(-4, 5):
+                i = np.arange(k)
+                rows.append(i)
+                cols.append((i + sft) % k)
+                vals.append(np.full(k, FD8[abs(sft)]))
+            D1 = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                               shape=(k, k))
+            mats.append(D1 / self.grid.h ** 2)
+        if self.grid.dim == 1:
+            lap = mats[0]
+        else:   # alpha = ix + nx * iy: x is the fast index
+            nx, ny = self.grid.n
+            lap = sp.kron(sp.identity(ny), mats[0]) + sp.kron(mats[1], sp.identity(nx))
+        return (-0.5 * lap + sp.diags(veff)).tocsr()
+
+    def ground_state_of(self, veff: np.ndarray, n_extra: int = 1, sparse: bool = False) -> GroundState:
+        """The lowest N_e + n_extra eigenpairs of H[veff] without SCF (dense eigh,
+        or shift-invert Lanczos below the spectrum on the sparse H followed by a
+        Rayleigh-Ritz step on the orthonormalised vectors); rho from the
+        occupied ones."""
+        n_e, k = self.n_e, self.n_e + n_extra
+        if not sparse:
+            w, v = self.lowest_eigenpairs(veff, k)
+        else:
+            import scipy.sparse.linalg as spla
+            H = self.hamiltonian_sparse(veff)
+            w0, v0 = spla.eigsh(H, k=k + 8, sigma=float(veff.min()) - 1.0, which="LM", tol=0.0)
+            Qv, _ = np.linalg.qr(v0[:, np.argsort(w0)])
+            wr, vr = np.linalg.eigh(Qv.T @ (H @ Qv))
+            w, v = wr[:k], Qv @ vr[:, :k]
+        phi = v[:, :n_e].copy()
+        return GroundState(phi=phi, eps=w, veff=veff.copy(), rho=self.density(phi), n_e=n_e,
+                           scf_iters=0, scf_residual=float("nan"))
+
     # -- energy and forces (Eq. (2.1), Eq. (2.9)) ---------------------------
     def energy(self, gs: GroundState) -> float:
         """E = (f/2) sum_i phi_i^T (-Delta_h) phi_i + (h^d/2)(rho+m)^T v_c (rho+m)

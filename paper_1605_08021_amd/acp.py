@@ -58,7 +58,7 @@ class AcpStats(C.Structure):
                 ("ms_dynmat", C.c_double), ("ms_solve_kernel", C.c_double),
                 ("solve_kernel_launches", C.c_int64), ("d_asymmetry", C.c_double),
                 ("krylov_bytes", C.c_double), ("krylov_flops", C.c_double),
-                ("krylov_group", C.c_int)]
+                ("krylov_group", C.c_int), ("n_mu", C.c_int)]
 
 
 class AcpBatchInfo(C.Structure):
@@ -255,11 +255,11 @@ class Context:
             si = np.ascontiguousarray(np.asarray(sel_in, dtype=np.int32))
         self._check(self.lib.acp_compress(self._ctx, _dptr(G), G.shape[1], _dptr(omega),
                                           None if si is None else si.ctypes.data, sel.ctypes.data))
-        return sel
+        return sel[: self.stats()["n_mu"]]
 
     def compress_get(self, what: str):
         idx = {"xi": 0, "rhs": 1, "w": 2, "z": 3}[what]
-        n_mu = self.opts.n_mu
+        n_mu = self.stats()["n_mu"]
         nc = self.n_shifts()
         cols = n_mu * nc if what == "z" else n_mu
         out = self._empty(self.n_g, cols)

@@ -1352,6 +1352,7 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
         return fail(ctx, ACP_EINVAL, "forced selection is rank deficient or repeats a point");
     nmu = got;
     ctx->nmu = nmu;
+    ctx->stats.n_mu = nmu;
     ctx->nmu_pad = (nmu + kTile - 1) / kTile * kTile;
     ctx->sel_host.resize(nmu);
     HIPCHK(hipMemcpyAsync(ctx->sel_host.data(), ctx->sel_dev.p, (size_t)nmu * 4,
@@ -2348,7 +2349,9 @@ acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out) {
 }
 
 void acp_reset_stats(acp_ctx *ctx) {
-    if (ctx) ctx->stats = acp_stats{};
+    if (!ctx) return;
+    ctx->stats = acp_stats{};
+    ctx->stats.n_mu = ctx->nmu;   // describes the compression still held, not a counter
 }
 
 const char *acp_last_error(const acp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }

@@ -92,10 +92,11 @@ def test_compress_matches_oracle(cid, solver):
 
 @pytest.mark.parametrize("cid", [11, 12, 1])
 def test_dyson_and_dynmat_match_oracle(cid):
-    """Alg. 4 and the dynamical matrix with the same selections as the oracle.
-    For the paper's model (11, 12) D and omega^2 agree to 1e-6 relative; for the
-    8-atom workload 1, whose Hessian is a cancellation of O(10) terms down to
-    O(1e-5), D is compared relative to the size of the cancelling terms."""
+    """Alg. 4 and the dynamical matrix with the same selections as the oracle:
+    D and omega^2 agree to 1e-6 relative (the FP64 target), also for the
+    8-atom workload 1, whose Hessian is a cancellation of O(10) response and
+    local terms down to O(1e-3) (the solves run to 1e-12, so U is accurate to
+    far better than the 1e-6 / 1e4 that the cancellation demands)."""
     cfg, m, gs, w, v, G, om, K = system(cid)
     kmax = 3
     solver = OA.ExactShiftedSolver(w, v, gs.n_e)
@@ -110,13 +111,12 @@ def test_dyson_and_dynmat_match_oracle(cid):
     masses = np.ones(m.n_atoms)
     D, lam = ctx.dynmat(to_dev(G), None, K, masses)
     Dref, lamref = OC.dynamical_matrix(OC.hessian_exact(m, gs, ref.U, G), masses, cfg.dim)
-    scale = np.linalg.norm(K)
-    if cid in (11, 12):
-        assert np.linalg.norm(D - Dref) <= 1e-6 * np.linalg.norm(Dref)
-        assert np.abs(lam - lamref).max() <= 1e-6 * np.abs(lamref).max()
-    else:
-        assert np.linalg.norm(D - Dref) <= 1e-9 * scale
-        assert np.abs(lam - lamref).max() <= 1e-9 * scale
+    ed = np.linalg.norm(D - Dref) / np.linalg.norm(Dref)
+    el = np.abs(lam - lamref).max() / np.abs(lamref).max()
+    print(f"cid {cid}: U {np.linalg.norm(U - ref.U) / np.linalg.norm(ref.U):.2e} D {ed:.2e} "
+          f"omega^2 {el:.2e} (|D| = {np.linalg.norm(Dref):.3e}, |K_local| = {np.linalg.norm(K):.3e})")
+    assert ed <= 1e-6
+    assert el <= 1e-6
     ctx.close()
 
 

@@ -174,3 +174,34 @@ def test_sites_are_deterministic_and_neutral():
         assert np.array_equal(R1, R2) and np.array_equal(Z1, Z2)
         assert abs(Z1.sum() - cfg.f * ne1) < 1e-10
         assert R1.shape == (int(np.prod(cfg.sites)), cfg.dim)
+
+
+def test_sparse_hamiltonian_and_non_scf_ground_state():
+    """The sparse H equals the stencil apply (plane waves are eigenvectors with
+    the closed-form symbol plus the constant potential); the shift-invert
+    eigenpairs equal the dense ones; the superposed-atom potential comes from a
+    neutral charge (rho_at + m integrates to zero) and has a positive gap."""
+    from workload.seeds import small_config
+    cfg = small_config(901, 2, 3, 10, a=6.0, sigma=0.8, jitter=0.05)
+    m = build_model(cfg)
+    n = m.grid.n_grid
+    H0 = m.hamiltonian_sparse(np.full(n, 0.25))
+    kx, ky = 3, 7
+    X = m.grid.coords()
+    L = np.array(m.grid.box)
+    pw = np.cos(2 * np.pi * (kx * X[:, 0] / L[0] + ky * X[:, 1] / L[1]))
+    from oracle.model import fd_symbol_1d
+    lam = 0.5 * (fd_symbol_1d(m.grid.n[0], m.grid.h)[kx] + fd_symbol_1d(m.grid.n[1], m.grid.h)[ky]) + 0.25
+    assert np.abs(H0 @ pw - lam * pw).max() < 1e-12 * lam
+    V = m.superposed_atoms_potential()
+    x = np.random.default_rng(1).standard_normal(n)
+    assert np.abs(m.hamiltonian_sparse(V) @ x - m.hamiltonian_apply(V, x)).max() < 1e-12
+    # V = v_c q with q neutral: v_c^{-1} V integrates to zero
+    assert abs(m.vc_inv(V).sum()) * m.grid.dv < 1e-10
+    gd = m.ground_state_of(V)
+    gsp = m.ground_state_of(V, sparse=True)
+    assert gd.gap > 0.1
+    assert np.abs(gd.eps - gsp.eps).max() < 1e-11
+    Hd = m.hamiltonian_dense(V)
+    assert np.abs(Hd @ gsp.phi - gsp.phi * gsp.eps[:m.n_e]).max() < 1e-11
+    assert np.abs(gsp.phi.T @ gsp.phi - np.eye(m.n_e)).max() < 1e-13
