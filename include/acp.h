@@ -217,6 +217,22 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
 acp_status acp_residual(acp_ctx *ctx, const double *shift, int n, const double *B,
                         const double *X, double *R);
 
+/* acp_residual_noalloc -- the same R = B - Q (H - shift[j]) Q X as acp_residual,
+ * for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  It allocates nothing:
+ * its workspace (the shifts, Q X, Phi^T X and the split-K partials of Phi^T X,
+ * (n + N_g n + N_e n + 8 N_e n) doubles with padding) lives in one fixed
+ * device array of ACP_NOALLOC_SCRATCH_BYTES per GPU, located when the first
+ * context on that GPU is set up and held until the process ends.  Every call on
+ * a GPU shares that array and leaves its last contents there (each call
+ * overwrites every part it reads), so calls that overlap on one GPU -- from
+ * several streams or threads -- race and must be serialised by the caller.
+ * Sizes beyond the array give ACP_EINVAL with nothing written.  Same arguments,
+ * layouts and results as acp_residual; synchronises the context's stream. */
+#define ACP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+acp_status acp_residual_noalloc(acp_ctx *ctx, const double *shift, int n, const double *B,
+                                const double *X, double *R);
+
 /* ---- Learned preconditioner (an addition to the paper's method) ----------
  * Network N: four periodic convolutions of width 5 per grid axis (5 taps in
  * 1D, 5 x 5 in 2D), channels 2 -> 32 -> 32 -> 32 -> 1, bias per channel, ReLU

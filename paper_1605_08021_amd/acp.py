@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_dyson": (I, [P, P, I, P, P, P, P, P]),
         "acp_dynmat": (I, [P, P, P, I, P, P, P, P]),
         "acp_residual": (I, [P, P, I, P, P, P]),
+        "acp_residual_noalloc": (I, [P, P, I, P, P, P]),
         "acp_precond_n_params": (I, [I]),
         "acp_precond_init": (I, [P, C.c_ulonglong]),
         "acp_precond_set": (I, [P, P, I]),
@@ -322,6 +323,17 @@ class Context:
         R = self._empty(*B.shape)
         self._check(self.lib.acp_residual(self._ctx, _hptr(sh), B.shape[1], _dptr(B), _dptr(X),
                                           _dptr(R)))
+        return R
+
+    def residual_noalloc(self, shifts, B, X, R=None):
+        """acp_residual_noalloc into R (allocated here when None: the library
+        call itself allocates nothing)."""
+        B, X = colmajor(B), colmajor(X)
+        sh = _hostd(shifts)
+        if R is None:
+            R = self._empty(*B.shape)
+        self._check(self.lib.acp_residual_noalloc(self._ctx, _hptr(sh), B.shape[1], _dptr(B),
+                                                  _dptr(X), _dptr(R)))
         return R
 
     # -- learned preconditioner (marshalling only) ----------------------------

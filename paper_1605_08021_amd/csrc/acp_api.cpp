@@ -14,6 +14,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "acp_internal.h"
@@ -114,6 +115,15 @@ struct acp_batch {
     std::string err;
     hipEvent_t ev[2]{};
 };
+
+// Workspace of acp_residual_noalloc: one fixed array per GPU, for callers that
+// cannot allocate.  Host code never passes the symbol itself as an address
+// (it names the host-side shadow): each GPU's copy is located once, with that
+// GPU current, and the device pointer is kept per GPU.
+static __device__ __align__(256) double scratch[ACP_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
 
 namespace {
 
@@ -790,31 +800,45 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
 
 // A X = Q (H - s_j) Q X for column-major X (n columns); result in Y.
 // C = Phi^T X (N_e x n, leading dimension N_e) for column-major X (leading
-// dimension ldx): split-K over the grid when the output has few tiles.
-acp_status phi_t_times(acp_ctx *ctx, int n, const double *X, int ldx, double *C) {
+// dimension ldx): split-K over the grid when the output has few tiles, with
+// at most 8 slices (work: 8 N_e n doubles), whatever the workspace holds.
+constexpr int kSplitSlices = 8;
+acp_status phi_t_times_ws(acp_ctx *ctx, int n, const double *X, int ldx, double *C, double *work) {
     const int ng = ctx->ng, ne = ctx->ne;
-    ENSURE(ctx->splitk, (size_t)8 * ne * n * 8);
     HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, dp<double>(ctx->phi_cm), ng, X, ldx, 0.0, C, ne,
-                       dp<double>(ctx->splitk), ctx->splitk.bytes / 8, ctx->stream));
+                       work, (size_t)kSplitSlices * ne * n, ctx->stream));
+    return ACP_OK;
+}
+
+acp_status phi_t_times(acp_ctx *ctx, int n, const double *X, int ldx, double *C) {
+    ENSURE(ctx->splitk, (size_t)kSplitSlices * ctx->ne * n * 8);
+    return phi_t_times_ws(ctx, n, X, ldx, C, dp<double>(ctx->splitk));
+}
+
+// The operator with caller-provided workspace: QX (N_g x n), C (N_e x n),
+// work (8 N_e n doubles).
+acp_status apply_operator_ws(acp_ctx *ctx, int n, const double *shifts_dev, const double *X, double *Y,
+                             double *QX, double *C, double *work) {
+    const int ng = ctx->ng, ne = ctx->ne;
+    hipStream_t s = ctx->stream;
+    const double *phi = dp<double>(ctx->phi_cm);
+    CHECK(phi_t_times_ws(ctx, n, X, ng, C, work));
+    HIPCHK(launch_scale_copy(ng, n, 1.0, X, ng, QX, ng, s));
+    HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, QX, ng, 0, 1, s));
+    HIPCHK(launch_stencil(ctx->gd, n, QX, ng, Y, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
+                          shifts_dev, s));
+    CHECK(phi_t_times_ws(ctx, n, Y, ng, C, work));
+    HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, Y, ng, 0, 1, s));
     return ACP_OK;
 }
 
 acp_status apply_operator(acp_ctx *ctx, int n, const double *shifts_dev, const double *X,
                           double *Y) {
-    const int ng = ctx->ng, ne = ctx->ne;
-    hipStream_t s = ctx->stream;
-    ENSURE(ctx->tmp2, (size_t)ng * n * 8);
+    ENSURE(ctx->tmp2, (size_t)ctx->ng * n * 8);
     ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
-    double *QX = dp<double>(ctx->tmp2), *C = dp<double>(ctx->c1);
-    const double *phi = dp<double>(ctx->phi_cm);
-    CHECK(phi_t_times(ctx, n, X, ng, C));
-    HIPCHK(launch_scale_copy(ng, n, 1.0, X, ng, QX, ng, s));
-    HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, QX, ng, 0, 1, s));
-    HIPCHK(launch_stencil(ctx->gd, n, QX, ng, Y, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
-                          shifts_dev, s));
-    CHECK(phi_t_times(ctx, n, Y, ng, C));
-    HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, Y, ng, 0, 1, s));
-    return ACP_OK;
+    ENSURE(ctx->splitk, (size_t)kSplitSlices * ctx->ne * n * 8);
+    return apply_operator_ws(ctx, n, shifts_dev, X, Y, dp<double>(ctx->tmp2), dp<double>(ctx->c1),
+                             dp<double>(ctx->splitk));
 }
 
 // max_j ||B_j - A X_j|| / ||B_j||, FP64, from freshly recomputed residuals.
@@ -1245,6 +1269,20 @@ acp_status flags_status(acp_ctx *ctx, int f) {
 }
 
 
+// Device address of this GPU's scratch array (the current device is the
+// context's), looked up once per GPU.
+acp_status scratch_locate(acp_ctx *ctx) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices) return fail(ctx, ACP_EDEVICE, "device index");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[ctx->device]) return ACP_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(ctx, ACP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[ctx->device] = (double *)p;
+    return ACP_OK;
+}
+
 acp_status setup_impl(acp_ctx *ctx, const acp_grid *grid, const acp_opts *opts, const double *psi,
                       const double *eps, int n_e, const double *veff, void *stream) {
     if (grid->dim != 1 && grid->dim != 2) return fail(ctx, ACP_EINVAL, "dim must be 1 or 2");
@@ -1269,6 +1307,7 @@ acp_status setup_impl(acp_ctx *ctx, const acp_grid *grid, const acp_opts *opts, 
     for (int i = 1; i < n_e; ++i)
         if (!(ctx->eps[i] >= ctx->eps[i - 1])) return fail(ctx, ACP_EINVAL, "eps must be ascending");
     HIPCHK(hipGetDevice(&ctx->device));
+    CHECK(scratch_locate(ctx));
     ctx->stream = (hipStream_t)stream;
     for (auto &e : ctx->ev) HIPCHK(hipEventCreate(&e));
     const int ng = ctx->ng, nep = ctx->nep;
@@ -1931,6 +1970,30 @@ acp_status acp_residual(acp_ctx *ctx, const double *shift, int n, const double *
     CHECK(apply_operator(ctx, n, dp<double>(ctx->dy_s), X, R));
     HIPCHK(launch_axpby(ctx->ng, n, 1.0, B, ctx->ng, -1.0, R, ctx->ng, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ACP_OK;
+}
+
+acp_status acp_residual_noalloc(acp_ctx *ctx, const double *shift, int n, const double *B,
+                                const double *X, double *R) {
+    if (!ctx || !shift || !B || !X || !R || n < 0) return ACP_EINVAL;
+    if (n == 0) return ACP_OK;
+    double *ws = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!ws) return fail(ctx, ACP_ESTATE, "scratch array not located");
+    // [shifts n | QX N_g n | C N_e n | split-K work 8 N_e n], each part 256-byte aligned
+    auto up = [](size_t d) { return (d + 31) / 32 * 32; };
+    const size_t o_qx = up((size_t)n), o_c = o_qx + up((size_t)ctx->ng * n),
+                 o_w = o_c + up((size_t)ctx->ne * n), need = o_w + (size_t)kSplitSlices * ctx->ne * n;
+    if (need * sizeof(double) > ACP_NOALLOC_SCRATCH_BYTES) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "acp_residual_noalloc needs %zu bytes of scratch, the array holds %zu",
+                      need * sizeof(double), (size_t)ACP_NOALLOC_SCRATCH_BYTES);
+        return fail(ctx, ACP_EINVAL, buf);
+    }
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipMemcpyAsync(ws, shift, (size_t)n * 8, hipMemcpyHostToDevice, s));
+    CHECK(apply_operator_ws(ctx, n, ws, X, R, ws + o_qx, ws + o_c, ws + o_w));
+    HIPCHK(launch_axpby(ctx->ng, n, 1.0, B, ctx->ng, -1.0, R, ctx->ng, s));
+    HIPCHK(hipStreamSynchronize(s));
     return ACP_OK;
 }
 
