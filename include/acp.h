@@ -295,6 +295,16 @@ acp_status acp_batch_info(const acp_batch *batch, acp_batch_info_t *out);
 const char *acp_batch_last_error(const acp_batch *batch);
 void acp_batch_destroy(acp_batch *batch);
 
+/* acp_syev -- eigenvalues and eigenvectors of a dense symmetric FP64 matrix
+ * (the eigenvalue step of Sec. 2.2 for the dynamical matrix, and the
+ * Rayleigh-Ritz step of the ground-state generator), by cyclic Jacobi spread
+ * over the device.  A dev n x n column-major (lda >= n), overwritten; w host n
+ * eigenvalues ascending; V dev n x n (ldv >= n; column j belongs to w[j]) or
+ * NULL for eigenvalues only.  Work memory is allocated and freed inside the
+ * call; the stream (hipStream_t, NULL = default) is synchronised.  ACP_ENOCONV
+ * if 30 sweeps left rotations above the threshold (outputs still written). */
+acp_status acp_syev(int n, double *A, int lda, double *w, double *V, int ldv, void *stream);
+
 acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out);
 void acp_reset_stats(acp_ctx *ctx);
 const char *acp_last_error(const acp_ctx *ctx);

@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_batch_last_error": (C.c_char_p, [P]),
         "acp_batch_destroy": (None, [P]),
         "acp_get_stats": (I, [P, C.POINTER(AcpStats)]),
+        "acp_syev": (I, [I, P, I, P, P, I, P]),
         "acp_reset_stats": (None, [P]),
         "acp_last_error": (C.c_char_p, [P]),
         "acp_destroy": (None, [P]),
@@ -156,6 +157,27 @@ def _hostd(a) -> np.ndarray:
 
 def _hptr(a: np.ndarray) -> int:
     return a.ctypes.data
+
+
+def syev(A, want_vectors: bool = True, stream=None):
+    """Eigenvalues (numpy, ascending) and eigenvectors (device, column-major) of
+    the symmetric device matrix A (not modified: a copy is passed)."""
+    import torch
+    lib = load_library()
+    A = colmajor(A).clone()
+    A = colmajor(A)
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = None
+    if want_vectors:
+        V = torch.empty((n, n), dtype=torch.float64, device=A.device).t()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib.acp_syev(n, _dptr(A), n, _hptr(w), None if V is None else _dptr(V), n,
+                      C.c_void_p(stream.cuda_stream))
+    if st != ACP_OK:
+        raise ACPError(st, "acp_syev")
+    return w, V
 
 
 class Context:

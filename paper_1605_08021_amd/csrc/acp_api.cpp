@@ -2393,8 +2393,15 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
     HIPCHK(launch_dynmat_assemble(n_p, ctx->grid.dim, dp<double>(ctx->dm_phi), Kd, Md,
                                   dp<double>(ctx->dm_d), dp<double>(ctx->dm_asym), s));
     HIPCHK(hipMemcpyAsync(D, ctx->dm_d.p, nn * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(sym_eigvals(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig),
-                          dp<double>(ctx->dm_work), s));
+    if (n_p <= 128) {   // Householder + bisection in one workgroup's LDS
+        HIPCHK(sym_eigvals(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig),
+                           dp<double>(ctx->dm_work), s));
+    } else {            // cyclic Jacobi over the whole device
+        ENSURE(ctx->dm_work, sym_eig_work_doubles(n_p, false) * 8);
+        int sweeps = 0;
+        HIPCHK(sym_eig_jacobi(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig), nullptr, 0,
+                              dp<double>(ctx->dm_work), 30, 1e-15, s, &sweeps));
+    }
     HIPCHK(hipMemcpyAsync(omega2, ctx->dm_eig.p, (size_t)n_p * 8, hipMemcpyDeviceToHost, s));
     double asym[2];
     HIPCHK(hipMemcpyAsync(asym, ctx->dm_asym.p, 16, hipMemcpyDeviceToHost, s));
@@ -2403,6 +2410,26 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
     ctx->stats.ms_dynmat += event_ms(ctx->ev[0], ctx->ev[1]);
     ctx->stats.d_asymmetry = asym[1] > 0 ? std::sqrt(asym[0] / asym[1]) : 0.0;
     return ACP_OK;
+}
+
+acp_status acp_syev(int n, double *A, int lda, double *w, double *V, int ldv, void *stream) {
+    if (n < 1 || !A || !w || lda < n || (V && ldv < n)) return ACP_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf work, eig;
+    auto cleanup = [&](acp_status st) {
+        release(work);
+        release(eig);
+        return st;
+    };
+    if (!ensure(work, sym_eig_work_doubles(n, V != nullptr) * 8) || !ensure(eig, (size_t)n * 8))
+        return cleanup(ACP_ENOMEM);
+    int sweeps = 0;
+    if (sym_eig_jacobi(n, A, lda, (double *)eig.p, V, ldv, (double *)work.p, 30, 1e-15, s, &sweeps) != hipSuccess)
+        return cleanup(ACP_EDEVICE);
+    if (hipMemcpyAsync(w, eig.p, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(ACP_EDEVICE);
+    return cleanup(sweeps >= 30 ? ACP_ENOCONV : ACP_OK);
 }
 
 acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out) {

@@ -276,6 +276,15 @@ hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int
 // beyond), A overwritten; eig sorted ascending;
 // work holds n + 2 doubles + n + 2 ints.
 hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s);
+// Symmetric eigenvalues (ascending, eig dev n) and, when V is not null, the
+// eigenvectors (V dev n x n, column j for eig[j]) by cyclic Jacobi over the
+// whole device (k_eig.hip); A is overwritten; work: sym_eig_work_doubles(n, V
+// != null) doubles.  Stops after a sweep with no rotation above the threshold
+// |A_pq| > tol sqrt(|A_pp A_qq|) or after max_sweeps (the sweeps performed go to
+// *sweeps_out).  Synchronises the stream once per sweep.
+size_t sym_eig_work_doubles(int n, bool vectors);
+hipError_t sym_eig_jacobi(int n, double *A, int lda, double *eig, double *V, int ldv, double *work,
+                          int max_sweeps, double tol, hipStream_t s, int *sweeps_out);
 hipError_t launch_dynmat_assemble(int np, int dim, const double *Phi_el, const double *K_local,
                                   const double *mass, double *D, double *asym2,
                                   hipStream_t s);

@@ -1,0 +1,41 @@
+"""Dense symmetric eigensolver (cyclic Jacobi over the device) against the
+library routine numpy.linalg.eigh: eigenvalues, eigenvector residuals and
+orthonormality, on matrices with odd order (a bye in every round), repeated
+and exactly zero eigenvalues (the acoustic modes of a dynamical matrix)."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _matrix(n, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(-1.0, 3.0, n)
+    lam[:3] = 0.0                      # a threefold zero eigenvalue
+    lam[3:5] = 1.25                    # a degenerate pair
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T), np.sort(lam)
+
+
+@pytest.mark.parametrize("n", [7, 129, 300, 601])
+def test_syev_matches_library(n):
+    from paper_1605_08021_amd import acp
+    A, lam = _matrix(n, n)
+    print(f"[eig] n = {n}", flush=True)
+    w, V = acp.syev(to_dev(A))
+    ref = np.linalg.eigvalsh(A)
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() <= 1e-13 * n * scale
+    V = to_host(V)
+    assert np.abs(A @ V - V * w).max() <= 1e-12 * n * scale
+    assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-13 * n
+    w2, _ = acp.syev(to_dev(A), want_vectors=False)
+    assert np.array_equal(w2, w)
