@@ -295,6 +295,35 @@ acp_status acp_batch_info(const acp_batch *batch, acp_batch_info_t *out);
 const char *acp_batch_last_error(const acp_batch *batch);
 void acp_batch_destroy(acp_batch *batch);
 
+/* ---- Ground state (input generator) -----------------------------------------
+ * acp_lowest_eigenpairs -- the n_want lowest eigenpairs of H = -1/2 Delta_h +
+ * diag(V) on the grid (the occupied orbitals phi_i and energies eps_i that
+ * acp_setup takes; the paper computes them by LOBPCG, Sec. 4), by
+ * Chebyshev-filtered subspace iteration on the device: a subspace of n_want +
+ * n_guard vectors from a seeded Gaussian start, filtered by the degree-m
+ * Chebyshev polynomial that damps [a, b] (a = the subspace's largest Ritz value,
+ * b = an upper bound of the spectrum), then Rayleigh-Ritz (two Gram
+ * orthonormalisations, projected H, acp_syev's Jacobi), until every returned
+ * pair has ||H x - lambda x||_2 <= tol.
+ *   grid: dim, n, h (kappa, eps0, occ unused);  veff dev N_g
+ *   psi dev N_g x n_want (output, l2-orthonormal columns, ascending energies)
+ *   lambda host n_want;  lambda_next host or NULL: the next Ritz value (an
+ *   estimate of eigenvalue n_want + 1, for the gap);  passes, max_resid host or NULL.
+ * Allocates its work memory (about 4 N_g (n_want + n_guard) doubles) and frees it
+ * before returning; synchronises the stream.  ACP_ENOCONV after max_pass passes
+ * (outputs still written).  Errors: acp_last_error(NULL). */
+typedef struct {
+    int n_want;                 /* eigenpairs returned */
+    int n_guard;                /* extra subspace vectors (0: max(16, n_want / 10)) */
+    int degree;                 /* filter degree per pass (0: 20) */
+    int max_pass;               /* filter + Rayleigh-Ritz passes (0: 60) */
+    double tol;                 /* residual norm bound of every returned pair (0: 1e-10) */
+    unsigned long long seed;    /* start block */
+} acp_eig_opts;
+acp_status acp_lowest_eigenpairs(const acp_grid *grid, const double *veff, const acp_eig_opts *opts,
+                                 double *psi, double *lambda, double *lambda_next, int *passes,
+                                 double *max_resid, void *stream);
+
 /* acp_syev -- eigenvalues and eigenvectors of a dense symmetric FP64 matrix
  * (the eigenvalue step of Sec. 2.2 for the dynamical matrix, and the
  * Rayleigh-Ritz step of the ground-state generator), by cyclic Jacobi spread
@@ -307,7 +336,7 @@ acp_status acp_syev(int n, double *A, int lda, double *w, double *V, int ldv, vo
 
 acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out);
 void acp_reset_stats(acp_ctx *ctx);
-const char *acp_last_error(const acp_ctx *ctx);
+const char *acp_last_error(const acp_ctx *ctx);   /* NULL: the last call without a context */
 void acp_destroy(acp_ctx *ctx);
 
 /* Version string of the library build. */

@@ -61,6 +61,11 @@ class AcpStats(C.Structure):
                 ("krylov_group", C.c_int), ("n_mu", C.c_int)]
 
 
+class AcpEigOpts(C.Structure):
+    _fields_ = [("n_want", C.c_int), ("n_guard", C.c_int), ("degree", C.c_int), ("max_pass", C.c_int),
+                ("tol", C.c_double), ("seed", C.c_ulonglong)]
+
+
 class AcpBatchInfo(C.Structure):
     _fields_ = [("n_systems", C.c_int), ("n_tiles", C.c_int), ("grid", C.c_int), ("order", C.c_int),
                 ("tuned", C.c_int), ("graph_replays", C.c_longlong), ("ms_last", C.c_double),
@@ -114,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_batch_destroy": (None, [P]),
         "acp_get_stats": (I, [P, C.POINTER(AcpStats)]),
         "acp_syev": (I, [I, P, I, P, P, I, P]),
+        "acp_lowest_eigenpairs": (I, [C.POINTER(AcpGrid), P, C.POINTER(AcpEigOpts), P, P, P, P, P, P]),
         "acp_reset_stats": (None, [P]),
         "acp_last_error": (C.c_char_p, [P]),
         "acp_destroy": (None, [P]),
@@ -178,6 +184,41 @@ def syev(A, want_vectors: bool = True, stream=None):
     if st != ACP_OK:
         raise ACPError(st, "acp_syev")
     return w, V
+
+
+def _grid_struct(grid: dict) -> AcpGrid:
+    g = AcpGrid()
+    g.dim = int(grid["dim"])
+    n = list(grid["n"]) + [1]
+    g.n[0], g.n[1] = int(n[0]), int(n[1])
+    g.h = float(grid["h"])
+    g.kappa, g.eps0, g.occ = (float(grid.get("kappa", 1.0)), float(grid.get("eps0", 1.0)),
+                              float(grid.get("occ", 2.0)))
+    return g
+
+
+def lowest_eigenpairs(grid: dict, veff, n_want: int, n_guard: int = 0, degree: int = 0,
+                      max_pass: int = 0, tol: float = 0.0, seed: int = 1, stream=None):
+    """acp_lowest_eigenpairs: (psi dev N_g x n_want, eps numpy n_want, next Ritz value,
+    passes, largest residual)."""
+    import torch
+    lib = load_library()
+    veff = veff.contiguous()
+    g = _grid_struct(grid)
+    o = AcpEigOpts(n_want, n_guard, degree, max_pass, tol, seed)
+    psi = torch.empty((n_want, veff.shape[0]), dtype=torch.float64, device=veff.device).t()
+    lam = np.zeros(n_want)
+    nxt = C.c_double(0.0)
+    passes = C.c_int(0)
+    res = C.c_double(0.0)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib.acp_lowest_eigenpairs(C.byref(g), _dptr(veff), C.byref(o), _dptr(psi), _hptr(lam),
+                                   C.byref(nxt), C.byref(passes), C.byref(res),
+                                   C.c_void_p(stream.cuda_stream))
+    if st != ACP_OK:
+        raise ACPError(st, lib.acp_last_error(None).decode())
+    return psi, lam, nxt.value, passes.value, res.value
 
 
 class Context:

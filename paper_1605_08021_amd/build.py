@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libacp.so")
 ARCH = os.environ.get("ACP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["acp_api.cpp", "k_util.hip", "k_gemm.hip", "k_krylov.hip", "k_mscg.hip", "k_dense.hip",
+SOURCES = ["acp_api.cpp", "ground_state.cpp", "k_util.hip", "k_gemm.hip", "k_krylov.hip", "k_mscg.hip", "k_dense.hip",
            "k_nn.hip", "k_eig.hip"]
 
 # Packed FP32 instructions are disabled for all device code (see the design notes).

@@ -2444,7 +2444,7 @@ void acp_reset_stats(acp_ctx *ctx) {
     ctx->stats.n_mu = ctx->nmu;   // describes the compression still held, not a counter
 }
 
-const char *acp_last_error(const acp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *acp_last_error(const acp_ctx *ctx) { return ctx ? ctx->err.c_str() : acp::g_free_error.c_str(); }
 
 void acp_destroy(acp_ctx *ctx) {
     if (!ctx) return;

@@ -31,6 +31,9 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Error text of the last call without a context (acp_last_error(NULL)).
+extern thread_local std::string g_free_error;
+
 // Grow-only device buffer; returns nullptr on failure.
 void *ensure(DevBuf &b, size_t bytes);
 void release(DevBuf &b);

@@ -29,7 +29,7 @@ def test_struct_layouts_match_header():
     import re
     text = re.sub(r"/\*.*?\*/", "", open(acp.HEADER).read(), flags=re.S)
     for cname, py in (("acp_opts", acp.AcpOpts), ("acp_stats", acp.AcpStats),
-                      ("acp_grid", acp.AcpGrid)):
+                      ("acp_grid", acp.AcpGrid), ("acp_eig_opts", acp.AcpEigOpts)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + r";", text).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         names = []
@@ -46,8 +46,10 @@ def test_struct_layouts_match_header():
 def test_null_context_calls_are_rejected():
     lib = acp.load_library()
     assert lib.acp_apply_chi0(None, None, 0, None) == acp.ACP_EINVAL
-    assert lib.acp_last_error(None) == b"null context"
     lib.acp_destroy(None)
+    # calls without a context report through acp_last_error(NULL)
+    assert lib.acp_lowest_eigenpairs(None, None, None, None, None, None, None, None, None) == acp.ACP_EINVAL
+    assert lib.acp_last_error(None) == b"null argument"
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
