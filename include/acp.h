@@ -318,7 +318,7 @@ typedef struct {
     int degree;                 /* filter degree per pass (0: 20) */
     int max_pass;               /* filter + Rayleigh-Ritz passes (0: 60) */
     double tol;                 /* residual norm bound of every returned pair (0: 1e-10) */
-    unsigned long long seed;    /* start block */
+    uint64_t seed;              /* start block */
 } acp_eig_opts;
 acp_status acp_lowest_eigenpairs(const acp_grid *grid, const double *veff, const acp_eig_opts *opts,
                                  double *psi, double *lambda, double *lambda_next, int *passes,
