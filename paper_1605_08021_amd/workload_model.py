@@ -83,11 +83,20 @@ class _Grid:
         return np.stack([q.ravel(order="F") for q in mesh], axis=1)
 
     def vc(self, x):
-        extra = x.shape[1:]
-        xx = x.reshape(self.shape + extra)
+        """v_c x by real FFTs over the grid axes, 256 columns at a time, threaded."""
+        import os
+        import scipy.fft as sf
         axes = tuple(range(self.d))
-        s = self.vc_sym.reshape(self.vc_sym.shape + (1,) * len(extra))
-        return np.fft.ifftn(np.fft.fftn(xx, axes=axes) * s, axes=axes).real.reshape(x.shape)
+        sym = self.vc_sym[..., : self.n[0] // 2 + 1]     # half spectrum along x (the last FFT axis)
+        cols = x.reshape(self.ng, -1)
+        out = np.empty_like(cols)
+        workers = min(16, os.cpu_count() or 1)
+        for j0 in range(0, cols.shape[1], 256):
+            blk = cols[:, j0:j0 + 256].reshape(self.shape + (-1,))
+            f = sf.rfftn(blk, axes=axes, workers=workers)
+            f *= sym[..., None]
+            out[:, j0:j0 + 256] = sf.irfftn(f, s=self.shape, axes=axes, workers=workers).reshape(self.ng, -1)
+        return out.reshape(x.shape)
 
     def kinetic_dense(self):
         """-1/2 Delta_h as a dense matrix."""
@@ -164,6 +173,25 @@ def _lowest_sparse(T, V, k):
     return w[o], v[:, o]
 
 
+def _lowest_gpu(cfg: Config, V: np.ndarray, n_e: int):
+    """The n_e lowest eigenpairs of H[V] (and the next Ritz value) from
+    acp_lowest_eigenpairs; eigenvalues n_e + 1 entries, vectors N_g x n_e."""
+    import sys
+    import time
+    import torch
+    from paper_1605_08021_amd import acp
+    if not torch.cuda.is_available():
+        raise RuntimeError("the ground state of a large grid is computed on the GPU")
+    t0 = time.perf_counter()
+    grid = dict(dim=cfg.dim, n=cfg.n, h=cfg.h)
+    psi, lam, nxt, passes, res = acp.lowest_eigenpairs(
+        grid, torch.from_numpy(np.ascontiguousarray(V)).cuda(), n_e, tol=1e-10, seed=cfg.cid)
+    v = psi.cpu().numpy()
+    print(f"[inputs] {n_e} lowest eigenpairs of {V.shape[0]} points on the GPU: {passes} passes, "
+          f"largest residual {res:.1e}, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return np.append(lam, nxt), v
+
+
 def _kerker(grid: _Grid, q0: float = 0.3) -> np.ndarray:
     q2 = np.zeros(grid.shape)
     for ax, k in enumerate(reversed(grid.n)):
@@ -225,12 +253,20 @@ def _atom_density(cfg: Config, z_ref: float) -> tuple:
 
 
 def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
+    import sys
+    import time
+    t0 = time.perf_counter()
+
+    def note(what):
+        print(f"[inputs] {what} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
     R, Z, n_e = draw_sites(cfg)
     grid = _Grid(cfg.n, cfg.h, cfg.kappa, cfg.eps0)
     m_each, D = _gaussians(grid, R, Z, cfg.sigma)
     m = m_each.sum(axis=1)
     z_ref = cfg.f
     r_tab, rho_tab = _atom_density(cfg, z_ref)
+    note("isolated-atom density")
     dist = np.sqrt((D ** 2).sum(axis=2))
     rho = np.zeros(grid.ng)
     for I in range(R.shape[0]):
@@ -241,10 +277,12 @@ def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
         T = grid.kinetic_dense()
         rho, V, w, v, sc = _scf(grid, T, m, rho, n_e, cfg.f, max(scf_iters, 0) + 1, 1e-8)
     else:
-        # large grids: the Harris potential only, diagonalised iteratively
+        # large grids: the Harris potential only, its lowest eigenpairs by the
+        # library's Chebyshev-filtered subspace iteration on the GPU
         V = grid.vc(rho + m)
-        w, v = _lowest_sparse(_kinetic_sparse(grid), V, n_e + 1)
+        w, v = _lowest_gpu(cfg, V, n_e)
         sc = False
+    note("ground state")
     phi = np.ascontiguousarray(v[:, :n_e])
     rho_gs = (cfg.f / grid.dv) * (phi ** 2).sum(axis=1)
     # perturbations g_{I,a} = v_c d m_I / d R_{I,a} and the local Hessian terms
@@ -252,6 +290,7 @@ def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
     n_a = R.shape[0]
     dm = (m_each[:, :, None] * D / cfg.sigma ** 2).reshape(grid.ng, n_a * d)
     G = grid.vc(dm)
+    note("perturbations")
     K = grid.dv * (dm.T @ G)
     pot = grid.vc(rho_gs + m)
     own = grid.vc(m_each)
@@ -259,6 +298,7 @@ def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
         d2 = m_each[:, I, None, None] * (D[:, I, :, None] * D[:, I, None, :] / cfg.sigma ** 4
                                           - np.eye(d)[None] / cfg.sigma ** 2)
         K[d * I:d * I + d, d * I:d * I + d] = grid.dv * np.einsum("gab,g->ab", d2, pot - own[:, I])
+    note("local Hessian terms")
     from workload.seeds import draw_sketch
     return Inputs(cfg=cfg, n=tuple(cfg.n), h=cfg.h, R=R, Z=Z, n_e=n_e, phi=phi, eps=w,
                   veff=V, rho=rho_gs, G=G, K_local=K, omega=draw_sketch(cfg, n_a * d),
