@@ -140,6 +140,11 @@ void acp_default_opts(acp_opts *opts);
  *         interval is [eps[0], eps[n_e-1]] (Sec. 3.1)
  *   veff  dev, N_g effective potential; copied
  *   stream  hipStream_t (NULL = default stream) on which all work is ordered
+ * Orbital counts: up to 256 the shifted solves run in the fused tile kernels
+ * (all solvers, FP64 or ACP_PREC_FP32_REFINE); above 256 the Krylov vectors are
+ * column-major blocks with the projector as two GEMMs (ACP_SOLVER_CG multi-shift
+ * and ACP_SOLVER_CG_SINGLE, FP64; other combinations give ACP_EINVAL at the
+ * solve), and acp_batch_create accepts at most 256.
  * The caller must also guarantee that the shifts stay below the lowest
  * unoccupied eigenvalue (a positive gap); a violation is detected as ACP_ENOTSPD.
  * On success *ctx owns device memory until acp_destroy. */

@@ -153,6 +153,27 @@ class DenseShiftedSolver:
         return np.linalg.solve(A, b)
 
 
+class ProjectedSpectralSolver:
+    """Same solution for any l2-orthonormal Phi (not necessarily eigenvectors of
+    H) from the eigenpairs of Q H Q + c Phi Phi^T, c above the spectrum of H:
+    its eigenvectors with eigenvalues below c span range(Q), so
+    z = sum_{mu_a < c} u_a (u_a^T b) / (mu_a - s)."""
+
+    def __init__(self, H: np.ndarray, phi: np.ndarray):
+        n = H.shape[0]
+        P = phi @ phi.T
+        Q = np.eye(n) - P
+        c = 2.0 * np.abs(H).sum(axis=1).max() + 1.0   # Gershgorin bound, doubled
+        mu, U = np.linalg.eigh(Q @ H @ Q + c * P)
+        keep = mu < 0.5 * c
+        self.mu, self.U = mu[keep], U[:, keep]
+
+    def __call__(self, shift: float, b: np.ndarray) -> np.ndarray:
+        y = self.U.T @ b
+        y /= (self.mu - shift)[:, None]
+        return self.U @ y
+
+
 def solve_compressed(solver: Callable, nodes: np.ndarray, R: np.ndarray) -> List[np.ndarray]:
     """Z_c (N_g x N_mu) for every shift eps~_c: Q(H - eps~_c)Q Z_c = R."""
     return [solver(float(s), R) for s in nodes]

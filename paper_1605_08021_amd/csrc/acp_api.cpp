@@ -87,6 +87,7 @@ struct acp_ctx {
     DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc, fc_idx;   // flexible CG
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
+    DevBuf wd_p, wd_r, wd_w, wd_c, wd_sc, wd_sig;   // multi-shift CG with GEMM projector (many orbitals)
     acp_stats stats{};
     std::string err;
     hipEvent_t ev[8]{};
@@ -798,11 +799,149 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     return ACP_OK;
 }
 
+// ---- multi-shift CG with the projector as two GEMMs (many orbitals)
+// Orbital counts above this use column-major Krylov blocks and GEMMs for the
+// projector (the fused kernels hold C = Phi^T y of a 16-system tile in
+// registers, up to 256 orbitals).
+constexpr int kFusedMaxNe = 256;
+// Split-K slices of the Phi^T X products (work: 8 N_e n doubles).
+constexpr int kSplitSlices = 8;
+bool wide_form(const acp_ctx *ctx) { return ctx->nep > kFusedMaxNe; }
+
+// Device memory budget of one wide solve (right-hand sides are processed in
+// column chunks that fit it): the nc search directions, r and w per column.
+constexpr double kWideBudgetBytes = 96.0 * 1024 * 1024 * 1024;
+
+// Solve Q (H - s_c) Q z = b for the nb columns of B (column-major, leading
+// dimension N_g, in range(Q)) at every shift s_c (c < nc; base = the largest,
+// nearest the LUMO) by multi-shift CG from z = 0; each shift of each column
+// stops on its recurrence residual |zeta_c| |r| <= tol |b|.  Solutions: Z +
+// c zstride (N_g x nb, leading dimension N_g).  iters (host nc x nb, [c][j]) or
+// null.  With col_shift_dev (device, nb) and one shift, column j is solved at
+// its own shift col_shift_dev[j] instead (plain CG per system).
+acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const std::vector<double> &shifts,
+                                 double tol, double *Z, long long zstride, int *flags_or, int *iters,
+                                 const double *col_shift_dev = nullptr) {
+    const int ng = ctx->ng, ne = ctx->ne, nc = (int)shifts.size();
+    hipStream_t s = ctx->stream;
+    const int base = (int)(std::max_element(shifts.begin(), shifts.end()) - shifts.begin());
+    std::vector<double> sig(nc);
+    for (int c = 0; c < nc; ++c) sig[c] = shifts[base] - shifts[c];
+    ENSURE(ctx->wd_sig, (size_t)nc * 8);
+    HIPCHK(hipMemcpyAsync(ctx->wd_sig.p, sig.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
+    const double per_col = (2.0 * nc + 2.0) * ng * 8.0;
+    int chunk = (int)std::max(16.0, std::min((double)nb, std::floor(kWideBudgetBytes / per_col)));
+    if (chunk < nb) chunk = std::max(16, chunk / 16 * 16);
+    ENSURE(ctx->wd_p, (size_t)nc * ng * chunk * 8);
+    ENSURE(ctx->wd_r, (size_t)ng * chunk * 8);
+    ENSURE(ctx->wd_w, (size_t)ng * chunk * 8);
+    ENSURE(ctx->wd_c, (size_t)ne * chunk * 8);
+    ENSURE(ctx->splitk, (size_t)kSplitSlices * ne * chunk * 8);
+    // scalars: 7 nb doubles (rr rrn bn al alp btp pw) + 6 nc nb doubles, then ints
+    const size_t nd = 7 * (size_t)chunk + 6 * (size_t)nc * chunk;
+    const size_t ni = (size_t)chunk + 3 * (size_t)nc * chunk + 2;
+    ENSURE(ctx->wd_sc, nd * 8 + ni * 4);
+    double *sd = dp<double>(ctx->wd_sc);
+    int *si = (int *)(sd + nd);
+    double *P = dp<double>(ctx->wd_p), *r = dp<double>(ctx->wd_r), *w = dp<double>(ctx->wd_w);
+    double *C = dp<double>(ctx->wd_c);
+    const double *phi = dp<double>(ctx->phi_cm);
+    std::vector<int> it_h((size_t)nc * chunk);
+    for (int j0 = 0; j0 < nb; j0 += chunk) {
+        const int n = std::min(chunk, nb - j0);
+        WideScalars ws;
+        ws.rr = sd;
+        ws.rrn = sd + n;
+        ws.bn = sd + 2 * n;
+        ws.al = sd + 3 * n;
+        ws.alp = sd + 4 * n;
+        ws.btp = sd + 5 * n;
+        double *pw = sd + 6 * n;
+        double *sc = sd + 7 * n;
+        ws.z = sc;
+        ws.zp = sc + (size_t)nc * n;
+        ws.ac = sc + 2 * (size_t)nc * n;
+        ws.zn = sc + 3 * (size_t)nc * n;
+        ws.bc = sc + 4 * (size_t)nc * n;
+        ws.res = sc + 5 * (size_t)nc * n;
+        ws.colact = si;
+        ws.act = si + n;
+        ws.upd = si + n + (size_t)nc * n;
+        ws.it = si + n + 2 * (size_t)nc * n;
+        ws.flags = si + n + 3 * (size_t)nc * n;
+        ws.nactive = ws.flags + 1;
+        const double *Bj = B + (size_t)j0 * ng;
+        double *Zj = Z + (size_t)j0 * ng;
+        for (int c = 0; c < nc; ++c) {
+            HIPCHK(hipMemsetAsync(Zj + c * zstride, 0, (size_t)ng * n * 8, s));
+            HIPCHK(hipMemcpyAsync(P + (size_t)c * ng * n, Bj, (size_t)ng * n * 8, hipMemcpyDeviceToDevice, s));
+        }
+        HIPCHK(hipMemcpyAsync(r, Bj, (size_t)ng * n * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(launch_col_sqnorm(ng, n, Bj, ng, ws.rrn, s));
+        HIPCHK(launch_fill_i32(ws.flags, 1, 0, s));
+        HIPCHK(wide_init(n, nc, ws.rrn, ws, s));
+        const double *pb = P + (size_t)base * ng * n;
+        int iter = 0;
+        for (; iter < ctx->opts.max_iter; ++iter) {
+            HIPCHK(hipEventRecord(ctx->ev[6], s));
+            // w = Q (H - s_base) p  (p in range(Q))
+            if (col_shift_dev)
+                HIPCHK(launch_stencil(ctx->gd, n, pb, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
+                                      col_shift_dev + j0, s));
+            else
+                HIPCHK(launch_stencil(ctx->gd, n, pb, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, -shifts[base],
+                                      nullptr, s));
+            HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, w, ng, 0.0, C, ne, dp<double>(ctx->splitk),
+                               (size_t)kSplitSlices * ne * n, s));
+            HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, w, ng, 0, 1, s));
+            HIPCHK(hipEventRecord(ctx->ev[7], s));
+            HIPCHK(launch_col_dot(ng, n, pb, ng, w, ng, pw, s));
+            HIPCHK(launch_fill_i32(ws.nactive, 1, 0, s));
+            HIPCHK(wide_step(ng, n, nc, base, dp<double>(ctx->wd_sig), tol, iter, pw, w, r, P, Zj, zstride, ws, s));
+            int live = 0;
+            HIPCHK(hipMemcpyAsync(&live, ws.nactive, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ctx->stats.ms_solve_kernel += event_ms(ctx->ev[6], ctx->ev[7]);
+            ctx->stats.solve_kernel_launches += 1;
+            ctx->stats.krylov_flops += 4.0 * ng * (double)ne * n;
+            ctx->stats.krylov_bytes += 8.0 * ng * (double)n * 5.0;   // stencil 2, Phi^T y 1, y - Phi C 2
+            if (live == 0) {
+                ++iter;
+                break;
+            }
+        }
+        int fl = 0;
+        HIPCHK(hipMemcpyAsync(it_h.data(), ws.it, (size_t)nc * n * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&fl, ws.flags, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (iter >= ctx->opts.max_iter) fl |= 1;
+        *flags_or |= fl;
+        int mn = 1 << 30, mx = 0;
+        for (int c = 0; c < nc; ++c)
+            for (int j = 0; j < n; ++j) {
+                const int v = it_h[(size_t)c * n + j];
+                mn = std::min(mn, v);
+                mx = std::max(mx, v);
+                ctx->stats.system_iterations += v;
+                if (iters) iters[(size_t)c * nb + j0 + j] = v;
+            }
+        ctx->stats.tile_iterations += (long long)iter * ((n + kTile - 1) / kTile);
+        ctx->stats.iters_min = j0 == 0 ? mn : std::min(ctx->stats.iters_min, mn);
+        ctx->stats.iters_max = j0 == 0 ? mx : std::max(ctx->stats.iters_max, mx);
+    }
+    ctx->stats.krylov_group = 0;
+    return ACP_OK;
+}
+
+// max over columns of ||B_j - A_c Z_j|| / ||B_j|| for the nc shift blocks of Z
+// (N_g x nb each, stride zstride) against the same B, in column chunks.
+acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std::vector<double> &shifts,
+                                const double *Z, long long zstride, double *max_rel);
+
 // A X = Q (H - s_j) Q X for column-major X (n columns); result in Y.
 // C = Phi^T X (N_e x n, leading dimension N_e) for column-major X (leading
 // dimension ldx): split-K over the grid when the output has few tiles, with
 // at most 8 slices (work: 8 N_e n doubles), whatever the workspace holds.
-constexpr int kSplitSlices = 8;
 acp_status phi_t_times_ws(acp_ctx *ctx, int n, const double *X, int ldx, double *C, double *work) {
     const int ng = ctx->ng, ne = ctx->ne;
     HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, dp<double>(ctx->phi_cm), ng, X, ldx, 0.0, C, ne,
@@ -857,6 +996,36 @@ acp_status true_residual(acp_ctx *ctx, int n, const double *shifts_dev, const do
     double m = 0.0;
     for (int j = 0; j < n; ++j)
         if (h[n + j] > 0.0) m = std::max(m, std::sqrt(h[j] / h[n + j]));
+    *max_rel = m;
+    return ACP_OK;
+}
+
+acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std::vector<double> &shifts,
+                                const double *Z, long long zstride, double *max_rel) {
+    const int ng = ctx->ng, nc = (int)shifts.size();
+    hipStream_t s = ctx->stream;
+    const int chunk = std::max(16, std::min(nb, (int)std::floor(4.0 * 1024 * 1024 * 1024 / (8.0 * ng))));
+    ENSURE(ctx->tmp1, (size_t)ng * chunk * 8);
+    ENSURE(ctx->dy_norm, (size_t)2 * chunk * 8);
+    ENSURE(ctx->dy_s, (size_t)chunk * 8);
+    double *rn = dp<double>(ctx->dy_norm), *bn = rn + chunk;
+    std::vector<double> h((size_t)2 * chunk), sh(chunk);
+    double m = 0.0;
+    for (int c = 0; c < nc; ++c)
+        for (int j0 = 0; j0 < nb; j0 += chunk) {
+            const int n = std::min(chunk, nb - j0);
+            std::fill(sh.begin(), sh.end(), shifts[c]);
+            HIPCHK(hipMemcpyAsync(ctx->dy_s.p, sh.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+            CHECK(apply_operator(ctx, n, dp<double>(ctx->dy_s), Z + c * zstride + (size_t)j0 * ng,
+                                 dp<double>(ctx->tmp1)));
+            HIPCHK(launch_col_diff_sqnorm(ng, n, B + (size_t)j0 * ng, ng, dp<double>(ctx->tmp1), ng, rn, s));
+            HIPCHK(launch_col_sqnorm(ng, n, B + (size_t)j0 * ng, ng, bn, s));
+            HIPCHK(hipMemcpyAsync(h.data(), rn, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h.data() + chunk, bn, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int j = 0; j < n; ++j)
+                if (h[chunk + j] > 0.0) m = std::max(m, std::sqrt(h[j] / h[chunk + j]));
+        }
     *max_rel = m;
     return ACP_OK;
 }
@@ -1298,7 +1467,6 @@ acp_status setup_impl(acp_ctx *ctx, const acp_grid *grid, const acp_opts *opts, 
     ctx->gd.h = grid->h;
     ctx->ng = ctx->gd.ng;
     if (n_e < 1 || n_e >= ctx->ng) return fail(ctx, ACP_EINVAL, "n_e out of range");
-    if (n_e > 256) return fail(ctx, ACP_EINVAL, "n_e > 256 is not supported by this build");
     CHECK(validate_opts(ctx, opts));
     ctx->opts = *opts;
     ctx->ne = n_e;
@@ -1432,10 +1600,13 @@ acp_status prepare_rhs(acp_ctx *ctx) {
     HIPCHK(gemm(Op::N, Op::N, ng, nmu, ne, 1.0, phi, ng, 0, C, ne, 0, 1.0, R, ng, 0, 1, s));
     HIPCHK(hipEventRecord(ctx->ev[2], s));
     // tiled right-hand sides (one copy, shared by every shift) and per-column shifts
+    // (the wide form works on the column-major R itself)
     const int rhs_tiles = nmp / kTile;
     const int ntiles = rhs_tiles * nc;
-    ENSURE(ctx->krhs, (size_t)rhs_tiles * ng * kTile * 8);
-    HIPCHK(launch_to_tiled(ng, nmu, nmp, R, ng, dp<double>(ctx->krhs), s));
+    if (!wide_form(ctx)) {
+        ENSURE(ctx->krhs, (size_t)rhs_tiles * ng * kTile * 8);
+        HIPCHK(launch_to_tiled(ng, nmu, nmp, R, ng, dp<double>(ctx->krhs), s));
+    }
     std::vector<double> sh((size_t)ntiles * kTile);
     for (int c = 0; c < nc; ++c)
         for (int j = 0; j < nmp; ++j) sh[(size_t)c * nmp + j] = ctx->nodes[c];
@@ -1481,6 +1652,21 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
         std::vector<int> it(ncols);
         CHECK(fcg_solve(ctx, ncols, shc.data(), dp<double>(ctx->shifts_dev), Bfull, dp<double>(ctx->z),
                         it.data(), &flags));
+    } else if (wide_form(ctx)) {
+        // many orbitals: column-major blocks, the projector by GEMMs, solutions
+        // straight into Z; per-system CG is the same iteration one shift at a time
+        if (mixed || ctx->opts.solver == ACP_SOLVER_MINRES)
+            return fail(ctx, ACP_EINVAL, "above 256 orbitals only the FP64 CG solvers are built");
+        ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
+        double *Z = dp<double>(ctx->z);
+        if (ctx->opts.solver == ACP_SOLVER_CG) {
+            CHECK(solve_multishift_wide(ctx, R, nmu, ctx->nodes, ctx->opts.tol, Z, (long long)ng * nmu, &flags,
+                                        nullptr));
+        } else {
+            for (int c = 0; c < nc; ++c)
+                CHECK(solve_multishift_wide(ctx, R, nmu, std::vector<double>{ctx->nodes[c]}, ctx->opts.tol,
+                                            Z + (size_t)c * ng * nmu, (long long)ng * nmu, &flags, nullptr));
+        }
     } else if (!mixed) {
         KrylovInputs<double> in{dp<double>(ctx->phi_rm), phi, dp<double>(ctx->krhs)};
         if (ctx->opts.solver == ACP_SOLVER_CG)
@@ -1506,6 +1692,27 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     return finish_compress(ctx, flags, learned);
 }
 
+// W = (2 f / h^d) sum_c Z_c o (Phi diag(L_c) Phi(Pi,:)^T)  (Eq. (3.7)) from ctx->z.
+acp_status assemble_w(acp_ctx *ctx) {
+    const int ng = ctx->ng, ne = ctx->ne, nmu = ctx->nmu;
+    const int nc = (int)ctx->nodes.size();
+    hipStream_t s = ctx->stream;
+    const double *phi = dp<double>(ctx->phi_cm);
+    const double *Z = dp<double>(ctx->z);
+    ENSURE(ctx->w, (size_t)ng * nmu * 8);
+    ENSURE(ctx->bc, (size_t)ne * nmu * 8);
+    double *W = dp<double>(ctx->w);
+    HIPCHK(hipMemsetAsync(W, 0, (size_t)ng * nmu * 8, s));
+    const double pref = 2.0 * ctx->grid.occ / std::pow(ctx->grid.h, ctx->grid.dim);
+    for (int c = 0; c < nc; ++c) {
+        HIPCHK(launch_weighted_rows(ne, nmu, dp<double>(ctx->lw_dev) + (size_t)c * ne,
+                                    dp<int>(ctx->sel_dev), phi, ng, dp<double>(ctx->bc), s));
+        HIPCHK(gemm(Op::N, Op::N, ng, nmu, ne, pref, phi, ng, 0, dp<double>(ctx->bc), ne, 0, 0.0, W,
+                    ng, 0, 1, s, Epi::HadamardAcc, Z + (size_t)c * nmu * ng, ng, 0));
+    }
+    return ACP_OK;
+}
+
 // Part 3: Z from the tiled solutions (unless the solver wrote Z), the mixed
 // form's refinement, W, timings, FP64 true residuals, status.
 acp_status finish_compress(acp_ctx *ctx, int flags, bool learned) {
@@ -1520,6 +1727,21 @@ acp_status finish_compress(acp_ctx *ctx, int flags, bool learned) {
     // Z (column-major, block c = shift c)
     ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
     double *Z = dp<double>(ctx->z);
+    if (wide_form(ctx) && !learned) {
+        // Z written by the solver; W, then the FP64 true residuals in column chunks
+        HIPCHK(hipEventRecord(ctx->ev[3], s));
+        CHECK(assemble_w(ctx));
+        HIPCHK(hipEventRecord(ctx->ev[4], s));
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->stats.ms_rhs += event_ms(ctx->ev[1], ctx->ev[2]);
+        ctx->stats.ms_solve += event_ms(ctx->ev[2], ctx->ev[3]);
+        ctx->stats.ms_w += event_ms(ctx->ev[3], ctx->ev[4]);
+        double mr = 0.0;
+        CHECK(true_residual_blocks(ctx, R, nmu, ctx->nodes, Z, (long long)ng * nmu, &mr));
+        ctx->stats.max_rel_residual = mr;
+        ctx->have_chi0 = true;
+        return flags_status(ctx, flags);
+    }
     if (!learned)
         for (int c = 0; c < nc; ++c)
             HIPCHK(launch_from_tiled(ng, nmu, dp<double>(ctx->kx) + (size_t)c * rhs_tiles * ng * kTile,
@@ -1542,18 +1764,7 @@ acp_status finish_compress(acp_ctx *ctx, int flags, bool learned) {
         CHECK(refine_fp32(ctx, ncols, dp<double>(ctx->dy_s), Bfull, Z, &flags, &mr));
     }
     HIPCHK(hipEventRecord(ctx->ev[3], s));
-    // W = (2 f / h^d) sum_c Z_c o (Phi diag(L_c) Phi(Pi,:)^T)
-    ENSURE(ctx->w, (size_t)ng * nmu * 8);
-    ENSURE(ctx->bc, (size_t)ne * nmu * 8);
-    double *W = dp<double>(ctx->w);
-    HIPCHK(hipMemsetAsync(W, 0, (size_t)ng * nmu * 8, s));
-    const double pref = 2.0 * ctx->grid.occ / std::pow(ctx->grid.h, ctx->grid.dim);
-    for (int c = 0; c < nc; ++c) {
-        HIPCHK(launch_weighted_rows(ne, nmu, dp<double>(ctx->lw_dev) + (size_t)c * ne,
-                                    dp<int>(ctx->sel_dev), phi, ng, dp<double>(ctx->bc), s));
-        HIPCHK(gemm(Op::N, Op::N, ng, nmu, ne, pref, phi, ng, 0, dp<double>(ctx->bc), ne, 0, 0.0, W,
-                    ng, 0, 1, s, Epi::HadamardAcc, Z + (size_t)c * nmu * ng, ng, 0));
-    }
+    CHECK(assemble_w(ctx));
     HIPCHK(hipEventRecord(ctx->ev[4], s));
     HIPCHK(hipStreamSynchronize(s));
     ctx->stats.ms_rhs += event_ms(ctx->ev[1], ctx->ev[2]);
@@ -1910,8 +2121,10 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
     hipStream_t s = ctx->stream;
     const int ntiles = (n + kTile - 1) / kTile;
     const int npad = ntiles * kTile;
-    ENSURE(ctx->krhs, (size_t)npad * ng * 8);
-    HIPCHK(launch_to_tiled(ng, n, npad, B, ng, dp<double>(ctx->krhs), s));
+    if (!wide_form(ctx)) {
+        ENSURE(ctx->krhs, (size_t)npad * ng * 8);
+        HIPCHK(launch_to_tiled(ng, n, npad, B, ng, dp<double>(ctx->krhs), s));
+    }
     std::vector<double> sh(npad, shift[n - 1]);
     for (int j = 0; j < n; ++j) sh[j] = shift[j];
     ENSURE(ctx->shifts_dev, (size_t)npad * 8);
@@ -1921,6 +2134,22 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
     if (ctx->opts.use_learned_precond) {
         std::vector<int> it(n);
         CHECK(fcg_solve(ctx, n, sh.data(), dp<double>(ctx->shifts_dev), B, X, it.data(), &flags));
+        HIPCHK(hipEventRecord(ctx->ev[3], s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (iters) std::memcpy(iters, it.data(), (size_t)n * 4);
+        ctx->stats.ms_solve += event_ms(ctx->ev[2], ctx->ev[3]);
+        ctx->stats.systems_solved += n;
+        double mr = 0.0;
+        CHECK(true_residual(ctx, n, dp<double>(ctx->shifts_dev), B, X, &mr));
+        ctx->stats.max_rel_residual = mr;
+        return flags_status(ctx, flags);
+    }
+    if (wide_form(ctx)) {
+        if (ctx->opts.precision != ACP_PREC_FP64 || ctx->opts.solver == ACP_SOLVER_MINRES)
+            return fail(ctx, ACP_EINVAL, "above 256 orbitals only the FP64 CG solvers are built");
+        std::vector<int> it(n);
+        CHECK(solve_multishift_wide(ctx, B, n, std::vector<double>{0.0}, ctx->opts.tol, X, (long long)ng * n,
+                                    &flags, it.data(), dp<double>(ctx->shifts_dev)));
         HIPCHK(hipEventRecord(ctx->ev[3], s));
         HIPCHK(hipStreamSynchronize(s));
         if (iters) std::memcpy(iters, it.data(), (size_t)n * 4);

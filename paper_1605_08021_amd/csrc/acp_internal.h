@@ -200,6 +200,26 @@ hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t s);
 hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);
 hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s);
 
+// ---------------------------------------------------------------- multi-shift CG, many orbitals
+// Scalar state of the wide multi-shift CG (k_wide.hip): per column j (nb) and
+// per (shift c, column j) at c * nb + j.
+struct WideScalars {
+    double *rr, *rrn, *bn, *al, *alp, *btp;          // nb each
+    double *z, *zp, *ac, *zn, *bc, *res;             // nc * nb each
+    int *colact;                                     // nb
+    int *act, *upd, *it;                             // nc * nb each
+    int *flags, *nactive;                            // 1 each
+};
+// rr = |b|^2 from bsq, every shift live for b != 0, zeta = 1.
+hipError_t wide_init(int nb, int nc, const double *bsq, const WideScalars &w, hipStream_t s);
+// One CG step after w = A p (p = P block `base`) and pw = p.w: alpha, r <- r - alpha w,
+// the shifted coefficients, x_c / p_c updates of every shift, the column state
+// (nactive += live columns).  P: nc blocks of N_g x nb (stride N_g nb); X: nc
+// blocks of N_g x nb with stride xs between the shifts' blocks.
+hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, const double *pw,
+                     const double *w_vec, double *r, double *P, double *X, long long xs, const WideScalars &w,
+                     hipStream_t s);
+
 // ---------------------------------------------------------------- learned preconditioner
 // Network of four periodic convolutions (channels kNnChannels), BF16 operands on
 // the matrix cores, FP32 accumulation (k_nn.hip).

@@ -240,3 +240,26 @@ def test_dyson_stop_rule(sys_):
     assert r.changes[0] == 1.0 and r.changes[1] < 1e-9
     assert A.acp_dyson(*args, k_max=3, delta=1.0, **common).iters == 1
     assert A.acp_dyson(*args, k_max=3, delta=0.0, **common).iters == 3
+
+
+def test_projected_spectral_solver(sys_):
+    """The eigenpairs of Q H Q + c P give the solution of Q (H - s) Q z = b for
+    any orthonormal Phi: equal to the dense factorisation (random Phi), to the
+    exact solver (Phi = occupied eigenvectors), and z solves the equation."""
+    cfg, m, gs, w, v, G, om = sys_
+    H = m.hamiltonian_dense(gs.veff)
+    rng = np.random.default_rng(2)
+    n = H.shape[0]
+    phi, _ = np.linalg.qr(rng.standard_normal((n, 12)))
+    b = A.project_q(phi, rng.standard_normal((n, 3)))
+    s = float(np.linalg.eigvalsh(H)[0]) - 0.5
+    z = A.ProjectedSpectralSolver(H, phi)(s, b)
+    zd = A.DenseShiftedSolver(H, phi)(s, b)
+    assert np.abs(z - zd).max() < 1e-10 * np.abs(zd).max()
+    Q = np.eye(n) - phi @ phi.T
+    assert np.abs(Q @ (H - s * np.eye(n)) @ Q @ z - b).max() < 1e-10 * np.abs(b).max()
+    R = A.project_q(gs.phi, rng.standard_normal((n, 3)))
+    s2 = float(gs.eps[0])
+    ze = A.ExactShiftedSolver(w, v, gs.n_e)(s2, R)
+    zp = A.ProjectedSpectralSolver(H, gs.phi)(s2, R)
+    assert np.abs(zp - ze).max() < 1e-9 * np.abs(ze).max()
