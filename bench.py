@@ -6,8 +6,13 @@ projected shifted solves to a relative residual of 1e-8, W), the Dyson updates,
 then the dynamical matrix and its eigenvalues.  value = shifted systems solved
 per second over the timed steps (whole job; inputs already in HBM).
 
-Input preparation (ground state, perturbations, local Hessian terms) is done
-once, untimed, by paper_1605_08021_amd.workload_model.
+Default workload: the 2D lattice of 32 x 32 sites on a 384 x 384 grid (1024
+occupied orbitals, 2048 perturbations, N_c = 8, N_mu = 4096: 32768 shifted
+systems per compression), one Dyson iteration per step (k_max = 1, so that the
+driver's 25 steps fit its time limit; --dyson-iters sets more).
+
+Input preparation (ground state by the library's GPU eigensolver, perturbations,
+local Hessian terms) is done once, untimed, by paper_1605_08021_amd.workload_model.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
                        [--form fast|mixed|learned|single|plain|batch]
@@ -38,30 +43,32 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+CSRC = os.path.join(ROOT, "paper_1605_08021_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mscg_kernel_cfg2_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1605_08021_amd", "csrc", f)
-                  for f in ("k_mscg.hip", "krylov_common.h")]
+KERNEL_SOURCES = [os.path.join(CSRC, f) for f in ("k_mscg.hip", "krylov_common.h")]
+GEMM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_projector_cfg5_traffic.json")
+GEMM_SOURCES = [os.path.join(CSRC, "k_gemm.hip")]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the multi-shift kernel from the committed rocprofv3
+def measured_traffic(workload: str, path: str = TRAFFIC_FILE, sources=None):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (scaled by the copy-kernel calibration), or None
     when the kernel source has changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != kernel_source_hash() or rec.get("workload") != workload:
+    if rec.get("kernel_source_sha256") != kernel_source_hash(sources) or rec.get("workload") != workload:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -93,15 +100,25 @@ def cpu_baseline(inp, sample_cols: int, tol: float):
     m = Model(grid, inp.R, inp.Z, inp.n_e, sigma=cfg.sigma, kappa=cfg.kappa, eps0=cfg.eps0,
               f=cfg.f)
     t0 = time.perf_counter()
-    dec = OA.isdf_qrcp(inp.phi, inp.G, inp.omega, cfg.n_mu)
     nodes, _ = OA.shifts_and_weights(inp.eps[: inp.n_e], cfg.n_cheb)
-    R = OA.rhs(inp.phi, dec.xi)
-    t_prep = time.perf_counter() - t0
-    # sample: the first sample_cols // N_c right-hand sides at every shift
     per = max(1, sample_cols // len(nodes))
-    B = np.tile(R[:, :per], (1, len(nodes)))
+    if grid.n_grid * cfg.r * inp.n_e * 8 <= 4e9:
+        # the first sample_cols // N_c right-hand sides of the oracle's own ISDF, every shift
+        dec = OA.isdf_qrcp(inp.phi, inp.G, inp.omega, cfg.n_mu)
+        R = OA.rhs(inp.phi, dec.xi)[:, :per]
+        what = "right-hand sides of the oracle's ISDF"
+    else:
+        # the sketched M~ would not fit: right-hand sides -Q e_alpha at evenly
+        # spaced grid points (interpolation vectors of the identity selection)
+        E = np.zeros((grid.n_grid, per))
+        E[np.linspace(0, grid.n_grid - 1, per).astype(int), np.arange(per)] = 1.0
+        R = OA.rhs(inp.phi, E)
+        what = "right-hand sides -Q e_alpha at evenly spaced grid points"
+    t_prep = time.perf_counter() - t0
+    B = np.tile(R, (1, len(nodes)))
     shifts = np.repeat(nodes, per)
-    op = OK.make_operator(m, inp.veff, inp.phi, shifts)
+    H = m.hamiltonian_sparse(inp.veff) if grid.n_grid > 20000 else None
+    op = OK.make_operator(m, inp.veff, inp.phi, shifts, H=H)
     t0 = time.perf_counter()
     x, it, _ = OK.cg(op, B, tol)
     t = time.perf_counter() - t0
@@ -111,9 +128,9 @@ def cpu_baseline(inp, sample_cols: int, tol: float):
         cores = os.cpu_count()
     return {"value": B.shape[1] / t, "unit": "systems/s", "cores": cores, "kind": "oracle",
             "sample": f"{B.shape[1]} of the {len(nodes) * cfg.n_mu} shifted systems of one "
-                      f"compression ({per} right-hand sides x {len(nodes)} shifts), plain batched "
+                      f"compression ({per} {what} x {len(nodes)} shifts), plain batched "
                       f"CG to {tol:g}, numpy/OpenBLAS; mean iterations {float(it.mean()):.0f}; "
-                      f"solve {t:.1f} s (ISDF+RHS preparation {t_prep:.1f} s not counted)"}
+                      f"solve {t:.1f} s (right-hand-side preparation {t_prep:.1f} s not counted)"}
 
 
 def main():
@@ -121,14 +138,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=5)
     ap.add_argument("--form", choices=["fast", "mixed", "learned", "single", "plain", "batch", "compress"],
                     default="fast")
     ap.add_argument("--batch-systems", type=int, default=16)
-    ap.add_argument("--dyson-iters", type=int, default=4)
+    ap.add_argument("--dyson-iters", type=int, default=0, help="k_max (0: 1 for workload 5, else 4)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="CPU baseline systems (0: 256, 16 above 100k points)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel used to calibrate the traffic counters")
     args = ap.parse_args()
@@ -153,6 +170,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cfg = get_config(args.config)
+    if args.dyson_iters <= 0:
+        args.dyson_iters = 1 if args.config == 5 else 4
     log(f"building inputs for workload {args.config}: {cfg.name}")
     t0 = time.perf_counter()
     inp = build_inputs(cfg)
@@ -249,6 +268,24 @@ def main():
                 "mfma_fp64_tflops": round(flops_per_launch / (ms_per_launch * 1e-3) / 1e12, 2),
                 "ms_per_launch": round(ms_per_launch, 3),
                 "workgroups_per_tile": st["krylov_group"]}
+    wide = ne > 256
+    if wide:
+        # many orbitals: the dominant kernel is the projector GEMM pair on the FP64
+        # matrix cores (gemm_f64_kernel<.., 2>: C = Phi^T y, then y - Phi C), timed
+        # by HIP events on the context's stream around the two launches of every
+        # iteration; achieved = 4 N_g N_e flops per live column and iteration
+        gemm_launches = 2 * launches
+        tflops = st["krylov_flops"] / (st["ms_solve_kernel"] * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic(f"config {args.config}", GEMM_TRAFFIC_FILE,
+                                                GEMM_SOURCES),
+                    "kernel": "gemm_f64_kernel<.., 2> (projector GEMMs of the many-orbital multi-shift CG, "
+                              "FP64 v_mfma_f64_16x16x4)",
+                    "algorithmic_flops_per_launch": st["krylov_flops"] / gemm_launches,
+                    "algorithmic_bytes_per_launch": st["krylov_bytes"] / gemm_launches,
+                    "ms_per_launch": round(st["ms_solve_kernel"] / gemm_launches, 3),
+                    "iterations": launches}
     if learned:
         roofline = None   # no single fused kernel: the flexible CG is a host-driven loop
     log(f"stats: {json.dumps(st)}")
@@ -266,7 +303,8 @@ def main():
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
-                               f"ground state, gap {inp.gap:.5f} Ha",
+                               f"ground state{' from the GPU eigensolver' if ng > 8000 else ''}, "
+                               f"gap {inp.gap:.5f} Ha",
                    "form": ("one compression per step (point selection, right-hand sides, "
                             "batched FP64 multi-shift CG, W); no Dyson update or dynamical matrix"
                             if compress_only else
@@ -289,9 +327,15 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    # release every device object before the interpreter's teardown (a profiler
+    # preloaded into the process has finalised by then)
+    del phi, veff, G, om
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle CG on a bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(inp, args.cpu_sample, args.tol)
+        sample = args.cpu_sample or (16 if inp.phi.shape[0] > 100000 else 256)
+        out["cpu_baseline"] = cpu_baseline(inp, sample, args.tol)
     print(json.dumps(out), flush=True)
 
 

@@ -329,6 +329,14 @@ acp_status acp_lowest_eigenpairs(const acp_grid *grid, const double *veff, const
                                  double *psi, double *lambda, double *lambda_next, int *passes,
                                  double *max_resid, void *stream);
 
+/* acp_gesv -- X = A^{-1} B for a dense FP64 matrix (the small solve
+ * (I - T) S = G(Pi, :) of each Dyson iteration, Eq. (3.13)): blocked LU with
+ * partial pivoting up to n = 1024 (32-column panels factored in registers,
+ * GEMM trailing updates), Gauss-Jordan with partial pivoting above.
+ * A dev n x n (lda >= n) and B dev n x nrhs (ldb >= n) are overwritten (B <- X);
+ * synchronises the stream. */
+acp_status acp_gesv(int n, int nrhs, double *A, int lda, double *B, int ldb, void *stream);
+
 /* acp_syev -- eigenvalues and eigenvectors of a dense symmetric FP64 matrix
  * (the eigenvalue step of Sec. 2.2 for the dynamical matrix, and the
  * Rayleigh-Ritz step of the ground-state generator), by cyclic Jacobi spread

@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_batch_destroy": (None, [P]),
         "acp_get_stats": (I, [P, C.POINTER(AcpStats)]),
         "acp_syev": (I, [I, P, I, P, P, I, P]),
+        "acp_gesv": (I, [I, I, P, I, P, I, P]),
         "acp_lowest_eigenpairs": (I, [C.POINTER(AcpGrid), P, C.POINTER(AcpEigOpts), P, P, P, P, P, P]),
         "acp_reset_stats": (None, [P]),
         "acp_last_error": (C.c_char_p, [P]),
@@ -184,6 +185,21 @@ def syev(A, want_vectors: bool = True, stream=None):
     if st != ACP_OK:
         raise ACPError(st, "acp_syev")
     return w, V
+
+
+def gesv(A, B, stream=None):
+    """X = A^{-1} B (device, column-major); A and B are copied first."""
+    import torch
+    lib = load_library()
+    A = colmajor(colmajor(A).clone())
+    X = colmajor(colmajor(B).clone())
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib.acp_gesv(A.shape[0], X.shape[1], _dptr(A), A.shape[0], _dptr(X), X.shape[0],
+                      C.c_void_p(stream.cuda_stream))
+    if st != ACP_OK:
+        raise ACPError(st, "acp_gesv")
+    return X
 
 
 def _grid_struct(grid: dict) -> AcpGrid:

@@ -883,17 +883,18 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         const double *pb = P + (size_t)base * ng * n;
         int iter = 0;
         for (; iter < ctx->opts.max_iter; ++iter) {
-            HIPCHK(hipEventRecord(ctx->ev[6], s));
-            // w = Q (H - s_base) p  (p in range(Q))
+            // w = Q (H - s_base) p  (p in range(Q)); the projector GEMMs are timed
             if (col_shift_dev)
                 HIPCHK(launch_stencil(ctx->gd, n, pb, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
                                       col_shift_dev + j0, s));
             else
                 HIPCHK(launch_stencil(ctx->gd, n, pb, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, -shifts[base],
                                       nullptr, s));
+            HIPCHK(hipEventRecord(ctx->ev[6], s));
             HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, w, ng, 0.0, C, ne, dp<double>(ctx->splitk),
-                               (size_t)kSplitSlices * ne * n, s));
-            HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, w, ng, 0, 1, s));
+                               (size_t)kSplitSlices * ne * n, s, Epi::StoreProjector));
+            HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, w, ng, 0, 1, s,
+                        Epi::StoreProjector));
             HIPCHK(hipEventRecord(ctx->ev[7], s));
             HIPCHK(launch_col_dot(ng, n, pb, ng, w, ng, pw, s));
             HIPCHK(launch_fill_i32(ws.nactive, 1, 0, s));
@@ -904,7 +905,9 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
             ctx->stats.ms_solve_kernel += event_ms(ctx->ev[6], ctx->ev[7]);
             ctx->stats.solve_kernel_launches += 1;
             ctx->stats.krylov_flops += 4.0 * ng * (double)ne * n;
-            ctx->stats.krylov_bytes += 8.0 * ng * (double)n * 5.0;   // stencil 2, Phi^T y 1, y - Phi C 2
+            // algorithmic bytes of the projector pair: y read twice, written once,
+            // Phi read once per GEMM, C written and read
+            ctx->stats.krylov_bytes += 8.0 * ((double)ng * n * 3.0 + 2.0 * ng * ne + 2.0 * ne * n);
             if (live == 0) {
                 ++iter;
                 break;
@@ -2639,6 +2642,17 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
     ctx->stats.ms_dynmat += event_ms(ctx->ev[0], ctx->ev[1]);
     ctx->stats.d_asymmetry = asym[1] > 0 ? std::sqrt(asym[0] / asym[1]) : 0.0;
     return ACP_OK;
+}
+
+acp_status acp_gesv(int n, int nrhs, double *A, int lda, double *B, int ldb, void *stream) {
+    if (n < 1 || nrhs < 0 || !A || !B || lda < n || ldb < n) return ACP_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf piv;
+    if (!ensure(piv, lu_pinfo_ints(n) * 4)) return ACP_ENOMEM;
+    const hipError_t e = lu_solve(n, nrhs, A, lda, B, ldb, (int *)piv.p, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    release(piv);
+    return (e != hipSuccess || e2 != hipSuccess) ? ACP_EDEVICE : ACP_OK;
 }
 
 acp_status acp_syev(int n, double *A, int lda, double *w, double *V, int ldv, void *stream) {

@@ -53,8 +53,10 @@ hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, do
 
 // ---------------------------------------------------------------- GEMM (FP64 MFMA)
 enum class Op { N, T };
-enum class Epi { Store, HadamardAcc };
-// C = alpha op(A) op(B) + beta C   (Store)
+enum class Epi { Store, HadamardAcc, StoreProjector };
+// C = alpha op(A) op(B) + beta C   (Store; StoreProjector is the same product
+//                                  under its own kernel symbol: the projector
+//                                  GEMMs of the many-orbital Krylov solver)
 // C += alpha (op(A) op(B)) o E     (HadamardAcc; beta ignored)
 // batched with strides sa, sb, sc, se (in elements).
 hipError_t gemm(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
@@ -67,7 +69,7 @@ hipError_t gemm(Op ta, Op tb, int m, int n, int k, double alpha, const double *A
 // summed in a fixed order.  Op::N/Op::T as above; beta applies to C.
 hipError_t gemm_splitk(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
                        const double *B, int ldb, double beta, double *C, int ldc, double *work,
-                       size_t work_elems, hipStream_t s);
+                       size_t work_elems, hipStream_t s, Epi epi = Epi::Store);
 
 // ---------------------------------------------------------------- small utilities
 hipError_t launch_scale_copy(int m, int n, double alpha, const double *X, int ldx, double *Y,

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
         if (gm < M && gn < N) {
             double v = alpha * Cs[col * LDC_S + row];
             double *cp = C + gm + (long long)gn * ldc;
-            if (EPI == 0) {
+            if (EPI != 1) {
                 if (beta != 0.0) v += beta * (*cp);
                 *cp = v;
             } else {
@@ -153,6 +153,9 @@ hipError_t dispatch_epi(int m, int n, int k, double alpha, const double *A, int 
     dim3 grid((m + BM - 1) / BM, (n + BN - 1) / BN, batch);
     if (epi == Epi::Store)
         hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 0>), grid, dim3(NT), 0, s, m, n, k, alpha, A,
+                           lda, sa, B, ldb, sb, beta, C, ldc, sc, E, lde, se);
+    else if (epi == Epi::StoreProjector)   // same code; its own symbol, so profiles separate it
+        hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 2>), grid, dim3(NT), 0, s, m, n, k, alpha, A,
                            lda, sa, B, ldb, sb, beta, C, ldc, sc, E, lde, se);
     else
         hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 1>), grid, dim3(NT), 0, s, m, n, k, alpha, A,
@@ -189,7 +192,7 @@ __global__ void splitk_reduce_kernel(int m, int n, int nsplit, const double *W, 
 
 hipError_t gemm_splitk(Op ta, Op tb, int m, int n, int k, double alpha, const double *A, int lda,
                        const double *B, int ldb, double beta, double *C, int ldc, double *work,
-                       size_t work_elems, hipStream_t s) {
+                       size_t work_elems, hipStream_t s, Epi epi) {
     // split so that the grid has >= ~512 workgroups; each slice handles a multiple
     // of 64 of K.  The slices of equal length run as one batched launch (batch
     // index = slice), a shorter last slice as a second launch.
@@ -199,7 +202,7 @@ hipError_t gemm_splitk(Op ta, Op tb, int m, int n, int k, double alpha, const do
     if (nsplit > kmax_split) nsplit = kmax_split;
     while (nsplit > 1 && (size_t)nsplit * m * n > work_elems) --nsplit;
     if (nsplit <= 1)
-        return gemm(ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, s);
+        return gemm(ta, tb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, s, epi);
     const int kc = ((k + nsplit - 1) / nsplit + 63) / 64 * 64;
     const int nfull = k / kc;
     const int rem = k - nfull * kc;
@@ -207,11 +210,11 @@ hipError_t gemm_splitk(Op ta, Op tb, int m, int n, int k, double alpha, const do
     const long long sa = (ta == Op::N) ? (long long)kc * lda : kc;
     const long long sb = (tb == Op::N) ? kc : (long long)kc * ldb;
     const long long sc = (long long)m * n;
-    hipError_t e = gemm(ta, tb, m, n, kc, 1.0, A, lda, sa, B, ldb, sb, 0.0, work, m, sc, nfull, s);
+    hipError_t e = gemm(ta, tb, m, n, kc, 1.0, A, lda, sa, B, ldb, sb, 0.0, work, m, sc, nfull, s, epi);
     if (e != hipSuccess) return e;
     if (rem > 0) {
         e = gemm(ta, tb, m, n, rem, 1.0, A + nfull * sa, lda, 0, B + nfull * sb, ldb, 0, 0.0,
-                 work + (size_t)nfull * m * n, m, 0, 1, s);
+                 work + (size_t)nfull * m * n, m, 0, 1, s, epi);
         if (e != hipSuccess) return e;
     }
     long long tot = (long long)m * n;
