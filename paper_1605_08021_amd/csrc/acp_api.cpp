@@ -64,6 +64,7 @@ struct acp_ctx {
     int u_np = 0;
     DevBuf gt, lchol, diag, isdf_scratch, l11, linv, c1, bc, tmp1, tmp2, tmp3, shifts_dev;
     DevBuf pgram;              // Phi Phi^T (N_g x N_g) for the point selection, when it fits
+    DevBuf isdf_panel;         // pools of the panel form of the point selection
     bool pgram_ready = false;
     DevBuf kx, kr, kpa, kpb, kw1, kw2, krhs, kiters, kresid, kflags, ktile;
     DevBuf msp, msgbuf, mscnt, msactive, mshalo, msabort, msprof;
@@ -1542,8 +1543,12 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
     // each greedy pivot step then reads one of its columns instead of all of Phi.
     // A forced selection keeps the direct products (its pivots may lie past the
     // numerical rank, where the sign of the rounding decides acceptance).
+    // the panel form when Phi Phi^T is not kept (or when ACP_ISDF_PANEL=1 asks for it)
+    const char *panel_env = std::getenv("ACP_ISDF_PANEL");
+    const bool gram_fits = (double)ng * ng * 8.0 <= kGramBudgetBytes;
+    const bool panel = !sel_in && (panel_env ? std::atoi(panel_env) != 0 : !gram_fits);
     const double *pgram = nullptr;
-    if (!sel_in && (double)ng * ng * 8.0 <= kGramBudgetBytes) {
+    if (!sel_in && !panel && gram_fits) {
         if (!ctx->pgram_ready) {
             ENSURE(ctx->pgram, (size_t)ng * ng * 8);
             HIPCHK(gemm(Op::N, Op::T, ng, ng, ctx->ne, 1.0, dp<double>(ctx->phi_cm), ng, 0,
@@ -1553,10 +1558,17 @@ acp_status isdf_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega
         pgram = dp<double>(ctx->pgram);
     }
     int got = 0;
-    HIPCHK(isdf_pivoted_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), pgram, dp<double>(ctx->gt), nmu,
-                                 sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol),
-                                 dp<double>(ctx->diag), dp<int>(ctx->sel_dev), forced, &got,
-                                 ctx->isdf_scratch.p, s));
+    if (panel) {
+        ENSURE(ctx->isdf_panel, isdf_panel_scratch_bytes(ng, ctx->ne, r, nmu));
+        HIPCHK(isdf_panel_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), dp<double>(ctx->gt), nmu,
+                                   ctx->opts.isdf_tol, dp<double>(ctx->lchol), dp<double>(ctx->diag),
+                                   dp<int>(ctx->sel_dev), &got, ctx->isdf_panel.p, s));
+    } else {
+        HIPCHK(isdf_pivoted_cholesky(ng, ctx->ne, r, dp<double>(ctx->phi_cm), pgram, dp<double>(ctx->gt), nmu,
+                                     sel_in ? 0.0 : ctx->opts.isdf_tol, dp<double>(ctx->lchol),
+                                     dp<double>(ctx->diag), dp<int>(ctx->sel_dev), forced, &got,
+                                     ctx->isdf_scratch.p, s));
+    }
     if (got < 1) return fail(ctx, ACP_EINVAL, "interpolative decomposition found no pivot");
     if (sel_in && got < nmu)
         return fail(ctx, ACP_EINVAL, "forced selection is rank deficient or repeats a point");
@@ -2695,7 +2707,7 @@ void acp_destroy(acp_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->phi_cm, &ctx->phi_rm, &ctx->veff, &ctx->lw_dev, &ctx->fx, &ctx->fy,
                       &ctx->svc, &ctx->sel_dev, &ctx->forced_dev, &ctx->xi, &ctx->rhs, &ctx->z,
                       &ctx->w, &ctx->u_last, &ctx->gt, &ctx->lchol, &ctx->diag,
-                      &ctx->isdf_scratch, &ctx->pgram, &ctx->l11, &ctx->linv, &ctx->c1, &ctx->bc, &ctx->tmp1,
+                      &ctx->isdf_scratch, &ctx->isdf_panel, &ctx->pgram, &ctx->l11, &ctx->linv, &ctx->c1, &ctx->bc, &ctx->tmp1,
                       &ctx->tmp2, &ctx->tmp3, &ctx->shifts_dev, &ctx->kx, &ctx->kr, &ctx->kpa,
                       &ctx->kpb, &ctx->kw1, &ctx->kw2, &ctx->krhs, &ctx->kiters, &ctx->kresid,
                       &ctx->kflags, &ctx->ktile, &ctx->dy_v, &ctx->dy_t, &ctx->dy_s, &ctx->dy_g,

@@ -280,6 +280,17 @@ hipError_t isdf_pivoted_cholesky(int ng, int ne, int r, const double *phi, const
                                  int *sel_dev, const int *forced, int *nmu_out_host, void *scratch,
                                  hipStream_t s);
 size_t isdf_scratch_bytes(int ng);
+// The same selection in panels (k_isdf_panel.hip), for grids whose Phi Phi^T
+// is not kept: pools of kIsdfPool rows with the largest remaining diagonal,
+// their residual Gram columns by GEMMs, up to kIsdfPanel pivots per pool, the
+// same pivots as the step-by-step rule.  Unforced only; scratch of
+// isdf_panel_scratch_bytes bytes.
+constexpr int kIsdfPool = 256;
+constexpr int kIsdfPanel = 64;
+size_t isdf_panel_scratch_bytes(int ng, int ne, int r, int nmu);
+hipError_t isdf_panel_cholesky(int ng, int ne, int r, const double *phi, const double *gt, int nmu_max, double tol,
+                               double *L, double *diag, int *sel_dev, int *nmu_out_host, void *scratch,
+                               hipStream_t s);
 // Order n2 >= n (32 times a power of two) of the padded inverse below.
 int tri_inverse_order(int n);
 // X (n2 x n2, leading dimension n2) = [L11 0; 0 I]^{-1} for L11(i, j) = L(sel[i], j),

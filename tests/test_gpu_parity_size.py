@@ -178,10 +178,14 @@ def test_2d_at_size_matches_oracle():
     _dyson_dynmat_parity("2d_large", kmax=2, z_tol=1e-8, u_tol=1e-8, d_tol=1e-6)
 
 
-def test_2d_at_size_point_selection():
-    """Unforced point selection above 8192 grid points (candidate loads shared
-    across the block): every GPU pivot is a greedy maximum by brute force, and
-    the interpolation error is within twice the oracle's QRCP error."""
+@pytest.mark.parametrize("form", ["gram", "panel"])
+def test_2d_at_size_point_selection(form, monkeypatch):
+    """Unforced point selection above 8192 grid points, with Phi Phi^T kept
+    (candidate loads shared across the block) and in panels (pools of rows with
+    their residual Gram columns by GEMMs, the form of grids whose Phi Phi^T is
+    not kept): every GPU pivot is a greedy maximum by brute force, and the
+    interpolation error is within twice the oracle's QRCP error."""
+    monkeypatch.setenv("ACP_ISDF_PANEL", "1" if form == "panel" else "0")
     cfg, m, gs, solver, G, om, K = _system("2d_large")
     ref = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
     ctx = _ctx(cfg, gs)
@@ -195,7 +199,7 @@ def test_2d_at_size_point_selection():
     n_same = next((k for k in range(cfg.n_mu) if sel[k] != ref.sel[k]), cfg.n_mu)
     res_gpu = np.linalg.norm(Mt - Xi @ Mt[sel])
     res_ref = OA.id_residual(gs.phi, G, om, ref)
-    print(f"[parity] 2D selection: pivots identical for {n_same} of {cfg.n_mu}; "
+    print(f"[parity] 2D selection ({form}): pivots identical for {n_same} of {cfg.n_mu}; "
           f"ID residual {res_gpu:.3e} vs oracle {res_ref:.3e}", flush=True)
     assert res_gpu <= 2.0 * res_ref + 1e-12 * np.linalg.norm(Mt)
 
@@ -208,10 +212,12 @@ def test_2d_general_gather_matches_oracle(solver_id):
                          solver_id=solver_id)
 
 
-def test_rank_rule_matches_oracle():
+@pytest.mark.parametrize("form", ["step", "panel"])
+def test_rank_rule_matches_oracle(form, monkeypatch):
     """Alg. 2 step 3 with a threshold: N_mu = the first k with
     |R_kk| < tol |R_11|; the GPU's rank and, with the oracle's pivots forced,
     its interpolation vectors match the oracle's."""
+    monkeypatch.setenv("ACP_ISDF_PANEL", "1" if form == "panel" else "0")
     cfg, m, gs, solver, G, om, K = _system("2d_small")
     full = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
     rd = full.rdiag / full.rdiag[0]
