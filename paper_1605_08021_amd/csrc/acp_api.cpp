@@ -810,8 +810,9 @@ constexpr int kSplitSlices = 8;
 bool wide_form(const acp_ctx *ctx) { return ctx->nep > kFusedMaxNe; }
 
 // Device memory budget of one wide solve (right-hand sides are processed in
-// column chunks that fit it): the nc search directions, r and w per column.
-constexpr double kWideBudgetBytes = 96.0 * 1024 * 1024 * 1024;
+// column chunks that fit it): the nc search directions, the residual ring and w
+// per column.
+constexpr double kWideBudgetBytes = 128.0 * 1024 * 1024 * 1024;
 
 // Solve Q (H - s_c) Q z = b for the nb columns of B (column-major, leading
 // dimension N_g, in range(Q)) at every shift s_c (c < nc; base = the largest,
@@ -830,21 +831,24 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
     for (int c = 0; c < nc; ++c) sig[c] = shifts[base] - shifts[c];
     ENSURE(ctx->wd_sig, (size_t)nc * 8);
     HIPCHK(hipMemcpyAsync(ctx->wd_sig.p, sig.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
-    const double per_col = (2.0 * nc + 2.0) * ng * 8.0;
+    constexpr int W = kWideWindow;
+    const double per_col = (nc + W + 1.0) * ng * 8.0;   // p_c, the residual ring, w
     int chunk = (int)std::max(16.0, std::min((double)nb, std::floor(kWideBudgetBytes / per_col)));
     if (chunk < nb) chunk = std::max(16, chunk / 16 * 16);
     ENSURE(ctx->wd_p, (size_t)nc * ng * chunk * 8);
-    ENSURE(ctx->wd_r, (size_t)ng * chunk * 8);
+    ENSURE(ctx->wd_r, (size_t)W * ng * chunk * 8);
     ENSURE(ctx->wd_w, (size_t)ng * chunk * 8);
     ENSURE(ctx->wd_c, (size_t)ne * chunk * 8);
     ENSURE(ctx->splitk, (size_t)kSplitSlices * ne * chunk * 8);
-    // scalars: 7 nb doubles (rr rrn bn al alp btp pw) + 6 nc nb doubles, then ints
-    const size_t nd = 7 * (size_t)chunk + 6 * (size_t)nc * chunk;
-    const size_t ni = (size_t)chunk + 3 * (size_t)nc * chunk + 2;
+    // scalars: 7 nb doubles (rr rrn bn al alp btp pw), 6 nc nb doubles, the window
+    // coefficients, then ints (colact, act, upd, it, touched, flags, nactive)
+    const size_t ncoef = (size_t)nc * chunk * (2 + 2 * W);
+    const size_t nd = 7 * (size_t)chunk + 6 * (size_t)nc * chunk + ncoef;
+    const size_t ni = (size_t)chunk + 4 * (size_t)nc * chunk + 2;
     ENSURE(ctx->wd_sc, nd * 8 + ni * 4);
     double *sd = dp<double>(ctx->wd_sc);
     int *si = (int *)(sd + nd);
-    double *P = dp<double>(ctx->wd_p), *r = dp<double>(ctx->wd_r), *w = dp<double>(ctx->wd_w);
+    double *P = dp<double>(ctx->wd_p), *ring = dp<double>(ctx->wd_r), *w = dp<double>(ctx->wd_w);
     double *C = dp<double>(ctx->wd_c);
     const double *phi = dp<double>(ctx->phi_cm);
     std::vector<int> it_h((size_t)nc * chunk);
@@ -865,11 +869,13 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         ws.zn = sc + 3 * (size_t)nc * n;
         ws.bc = sc + 4 * (size_t)nc * n;
         ws.res = sc + 5 * (size_t)nc * n;
+        ws.coef = sc + 6 * (size_t)nc * n;
         ws.colact = si;
         ws.act = si + n;
         ws.upd = si + n + (size_t)nc * n;
         ws.it = si + n + 2 * (size_t)nc * n;
-        ws.flags = si + n + 3 * (size_t)nc * n;
+        ws.touched = si + n + 3 * (size_t)nc * n;
+        ws.flags = si + n + 4 * (size_t)nc * n;
         ws.nactive = ws.flags + 1;
         const double *Bj = B + (size_t)j0 * ng;
         double *Zj = Z + (size_t)j0 * ng;
@@ -877,12 +883,13 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
             HIPCHK(hipMemsetAsync(Zj + c * zstride, 0, (size_t)ng * n * 8, s));
             HIPCHK(hipMemcpyAsync(P + (size_t)c * ng * n, Bj, (size_t)ng * n * 8, hipMemcpyDeviceToDevice, s));
         }
-        HIPCHK(hipMemcpyAsync(r, Bj, (size_t)ng * n * 8, hipMemcpyDeviceToDevice, s));
+        const long long rs = (long long)ng * n;   // ring slot q holds r^k for k mod W = q
+        HIPCHK(hipMemcpyAsync(ring, Bj, (size_t)ng * n * 8, hipMemcpyDeviceToDevice, s));
         HIPCHK(launch_col_sqnorm(ng, n, Bj, ng, ws.rrn, s));
         HIPCHK(launch_fill_i32(ws.flags, 1, 0, s));
         HIPCHK(wide_init(n, nc, ws.rrn, ws, s));
         const double *pb = P + (size_t)base * ng * n;
-        int iter = 0;
+        int iter = 0, k0 = 0;
         for (; iter < ctx->opts.max_iter; ++iter) {
             // w = Q (H - s_base) p  (p in range(Q)); the projector GEMMs are timed
             if (col_shift_dev)
@@ -899,7 +906,12 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
             HIPCHK(hipEventRecord(ctx->ev[7], s));
             HIPCHK(launch_col_dot(ng, n, pb, ng, w, ng, pw, s));
             HIPCHK(launch_fill_i32(ws.nactive, 1, 0, s));
-            HIPCHK(wide_step(ng, n, nc, base, dp<double>(ctx->wd_sig), tol, iter, pw, w, r, P, Zj, zstride, ws, s));
+            HIPCHK(wide_step(ng, n, nc, base, dp<double>(ctx->wd_sig), tol, iter, k0, pw, w, ring + (iter % W) * rs,
+                             ring + ((iter + 1) % W) * rs, P, Zj, zstride, ws, s));
+            if (iter - k0 + 1 == W) {   // window full: the other shifts' deferred updates
+                HIPCHK(wide_flush(ng, n, nc, base, k0, W, ring, P, Zj, zstride, ws, s));
+                k0 = iter + 1;
+            }
             int live = 0;
             HIPCHK(hipMemcpyAsync(&live, ws.nactive, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -914,6 +926,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
                 break;
             }
         }
+        HIPCHK(wide_flush(ng, n, nc, base, k0, iter - k0, ring, P, Zj, zstride, ws, s));
         int fl = 0;
         HIPCHK(hipMemcpyAsync(it_h.data(), ws.it, (size_t)nc * n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&fl, ws.flags, 4, hipMemcpyDeviceToHost, s));

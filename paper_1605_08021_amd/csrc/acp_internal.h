@@ -205,22 +205,29 @@ hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s);
 // ---------------------------------------------------------------- multi-shift CG, many orbitals
 // Scalar state of the wide multi-shift CG (k_wide.hip): per column j (nb) and
 // per (shift c, column j) at c * nb + j.
+constexpr int kWideWindow = 8;   // iterations between the deferred updates of the other shifts
 struct WideScalars {
     double *rr, *rrn, *bn, *al, *alp, *btp;          // nb each
     double *z, *zp, *ac, *zn, *bc, *res;             // nc * nb each
+    double *coef;                                    // nc * nb * (2 + 2 kWideWindow): window coefficients
     int *colact;                                     // nb
-    int *act, *upd, *it;                             // nc * nb each
+    int *act, *upd, *it, *touched;                   // nc * nb each
     int *flags, *nactive;                            // 1 each
 };
 // rr = |b|^2 from bsq, every shift live for b != 0, zeta = 1.
 hipError_t wide_init(int nb, int nc, const double *bsq, const WideScalars &w, hipStream_t s);
-// One CG step after w = A p (p = P block `base`) and pw = p.w: alpha, r <- r - alpha w,
-// the shifted coefficients, x_c / p_c updates of every shift, the column state
-// (nactive += live columns).  P: nc blocks of N_g x nb (stride N_g nb); X: nc
-// blocks of N_g x nb with stride xs between the shifts' blocks.
-hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, const double *pw,
-                     const double *w_vec, double *r, double *P, double *X, long long xs, const WideScalars &w,
-                     hipStream_t s);
+// One CG step after w = A p (p = P block `base`) and pw = p.w, iteration `iter`
+// of the window started at k0: alpha, rn = r - alpha w (r = r^iter, rn = r^{iter+1},
+// ring slots), the shifted coefficients (advanced in the window), the base
+// shift's x and p, the column state (nactive += live columns).  P: nc blocks of
+// N_g x nb (stride N_g nb); X: nc blocks with stride xs.
+hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, int k0,
+                     const double *pw, const double *w_vec, const double *r, double *rn, double *P, double *X,
+                     long long xs, const WideScalars &w, hipStream_t s);
+// End of a window of wl steps started at k0: the other shifts' p_c and x_c from
+// the ring of residuals (slot q holds r^k for k mod kWideWindow = q, stride N_g nb).
+hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
+                      long long xs, const WideScalars &w, hipStream_t s);
 
 // ---------------------------------------------------------------- learned preconditioner
 // Network of four periodic convolutions (channels kNnChannels), BF16 operands on

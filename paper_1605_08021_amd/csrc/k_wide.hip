@@ -13,6 +13,16 @@
 // step coefficients of this iteration (ac = alpha^c_k, zn = zeta_{k+1},
 // bc = beta^c_k), upd (bit 0: x_c moves, bit 1: p_c moves), iterations and the
 // final recurrence residual.
+//
+// Deferred updates: the base shift's search direction p (the stencil's input)
+// and its solution move every iteration; every other shift's p_c and x_c move
+// once per window of kWideWindow iterations.  Within a window started at k0,
+//   p_c^k = B p_c^{k0} + sum_{s} gamma_s r^{k0+1+s},
+//   x_c^k = x_c^{k0} + A p_c^{k0} + sum_{s} chi_s r^{k0+1+s},
+// with the coefficients advanced by each step (A += a B, chi += a gamma, then
+// B *= b, gamma *= b, gamma_w = zeta_{k+1}); the residuals of the window stay
+// in a ring (r^k in slot k mod kWideWindow), and one sweep at the window's end
+// reads them once for all shifts.
 #include "acp_internal.h"
 
 namespace acp {
@@ -56,20 +66,22 @@ __global__ void wide_alpha_kernel(int nb, const double *rr, const double *pw, in
     al[j] = a;
 }
 
-// r(:, j) -= alpha_j w(:, j) and rrn_j = |r(:, j)|^2 (one block per column,
-// fixed reduction order).
+// rn(:, j) = r(:, j) - alpha_j w(:, j) and rrn_j = |rn(:, j)|^2 (one block per
+// column, fixed reduction order).
 __global__ __launch_bounds__(256) void wide_residual_kernel(int ng, const double *al, const int *colact,
-                                                            const double *w, double *r, double *rrn) {
+                                                            const double *w, const double *r, double *rn,
+                                                            double *rrn) {
     const int j = blockIdx.x;
     __shared__ double red[256];
     double acc = 0.0;
     if (colact[j]) {
         const double a = al[j];
         const double *wj = w + (long long)j * ng;
-        double *rj = r + (long long)j * ng;
+        const double *rj = r + (long long)j * ng;
+        double *rnj = rn + (long long)j * ng;
         for (int i = threadIdx.x; i < ng; i += 256) {
             const double v = rj[i] - a * wj[i];
-            rj[i] = v;
+            rnj[i] = v;
             acc += v * v;
         }
     }
@@ -90,13 +102,21 @@ __global__ __launch_bounds__(256) void wide_residual_kernel(int ng, const double
 // converges when |zeta_{k+1}| |r_{k+1}| <= tol |b|.  The base shift keeps
 // moving its search direction while any shift of the column runs.
 __global__ void wide_shift_scalars_kernel(int nb, int nc, int base, const double *sig, double tol, int iter,
-                                          const double *al, const double *alp, const double *btp, const double *rr,
-                                          const double *rrn, const double *bn, const int *colact, double *z,
-                                          double *zp, int *act, int *upd, double *ac, double *zn, double *bc,
-                                          int *it, double *res) {
+                                          int wpos, const double *al, const double *alp, const double *btp,
+                                          const double *rr, const double *rrn, const double *bn, const int *colact,
+                                          double *z, double *zp, int *act, int *upd, double *ac, double *zn,
+                                          double *bc, int *it, double *res, double *coef, int *touched) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nb * nc) return;
     const int c = idx / nb, j = idx % nb;
+    constexpr int W = kWideWindow;
+    double *co = coef + (size_t)idx * (2 + 2 * W);   // B, A, gamma[W], chi[W]
+    if (wpos == 0) {   // a new window: every shift starts from its stored p_c, x_c
+        touched[idx] = 0;
+        co[0] = 1.0;
+        co[1] = 0.0;
+        for (int q = 0; q < 2 * W; ++q) co[2 + q] = 0.0;
+    }
     if (!colact[j]) {
         upd[idx] = 0;
         act[idx] = 0;
@@ -127,10 +147,18 @@ __global__ void wide_shift_scalars_kernel(int nb, int nc, int base, const double
     const double den = a * bp * (zkm - zk) + zkm * ap * (1.0 + sig[c] * a);
     const double znew = den != 0.0 ? zk * zkm * ap / den : 0.0;
     const double ratio = zk != 0.0 ? znew / zk : 0.0;
+    const double a_c = a * ratio, b_c = beta * ratio * ratio;
     upd[idx] = 3;
-    ac[idx] = a * ratio;
+    ac[idx] = a_c;
     zn[idx] = znew;
-    bc[idx] = beta * ratio * ratio;
+    bc[idx] = b_c;
+    // window coefficients: x_c^{k+1} = x_c^k + a_c p_c^k, p_c^{k+1} = zeta_{k+1} r^{k+1} + b_c p_c^k
+    touched[idx] = 1;
+    co[1] += a_c * co[0];
+    for (int q = 0; q < wpos; ++q) co[2 + W + q] += a_c * co[2 + q];
+    co[0] *= b_c;
+    for (int q = 0; q < wpos; ++q) co[2 + q] *= b_c;
+    co[2 + wpos] = znew;
     zp[idx] = zk;
     z[idx] = znew;
     it[idx] = iter + 1;
@@ -141,21 +169,46 @@ __global__ void wide_shift_scalars_kernel(int nb, int nc, int base, const double
     }
 }
 
-// x_c += a^c_k p_c (with the old p_c), p_c = zeta_{k+1} r_{k+1} + b^c_k p_c.
-__global__ void wide_shift_update_kernel(int ng, int nb, int nc, const int *upd, const double *ac, const double *zn,
-                                         const double *bc, const double *r, double *P, double *X, long long xs) {
+// The base shift every iteration: x_b += a_k p (with the old p), p = r^{k+1} + b_k p.
+__global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd, const double *ac,
+                                        const double *bc, const double *rn, double *P, double *X) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= ng) return;
+    const int u = upd[base * nb + j];
+    if (!u) return;
+    const long long off = (long long)j * ng + i;
+    const double p = P[off];
+    if (u & 1) X[off] += ac[base * nb + j] * p;
+    if (u & 2) P[off] = rn[off] + bc[base * nb + j] * p;
+}
+
+// End of a window of wl steps started at k0: for every other shift touched in
+// it, x_c += A p_c + sum_s chi_s r^{k0+1+s}, p_c = B p_c + sum_s gamma_s r^{k0+1+s}.
+__global__ void wide_flush_kernel(int ng, int nb, int nc, int base, int k0, int wl, const double *ring,
+                                  long long rs, const double *coef, const int *touched, double *P, double *X,
+                                  long long xs) {
+    constexpr int W = kWideWindow;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= ng) return;
     const long long off = (long long)j * ng + i;
     const long long cs = (long long)nb * ng;
-    const double rv = r[off];
+    double rv[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) rv[q] = q < wl ? ring[((k0 + 1 + q) % W) * rs + off] : 0.0;
     for (int c = 0; c < nc; ++c) {
-        const int u = upd[c * nb + j];
-        if (!u) continue;
+        if (c == base || !touched[c * nb + j]) continue;
+        const double *co = coef + (size_t)(c * nb + j) * (2 + 2 * W);
         const double p = P[c * cs + off];
-        if (u & 1) X[c * xs + off] += ac[c * nb + j] * p;
-        if (u & 2) P[c * cs + off] = zn[c * nb + j] * rv + bc[c * nb + j] * p;
+        double xn = X[c * xs + off] + co[1] * p, pn = co[0] * p;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            xn += co[2 + W + q] * rv[q];
+            pn += co[2 + q] * rv[q];
+        }
+        X[c * xs + off] = xn;
+        P[c * cs + off] = pn;
     }
 }
 
@@ -183,22 +236,30 @@ hipError_t wide_init(int nb, int nc, const double *bsq, const WideScalars &w, hi
     return hipGetLastError();
 }
 
-hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, const double *pw,
-                     const double *w_vec, double *r, double *P, double *X, long long xs, const WideScalars &w,
-                     hipStream_t s) {
+hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, int k0,
+                     const double *pw, const double *w_vec, const double *r, double *rn, double *P, double *X,
+                     long long xs, const WideScalars &w, hipStream_t s) {
     hipLaunchKernelGGL(wide_alpha_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, (const double *)w.rr, pw,
                        w.colact, w.al, w.flags);
     hipLaunchKernelGGL(wide_residual_kernel, dim3(nb), dim3(256), 0, s, ng, (const double *)w.al,
-                       (const int *)w.colact, w_vec, r, w.rrn);
+                       (const int *)w.colact, w_vec, r, rn, w.rrn);
     hipLaunchKernelGGL(wide_shift_scalars_kernel, dim3((nb * nc + 255) / 256), dim3(256), 0, s, nb, nc, base, sig,
-                       tol, iter, (const double *)w.al, (const double *)w.alp, (const double *)w.btp,
+                       tol, iter, iter - k0, (const double *)w.al, (const double *)w.alp, (const double *)w.btp,
                        (const double *)w.rr, (const double *)w.rrn, (const double *)w.bn, (const int *)w.colact,
-                       w.z, w.zp, w.act, w.upd, w.ac, w.zn, w.bc, w.it, w.res);
-    hipLaunchKernelGGL(wide_shift_update_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, nc,
-                       (const int *)w.upd, (const double *)w.ac, (const double *)w.zn, (const double *)w.bc,
-                       (const double *)r, P, X, xs);
+                       w.z, w.zp, w.act, w.upd, w.ac, w.zn, w.bc, w.it, w.res, w.coef, w.touched);
+    hipLaunchKernelGGL(wide_base_update_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, base,
+                       (const int *)w.upd, (const double *)w.ac, (const double *)w.bc, (const double *)rn,
+                       P + (size_t)base * nb * ng, X + (size_t)base * xs);
     hipLaunchKernelGGL(wide_column_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, nc, (const int *)w.act,
                        w.colact, w.rr, (const double *)w.rrn, w.alp, (const double *)w.al, w.btp, w.nactive);
+    return hipGetLastError();
+}
+
+hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
+                      long long xs, const WideScalars &w, hipStream_t s) {
+    if (wl <= 0 || nc < 2) return hipSuccess;
+    hipLaunchKernelGGL(wide_flush_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, nc, base, k0, wl, ring,
+                       (long long)ng * nb, (const double *)w.coef, (const int *)w.touched, P, X, xs);
     return hipGetLastError();
 }
 
