@@ -40,8 +40,28 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
     C += bz * sc;
     if (EPI == 1) E += bz * se;
 
-    const int m0 = blockIdx.x * BM;
-    const int n0 = blockIdx.y * BN;
+    // XCD-aware tile order: workgroup b runs on XCD b mod 8, so each XCD takes a
+    // contiguous range of the tile sequence, in which the index over the
+    // dimension with fewer tiles runs fastest: consecutive tiles of one XCD share
+    // a panel of the other operand, which its L2 then serves to all of them.
+    int bm, bn;
+    {
+        const int mt = gridDim.x, nt = gridDim.y;
+        const int T = mt * nt;
+        const int lin = blockIdx.x + mt * blockIdx.y;
+        const int x = lin & 7, slot = lin >> 3;
+        const int q = T >> 3, rem = T & 7;
+        const int tile = x * q + (x < rem ? x : rem) + slot;
+        if (mt <= nt) {
+            bm = tile % mt;
+            bn = tile / mt;
+        } else {
+            bn = tile % nt;
+            bm = tile / nt;
+        }
+    }
+    const int m0 = bm * BM;
+    const int n0 = bn * BN;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
