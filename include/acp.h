@@ -217,6 +217,22 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
                       const double *K_local, const double *mass, double *D,
                       double *omega2);
 
+/* acp_dfpt -- the comparator ACP is measured against (density functional
+ * perturbation theory, Sec. 2.2): U = chi G for the columns of G by the
+ * Dyson equation u = chi0 g + chi0 v_c u, solved by fixed-point iteration
+ * with Anderson mixing over the last `history` differences (mixing weight
+ * beta; history 0 = plain damped fixed point), where every application of
+ * chi0 is Alg. 1: for each occupied orbital i the projected Sternheimer
+ * equation Q (H - eps_i) Q z = -Q (psi_i o v) at the occupied energy eps_i
+ * (N_e n_p systems per application, the context's per-system solver at
+ * opts.tol), chi0 v = (2 f / h^d) sum_i psi_i o z_i.
+ *   G dev N_g x n_p; U dev N_g x n_p (output, also usable by acp_dynmat);
+ *   stops when |F(U^k) - U^k|_F <= tol |F(U^k)|_F (F the right side) or after
+ *   max_iter applications (ACP_ENOCONV, U still written);
+ *   iters_out host: chi0 applications; change_out host: the last relative change. */
+acp_status acp_dfpt(acp_ctx *ctx, const double *G, int n_p, int max_iter, double tol, int history,
+                    double beta, double *U, int *iters_out, double *change_out);
+
 /* acp_residual -- R = B - Q (H - shift[j]) Q X column by column, in FP64.
  * shift host n; B, X, R dev N_g x n. */
 acp_status acp_residual(acp_ctx *ctx, const double *shift, int n, const double *B,

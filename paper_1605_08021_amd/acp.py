@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_dynmat": (I, [P, P, P, I, P, P, P, P]),
         "acp_residual": (I, [P, P, I, P, P, P]),
         "acp_residual_noalloc": (I, [P, P, I, P, P, P]),
+        "acp_dfpt": (I, [P, P, I, I, C.c_double, I, C.c_double, P, P, P]),
         "acp_precond_n_params": (I, [I]),
         "acp_precond_init": (I, [P, C.c_ulonglong]),
         "acp_precond_set": (I, [P, P, I]),
@@ -403,6 +404,16 @@ class Context:
         self._check(self.lib.acp_residual(self._ctx, _hptr(sh), B.shape[1], _dptr(B), _dptr(X),
                                           _dptr(R)))
         return R
+
+    def dfpt(self, G, max_iter=60, tol=1e-10, history=8, beta=0.5):
+        """acp_dfpt: (U = chi G on the device, chi0 applications, last relative change)."""
+        G = colmajor(G)
+        U = self._empty(*G.shape)
+        it = C.c_int(0)
+        ch = C.c_double(0.0)
+        self._check(self.lib.acp_dfpt(self._ctx, _dptr(G), G.shape[1], int(max_iter), float(tol), int(history),
+                                      float(beta), _dptr(U), C.byref(it), C.byref(ch)))
+        return U, it.value, ch.value
 
     def residual_noalloc(self, shifts, B, X, R=None):
         """acp_residual_noalloc into R (allocated here when None: the library

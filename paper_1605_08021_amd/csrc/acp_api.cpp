@@ -89,6 +89,7 @@ struct acp_ctx {
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     DevBuf wd_p, wd_r, wd_w, wd_c, wd_sc, wd_sig;   // multi-shift CG with GEMM projector (many orbitals)
+    DevBuf df_b, df_z, df_c, df_u, df_f, df_v, df_r, df_du, df_dr, df_pu, df_pr, df_dot;   // DFPT comparator
     acp_stats stats{};
     std::string err;
     hipEvent_t ev[8]{};
@@ -2051,6 +2052,72 @@ acp_status batch_finish(acp_batch *b, size_t i) {
     return ACP_OK;
 }
 
+// Q (H - shift[j]) Q X(:, j) = B(:, j), X = 0 at the start, for n columns in
+// FP64 with the context's per-system solver (fused 16-column tiles up to 256
+// orbitals: CG or MINRES; GEMM projector beyond: CG); the per-column shifts
+// go to ctx->shifts_dev; iterations per column into iters (host n).
+acp_status solve_columns_fp64(acp_ctx *ctx, const double *shift, int n, const double *B, double *X, double tol,
+                              int *iters, int *flags) {
+    const int ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    const int ntiles = (n + kTile - 1) / kTile;
+    const int npad = ntiles * kTile;
+    std::vector<double> sh(npad, shift[n - 1]);
+    for (int j = 0; j < n; ++j) sh[j] = shift[j];
+    ENSURE(ctx->shifts_dev, (size_t)npad * 8);
+    HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, sh.data(), (size_t)npad * 8, hipMemcpyHostToDevice, s));
+    if (wide_form(ctx)) {
+        if (ctx->opts.solver == ACP_SOLVER_MINRES)
+            return fail(ctx, ACP_EINVAL, "above 256 orbitals only the FP64 CG solvers are built");
+        CHECK(solve_multishift_wide(ctx, B, n, std::vector<double>{0.0}, tol, X, (long long)ng * n, flags, iters,
+                                    dp<double>(ctx->shifts_dev)));
+        HIPCHK(hipStreamSynchronize(s));   // sh is released on return
+        return ACP_OK;
+    }
+    ENSURE(ctx->krhs, (size_t)npad * ng * 8);
+    HIPCHK(launch_to_tiled(ng, n, npad, B, ng, dp<double>(ctx->krhs), s));
+    KrylovInputs<double> in{dp<double>(ctx->phi_rm), dp<double>(ctx->phi_cm), dp<double>(ctx->krhs)};
+    CHECK(solve_tiled<double>(ctx, ntiles, ntiles, dp<double>(ctx->shifts_dev), in, tol, flags));
+    HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), X, ng, s));
+    if (iters) HIPCHK(hipMemcpyAsync(iters, ctx->kiters.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ACP_OK;
+}
+
+// chi0 V for the n columns of V by Alg. 1: for every occupied orbital i and
+// column j, Q (H - eps_i) Q z = -Q (phi_i o v_j) (the positive-definite form of
+// the Sternheimer equation at eps_i), then chi0 v_j = (2 f / h^d) sum_i phi_i o z_ij.
+acp_status chi0_alg1(acp_ctx *ctx, int n, const double *V, double *Y, double tol, int *flags) {
+    const int ng = ctx->ng, ne = ctx->ne;
+    hipStream_t s = ctx->stream;
+    const double *phi = dp<double>(ctx->phi_cm);
+    // columns (i, j) in chunks of whole j (at most about 2^20 N_g doubles per block)
+    const int per = std::max(1, std::min(n, (int)std::max<long long>(1, (1LL << 27) / ((long long)ng * ne))));
+    const size_t ncol = (size_t)ne * per;
+    ENSURE(ctx->df_b, (size_t)ng * ncol * 8);
+    ENSURE(ctx->df_z, (size_t)ng * ncol * 8);
+    ENSURE(ctx->df_c, (size_t)ne * ncol * 8);
+    ENSURE(ctx->splitk, (size_t)kSplitSlices * ne * ncol * 8);
+    double *Bm = dp<double>(ctx->df_b), *Z = dp<double>(ctx->df_z), *C = dp<double>(ctx->df_c);
+    std::vector<double> sh(ncol);
+    std::vector<int> it(ncol);
+    const double pref = 2.0 * ctx->grid.occ / std::pow(ctx->grid.h, ctx->grid.dim);
+    for (int j0 = 0; j0 < n; j0 += per) {
+        const int m = std::min(per, n - j0);
+        const int nc = ne * m;
+        HIPCHK(launch_dfpt_products(ng, ne, m, phi, V + (size_t)j0 * ng, Bm, s));
+        HIPCHK(gemm_splitk(Op::T, Op::N, ne, nc, ng, 1.0, phi, ng, Bm, ng, 0.0, C, ne, dp<double>(ctx->splitk),
+                           (size_t)kSplitSlices * ne * nc, s));
+        HIPCHK(gemm(Op::N, Op::N, ng, nc, ne, 1.0, phi, ng, 0, C, ne, 0, -1.0, Bm, ng, 0, 1, s));   // -Q P
+        for (int q = 0; q < nc; ++q) sh[q] = ctx->eps[q % ne];
+        CHECK(solve_columns_fp64(ctx, sh.data(), nc, Bm, Z, tol, it.data(), flags));
+        for (int q = 0; q < nc; ++q) ctx->stats.system_iterations += it[q];
+        ctx->stats.systems_solved += nc;
+        HIPCHK(launch_dfpt_response(ng, ne, m, pref, phi, Z, Y + (size_t)j0 * ng, s));
+    }
+    return ACP_OK;
+}
+
 acp_status compress_impl(acp_ctx *ctx, const double *G, int n_p, const double *omega,
                          const int *sel_in, int *sel_out) {
     if (!G || !omega || n_p < 1) return fail(ctx, ACP_EINVAL, "G, omega, n_p");
@@ -2172,12 +2239,9 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
         ctx->stats.max_rel_residual = mr;
         return flags_status(ctx, flags);
     }
-    if (wide_form(ctx)) {
-        if (ctx->opts.precision != ACP_PREC_FP64 || ctx->opts.solver == ACP_SOLVER_MINRES)
-            return fail(ctx, ACP_EINVAL, "above 256 orbitals only the FP64 CG solvers are built");
+    if (ctx->opts.precision == ACP_PREC_FP64) {
         std::vector<int> it(n);
-        CHECK(solve_multishift_wide(ctx, B, n, std::vector<double>{0.0}, ctx->opts.tol, X, (long long)ng * n,
-                                    &flags, it.data(), dp<double>(ctx->shifts_dev)));
+        CHECK(solve_columns_fp64(ctx, shift, n, B, X, ctx->opts.tol, it.data(), &flags));
         HIPCHK(hipEventRecord(ctx->ev[3], s));
         HIPCHK(hipStreamSynchronize(s));
         if (iters) std::memcpy(iters, it.data(), (size_t)n * 4);
@@ -2188,7 +2252,8 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
         ctx->stats.max_rel_residual = mr;
         return flags_status(ctx, flags);
     }
-    if (ctx->opts.precision == ACP_PREC_FP32_REFINE) {
+    if (wide_form(ctx)) return fail(ctx, ACP_EINVAL, "above 256 orbitals only the FP64 CG solvers are built");
+    {
         CHECK(ensure_phi32(ctx));
         ENSURE(ctx->krhs32, (size_t)npad * ng * 4);
         HIPCHK(launch_to_f32((size_t)npad * ng, dp<double>(ctx->krhs), dp<float>(ctx->krhs32), s));
@@ -2200,12 +2265,6 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
         HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), X, ng, s));
         double mr = 0.0;
         CHECK(refine_fp32(ctx, n, dp<double>(ctx->shifts_dev), B, X, &flags, &mr));
-    } else {
-        KrylovInputs<double> in{dp<double>(ctx->phi_rm), dp<double>(ctx->phi_cm),
-                                dp<double>(ctx->krhs)};
-        CHECK(solve_tiled<double>(ctx, ntiles, ntiles, dp<double>(ctx->shifts_dev), in,
-                                  ctx->opts.tol, &flags));
-        HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), X, ng, s));
     }
     HIPCHK(hipEventRecord(ctx->ev[3], s));
     if (iters) HIPCHK(hipMemcpyAsync(iters, ctx->kiters.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
@@ -2666,6 +2725,130 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
     HIPCHK(hipStreamSynchronize(s));
     ctx->stats.ms_dynmat += event_ms(ctx->ev[0], ctx->ev[1]);
     ctx->stats.d_asymmetry = asym[1] > 0 ? std::sqrt(asym[0] / asym[1]) : 0.0;
+    return ACP_OK;
+}
+
+acp_status acp_dfpt(acp_ctx *ctx, const double *G, int n_p, int max_iter, double tol, int history, double beta,
+                    double *U, int *iters_out, double *change_out) {
+    if (!ctx || !G || !U || n_p < 1 || max_iter < 1 || !(tol > 0) || history < 0 || !(beta > 0)) return ACP_EINVAL;
+    const int ng = ctx->ng;
+    const long long N = (long long)ng * n_p;
+    if (N > 0x7fffffffLL) return fail(ctx, ACP_EINVAL, "N_g n_p too large for one response block");
+    hipStream_t s = ctx->stream;
+    const int m = std::max(0, std::min(history, 16));
+    ENSURE(ctx->df_u, (size_t)N * 8);
+    ENSURE(ctx->df_f, (size_t)N * 8);
+    ENSURE(ctx->df_v, (size_t)N * 8);
+    ENSURE(ctx->df_r, (size_t)N * 8);
+    ENSURE(ctx->df_pu, (size_t)N * 8);
+    ENSURE(ctx->df_pr, (size_t)N * 8);
+    ENSURE(ctx->df_du, (size_t)std::max(1, m) * N * 8);
+    ENSURE(ctx->df_dr, (size_t)std::max(1, m) * N * 8);
+    ENSURE(ctx->df_dot, (size_t)(m * m + m + 4) * 8);
+    double *Uk = dp<double>(ctx->df_u), *F = dp<double>(ctx->df_f), *Vt = dp<double>(ctx->df_v);
+    double *R = dp<double>(ctx->df_r), *Up = dp<double>(ctx->df_pu), *Rp = dp<double>(ctx->df_pr);
+    double *dU = dp<double>(ctx->df_du), *dR = dp<double>(ctx->df_dr), *dots = dp<double>(ctx->df_dot);
+    HIPCHK(hipEventRecord(ctx->ev[0], s));
+    HIPCHK(hipMemsetAsync(Uk, 0, (size_t)N * 8, s));
+    int flags = 0, nh = 0, head = 0, it = 0;
+    double change = INFINITY;
+    for (it = 1; it <= max_iter; ++it) {
+        // F = chi0 (G + v_c U^k): the right side of the Dyson equation
+        if (it == 1) {
+            HIPCHK(hipMemcpyAsync(Vt, G, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        } else {
+            CHECK(vc_apply(ctx, n_p, Uk, Vt));
+            HIPCHK(launch_axpby((int)N, 1, 1.0, G, (int)N, 1.0, Vt, (int)N, s));
+        }
+        CHECK(chi0_alg1(ctx, n_p, Vt, F, ctx->opts.tol, &flags));
+        // R = F - U^k; stop when |R| <= tol |F|
+        HIPCHK(hipMemcpyAsync(R, F, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(launch_axpby((int)N, 1, -1.0, Uk, (int)N, 1.0, R, (int)N, s));
+        HIPCHK(launch_col_sqnorm((int)N, 1, R, (int)N, dots, s));
+        HIPCHK(launch_col_sqnorm((int)N, 1, F, (int)N, dots + 1, s));
+        double hn[2];
+        HIPCHK(hipMemcpyAsync(hn, dots, 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        change = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : 0.0;
+        if (change <= tol) {
+            HIPCHK(hipMemcpyAsync(Uk, F, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+            break;
+        }
+        // Anderson mixing over the last m differences (Delta U, Delta R):
+        //   gamma = argmin |R - dR gamma|,  U^{k+1} = U^k + beta R - (dU + beta dR) gamma
+        if (m > 0 && it > 1) {
+            double *du = dU + (size_t)head * N, *dr = dR + (size_t)head * N;
+            HIPCHK(hipMemcpyAsync(du, Uk, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+            HIPCHK(launch_axpby((int)N, 1, -1.0, Up, (int)N, 1.0, du, (int)N, s));
+            HIPCHK(hipMemcpyAsync(dr, R, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+            HIPCHK(launch_axpby((int)N, 1, -1.0, Rp, (int)N, 1.0, dr, (int)N, s));
+            head = (head + 1) % m;
+            nh = std::min(nh + 1, m);
+        }
+        if (m > 0) {
+            HIPCHK(hipMemcpyAsync(Up, Uk, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(Rp, R, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        }
+        std::vector<double> gam(nh, 0.0);
+        if (nh > 0) {
+            for (int a = 0; a < nh; ++a) {
+                for (int b = 0; b <= a; ++b)
+                    HIPCHK(launch_col_dot((int)N, 1, dR + (size_t)a * N, (int)N, dR + (size_t)b * N, (int)N,
+                                          dots + a * nh + b, s));
+                HIPCHK(launch_col_dot((int)N, 1, dR + (size_t)a * N, (int)N, R, (int)N, dots + nh * nh + a, s));
+            }
+            std::vector<double> h((size_t)nh * nh + nh);
+            HIPCHK(hipMemcpyAsync(h.data(), dots, h.size() * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            // normal equations (A + 1e-12 tr(A)/nh I) gamma = rhs, Cholesky on the host (nh <= 16)
+            std::vector<double> A((size_t)nh * nh);
+            double tr = 0.0;
+            for (int a = 0; a < nh; ++a)
+                for (int b = 0; b <= a; ++b) A[a * nh + b] = A[b * nh + a] = h[a * nh + b];
+            for (int a = 0; a < nh; ++a) tr += A[a * nh + a];
+            for (int a = 0; a < nh; ++a) A[a * nh + a] += 1e-12 * tr / nh;
+            bool ok = true;
+            for (int a = 0; a < nh && ok; ++a) {
+                for (int b = 0; b < a; ++b) A[a * nh + a] -= A[a * nh + b] * A[a * nh + b];
+                if (!(A[a * nh + a] > 0)) ok = false;
+                else A[a * nh + a] = std::sqrt(A[a * nh + a]);
+                for (int c = a + 1; c < nh && ok; ++c) {
+                    for (int b = 0; b < a; ++b) A[c * nh + a] -= A[c * nh + b] * A[a * nh + b];
+                    A[c * nh + a] /= A[a * nh + a];
+                }
+            }
+            if (ok) {
+                for (int a = 0; a < nh; ++a) {
+                    double v = h[(size_t)nh * nh + a];
+                    for (int b = 0; b < a; ++b) v -= A[a * nh + b] * gam[b];
+                    gam[a] = v / A[a * nh + a];
+                }
+                for (int a = nh - 1; a >= 0; --a) {
+                    double v = gam[a];
+                    for (int b = a + 1; b < nh; ++b) v -= A[b * nh + a] * gam[b];
+                    gam[a] = v / A[a * nh + a];
+                }
+            } else {
+                std::fill(gam.begin(), gam.end(), 0.0);
+            }
+        }
+        HIPCHK(launch_axpby((int)N, 1, beta, R, (int)N, 1.0, Uk, (int)N, s));
+        for (int a = 0; a < nh; ++a) {
+            if (gam[a] == 0.0) continue;
+            HIPCHK(launch_axpby((int)N, 1, -gam[a], dU + (size_t)a * N, (int)N, 1.0, Uk, (int)N, s));
+            HIPCHK(launch_axpby((int)N, 1, -gam[a] * beta, dR + (size_t)a * N, (int)N, 1.0, Uk, (int)N, s));
+        }
+    }
+    const int done = std::min(it, max_iter);
+    HIPCHK(hipMemcpyAsync(U, Uk, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipEventRecord(ctx->ev[1], s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->stats.ms_solve += event_ms(ctx->ev[0], ctx->ev[1]);
+    ctx->stats.dyson_iters = done;
+    if (iters_out) *iters_out = done;
+    if (change_out) *change_out = change;
+    CHECK(flags_status(ctx, flags));
+    if (change > tol) return fail(ctx, ACP_ENOCONV, "the Dyson iteration did not reach tol");
     return ACP_OK;
 }
 

@@ -229,6 +229,12 @@ hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double
 hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
                       long long xs, const WideScalars &w, hipStream_t s);
 
+// ---------------------------------------------------------------- DFPT comparator (k_dfpt.hip)
+// P(:, i + ne j) = phi_i o V(:, j);  Y(:, j) = scale sum_i phi_i o Z(:, i + ne j).
+hipError_t launch_dfpt_products(int ng, int ne, int n, const double *phi, const double *V, double *P, hipStream_t s);
+hipError_t launch_dfpt_response(int ng, int ne, int n, double scale, const double *phi, const double *Z, double *Y,
+                                hipStream_t s);
+
 // ---------------------------------------------------------------- learned preconditioner
 // Network of four periodic convolutions (channels kNnChannels), BF16 operands on
 // the matrix cores, FP32 accumulation (k_nn.hip).
