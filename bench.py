@@ -139,7 +139,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=5)
-    ap.add_argument("--form", choices=["fast", "mixed", "learned", "single", "plain", "batch", "compress"],
+    ap.add_argument("--form", choices=["fast", "mixed", "learned", "single", "plain", "batch", "compress", "dfpt"],
                     default="fast")
     ap.add_argument("--batch-systems", type=int, default=16)
     ap.add_argument("--dyson-iters", type=int, default=0, help="k_max (0: 1 for workload 5, else 4)")
@@ -188,7 +188,8 @@ def main():
     phi, veff, G, om = T(inp.phi), T(inp.veff), T(inp.G), T(inp.omega)
     solver = {"fast": acp.SOLVER_CG, "mixed": acp.SOLVER_CG, "single": acp.SOLVER_CG_SINGLE,
               "plain": acp.SOLVER_MINRES, "learned": acp.SOLVER_CG_SINGLE,
-              "compress": acp.SOLVER_CG}[args.form]
+              "compress": acp.SOLVER_CG, "dfpt": acp.SOLVER_CG_SINGLE}[args.form]
+    dfpt = args.form == "dfpt"
     compress_only = args.form == "compress"
     learned = args.form == "learned"
     mixed = args.form == "mixed"
@@ -222,6 +223,10 @@ def main():
         if compress_only:
             ctx.compress(G, om)
             return 1, None
+        if dfpt:   # the comparator: Alg. 1 + Anderson-mixed Dyson to the same tolerance
+            U, iters, _ = ctx.dfpt(G, max_iter=200, tol=args.tol, history=8, beta=0.5)
+            D, w2 = ctx.dynmat(G, U, inp.K_local, masses)
+            return iters, w2
         U, iters, _ = ctx.dyson(G, om)
         D, w2 = ctx.dynmat(G, U, inp.K_local, masses)
         return iters, w2
@@ -305,12 +310,15 @@ def main():
         "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
                                f"ground state{' from the GPU eigensolver' if ng > 8000 else ''}, "
                                f"gap {inp.gap:.5f} Ha",
-                   "form": ("one compression per step (point selection, right-hand sides, "
+                   "form": ("DFPT (Alg. 1 Sternheimer solves at the occupied energies, FP64 CG per system; "
+                            "Dyson equation by Anderson mixing to the same tolerance) + dynamical matrix"
+                            if dfpt else
+                            "one compression per step (point selection, right-hand sides, "
                             "batched FP64 multi-shift CG, W); no Dyson update or dynamical matrix"
                             if compress_only else
                             "flexible CG with the learned BF16 conv preconditioner (FP64 vectors)"
                             if learned else
-                            "FP32-storage multi-shift CG + FP64 iterative refinement") if (mixed or learned or compress_only) else
+                            "FP32-storage multi-shift CG + FP64 iterative refinement") if (mixed or learned or compress_only or dfpt) else
                            {acp.SOLVER_CG: "batched FP64 multi-shift CG",
                             acp.SOLVER_CG_SINGLE: "batched FP64 CG, one sequence per system",
                             acp.SOLVER_MINRES: "plain FP64 MINRES"}[solver],

@@ -2770,6 +2770,7 @@ acp_status acp_dfpt(acp_ctx *ctx, const double *G, int n_p, int max_iter, double
         HIPCHK(hipMemcpyAsync(hn, dots, 16, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         change = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : 0.0;
+        if (std::getenv("ACP_DFPT_VERBOSE")) std::fprintf(stderr, "[dfpt] %d %.3e\n", it, change);
         if (change <= tol) {
             HIPCHK(hipMemcpyAsync(Uk, F, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
             break;
