@@ -345,6 +345,34 @@ acp_status acp_lowest_eigenpairs(const acp_grid *grid, const double *veff, const
                                  double *psi, double *lambda, double *lambda_next, int *passes,
                                  double *max_resid, void *stream);
 
+/* acp_scf -- the self-consistent ground state of the model (the density and
+ * effective potential of the paper's reduced Hartree-Fock model, Sec. 4.1 and
+ * 4.2: V_eff = v_c (rho + m), rho = (f / h^d) sum_{i <= n_e} psi_i^2), on the
+ * device: each iteration takes the n_e lowest eigenpairs of H[V_eff] by
+ * acp_lowest_eigenpairs's Chebyshev-filtered subspace iteration (warm-started
+ * from the previous iteration's subspace), then mixes the density by Anderson
+ * extrapolation over the last `history` pairs with a Kerker-preconditioned
+ * step (the paper uses Anderson mixing, Sec. 4.1).  v_c and the Kerker filter
+ * are diagonal in the real Fourier basis of the FD Laplacian and applied as
+ * dense products.
+ *   grid: dim, n, h, kappa, eps0, occ (f);  m dev N_g: the pseudocharge
+ *   density sum_I m_I (negative);  rho0 dev N_g or NULL (then -m scaled to
+ *   f n_e electrons);  psi dev N_g x n_e, eps host n_e + 1 (the last one the
+ *   next Ritz value), veff dev N_g, rho dev N_g (outputs);  iters, max_res host
+ *   or NULL.  Stops when max |rho_out - rho_in| <= tol max rho_out (ACP_ENOCONV
+ *   after max_iter, outputs still written).  Errors: acp_last_error(NULL). */
+typedef struct {
+    int max_iter;              /* SCF iterations (0: 200) */
+    double tol;                /* density residual bound (0: 1e-10) */
+    double beta;               /* mixing weight (0: 0.3) */
+    int history;               /* Anderson pairs kept (0: 12; negative: plain mixing) */
+    double kerker_q0;          /* Kerker q0 (0: 0.3; negative: no preconditioner) */
+    acp_eig_opts eig;          /* eigensolver per iteration (n_want is ignored) */
+} acp_scf_opts;
+acp_status acp_scf(const acp_grid *grid, const double *m, const double *rho0, int n_e,
+                   const acp_scf_opts *opts, double *psi, double *eps, double *veff, double *rho,
+                   int *iters, double *max_res, void *stream);
+
 /* acp_gesv -- X = A^{-1} B for a dense FP64 matrix (the small solve
  * (I - T) S = G(Pi, :) of each Dyson iteration, Eq. (3.13)): blocked LU with
  * partial pivoting up to n = 1024 (32-column panels factored in registers,

@@ -66,6 +66,11 @@ class AcpEigOpts(C.Structure):
                 ("tol", C.c_double), ("seed", C.c_ulonglong)]
 
 
+class AcpScfOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("beta", C.c_double), ("history", C.c_int),
+                ("kerker_q0", C.c_double), ("eig", AcpEigOpts)]
+
+
 class AcpBatchInfo(C.Structure):
     _fields_ = [("n_systems", C.c_int), ("n_tiles", C.c_int), ("grid", C.c_int), ("order", C.c_int),
                 ("tuned", C.c_int), ("graph_replays", C.c_longlong), ("ms_last", C.c_double),
@@ -121,6 +126,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_get_stats": (I, [P, C.POINTER(AcpStats)]),
         "acp_syev": (I, [I, P, I, P, P, I, P]),
         "acp_gesv": (I, [I, I, P, I, P, I, P]),
+        "acp_scf": (I, [C.POINTER(AcpGrid), P, P, I, C.POINTER(AcpScfOpts), P, P, P, P, P, P, P]),
         "acp_lowest_eigenpairs": (I, [C.POINTER(AcpGrid), P, C.POINTER(AcpEigOpts), P, P, P, P, P, P]),
         "acp_reset_stats": (None, [P]),
         "acp_last_error": (C.c_char_p, [P]),
@@ -236,6 +242,32 @@ def lowest_eigenpairs(grid: dict, veff, n_want: int, n_guard: int = 0, degree: i
     if st != ACP_OK:
         raise ACPError(st, lib.acp_last_error(None).decode())
     return psi, lam, nxt.value, passes.value, res.value
+
+
+def scf(grid: dict, m, n_e: int, rho0=None, max_iter: int = 0, tol: float = 0.0, beta: float = 0.0,
+        history: int = 0, kerker_q0: float = 0.0, eig_tol: float = 0.0, seed: int = 1, stream=None):
+    """acp_scf: (psi dev N_g x n_e, eps numpy n_e + 1, veff dev, rho dev, iterations, residual)."""
+    import torch
+    lib = load_library()
+    m = m.contiguous()
+    g = _grid_struct(grid)
+    o = AcpScfOpts(max_iter, tol, beta, history, kerker_q0, AcpEigOpts(n_e, 0, 0, 0, eig_tol, seed))
+    ng = m.shape[0]
+    psi = torch.empty((n_e, ng), dtype=torch.float64, device=m.device).t()
+    eps = np.zeros(n_e + 1)
+    veff = torch.empty(ng, dtype=torch.float64, device=m.device)
+    rho = torch.empty(ng, dtype=torch.float64, device=m.device)
+    it = C.c_int(0)
+    res = C.c_double(0.0)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    r0 = None if rho0 is None else rho0.contiguous()
+    st = lib.acp_scf(C.byref(g), _dptr(m), None if r0 is None else _dptr(r0), n_e, C.byref(o), _dptr(psi),
+                     _hptr(eps), _dptr(veff), _dptr(rho), C.byref(it), C.byref(res),
+                     C.c_void_p(stream.cuda_stream))
+    if st != ACP_OK:
+        raise ACPError(st, lib.acp_last_error(None).decode())
+    return psi, eps, veff, rho, it.value, res.value
 
 
 class Context:

@@ -29,7 +29,8 @@ def test_struct_layouts_match_header():
     import re
     text = re.sub(r"/\*.*?\*/", "", open(acp.HEADER).read(), flags=re.S)
     for cname, py in (("acp_opts", acp.AcpOpts), ("acp_stats", acp.AcpStats),
-                      ("acp_grid", acp.AcpGrid), ("acp_eig_opts", acp.AcpEigOpts)):
+                      ("acp_grid", acp.AcpGrid), ("acp_eig_opts", acp.AcpEigOpts),
+                      ("acp_scf_opts", acp.AcpScfOpts)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + r";", text).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         names = []
