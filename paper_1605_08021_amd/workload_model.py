@@ -252,6 +252,29 @@ def _atom_density(cfg: Config, z_ref: float) -> tuple:
     return r[order], rho[order]
 
 
+def _scf_gpu(cfg: Config, m: np.ndarray, rho0: np.ndarray, n_e: int, max_iter: int):
+    """The self-consistent ground state from the library's acp_scf, started from
+    rho0; returns (rho, V, eigenvalues n_e + 1, vectors N_g x n_e, converged)."""
+    import sys
+    import time
+    import torch
+    from paper_1605_08021_amd import acp
+    t0 = time.perf_counter()
+    grid = dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0, occ=cfg.f)
+    dev = torch.device("cuda:0")
+    try:
+        psi, eps, veff, rho, it, res = acp.scf(grid, torch.from_numpy(np.ascontiguousarray(m)).to(dev), n_e,
+                                               rho0=torch.from_numpy(np.ascontiguousarray(rho0)).to(dev),
+                                               max_iter=max_iter, tol=1e-8, eig_tol=1e-10, seed=cfg.cid)
+        conv = True
+    except acp.ACPError as e:
+        print(f"[inputs] SCF: {e}", file=sys.stderr, flush=True)
+        return None
+    print(f"[inputs] SCF on the GPU: {it} iterations, density residual {res:.1e}, "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return rho.cpu().numpy(), veff.cpu().numpy(), eps, psi.cpu().numpy(), conv
+
+
 def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
     import sys
     import time
@@ -277,11 +300,16 @@ def build_inputs(cfg: Config, scf_iters: int = 0) -> Inputs:
         T = grid.kinetic_dense()
         rho, V, w, v, sc = _scf(grid, T, m, rho, n_e, cfg.f, max(scf_iters, 0) + 1, 1e-8)
     else:
-        # large grids: the Harris potential only, its lowest eigenpairs by the
-        # library's Chebyshev-filtered subspace iteration on the GPU
-        V = grid.vc(rho + m)
-        w, v = _lowest_gpu(cfg, V, n_e)
-        sc = False
+        # large grids: the self-consistent ground state on the GPU when asked
+        # (scf_iters > 0) and reached, else the Harris potential and its lowest
+        # eigenpairs by the library's Chebyshev-filtered subspace iteration
+        out = _scf_gpu(cfg, m, rho, n_e, scf_iters) if scf_iters > 0 else None
+        if out is not None:
+            _, V, w, v, sc = out
+        else:
+            V = grid.vc(rho + m)
+            w, v = _lowest_gpu(cfg, V, n_e)
+            sc = False
     note("ground state")
     phi = np.ascontiguousarray(v[:, :n_e])
     rho_gs = (cfg.f / grid.dv) * (phi ** 2).sum(axis=1)
