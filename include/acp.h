@@ -105,6 +105,10 @@ typedef struct {
                                  finishing any system it leaves unconverged;
                                  2 = the same host-driven CG without the network (the
                                  comparison the network is measured against) */
+    int reorthonormalize;     /* acp_setup: 1 = orthonormalise Psi in FP64 on the device
+                                 (Loewdin: Psi (Psi^T Psi)^{-1/2}, the nearest orthonormal
+                                 set) when max |Psi^T Psi - I| exceeds 1e-10, e.g. orbitals
+                                 stored in reduced precision; 0 = reject them (ACP_EINVAL) */
 } acp_opts;
 
 typedef struct {
@@ -135,7 +139,8 @@ void acp_default_opts(acp_opts *opts);
 /* acp_setup -- prepare a context for the occupied space {phi_i, eps_i} of
  * H[V_eff] (Sec. 2.2: the Sternheimer form needs only occupied states).
  *   psi   dev, N_g x n_e column-major, l2-orthonormal (max |Psi^T Psi - I| must
- *         be <= 1e-10, else ACP_EINVAL); copied, not retained
+ *         be <= 1e-10, else ACP_EINVAL, unless opts.reorthonormalize); copied,
+ *         not retained
  *   eps   host, n_e occupied eigenvalues, ascending (else ACP_EINVAL); the shift
  *         interval is [eps[0], eps[n_e-1]] (Sec. 3.1)
  *   veff  dev, N_g effective potential; copied

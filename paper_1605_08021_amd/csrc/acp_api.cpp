@@ -1503,17 +1503,40 @@ acp_status setup_impl(acp_ctx *ctx, const acp_grid *grid, const acp_opts *opts, 
     ENSURE(ctx->veff, (size_t)ng * 8);
     HIPCHK(hipMemsetAsync(ctx->phi_cm.p, 0, (size_t)ng * nep * 8, s));
     HIPCHK(hipMemcpyAsync(ctx->phi_cm.p, psi, (size_t)ng * n_e * 8, hipMemcpyDeviceToDevice, s));
-    HIPCHK(launch_transpose(ng, nep, dp<double>(ctx->phi_cm), ng, dp<double>(ctx->phi_rm), nep, s));
     HIPCHK(hipMemcpyAsync(ctx->veff.p, veff, (size_t)ng * 8, hipMemcpyDeviceToDevice, s));
     // orthonormality: max |Psi^T Psi - I| <= 1e-10
     ENSURE(ctx->c1, (size_t)n_e * n_e * 8);
     ENSURE(ctx->dy_norm, 16);
-    HIPCHK(gemm(Op::T, Op::N, n_e, n_e, ng, 1.0, dp<double>(ctx->phi_cm), ng, 0,
-                dp<double>(ctx->phi_cm), ng, 0, 0.0, dp<double>(ctx->c1), n_e, 0, 1, s));
-    HIPCHK(launch_gram_check(n_e, 0, dp<double>(ctx->c1), dp<double>(ctx->dy_norm), s));
     double dev = 0.0;
-    HIPCHK(hipMemcpyAsync(&dev, ctx->dy_norm.p, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    auto gram_dev = [&]() -> acp_status {
+        HIPCHK(gemm_splitk(Op::T, Op::N, n_e, n_e, ng, 1.0, dp<double>(ctx->phi_cm), ng, dp<double>(ctx->phi_cm), ng,
+                           0.0, dp<double>(ctx->c1), n_e, dp<double>(ctx->splitk), ctx->splitk.bytes / 8, s));
+        HIPCHK(launch_gram_check(n_e, 0, dp<double>(ctx->c1), dp<double>(ctx->dy_norm), s));
+        HIPCHK(hipMemcpyAsync(&dev, ctx->dy_norm.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return ACP_OK;
+    };
+    ENSURE(ctx->splitk, (size_t)kSplitSlices * n_e * n_e * 8);
+    CHECK(gram_dev());
+    if (!(dev <= 1e-10) && opts->reorthonormalize) {
+        // Loewdin in FP64: S = Psi^T Psi = V D V^T, Psi <- Psi V D^{-1/2} V^T
+        ENSURE(ctx->dm_work, sym_eig_work_doubles(n_e, true) * 8);
+        ENSURE(ctx->dm_d, (size_t)n_e * n_e * 8);
+        ENSURE(ctx->dm_eig, (size_t)n_e * 8);
+        ENSURE(ctx->tmp2, (size_t)2 * n_e * n_e * 8);
+        ENSURE(ctx->tmp1, (size_t)ng * n_e * 8);
+        double *V = dp<double>(ctx->dm_d), *VS = dp<double>(ctx->tmp2), *T = VS + (size_t)n_e * n_e;
+        HIPCHK(sym_eig_jacobi(n_e, dp<double>(ctx->c1), n_e, dp<double>(ctx->dm_eig), V, n_e,
+                              dp<double>(ctx->dm_work), 30, 1e-15, s, nullptr));
+        HIPCHK(launch_scale_copy(n_e, n_e, 1.0, V, n_e, VS, n_e, s));
+        HIPCHK(launch_col_scale_rsqrt(n_e, n_e, VS, n_e, dp<double>(ctx->dm_eig), s));
+        HIPCHK(gemm(Op::N, Op::T, n_e, n_e, n_e, 1.0, VS, n_e, 0, V, n_e, 0, 0.0, T, n_e, 0, 1, s));
+        HIPCHK(gemm(Op::N, Op::N, ng, n_e, n_e, 1.0, dp<double>(ctx->phi_cm), ng, 0, T, n_e, 0, 0.0,
+                    dp<double>(ctx->tmp1), ng, 0, 1, s));
+        HIPCHK(hipMemcpyAsync(ctx->phi_cm.p, ctx->tmp1.p, (size_t)ng * n_e * 8, hipMemcpyDeviceToDevice, s));
+        CHECK(gram_dev());
+    }
+    HIPCHK(launch_transpose(ng, nep, dp<double>(ctx->phi_cm), ng, dp<double>(ctx->phi_rm), nep, s));
     if (!(dev <= 1e-10)) {
         char buf[128];
         std::snprintf(buf, sizeof buf, "psi is not orthonormal: max |Psi^T Psi - I| = %.3e", dev);

@@ -332,6 +332,8 @@ hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hip
 // |A_pq| > tol sqrt(|A_pp A_qq|) or after max_sweeps (the sweeps performed go to
 // *sweeps_out).  Synchronises the stream once per sweep.
 size_t sym_eig_work_doubles(int n, bool vectors);
+// W(:, j) /= sqrt(d[j]) (d floored at 1e-300), m x n, d on the device.
+hipError_t launch_col_scale_rsqrt(int m, int n, double *W, int ldw, const double *d, hipStream_t s);
 hipError_t sym_eig_jacobi(int n, double *A, int lda, double *eig, double *V, int ldv, double *work,
                           int max_sweeps, double tol, hipStream_t s, int *sweeps_out);
 hipError_t launch_dynmat_assemble(int np, int dim, const double *Phi_el, const double *K_local,

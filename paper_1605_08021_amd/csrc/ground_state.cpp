@@ -615,6 +615,12 @@ acp_status scf(const acp_grid *grid, const double *m, const double *rho0, int n_
     return ACP_OK;
 }
 
+hipError_t launch_col_scale_rsqrt(int m, int n, double *W, int ldw, const double *d, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_cols_rsqrt_kernel, dim3((m + 255) / 256, n), dim3(256), 0, s, m, n, W, ldw, d);
+    return hipGetLastError();
+}
+
 }  // namespace acp
 
 extern "C" acp_status acp_lowest_eigenpairs(const acp_grid *grid, const double *veff, const acp_eig_opts *opts,

@@ -171,3 +171,32 @@ def test_failure_paths():
         ctx.sternheimer(np.full(R.shape[1], gs.eps[gs.n_e] + 1.0), to_dev(R))
     assert e.value.status == acp.ACP_ENOTSPD
     ctx.close()
+
+
+def test_reorthonormalised_orbitals():
+    """Orbitals stored in single precision (FP32-rounded): acp_setup rejects
+    them, or with reorthonormalize = 1 orthonormalises them in FP64
+    (Loewdin, Psi (Psi^T Psi)^{-1/2}); the compression then equals the oracle's
+    on the same Loewdin-orthonormalised orbitals."""
+    from paper_1605_08021_amd import acp
+    cfg, m, gs, w, v, G, om, K = system(11)
+    psi32 = gs.phi.astype(np.float32).astype(np.float64)
+    grid = dict(dim=1, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0, occ=cfg.f)
+    opts = dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=1e-12, max_iter=5000)
+    with pytest.raises(acp.ACPError) as e:
+        acp.Context(grid, opts, to_dev(psi32), gs.eps[:gs.n_e], to_dev(gs.veff))
+    assert e.value.status == acp.ACP_EINVAL
+    ctx = acp.Context(grid, dict(opts, reorthonormalize=1), to_dev(psi32), gs.eps[:gs.n_e], to_dev(gs.veff))
+    # the oracle's Loewdin orthonormalisation of the same orbitals
+    S = psi32.T @ psi32
+    d, V = np.linalg.eigh(S)
+    phi_l = psi32 @ (V / np.sqrt(d)) @ V.T
+    dec = OA.isdf_qrcp(phi_l, G, om, cfg.n_mu)
+    ref = OA.compress(phi_l, gs.eps[:gs.n_e], G, om, cfg.n_cheb, cfg.n_mu,
+                      OA.ProjectedSpectralSolver(m.hamiltonian_dense(gs.veff), phi_l), m.f, m.grid.dv,
+                      sel=dec.sel)
+    ctx.compress(to_dev(G), to_dev(om), sel_in=dec.sel)
+    eW = _rel(to_host(ctx.compress_get("w")), ref.W)
+    print(f"Loewdin: |Psi32^T Psi32 - I| = {np.abs(S - np.eye(gs.n_e)).max():.1e}, W rel err {eW:.1e}")
+    assert eW < 1e-8
+    ctx.close()
