@@ -14,9 +14,15 @@ driver's 25 steps fit its time limit; --dyson-iters sets more).
 Input preparation (ground state by the library's GPU eigensolver, perturbations,
 local Hessian terms) is done once, untimed, by paper_1605_08021_amd.workload_model.
 
+Default form (more than 256 orbitals): the projector GEMMs in BF16 with FP32
+accumulation on the deflated operator, FP64 vectors, every solution projected
+and its residual recomputed in FP64; one step of the batched FP64 multi-shift
+form is timed beside it and the difference of the two dynamical matrices
+reported (--no-fp64-compare skips it).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--form fast|mixed|learned|single|plain|batch]
-                       [--no-cpu-baseline] [--calibrate-copy]
+                       [--form auto|fast|bf16|mixed|learned|single|plain|batch|compress|dfpt]
+                       [--no-cpu-baseline] [--no-fp64-compare] [--calibrate-copy]
 
 --form batch: the uneven batch instead (a ragged set of 1D chains whose shifted
 solves share one persistent launch, replayed from a hipGraph); one step = one
@@ -37,6 +43,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector and matrix), vendor figure
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix, vendor figure
 
 
 def log(msg):
@@ -139,8 +146,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=5)
-    ap.add_argument("--form", choices=["fast", "mixed", "learned", "single", "plain", "batch", "compress", "dfpt"],
-                    default="fast")
+    ap.add_argument("--form", choices=["auto", "fast", "bf16", "mixed", "learned", "single", "plain", "batch",
+                                       "compress", "dfpt"],
+                    default="auto", help="auto: bf16 above 256 orbitals, else fast")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="bf16 form: skip the FP64-form step timed beside it")
     ap.add_argument("--batch-systems", type=int, default=16)
     ap.add_argument("--dyson-iters", type=int, default=0, help="k_max (0: 1 for workload 5, else 4)")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -178,6 +188,8 @@ def main():
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s; gap {inp.gap:.5f}, "
         f"self-consistent {inp.self_consistent}")
     dev = torch.device("cuda:0")
+    if args.form == "auto":
+        args.form = "bf16" if inp.n_e > 256 else "fast"
 
     def T(a):
         a = np.asarray(a, dtype=np.float64)
@@ -186,16 +198,19 @@ def main():
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
     phi, veff, G, om = T(inp.phi), T(inp.veff), T(inp.G), T(inp.omega)
-    solver = {"fast": acp.SOLVER_CG, "mixed": acp.SOLVER_CG, "single": acp.SOLVER_CG_SINGLE,
+    solver = {"fast": acp.SOLVER_CG, "bf16": acp.SOLVER_CG, "mixed": acp.SOLVER_CG,
+              "single": acp.SOLVER_CG_SINGLE,
               "plain": acp.SOLVER_MINRES, "learned": acp.SOLVER_CG_SINGLE,
               "compress": acp.SOLVER_CG, "dfpt": acp.SOLVER_CG_SINGLE}[args.form]
     dfpt = args.form == "dfpt"
     compress_only = args.form == "compress"
     learned = args.form == "learned"
     mixed = args.form == "mixed"
+    bf16 = args.form == "bf16"
     opts = dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol, max_iter=20000,
                 solver=solver, dyson_max_iter=args.dyson_iters,
-                precision=acp.PREC_FP32_REFINE if mixed else acp.PREC_FP64, inner_tol=1e-5)
+                precision=(acp.PREC_FP32_REFINE if mixed else acp.PREC_BF16_PROJ if bf16 else acp.PREC_FP64),
+                inner_tol=1e-5)
     ctx = acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0,
                            occ=cfg.f), opts, phi, inp.eps[: inp.n_e], veff)
     masses = np.ones(inp.R.shape[0])
@@ -222,14 +237,14 @@ def main():
     def step():
         if compress_only:
             ctx.compress(G, om)
-            return 1, None
+            return 1, None, None
         if dfpt:   # the comparator: Alg. 1 + Anderson-mixed Dyson to the same tolerance
             U, iters, _ = ctx.dfpt(G, max_iter=200, tol=args.tol, history=8, beta=0.5)
             D, w2 = ctx.dynmat(G, U, inp.K_local, masses)
-            return iters, w2
+            return iters, w2, D
         U, iters, _ = ctx.dyson(G, om)
         D, w2 = ctx.dynmat(G, U, inp.K_local, masses)
-        return iters, w2
+        return iters, w2, D
 
     for i in range(args.warmup):
         log(f"warmup step {i + 1}/{args.warmup}")
@@ -238,11 +253,30 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        iters, w2 = step()
+        iters, w2, D = step()
         log(f"step {i + 1}/{args.steps} done ({iters} compressions)")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = ctx.stats()
+    fp64_form = None
+    if bf16 and not args.no_fp64_compare:
+        # the fastest FP64 form (batched FP64 multi-shift CG) on the same inputs:
+        # one untimed and one timed step, and the difference of its dynamical matrix
+        # and frequencies from the BF16 form's last step
+        ctx.set_opts(precision=acp.PREC_FP64)
+        log("FP64 form beside it: one untimed step")
+        step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, w2_64, D64 = step()
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t1)
+        log(f"FP64 form step: {ms64:.1f} ms")
+        fp64_form = {"form": "batched FP64 multi-shift CG, same workload and tolerance",
+                     "ms_per_step": round(ms64, 2),
+                     "speedup_of_bf16_form": round(ms64 / (1e3 * elapsed / args.steps), 3),
+                     "rel_diff_D": float(np.linalg.norm(D - D64) / np.linalg.norm(D64)),
+                     "max_rel_diff_omega2": float(np.abs(w2 - w2_64).max() / np.abs(w2_64).max())}
     systems = st["systems_solved"]
     value = systems / elapsed
     ms_step = 1e3 * elapsed / args.steps
@@ -281,6 +315,23 @@ def main():
         # iteration; achieved = 4 N_g N_e flops per live column and iteration
         gemm_launches = 2 * launches
         tflops = st["krylov_flops"] / (st["ms_solve_kernel"] * 1e-3) / 1e12
+        if bf16:
+            # the same pair in BF16 (gemm_bf16_tn_kernel<2,2,0>: Phi^T p with both
+            # operands in two terms, <3,1,1>: w += Phi (T - Lambda) C with Phi in
+            # three), timed together with the small kernel between them; achieved =
+            # the same algorithmic 4 N_g N_e flops per column and iteration, against
+            # the dense BF16 peak (the split terms execute 3x as many)
+            roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": BF16_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
+                        "traffic": None,
+                        "kernel": "gemm_bf16_tn_kernel<2,2,0> + <3,1,1> (projector GEMMs of the many-orbital "
+                                  "multi-shift CG, v_mfma_f32_16x16x32_bf16, FP32 accumulation)",
+                        "algorithmic_flops_per_launch": st["krylov_flops"] / gemm_launches,
+                        "executed_mfma_tflops": round(3.0 * tflops, 2),
+                        "algorithmic_bytes_per_launch": st["krylov_bytes"] / gemm_launches,
+                        "ms_per_launch": round(st["ms_solve_kernel"] / gemm_launches, 3),
+                        "iterations": launches}
+    if wide and not bf16:
         roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
                     "traffic": measured_traffic(f"config {args.config}", GEMM_TRAFFIC_FILE,
@@ -305,7 +356,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f64",
+        "dtype": "f32+f64" if mixed else "bf16+f64" if bf16 else "f64",
         "data": "synthetic",
         "config": {"workload": f"config {args.config}: {cfg.name}; Harris (non-self-consistent) "
                                f"ground state{' from the GPU eigensolver' if ng > 8000 else ''}, "
@@ -318,7 +369,11 @@ def main():
                             if compress_only else
                             "flexible CG with the learned BF16 conv preconditioner (FP64 vectors)"
                             if learned else
-                            "FP32-storage multi-shift CG + FP64 iterative refinement") if (mixed or learned or compress_only or dfpt) else
+                            "batched multi-shift CG with the projector GEMMs in BF16 (FP32 accumulation) on the "
+                            "deflated operator, FP64 stencil and vectors; every solution projected and its "
+                            "residual recomputed in FP64"
+                            if bf16 else
+                            "FP32-storage multi-shift CG + FP64 iterative refinement") if (mixed or learned or compress_only or dfpt or bf16) else
                            {acp.SOLVER_CG: "batched FP64 multi-shift CG",
                             acp.SOLVER_CG_SINGLE: "batched FP64 CG, one sequence per system",
                             acp.SOLVER_MINRES: "plain FP64 MINRES"}[solver],
@@ -334,6 +389,17 @@ def main():
                                "ms_dynmat")},
         "roofline": roofline,
     }
+    if wide:
+        # the Krylov vector kernels of the many-orbital solver (stencil, p.w, residual,
+        # base update, deferred shifted updates): algorithmic bytes over their time
+        # (each iteration's events minus the projector pair)
+        if st["ms_vectors"] > 0:
+            gbs = st["vector_bytes"] / (st["ms_vectors"] * 1e-3) / 1e9
+            out["roofline_vector_kernels"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                              "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                              "bytes_per_step": st["vector_bytes"] / args.steps,
+                                              "ms_per_step": round(st["ms_vectors"] / args.steps, 2)}
+        out["fp64_form"] = fp64_form
     ctx.close()
     # release every device object before the interpreter's teardown (a profiler
     # preloaded into the process has finalised by then)

@@ -54,13 +54,26 @@ typedef enum {
 
 typedef enum {
     ACP_PREC_FP64 = 0,         /* every Krylov step in FP64 */
-    ACP_PREC_FP32_REFINE = 1   /* FP32 inner solves, FP64 residual refinement: Phi, the
+    ACP_PREC_FP32_REFINE = 1,  /* FP32 inner solves, FP64 residual refinement: Phi, the
                                   right-hand sides and the Krylov vectors are stored in FP32
                                   (arithmetic in FP64, solutions accumulated in FP64); the
                                   first solve (multi-shift with ACP_SOLVER_CG) runs to
                                   inner_tol, then r = b - A x is recomputed in FP64 and FP32
                                   per-system corrections run until every system meets tol
                                   (at most 8 corrections, else ACP_ENOCONV).  CG only. */
+    ACP_PREC_BF16_PROJ = 2     /* more than 256 orbitals only (the GEMM-projector form; else
+                                  ACP_EINVAL at acp_compress): the orbital products of every
+                                  CG step run as BF16 GEMMs on the matrix cores with FP32
+                                  accumulation, Phi^T p with both operands split into two
+                                  BF16 terms and Phi (T - Lambda) C with Phi split into three,
+                                  on the deflated operator H + Phi (T - Lambda) Phi^T - s
+                                  (T = eps_N + 1 Ha), which equals Q (H - s) Q on range(Q):
+                                  the rounding of those products only moves occupied
+                                  components, which this operator damps like any other.  The
+                                  stencil, the Krylov vectors and the solutions stay FP64; the
+                                  solutions are projected onto range(Q) in FP64 and every
+                                  system's residual is recomputed in FP64 (max_rel_residual).
+                                  CG solvers only. */
 } acp_precision;
 
 typedef enum {
@@ -128,6 +141,11 @@ typedef struct {
     int krylov_group;            /* workgroups per 16-system tile in the last multi-shift solve */
     int n_mu;                    /* rank N_mu of the last compression (below opts.n_mu when the
                                     rank rule of isdf_tol stopped the point selection early) */
+    double vector_bytes;         /* more than 256 orbitals: algorithmic HBM bytes of the Krylov
+                                    vector kernels (stencil, p.w, residual, base update, deferred
+                                    shifted updates) for the live columns (accumulated) */
+    double ms_vectors;           /* their time: each iteration's stretch (HIP events) minus the
+                                    projector pair (accumulated) */
 } acp_stats;
 
 typedef struct acp_ctx acp_ctx;

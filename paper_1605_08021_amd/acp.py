@@ -25,7 +25,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "acp.h")
 ACP_OK, ACP_EINVAL, ACP_ENOMEM, ACP_EDEVICE, ACP_ENOCONV, ACP_ENOTSPD, ACP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "ACP_OK", -1: "ACP_EINVAL", -2: "ACP_ENOMEM", -3: "ACP_EDEVICE",
                 -4: "ACP_ENOCONV", -5: "ACP_ENOTSPD", -6: "ACP_ESTATE"}
-PREC_FP64, PREC_FP32_REFINE = 0, 1
+PREC_FP64, PREC_FP32_REFINE, PREC_BF16_PROJ = 0, 1, 2
 SOLVER_CG, SOLVER_MINRES, SOLVER_CG_SINGLE = 0, 1, 2
 NODES_CHEBYSHEV, NODES_OCCUPIED = 0, 1
 
@@ -58,7 +58,8 @@ class AcpStats(C.Structure):
                 ("ms_dynmat", C.c_double), ("ms_solve_kernel", C.c_double),
                 ("solve_kernel_launches", C.c_int64), ("d_asymmetry", C.c_double),
                 ("krylov_bytes", C.c_double), ("krylov_flops", C.c_double),
-                ("krylov_group", C.c_int), ("n_mu", C.c_int)]
+                ("krylov_group", C.c_int), ("n_mu", C.c_int), ("vector_bytes", C.c_double),
+                ("ms_vectors", C.c_double)]
 
 
 class AcpEigOpts(C.Structure):

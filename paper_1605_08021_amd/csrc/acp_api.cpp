@@ -89,10 +89,16 @@ struct acp_ctx {
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     DevBuf wd_p, wd_r, wd_w, wd_c, wd_sc, wd_sig;   // multi-shift CG with GEMM projector (many orbitals)
+    // its BF16 projector: Phi split in 2 terms (orbital rows, K = grid) and in 3
+    // terms (grid rows, K = orbitals), the base p in 2 terms, split-K partials of
+    // Phi^T p, the deflation coefficients, the occupied energies
+    DevBuf bf_phi_cm[2], bf_phi_rm[3], bf_p[2], bf_part, bf_c, eps_dev;
+    bool bf_ready = false;
     DevBuf df_b, df_z, df_c, df_u, df_f, df_v, df_r, df_du, df_dr, df_pu, df_pr, df_dot;   // DFPT comparator
     acp_stats stats{};
     std::string err;
-    hipEvent_t ev[8]{};
+    // 0-7: phases and the projector pair; 8-9: one iteration of the many-orbital solver
+    hipEvent_t ev[10]{};
 };
 
 // A ragged batch of systems (contexts) whose shifted solves share one
@@ -200,8 +206,11 @@ acp_status validate_opts(acp_ctx *ctx, const acp_opts *o) {
     if (o->solver != ACP_SOLVER_CG && o->solver != ACP_SOLVER_MINRES &&
         o->solver != ACP_SOLVER_CG_SINGLE)
         return fail(ctx, ACP_EINVAL, "unknown solver");
-    if (o->precision != ACP_PREC_FP64 && o->precision != ACP_PREC_FP32_REFINE)
+    if (o->precision != ACP_PREC_FP64 && o->precision != ACP_PREC_FP32_REFINE &&
+        o->precision != ACP_PREC_BF16_PROJ)
         return fail(ctx, ACP_EINVAL, "unknown precision");
+    if (o->precision == ACP_PREC_BF16_PROJ && o->solver == ACP_SOLVER_MINRES)
+        return fail(ctx, ACP_EINVAL, "the BF16 projector form uses CG");
     if (o->precision == ACP_PREC_FP32_REFINE && o->solver == ACP_SOLVER_MINRES)
         return fail(ctx, ACP_EINVAL, "the mixed-precision form uses CG (MINRES runs in FP64)");
     if (o->precision == ACP_PREC_FP32_REFINE && !(o->inner_tol > 0.0 && o->inner_tol < 1.0))
@@ -822,18 +831,53 @@ constexpr double kWideBudgetBytes = 128.0 * 1024 * 1024 * 1024;
 // c zstride (N_g x nb, leading dimension N_g).  iters (host nc x nb, [c][j]) or
 // null.  With col_shift_dev (device, nb) and one shift, column j is solved at
 // its own shift col_shift_dev[j] instead (plain CG per system).
+// BF16 operands of the reduced-precision projector, once per context: Phi in
+// two terms with orbital rows (K = grid, leading dimension N_g rounded up to 8)
+// and in three terms with grid rows (K = orbitals, rounded up to 8), and the
+// occupied energies on the device.
+inline long long round8(long long x) { return (x + 7) / 8 * 8; }
+// Deflation level of the BF16 form: the occupied block of H + Phi (T - Lambda)
+// Phi^T - s has eigenvalue T - s, above 1 Ha for every shift in [eps_1, eps_N].
+double bf16_deflation_level(const acp_ctx *ctx) { return ctx->eps[ctx->ne - 1] + 1.0; }
+
+acp_status prepare_bf16(acp_ctx *ctx) {
+    if (ctx->bf_ready) return ACP_OK;
+    const int ng = ctx->ng, ne = ctx->ne;
+    const long long ngk = round8(ng), nek = round8(ne);
+    hipStream_t s = ctx->stream;
+    unsigned short *cm[2], *rm[3];
+    for (int t = 0; t < 2; ++t) {
+        ENSURE(ctx->bf_phi_cm[t], (size_t)ngk * ne * 2);
+        cm[t] = dp<unsigned short>(ctx->bf_phi_cm[t]);
+    }
+    for (int t = 0; t < 3; ++t) {
+        ENSURE(ctx->bf_phi_rm[t], (size_t)ng * nek * 2);
+        rm[t] = dp<unsigned short>(ctx->bf_phi_rm[t]);
+    }
+    HIPCHK(launch_split_bf16(ng, ne, dp<double>(ctx->phi_cm), ng, 2, cm, ngk, s));
+    HIPCHK(launch_split_bf16_transpose(ng, ne, dp<double>(ctx->phi_cm), ng, 3, rm, nek, s));
+    ENSURE(ctx->eps_dev, (size_t)ne * 8);
+    HIPCHK(hipMemcpyAsync(ctx->eps_dev.p, ctx->eps.data(), (size_t)ne * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->bf_ready = true;
+    return ACP_OK;
+}
+
 acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const std::vector<double> &shifts,
                                  double tol, double *Z, long long zstride, int *flags_or, int *iters,
-                                 const double *col_shift_dev = nullptr) {
+                                 const double *col_shift_dev = nullptr, bool bf16 = false) {
     const int ng = ctx->ng, ne = ctx->ne, nc = (int)shifts.size();
     hipStream_t s = ctx->stream;
+    const long long ngk = round8(ng), nek = round8(ne), ldp = (ne + 3) / 4 * 4;
+    if (bf16) CHECK(prepare_bf16(ctx));
     const int base = (int)(std::max_element(shifts.begin(), shifts.end()) - shifts.begin());
     std::vector<double> sig(nc);
     for (int c = 0; c < nc; ++c) sig[c] = shifts[base] - shifts[c];
     ENSURE(ctx->wd_sig, (size_t)nc * 8);
     HIPCHK(hipMemcpyAsync(ctx->wd_sig.p, sig.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
     constexpr int W = kWideWindow;
-    const double per_col = (nc + W + 1.0) * ng * 8.0;   // p_c, the residual ring, w
+    // p_c, the residual ring, w (and the BF16 split of the base p)
+    const double per_col = (nc + W + 1.0) * ng * 8.0 + (bf16 ? 4.0 * ngk : 0.0);
     int chunk = (int)std::max(16.0, std::min((double)nb, std::floor(kWideBudgetBytes / per_col)));
     if (chunk < nb) chunk = std::max(16, chunk / 16 * 16);
     ENSURE(ctx->wd_p, (size_t)nc * ng * chunk * 8);
@@ -841,6 +885,24 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
     ENSURE(ctx->wd_w, (size_t)ng * chunk * 8);
     ENSURE(ctx->wd_c, (size_t)ne * chunk * 8);
     ENSURE(ctx->splitk, (size_t)kSplitSlices * ne * chunk * 8);
+    // BF16 form: split-K slices of Phi^T p so that the grid has >= ~1024 workgroups
+    int bf_split = 1;
+    unsigned short *pb[2] = {nullptr, nullptr};
+    const unsigned short *phi_cm_b[2] = {nullptr, nullptr}, *phi_rm_b[3] = {nullptr, nullptr, nullptr};
+    if (bf16) {
+        const int tiles = ((ne + 127) / 128) * ((chunk + 127) / 128);
+        bf_split = std::max(1, std::min(8, (1024 + tiles - 1) / tiles));
+        bf_split = bf16_split_count((int)ngk, bf_split);
+        for (int t = 0; t < 2; ++t) {
+            ENSURE(ctx->bf_p[t], (size_t)ngk * chunk * 2);
+            pb[t] = dp<unsigned short>(ctx->bf_p[t]);
+            phi_cm_b[t] = dp<unsigned short>(ctx->bf_phi_cm[t]);
+        }
+        for (int t = 0; t < 3; ++t) phi_rm_b[t] = dp<unsigned short>(ctx->bf_phi_rm[t]);
+        ENSURE(ctx->bf_part, (size_t)bf_split * ldp * chunk * 4);
+        ENSURE(ctx->bf_c, (size_t)nek * chunk * 2);
+    }
+    const double Tdef = bf16 ? bf16_deflation_level(ctx) : 0.0;
     // scalars: 7 nb doubles (rr rrn bn al alp btp pw), 6 nc nb doubles, the window
     // coefficients, then ints (colact, act, upd, it, touched, flags, nactive)
     const size_t ncoef = (size_t)nc * chunk * (2 + 2 * W);
@@ -886,42 +948,74 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         }
         const long long rs = (long long)ng * n;   // ring slot q holds r^k for k mod W = q
         HIPCHK(hipMemcpyAsync(ring, Bj, (size_t)ng * n * 8, hipMemcpyDeviceToDevice, s));
+        if (bf16) HIPCHK(launch_split_bf16(ng, n, Bj, ng, 2, pb, ngk, s));
         HIPCHK(launch_col_sqnorm(ng, n, Bj, ng, ws.rrn, s));
         HIPCHK(launch_fill_i32(ws.flags, 1, 0, s));
         HIPCHK(wide_init(n, nc, ws.rrn, ws, s));
-        const double *pb = P + (size_t)base * ng * n;
-        int iter = 0, k0 = 0;
+        const double *pb_base = P + (size_t)base * ng * n;
+        int iter = 0, k0 = 0, live_prev = n;
         for (; iter < ctx->opts.max_iter; ++iter) {
+            HIPCHK(hipEventRecord(ctx->ev[8], s));
             // w = Q (H - s_base) p  (p in range(Q)); the projector GEMMs are timed
             if (col_shift_dev)
-                HIPCHK(launch_stencil(ctx->gd, n, pb, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
+                HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
                                       col_shift_dev + j0, s));
             else
-                HIPCHK(launch_stencil(ctx->gd, n, pb, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, -shifts[base],
-                                      nullptr, s));
+                HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0,
+                                      -shifts[base], nullptr, s));
             HIPCHK(hipEventRecord(ctx->ev[6], s));
-            HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, w, ng, 0.0, C, ne, dp<double>(ctx->splitk),
-                               (size_t)kSplitSlices * ne * n, s, Epi::StoreProjector));
-            HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, w, ng, 0, 1, s,
-                        Epi::StoreProjector));
+            if (bf16) {
+                // deflated operator: w += Phi (T - Lambda) Phi^T p, both products in BF16
+                float *part = dp<float>(ctx->bf_part);
+                unsigned short *cb = dp<unsigned short>(ctx->bf_c);
+                const unsigned short *cbv[1] = {cb};
+                HIPCHK(gemm_bf16_tn(2, 2, 0, ne, n, (int)ngk, phi_cm_b, ngk, pb, ngk, bf_split, part, ldp, nullptr,
+                                    0, 0.0, s));
+                HIPCHK(launch_deflate_coef(ne, n, bf_split, part, ldp, dp<double>(ctx->eps_dev), Tdef, cb, nek, s));
+                HIPCHK(gemm_bf16_tn(3, 1, 1, ng, n, (int)nek, phi_rm_b, nek, cbv, nek, 1, nullptr, 0, w,
+                                    ng, 1.0, s));
+            } else {
+                HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, w, ng, 0.0, C, ne, dp<double>(ctx->splitk),
+                                   (size_t)kSplitSlices * ne * n, s, Epi::StoreProjector));
+                HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, w, ng, 0, 1, s,
+                            Epi::StoreProjector));
+            }
             HIPCHK(hipEventRecord(ctx->ev[7], s));
-            HIPCHK(launch_col_dot(ng, n, pb, ng, w, ng, pw, s));
+            HIPCHK(launch_col_dot(ng, n, pb_base, ng, w, ng, pw, s));
             HIPCHK(launch_fill_i32(ws.nactive, 1, 0, s));
             HIPCHK(wide_step(ng, n, nc, base, dp<double>(ctx->wd_sig), tol, iter, k0, pw, w, ring + (iter % W) * rs,
-                             ring + ((iter + 1) % W) * rs, P, Zj, zstride, ws, s));
+                             ring + ((iter + 1) % W) * rs, P, Zj, zstride, ws, s, bf16 ? pb : nullptr, ngk));
+            double flush_units = 0.0;
             if (iter - k0 + 1 == W) {   // window full: the other shifts' deferred updates
                 HIPCHK(wide_flush(ng, n, nc, base, k0, W, ring, P, Zj, zstride, ws, s));
                 k0 = iter + 1;
+                if (nc > 1) flush_units = W + 4.0 * (nc - 1);
             }
+            HIPCHK(hipEventRecord(ctx->ev[9], s));
             int live = 0;
             HIPCHK(hipMemcpyAsync(&live, ws.nactive, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            ctx->stats.ms_solve_kernel += event_ms(ctx->ev[6], ctx->ev[7]);
+            const double ms_pair = event_ms(ctx->ev[6], ctx->ev[7]);
+            ctx->stats.ms_solve_kernel += ms_pair;
+            ctx->stats.ms_vectors += event_ms(ctx->ev[8], ctx->ev[9]) - ms_pair;
+            // algorithmic bytes of the vector kernels for the columns live in this
+            // iteration, in N_g doubles: stencil (p read, w written), p.w (2), the
+            // residual (r, w read, rn written), the base update (x and p read and
+            // written, rn read; BF16: the two terms of p written, 0.5), and at a
+            // window's end the deferred updates (the wl ring slots read, p_c and x_c
+            // of the other nc - 1 shifts read and written)
+            const double units = 2.0 + 2.0 + 3.0 + 5.0 + (bf16 ? 0.5 : 0.0) + flush_units;
+            ctx->stats.vector_bytes += 8.0 * ng * (double)live_prev * units;
+            live_prev = live;
             ctx->stats.solve_kernel_launches += 1;
             ctx->stats.krylov_flops += 4.0 * ng * (double)ne * n;
-            // algorithmic bytes of the projector pair: y read twice, written once,
-            // Phi read once per GEMM, C written and read
-            ctx->stats.krylov_bytes += 8.0 * ((double)ng * n * 3.0 + 2.0 * ng * ne + 2.0 * ne * n);
+            // algorithmic bytes of the projector pair: FP64, y read twice and written
+            // once, Phi read once per GEMM, C written and read; BF16, the two terms
+            // of p read, w read and written, the five terms of Phi read once, C
+            if (bf16)
+                ctx->stats.krylov_bytes += (double)ng * n * (4.0 + 16.0) + 10.0 * ng * ne + 6.0 * ne * n;
+            else
+                ctx->stats.krylov_bytes += 8.0 * ((double)ng * n * 3.0 + 2.0 * ng * ne + 2.0 * ne * n);
             if (live == 0) {
                 ++iter;
                 break;
@@ -953,8 +1047,10 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
 
 // max over columns of ||B_j - A_c Z_j|| / ||B_j|| for the nc shift blocks of Z
 // (N_g x nb each, stride zstride) against the same B, in column chunks.
+// With project, Z is first replaced by Q Z in place (FP64), and the residual is
+// that of the projected solutions.
 acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std::vector<double> &shifts,
-                                const double *Z, long long zstride, double *max_rel);
+                                double *Z, long long zstride, double *max_rel, bool project = false);
 
 // A X = Q (H - s_j) Q X for column-major X (n columns); result in Y.
 // C = Phi^T X (N_e x n, leading dimension N_e) for column-major X (leading
@@ -1019,7 +1115,7 @@ acp_status true_residual(acp_ctx *ctx, int n, const double *shifts_dev, const do
 }
 
 acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std::vector<double> &shifts,
-                                const double *Z, long long zstride, double *max_rel) {
+                                double *Z, long long zstride, double *max_rel, bool project) {
     const int ng = ctx->ng, nc = (int)shifts.size();
     hipStream_t s = ctx->stream;
     const int chunk = std::max(16, std::min(nb, (int)std::floor(4.0 * 1024 * 1024 * 1024 / (8.0 * ng))));
@@ -1034,8 +1130,15 @@ acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std
             const int n = std::min(chunk, nb - j0);
             std::fill(sh.begin(), sh.end(), shifts[c]);
             HIPCHK(hipMemcpyAsync(ctx->dy_s.p, sh.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
-            CHECK(apply_operator(ctx, n, dp<double>(ctx->dy_s), Z + c * zstride + (size_t)j0 * ng,
-                                 dp<double>(ctx->tmp1)));
+            double *Zc = Z + c * zstride + (size_t)j0 * ng;
+            if (project) {   // the operator's first projection writes Q Z over Z
+                ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+                ENSURE(ctx->splitk, (size_t)kSplitSlices * ctx->ne * n * 8);
+                CHECK(apply_operator_ws(ctx, n, dp<double>(ctx->dy_s), Zc, dp<double>(ctx->tmp1), Zc,
+                                        dp<double>(ctx->c1), dp<double>(ctx->splitk)));
+            } else {
+                CHECK(apply_operator(ctx, n, dp<double>(ctx->dy_s), Zc, dp<double>(ctx->tmp1)));
+            }
             HIPCHK(launch_col_diff_sqnorm(ng, n, B + (size_t)j0 * ng, ng, dp<double>(ctx->tmp1), ng, rn, s));
             HIPCHK(launch_col_sqnorm(ng, n, B + (size_t)j0 * ng, ng, bn, s));
             HIPCHK(hipMemcpyAsync(h.data(), rn, (size_t)n * 8, hipMemcpyDeviceToHost, s));
@@ -1684,7 +1787,11 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
     int flags = 0;
     bool ms_used = false;
     const bool mixed = ctx->opts.precision == ACP_PREC_FP32_REFINE;
+    const bool bf16 = ctx->opts.precision == ACP_PREC_BF16_PROJ;
     const bool learned = ctx->opts.use_learned_precond != 0;
+    if (bf16 && (learned || !wide_form(ctx)))
+        return fail(ctx, ACP_EINVAL, "the BF16 projector form is built for more than 256 orbitals, without the "
+                                     "learned preconditioner");
     if (learned) {
         // per-system flexible CG (the network, or none in mode 2) on every
         // system, column-major like Z
@@ -1713,11 +1820,12 @@ acp_status solve_and_assemble(acp_ctx *ctx) {
         double *Z = dp<double>(ctx->z);
         if (ctx->opts.solver == ACP_SOLVER_CG) {
             CHECK(solve_multishift_wide(ctx, R, nmu, ctx->nodes, ctx->opts.tol, Z, (long long)ng * nmu, &flags,
-                                        nullptr));
+                                        nullptr, nullptr, bf16));
         } else {
             for (int c = 0; c < nc; ++c)
                 CHECK(solve_multishift_wide(ctx, R, nmu, std::vector<double>{ctx->nodes[c]}, ctx->opts.tol,
-                                            Z + (size_t)c * ng * nmu, (long long)ng * nmu, &flags, nullptr));
+                                            Z + (size_t)c * ng * nmu, (long long)ng * nmu, &flags, nullptr,
+                                            nullptr, bf16));
         }
     } else if (!mixed) {
         KrylovInputs<double> in{dp<double>(ctx->phi_rm), phi, dp<double>(ctx->krhs)};
@@ -1780,16 +1888,22 @@ acp_status finish_compress(acp_ctx *ctx, int flags, bool learned) {
     ENSURE(ctx->z, (size_t)ng * nmu * nc * 8);
     double *Z = dp<double>(ctx->z);
     if (wide_form(ctx) && !learned) {
-        // Z written by the solver; W, then the FP64 true residuals in column chunks
+        // Z written by the solver; W, then the FP64 true residuals in column chunks.
+        // The BF16 form first projects Z onto range(Q) in FP64 (its solutions carry
+        // occupied components at the level of the BF16 rounding) within the residual
+        // pass, then assembles W from the projected Z.
+        const bool bf16 = ctx->opts.precision == ACP_PREC_BF16_PROJ;
+        double mr = 0.0;
         HIPCHK(hipEventRecord(ctx->ev[3], s));
+        if (bf16) CHECK(true_residual_blocks(ctx, R, nmu, ctx->nodes, Z, (long long)ng * nmu, &mr, true));
+        HIPCHK(hipEventRecord(ctx->ev[5], s));
         CHECK(assemble_w(ctx));
         HIPCHK(hipEventRecord(ctx->ev[4], s));
         HIPCHK(hipStreamSynchronize(s));
         ctx->stats.ms_rhs += event_ms(ctx->ev[1], ctx->ev[2]);
         ctx->stats.ms_solve += event_ms(ctx->ev[2], ctx->ev[3]);
-        ctx->stats.ms_w += event_ms(ctx->ev[3], ctx->ev[4]);
-        double mr = 0.0;
-        CHECK(true_residual_blocks(ctx, R, nmu, ctx->nodes, Z, (long long)ng * nmu, &mr));
+        ctx->stats.ms_w += event_ms(ctx->ev[5], ctx->ev[4]);
+        if (!bf16) CHECK(true_residual_blocks(ctx, R, nmu, ctx->nodes, Z, (long long)ng * nmu, &mr));
         ctx->stats.max_rel_residual = mr;
         ctx->have_chi0 = true;
         return flags_status(ctx, flags);
@@ -2945,7 +3059,12 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->fc_r, &ctx->fc_z, &ctx->fc_p, &ctx->fc_q, &ctx->fc_sc, &ctx->fc_idx, &ctx->dy_piv,
                       &ctx->vc_g, &ctx->cm_x[0], &ctx->cm_x[1], &ctx->cm_p[0], &ctx->cm_p[1],
                       &ctx->cm_r[0], &ctx->cm_r[1], &ctx->cm_pa[0], &ctx->cm_pa[1], &ctx->cm_state[0],
-                      &ctx->cm_state[1], &ctx->cm_map, &ctx->cm_map0};
+                      &ctx->cm_state[1], &ctx->cm_map, &ctx->cm_map0,
+                      &ctx->wd_p, &ctx->wd_r, &ctx->wd_w, &ctx->wd_c, &ctx->wd_sc, &ctx->wd_sig,
+                      &ctx->bf_phi_cm[0], &ctx->bf_phi_cm[1], &ctx->bf_phi_rm[0], &ctx->bf_phi_rm[1],
+                      &ctx->bf_phi_rm[2], &ctx->bf_p[0], &ctx->bf_p[1], &ctx->bf_part, &ctx->bf_c, &ctx->eps_dev,
+                      &ctx->df_b, &ctx->df_z, &ctx->df_c, &ctx->df_u, &ctx->df_f, &ctx->df_v, &ctx->df_r,
+                      &ctx->df_du, &ctx->df_dr, &ctx->df_pu, &ctx->df_pr, &ctx->df_dot};
     for (DevBuf *b : bufs) release(*b);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
     for (auto &e : ctx->ev)

@@ -221,13 +221,49 @@ hipError_t wide_init(int nb, int nc, const double *bsq, const WideScalars &w, hi
 // ring slots), the shifted coefficients (advanced in the window), the base
 // shift's x and p, the column state (nactive += live columns).  P: nc blocks of
 // N_g x nb (stride N_g nb); X: nc blocks with stride xs.
+// With pb (two arrays, leading dimension ldpb) the base p is also written as
+// its two-term BF16 split (the operand of the reduced-precision projector).
 hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, int k0,
                      const double *pw, const double *w_vec, const double *r, double *rn, double *P, double *X,
-                     long long xs, const WideScalars &w, hipStream_t s);
+                     long long xs, const WideScalars &w, hipStream_t s, unsigned short *const *pb = nullptr,
+                     long long ldpb = 0);
 // End of a window of wl steps started at k0: the other shifts' p_c and x_c from
 // the ring of residuals (slot q holds r^k for k mod kWideWindow = q, stride N_g nb).
 hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
                       long long xs, const WideScalars &w, hipStream_t s);
+
+// ---------------------------------------------------------------- BF16 projector (k_gemm_bf16.hip)
+// bf16 of x: FP64 -> FP32 (nearest), then nearest-even to 8 significant bits.
+// Splitting needs no exact rounding: x - bf16(x) is exact in FP64, and the next
+// term carries it.
+__device__ inline unsigned short f64_to_bf16(double x) {
+    unsigned int fb = __float_as_uint((float)x);
+    if ((fb & 0x7f800000u) == 0x7f800000u) return (unsigned short)((fb >> 16) | ((fb & 0xffffu) ? 0x40u : 0u));
+    fb += 0x7fffu + ((fb >> 16) & 1u);
+    return (unsigned short)(fb >> 16);
+}
+__device__ inline double bf16_to_f64(unsigned short h) { return (double)__uint_as_float((unsigned int)h << 16); }
+// X column-major (m x n, ldx) -> nt (1..3) BF16 terms O[s][j ldo + i], rows
+// m..ldo-1 zero.
+hipError_t launch_split_bf16(int m, int n, const double *X, long long ldx, int nt, unsigned short *const *O,
+                             long long ldo, hipStream_t s);
+// The same split written transposed: O[s][i ldo + j], columns n..ldo-1 zero.
+hipError_t launch_split_bf16_transpose(int m, int n, const double *X, long long ldx, int nt,
+                                       unsigned short *const *O, long long ldo, hipStream_t s);
+// D = sum_{a + b < max(na, nb)} A_a B_b^T with A_a[m lda + k] (M x K) and
+// B_b[n ldb + k] (N x K), BF16 operands, FP32 accumulation on the matrix cores.
+// epi 0: split-K over nsplit slices, slice z stored to P[z ldp N + n ldp + m]
+// (FP32; ldp a multiple of 4); epi 1 (nsplit = 1): Wd[n ldw + m] += alpha D.
+// K, lda, ldb multiples of 8; supported (na, nb, epi): (1,1,*), (2,2,0),
+// (3,1,1), (2,1,1).
+hipError_t gemm_bf16_tn(int na, int nb, int epi, int M, int N, int K, const unsigned short *const *A, long long lda,
+                        const unsigned short *const *B, long long ldb, int nsplit, float *P, long long ldp,
+                        double *Wd, long long ldw, double alpha, hipStream_t s);
+// Number of split-K slices gemm_bf16_tn actually uses for K and nsplit.
+int bf16_split_count(int K, int nsplit);
+// Cb[j ldc + i] = bf16((T - eps_i) sum_z P[z ldp n + j ldp + i]) for i < m, 0 below ldc.
+hipError_t launch_deflate_coef(int m, int n, int nsplit, const float *P, long long ldp, const double *eps, double T,
+                               unsigned short *Cb, long long ldc, hipStream_t s);
 
 // ---------------------------------------------------------------- DFPT comparator (k_dfpt.hip)
 // P(:, i + ne j) = phi_i o V(:, j);  Y(:, j) = scale sum_i phi_i o Z(:, i + ne j).

@@ -170,8 +170,11 @@ __global__ void wide_shift_scalars_kernel(int nb, int nc, int base, const double
 }
 
 // The base shift every iteration: x_b += a_k p (with the old p), p = r^{k+1} + b_k p.
+// With pb0 (and pb1) the new p is also written as its two-term BF16 split at
+// j ldpb + i.
 __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd, const double *ac,
-                                        const double *bc, const double *rn, double *P, double *X) {
+                                        const double *bc, const double *rn, double *P, double *X,
+                                        unsigned short *pb0, unsigned short *pb1, long long ldpb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= ng) return;
@@ -180,7 +183,15 @@ __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd
     const long long off = (long long)j * ng + i;
     const double p = P[off];
     if (u & 1) X[off] += ac[base * nb + j] * p;
-    if (u & 2) P[off] = rn[off] + bc[base * nb + j] * p;
+    if (u & 2) {
+        const double pn = rn[off] + bc[base * nb + j] * p;
+        P[off] = pn;
+        if (pb0) {
+            const unsigned short h = f64_to_bf16(pn);
+            pb0[(long long)j * ldpb + i] = h;
+            pb1[(long long)j * ldpb + i] = f64_to_bf16(pn - bf16_to_f64(h));
+        }
+    }
 }
 
 // End of a window of wl steps started at k0: for every other shift touched in
@@ -238,7 +249,7 @@ hipError_t wide_init(int nb, int nc, const double *bsq, const WideScalars &w, hi
 
 hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, int k0,
                      const double *pw, const double *w_vec, const double *r, double *rn, double *P, double *X,
-                     long long xs, const WideScalars &w, hipStream_t s) {
+                     long long xs, const WideScalars &w, hipStream_t s, unsigned short *const *pb, long long ldpb) {
     hipLaunchKernelGGL(wide_alpha_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, (const double *)w.rr, pw,
                        w.colact, w.al, w.flags);
     hipLaunchKernelGGL(wide_residual_kernel, dim3(nb), dim3(256), 0, s, ng, (const double *)w.al,
@@ -249,7 +260,8 @@ hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double
                        w.z, w.zp, w.act, w.upd, w.ac, w.zn, w.bc, w.it, w.res, w.coef, w.touched);
     hipLaunchKernelGGL(wide_base_update_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, base,
                        (const int *)w.upd, (const double *)w.ac, (const double *)w.bc, (const double *)rn,
-                       P + (size_t)base * nb * ng, X + (size_t)base * xs);
+                       P + (size_t)base * nb * ng, X + (size_t)base * xs, pb ? pb[0] : nullptr,
+                       pb ? pb[1] : nullptr, ldpb);
     hipLaunchKernelGGL(wide_column_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, nc, (const int *)w.act,
                        w.colact, w.rr, (const double *)w.rrn, w.alp, (const double *)w.al, w.btp, w.nactive);
     return hipGetLastError();

@@ -1,0 +1,111 @@
+"""Reduced-precision form of the many-orbital solver (ACP_PREC_BF16_PROJ): the
+orbital products of every CG step as BF16 GEMMs (FP32 accumulation) on the
+deflated operator H + Phi (T - Lambda) Phi^T - s, the solutions projected onto
+range(Q) and their residuals recomputed in FP64.  Against the oracle's Alg. 2,
+Alg. 3, Alg. 4 and Sec. 2.2 on a 48 x 48 grid whose orbitals are the 389 lowest
+eigenvectors of H (the largest gap between levels 260 and 420: 0.226 Ha), with
+the oracle's selections forced on the GPU.  The bar for a reduced-precision form
+is 1e-4 on D and omega^2; the measured errors are printed per result."""
+import functools
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import grid_dict, require_gpu, to_dev, to_host
+from oracle import acp as OA
+from oracle import chi0 as OC
+from oracle.model import build_model
+from workload.seeds import draw_sketch, small_config
+
+pytestmark = pytest.mark.gpu
+
+CFG = small_config(903, 2, 4, 12, a=6.0, sigma=0.8, jitter=0.05, n_cheb=4, r=16)
+N_MU = 128
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@functools.lru_cache(maxsize=None)
+def _system():
+    m = build_model(CFG)
+    V = m.superposed_atoms_potential()
+    H = m.hamiltonian_dense(V)
+    w, v = np.linalg.eigh(H)
+    gaps = np.diff(w)
+    n_e = 260 + int(np.argmax(gaps[259:419])) + 1
+    phi, eps = v[:, :n_e].copy(), w[:n_e].copy()
+    G = m.perturbations()
+    om = draw_sketch(CFG, G.shape[1])
+    solver = OA.ExactShiftedSolver(w, v, n_e)
+    return m, V, phi, eps, G, om, solver
+
+
+def _ctx(**opts):
+    from paper_1605_08021_amd import acp
+    m, V, phi, eps, G, om, solver = _system()
+    o = dict(n_cheb=CFG.n_cheb, n_mu=N_MU, sketch_r=CFG.r, tol=1e-10, max_iter=5000)
+    o.update(opts)
+    print(f"[gpu] N_g={m.grid.n_grid} N_e={phi.shape[1]} opts={o}", flush=True)
+    return acp.Context(grid_dict(CFG), o, to_dev(phi), eps, to_dev(V))
+
+
+@pytest.mark.parametrize("solver_id", [0, 2])
+def test_bf16_projector_dyson_dynmat_match_oracle(solver_id):
+    from paper_1605_08021_amd import acp
+    m, V, phi, eps, G, om, solver = _system()
+    kmax = 2
+    ref = OA.acp_dyson(phi, eps, G, om, CFG.n_cheb, N_MU, solver, vc=m.vc, vc_inv=m.vc_inv, f=m.f,
+                       dv=m.grid.dv, k_max=kmax)
+    K = np.random.default_rng(5).standard_normal((G.shape[1], G.shape[1]))
+    K = K + K.T
+    masses = np.ones(m.n_atoms)
+    Dref, lamref = OC.dynamical_matrix(m.grid.dv * (G.T @ ref.U) + K, masses, CFG.dim)
+    out = {}
+    for prec in (acp.PREC_FP64, acp.PREC_BF16_PROJ):
+        ctx = _ctx(solver=solver_id, dyson_max_iter=kmax, precision=prec)
+        U, iters, _ = ctx.dyson(to_dev(G), to_dev(om), sel_hist_in=np.stack(ref.sel_hist))
+        assert iters == kmax
+        st = ctx.stats()
+        last = ref.last
+        ez = _rel(to_host(ctx.compress_get("z")), np.concatenate(last.Z, axis=1))
+        ew = _rel(to_host(ctx.compress_get("w")), last.W)
+        eu = float(np.linalg.norm(to_host(U) - ref.U) / np.linalg.norm(ref.U))
+        D, lam = ctx.dynmat(to_dev(G), None, K, masses)
+        ed = float(np.linalg.norm(D - Dref) / np.linalg.norm(Dref))
+        el = float(np.abs(lam - lamref).max() / np.abs(lamref).max())
+        out[prec] = (ez, ew, eu, ed, el, st)
+        print(f"[bf16] precision={prec} solver={solver_id}: Z {ez:.2e} W {ew:.2e} U {eu:.2e} D {ed:.2e} "
+              f"omega^2 {el:.2e}; true residual {st['max_rel_residual']:.2e}, iterations "
+              f"{st['iters_min']}-{st['iters_max']}, projector {st['ms_solve_kernel']:.1f} ms", flush=True)
+        ctx.close()
+    ez, ew, eu, ed, el, st = out[acp.PREC_BF16_PROJ]
+    # every system's FP64 residual (after the FP64 projection) meets the tolerance
+    assert st["max_rel_residual"] <= 2e-10
+    assert ez <= 1e-7 and ew <= 1e-7 and eu <= 1e-7
+    assert ed <= 1e-4 and el <= 1e-4
+    # the BF16 rounding costs few extra iterations
+    assert st["iters_max"] <= 1.25 * out[acp.PREC_FP64][5]["iters_max"] + 5
+
+
+def test_bf16_projector_needs_the_many_orbital_form():
+    """Up to 256 orbitals (the fused kernels) the BF16 projector is refused at
+    acp_compress, and MINRES at acp_set_opts."""
+    from paper_1605_08021_amd import acp
+    m, V, phi, eps, G, om, solver = _system()
+    ctx = acp.Context(grid_dict(CFG), dict(n_cheb=CFG.n_cheb, n_mu=64, sketch_r=CFG.r,
+                                           precision=acp.PREC_BF16_PROJ),
+                      to_dev(phi[:, :200].copy()), eps[:200].copy(), to_dev(V))
+    with pytest.raises(acp.ACPError) as e:
+        ctx.compress(to_dev(G), to_dev(om))
+    assert e.value.status == acp.ACP_EINVAL
+    with pytest.raises(acp.ACPError) as e:
+        ctx.set_opts(solver=1)
+    assert e.value.status == acp.ACP_EINVAL
+    ctx.close()
