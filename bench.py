@@ -55,6 +55,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mscg_kernel_cfg2_traffic.json")
 KERNEL_SOURCES = [os.path.join(CSRC, f) for f in ("k_mscg.hip", "krylov_common.h")]
 GEMM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_projector_cfg5_traffic.json")
 GEMM_SOURCES = [os.path.join(CSRC, "k_gemm.hip")]
+BF16_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_bf16_projector_cfg5_traffic.json")
+BF16_SOURCES = [os.path.join(CSRC, "k_gemm_bf16.hip")]
 
 
 def kernel_source_hash(sources=None) -> str:
@@ -323,7 +325,7 @@ def main():
             # the dense BF16 peak (the split terms execute 3x as many)
             roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": BF16_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
-                        "traffic": None,
+                        "traffic": measured_traffic(f"config {args.config}", BF16_TRAFFIC_FILE, BF16_SOURCES),
                         "kernel": "gemm_bf16_tn_kernel<2,2,0> + <3,1,1> (projector GEMMs of the many-orbital "
                                   "multi-shift CG, v_mfma_f32_16x16x32_bf16, FP32 accumulation)",
                         "algorithmic_flops_per_launch": st["krylov_flops"] / gemm_launches,
