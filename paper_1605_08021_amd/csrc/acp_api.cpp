@@ -858,7 +858,29 @@ acp_status prepare_bf16(acp_ctx *ctx) {
     HIPCHK(launch_split_bf16_transpose(ng, ne, dp<double>(ctx->phi_cm), ng, 3, rm, nek, s));
     ENSURE(ctx->eps_dev, (size_t)ne * 8);
     HIPCHK(hipMemcpyAsync(ctx->eps_dev.p, ctx->eps.data(), (size_t)ne * 8, hipMemcpyHostToDevice, s));
+    // The deflated operator equals Q (H - s) Q on range(Q) only for eigenvectors:
+    // with H phi_j = eps_j phi_j + r_j the projected solutions are off by
+    // O(|r|^2 / (T - s)), so orbitals with max_j |r_j| above 1e-5 (1 + max |eps|)
+    // are refused.
+    ENSURE(ctx->tmp1, (size_t)ng * ne * 8);
+    ENSURE(ctx->dy_norm, (size_t)ne * 8);
+    HIPCHK(launch_stencil(ctx->gd, ne, dp<double>(ctx->phi_cm), ng, dp<double>(ctx->tmp1), ng,
+                          dp<double>(ctx->veff), -0.5, 1.0, 0.0, dp<double>(ctx->eps_dev), s));
+    HIPCHK(launch_col_sqnorm(ng, ne, dp<double>(ctx->tmp1), ng, dp<double>(ctx->dy_norm), s));
+    std::vector<double> r2(ne);
+    HIPCHK(hipMemcpyAsync(r2.data(), ctx->dy_norm.p, (size_t)ne * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    double rmax = 0.0, emax = 0.0;
+    for (int j = 0; j < ne; ++j) {
+        rmax = std::max(rmax, std::sqrt(r2[j]));
+        emax = std::max(emax, std::fabs(ctx->eps[j]));
+    }
+    if (!(rmax <= 1e-5 * (1.0 + emax))) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "the BF16 projector form needs eigenvectors of H: max |H phi_j - eps_j phi_j| = %.3e", rmax);
+        return fail(ctx, ACP_EINVAL, msg);
+    }
     ctx->bf_ready = true;
     return ACP_OK;
 }
@@ -887,13 +909,17 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
     ENSURE(ctx->splitk, (size_t)kSplitSlices * ne * chunk * 8);
     // BF16 form: split-K slices of Phi^T p so that the grid has >= ~1024 workgroups
     int bf_split = 1;
+    // BF16 terms of Phi and p in Phi^T p: with one term each the occupied noise of
+    // w grows ~100x and GEMM2's Phi error carries it into range(Q) (measured:
+    // true residuals 3e-9 at tol 1e-10), so two
+    constexpr int pterms = 2;
     unsigned short *pb[2] = {nullptr, nullptr};
     const unsigned short *phi_cm_b[2] = {nullptr, nullptr}, *phi_rm_b[3] = {nullptr, nullptr, nullptr};
     if (bf16) {
         const int tiles = ((ne + 127) / 128) * ((chunk + 127) / 128);
         bf_split = std::max(1, std::min(8, (1024 + tiles - 1) / tiles));
         bf_split = bf16_split_count((int)ngk, bf_split);
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < pterms; ++t) {
             ENSURE(ctx->bf_p[t], (size_t)ngk * chunk * 2);
             pb[t] = dp<unsigned short>(ctx->bf_p[t]);
             phi_cm_b[t] = dp<unsigned short>(ctx->bf_phi_cm[t]);
@@ -948,7 +974,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         }
         const long long rs = (long long)ng * n;   // ring slot q holds r^k for k mod W = q
         HIPCHK(hipMemcpyAsync(ring, Bj, (size_t)ng * n * 8, hipMemcpyDeviceToDevice, s));
-        if (bf16) HIPCHK(launch_split_bf16(ng, n, Bj, ng, 2, pb, ngk, s));
+        if (bf16) HIPCHK(launch_split_bf16(ng, n, Bj, ng, pterms, pb, ngk, s));
         HIPCHK(launch_col_sqnorm(ng, n, Bj, ng, ws.rrn, s));
         HIPCHK(launch_fill_i32(ws.flags, 1, 0, s));
         HIPCHK(wide_init(n, nc, ws.rrn, ws, s));
@@ -969,8 +995,8 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
                 float *part = dp<float>(ctx->bf_part);
                 unsigned short *cb = dp<unsigned short>(ctx->bf_c);
                 const unsigned short *cbv[1] = {cb};
-                HIPCHK(gemm_bf16_tn(2, 2, 0, ne, n, (int)ngk, phi_cm_b, ngk, pb, ngk, bf_split, part, ldp, nullptr,
-                                    0, 0.0, s));
+                HIPCHK(gemm_bf16_tn(pterms, pterms, 0, ne, n, (int)ngk, phi_cm_b, ngk, pb, ngk, bf_split, part, ldp,
+                                    nullptr, 0, 0.0, s));
                 HIPCHK(launch_deflate_coef(ne, n, bf_split, part, ldp, dp<double>(ctx->eps_dev), Tdef, cb, nek, s));
                 HIPCHK(gemm_bf16_tn(3, 1, 1, ng, n, (int)nek, phi_rm_b, nek, cbv, nek, 1, nullptr, 0, w,
                                     ng, 1.0, s));

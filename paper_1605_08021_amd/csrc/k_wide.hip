@@ -170,8 +170,8 @@ __global__ void wide_shift_scalars_kernel(int nb, int nc, int base, const double
 }
 
 // The base shift every iteration: x_b += a_k p (with the old p), p = r^{k+1} + b_k p.
-// With pb0 (and pb1) the new p is also written as its two-term BF16 split at
-// j ldpb + i.
+// With pb0 the new p is also written as its BF16 split at j ldpb + i (two
+// terms with pb1, else one).
 __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd, const double *ac,
                                         const double *bc, const double *rn, double *P, double *X,
                                         unsigned short *pb0, unsigned short *pb1, long long ldpb) {
@@ -189,7 +189,7 @@ __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd
         if (pb0) {
             const unsigned short h = f64_to_bf16(pn);
             pb0[(long long)j * ldpb + i] = h;
-            pb1[(long long)j * ldpb + i] = f64_to_bf16(pn - bf16_to_f64(h));
+            if (pb1) pb1[(long long)j * ldpb + i] = f64_to_bf16(pn - bf16_to_f64(h));
         }
     }
 }

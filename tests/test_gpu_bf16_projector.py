@@ -96,9 +96,19 @@ def test_bf16_projector_dyson_dynmat_match_oracle(solver_id):
 
 def test_bf16_projector_needs_the_many_orbital_form():
     """Up to 256 orbitals (the fused kernels) the BF16 projector is refused at
-    acp_compress, and MINRES at acp_set_opts."""
+    acp_compress, MINRES at acp_set_opts, and orthonormal orbitals that are not
+    eigenvectors of H (the deflated operator then differs from Q (H - s) Q on
+    range(Q)) at acp_compress."""
     from paper_1605_08021_amd import acp
     m, V, phi, eps, G, om, solver = _system()
+    q, _ = np.linalg.qr(np.random.default_rng(4).standard_normal(phi.shape))
+    ctx = acp.Context(grid_dict(CFG), dict(n_cheb=CFG.n_cheb, n_mu=N_MU, sketch_r=CFG.r,
+                                           precision=acp.PREC_BF16_PROJ),
+                      to_dev(q), eps - 10.0, to_dev(V))
+    with pytest.raises(acp.ACPError) as e:
+        ctx.compress(to_dev(G), to_dev(om))
+    assert e.value.status == acp.ACP_EINVAL and "eigenvectors" in str(e.value)
+    ctx.close()
     ctx = acp.Context(grid_dict(CFG), dict(n_cheb=CFG.n_cheb, n_mu=64, sketch_r=CFG.r,
                                            precision=acp.PREC_BF16_PROJ),
                       to_dev(phi[:, :200].copy()), eps[:200].copy(), to_dev(V))
