@@ -73,7 +73,9 @@ typedef enum {
                                   stencil, the Krylov vectors and the solutions stay FP64; the
                                   solutions are projected onto range(Q) in FP64 and every
                                   system's residual is recomputed in FP64 (max_rel_residual).
-                                  CG solvers only. */
+                                  CG solvers only; acp_sternheimer runs in FP64. Orbitals
+                                  with max_j |H phi_j - eps_j phi_j| > 1e-5 (1 + max |eps|)
+                                  are refused (ACP_EINVAL at acp_compress). */
 } acp_precision;
 
 typedef enum {
@@ -114,8 +116,11 @@ typedef struct {
     double inner_tol;    /* relative tolerance of each inner FP32 solve (ACP_PREC_FP32_REFINE) */
     int use_learned_precond;  /* acp_sternheimer and acp_compress: 0 = the fused Krylov kernels;
                                  1 = flexible CG preconditioned by the learned network
-                                 (d = Q N(r/rms(r), shift) rms(r)), plain FP64 MINRES
-                                 finishing any system it leaves unconverged;
+                                 (d = Q N(r/rms(r), shift) rms(r)); a system whose residual
+                                 has not halved in 30 iterations, whose p.Ap <= 0 or that is
+                                 open at max_iter is finished in FP64 from its recomputed
+                                 residual b - A x (MINRES up to 256 orbitals, CG per system
+                                 above; stats.refinements counts these passes);
                                  2 = the same host-driven CG without the network (the
                                  comparison the network is measured against) */
     int reorthonormalize;     /* acp_setup: 1 = orthonormalise Psi in FP64 on the device

@@ -1409,7 +1409,12 @@ double splitmix_uniform(unsigned long long &state) {
 //   z = M(r), p = z;  alpha = r.z / p.Ap;  x += alpha p;  r -= alpha Ap;
 //   z' = M(r);  beta = -alpha z'.Ap / r.z;  p = z' + beta p.
 // M is the network (mode 1) or the identity (mode 2, plain CG in the same form).
-// Columns that reach tol stop; the rest are finished by FP64 MINRES (mode 1).
+// Columns that reach tol stop.  With the network, a column also leaves the
+// flexible iteration when its residual has not halved in kFcgStall iterations
+// or when p.Ap <= 0 (the network's direction is useless there); those columns
+// and any still open at max_iter are finished in FP64 from their recomputed
+// residual b - A x: MINRES up to 256 orbitals, CG per system above.
+constexpr int kFcgStall = 30;
 acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *shifts_dev,
                      const double *B, double *X, int *iters, int *flags_or) {
     const int ng = ctx->ng, mode = ctx->opts.use_learned_precond;
@@ -1453,11 +1458,14 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
     HIPCHK(hipMemcpyAsync(d_cols, cols.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_sh, shc.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     CHECK(col(launch_col_dot, B, B, bn));
-    std::vector<int> act(n);
+    std::vector<int> act(n), done(n, 0), stall_it(n, 0);   // done: converged (system order)
+    std::vector<double> stall_ref(n);
     for (int j = 0; j < n; ++j) {
         bn[j] = std::sqrt(bn[j]);
         act[j] = bn[j] > 0.0;
+        done[j] = !act[j];
         iters[j] = 0;
+        stall_ref[j] = bn[j];
     }
     CHECK(precond(R, Z));
     HIPCHK(hipMemcpyAsync(P, Z, bytes, hipMemcpyDeviceToDevice, s));
@@ -1483,6 +1491,8 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
                 bn[i] = bn[o];
                 rz[i] = rz[o];
                 shc[i] = shc[o];
+                stall_ref[i] = stall_ref[o];
+                stall_it[i] = stall_it[o];
                 act[i] = 1;
             }
             w = open;
@@ -1496,7 +1506,7 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
             al[i] = 0.0;
             if (!act[i]) continue;
             if (!(pq[i] > 0.0)) {
-                *flags_or |= 2;
+                if (mode != 1) *flags_or |= 2;   // with the network: handed to the FP64 solver
                 act[i] = 0;
                 continue;
             }
@@ -1511,7 +1521,16 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
         for (int i = 0; i < w; ++i)
             if (act[i]) {
                 iters[cols[i]] += 1;
-                if (std::sqrt(rr[i]) <= ctx->opts.tol * bn[i]) act[i] = 0;
+                const double rn = std::sqrt(rr[i]);
+                if (rn <= ctx->opts.tol * bn[i]) {
+                    act[i] = 0;
+                    done[cols[i]] = 1;
+                } else if (rn <= 0.5 * stall_ref[i]) {
+                    stall_ref[i] = rn;
+                    stall_it[i] = k;
+                } else if (mode == 1 && k - stall_it[i] >= kFcgStall) {
+                    act[i] = 0;   // stagnated: handed to the FP64 solver
+                }
             }
         open = 0;
         for (int i = 0; i < w; ++i) open += act[i];
@@ -1527,39 +1546,53 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
         HIPCHK(hipMemcpyAsync(d_t, be.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
         HIPCHK(launch_col_axpby(ng, w, nullptr, Z, ng, d_t, P, ng, s));   // p = z + beta p
     }
-    // the still-open systems, back in system order: R(:, i) -> Z(:, cols[i])
-    {
-        std::vector<double> mask(w);
-        for (int i = 0; i < w; ++i) mask[i] = act[i] ? 1.0 : 0.0;
-        HIPCHK(hipMemcpyAsync(d_a, mask.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemsetAsync(Z, 0, bytes, s));
-        HIPCHK(launch_col_axpy_scatter(ng, w, d_a, R, ng, d_cols, Z, ng, s));
-        HIPCHK(hipStreamSynchronize(s));
-    }
-    std::vector<int> act_sys(n, 0);
-    for (int i = 0; i < w; ++i) act_sys[cols[i]] = act[i];
     int open = 0;
-    for (int j = 0; j < n; ++j) open += act_sys[j];
+    for (int j = 0; j < n; ++j) open += !done[j];
     if (open && mode == 1) {
-        // fallback: FP64 MINRES solves A d = r for the columns still open (Z holds
-        // their residuals; the others get a zero right-hand side and stop at
-        // once); x += d
-        const int ntiles = (n + kTile - 1) / kTile, npad = ntiles * kTile;
-        ENSURE(ctx->krhs, (size_t)npad * ng * 8);
-        HIPCHK(launch_to_tiled(ng, n, npad, Z, ng, dp<double>(ctx->krhs), s));
-        const int saved = ctx->opts.solver;
-        ctx->opts.solver = ACP_SOLVER_MINRES;
-        KrylovInputs<double> in{dp<double>(ctx->phi_rm), dp<double>(ctx->phi_cm), dp<double>(ctx->krhs)};
-        int f = 0;
-        acp_status st = solve_tiled<double>(ctx, ntiles, ntiles, shifts_dev, in, ctx->opts.tol, &f);
-        ctx->opts.solver = saved;
-        CHECK(st);
-        *flags_or |= f;
-        HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), Z, ng, s));
-        HIPCHK(launch_col_axpby(ng, n, nullptr, Z, ng, nullptr, X, ng, s));   // x += d
-        std::vector<int> it2(n);
-        HIPCHK(hipMemcpyAsync(it2.data(), ctx->kiters.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        // the columns not converged: their FP64 residual b - A x (Z; zero for the
+        // converged ones, which then stop at once), A d = r by the FP64 solver,
+        // x += d
+        std::vector<double> mask(n);
+        for (int j = 0; j < n; ++j) mask[j] = done[j] ? 0.0 : 1.0;
+        HIPCHK(hipMemcpyAsync(d_a, mask.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+        CHECK(apply_operator(ctx, n, shifts_dev, X, Q));
+        HIPCHK(launch_axpby(ng, n, 1.0, B, ng, -1.0, Q, ng, s));
+        HIPCHK(hipMemsetAsync(Z, 0, bytes, s));
+        HIPCHK(launch_col_axpby(ng, n, d_a, Q, ng, nullptr, Z, ng, s));   // Z = mask o (B - A X)
+        // the residual may have grown past |b| in the flexible iteration: the FP64
+        // solve runs to tol min_j |b_j| / |r_j| relative to each r_j
+        HIPCHK(launch_col_sqnorm(ng, n, Z, ng, d_t, s));
+        HIPCHK(launch_col_sqnorm(ng, n, B, ng, d_b, s));
+        std::vector<double> r2(n), b2(n);
+        HIPCHK(hipMemcpyAsync(r2.data(), d_t, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(b2.data(), d_b, (size_t)n * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        double ratio = 1.0;
+        for (int j = 0; j < n; ++j)
+            if (!done[j] && r2[j] > 0.0) ratio = std::min(ratio, std::sqrt(b2[j] / r2[j]));
+        const double tol_fb = ctx->opts.tol * ratio;
+        std::vector<int> it2(n, 0);
+        int f = 0;
+        if (wide_form(ctx)) {
+            CHECK(solve_multishift_wide(ctx, Z, n, std::vector<double>{0.0}, tol_fb, P, (long long)ng * n,
+                                        &f, it2.data(), shifts_dev));
+            HIPCHK(launch_col_axpby(ng, n, nullptr, P, ng, nullptr, X, ng, s));   // x += d
+        } else {
+            const int ntiles = (n + kTile - 1) / kTile, npad = ntiles * kTile;
+            ENSURE(ctx->krhs, (size_t)npad * ng * 8);
+            HIPCHK(launch_to_tiled(ng, n, npad, Z, ng, dp<double>(ctx->krhs), s));
+            const int saved = ctx->opts.solver;
+            ctx->opts.solver = ACP_SOLVER_MINRES;
+            KrylovInputs<double> in{dp<double>(ctx->phi_rm), dp<double>(ctx->phi_cm), dp<double>(ctx->krhs)};
+            acp_status st = solve_tiled<double>(ctx, ntiles, ntiles, shifts_dev, in, tol_fb, &f);
+            ctx->opts.solver = saved;
+            CHECK(st);
+            HIPCHK(launch_from_tiled(ng, n, dp<double>(ctx->kx), Z, ng, s));
+            HIPCHK(launch_col_axpby(ng, n, nullptr, Z, ng, nullptr, X, ng, s));   // x += d
+            HIPCHK(hipMemcpyAsync(it2.data(), ctx->kiters.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        *flags_or |= f;
         for (int j = 0; j < n; ++j) iters[j] += it2[j];
         ctx->stats.refinements += 1;
     } else if (open) {
@@ -2402,7 +2435,7 @@ acp_status acp_sternheimer(acp_ctx *ctx, const double *shift, int n, const doubl
         ctx->stats.max_rel_residual = mr;
         return flags_status(ctx, flags);
     }
-    if (ctx->opts.precision == ACP_PREC_FP64) {
+    if (ctx->opts.precision != ACP_PREC_FP32_REFINE) {   // FP64 (the BF16 form is for compressions)
         std::vector<int> it(n);
         CHECK(solve_columns_fp64(ctx, shift, n, B, X, ctx->opts.tol, it.data(), &flags));
         HIPCHK(hipEventRecord(ctx->ev[3], s));

@@ -105,3 +105,26 @@ def test_many_orbitals_sternheimer_per_column_shifts(n_e):
     assert err <= 1e-10
     assert ctx.stats()["max_rel_residual"] <= 2e-12
     ctx.close()
+
+
+def test_many_orbitals_learned_fallback():
+    """The learned form above 256 orbitals with a network that returns 0: every
+    column breaks down at once and is finished by the FP64 per-system CG of the
+    many-orbital form from its recomputed residual."""
+    m, V, H, phi, eps, G, om, solver = _system(300)
+    rng = np.random.default_rng(12)
+    B = OA.project_q(phi, rng.standard_normal((m.grid.n_grid, 20)))
+    sh = rng.uniform(eps[0], eps[-1], 20)
+    ctx = _ctx(300, tol=1e-10)
+    ctx.precond_init(3)
+    ctx.precond_set(np.zeros(ctx.precond_n_params(), dtype=np.float32))
+    ctx.set_opts(use_learned_precond=1)
+    X, it, _ = ctx.sternheimer(sh, to_dev(B))
+    X = to_host(X)
+    Xref = np.stack([solver(float(sh[j]), B[:, j:j + 1])[:, 0] for j in range(20)], axis=1)
+    err = float(np.abs(X - Xref).max() / np.abs(Xref).max())
+    print(f"[wide] learned fallback: rel err {err:.2e}, iterations {it.min()}-{it.max()}, "
+          f"fallback passes {ctx.stats()['refinements']}", flush=True)
+    assert ctx.stats()["refinements"] >= 1
+    assert err <= 1e-8
+    ctx.close()

@@ -208,3 +208,40 @@ def test_training_and_what_the_network_gains():
     print(f"iterations without / with the network: {gain:.2f}")
     assert gain > 2.0
     ctx.close()
+
+
+@pytest.mark.parametrize("net", ["untrained", "zero"])
+def test_bad_network_falls_back_to_fp64(net):
+    """A network that was never trained (random weights) or one that returns 0:
+    the flexible CG stalls or breaks down (p.Ap = 0) in those columns, which are
+    then finished in FP64 MINRES from their recomputed residual, so the answer
+    is the one of plain CG to the same tolerance."""
+    from oracle import acp as OA, krylov as OK
+    cfg, m, gs, w, v, G, om, K = system(1)
+    dec = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
+    nodes, _ = OA.shifts_and_weights(gs.eps[:gs.n_e], cfg.n_cheb)
+    R0 = OA.rhs(gs.phi, dec.xi)
+    cols = np.arange(0, 12)
+    B = np.concatenate([R0[:, cols]] * len(nodes), axis=1)
+    sh = np.repeat(nodes, len(cols))
+    op = OK.make_operator(m, gs.veff, gs.phi, sh)
+    ctx = make_ctx(1, tol=1e-8, max_iter=5000)
+    ctx.precond_init(99)
+    if net == "zero":
+        ctx.precond_set(np.zeros(ctx.precond_n_params(), dtype=np.float32))
+    ctx.set_opts(use_learned_precond=2)
+    X2, it2, _ = ctx.sternheimer(sh, to_dev(B))
+    ctx.set_opts(use_learned_precond=1)
+    ctx.reset_stats()
+    X1, it1, st = ctx.sternheimer(sh, to_dev(B))
+    fell_back = ctx.stats()["refinements"]
+    X1, X2 = to_host(X1), to_host(X2)
+    tr = OK.true_residual(op, X1, B).max()
+    diff = float(np.abs(X1 - X2).max() / np.abs(X2).max())
+    print(f"[fallback] {net} network: iterations {it1.min()}-{it1.max()} (plain CG {it2.min()}-{it2.max()}), "
+          f"fallback passes {fell_back}, true residual {tr:.2e}, vs plain CG {diff:.2e}", flush=True)
+    assert tr <= 1e-8
+    assert diff <= 1e-6
+    if net == "zero":
+        assert fell_back >= 1
+    ctx.close()
