@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libacp.so")
 ARCH = os.environ.get("ACP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["acp_api.cpp", "ground_state.cpp", "k_util.hip", "k_gemm.hip", "k_krylov.hip", "k_mscg.hip", "k_dense.hip",
-           "k_nn.hip", "k_eig.hip", "k_wide.hip", "k_isdf_panel.hip", "k_dfpt.hip", "k_gemm_bf16.hip"]
+           "k_nn.hip", "k_eig.hip", "k_wide.hip", "k_isdf_panel.hip", "k_dfpt.hip", "k_gemm_bf16.hip", "k_fcg.hip"]
 
 # Packed FP32 instructions are disabled for all device code (see the design notes).
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -86,6 +86,7 @@ struct acp_ctx {
     size_t pin_bytes = 0;
     DevBuf nn_wf[4], nn_wb[4], nn_act[4], nn_g[4];
     DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc, fc_idx;   // flexible CG
+    int *fc_pin = nullptr;                          // its open-column counts (pinned host, 2 ints)
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
     DevBuf wd_p, wd_r, wd_w, wd_c, wd_sc, wd_sig;   // multi-shift CG with GEMM projector (many orbitals)
@@ -463,6 +464,7 @@ acp_status ms_run_phased(acp_ctx *ctx, MsArgsT<T> a, int K0, int SG0, const std:
     if (ctx->pin_bytes < pin_need) {
         HIPCHK(hipStreamSynchronize(s));   // no copy of an earlier solve still reads it
         if (ctx->pin) (void)hipHostFree(ctx->pin);
+    if (ctx->fc_pin) (void)hipHostFree(ctx->fc_pin);
         ctx->pin = nullptr;
         ctx->pin_bytes = 0;
         HIPCHK(hipHostMalloc(&ctx->pin, pin_need, hipHostMallocDefault));
@@ -1376,6 +1378,17 @@ acp_status nn_run_forward(acp_ctx *ctx, const double *shift, int n, const double
     return ACP_OK;
 }
 
+// The same forward pass with the normalised shifts already on the device (no
+// host work, no synchronisation).
+acp_status nn_run_forward_dev(acp_ctx *ctx, const double *shat_dev, int n, const double *R, int ldr) {
+    if (!ctx->nn_ready) return fail(ctx, ACP_ESTATE, "no preconditioner weights (init or set first)");
+    CHECK(nn_batch(ctx, n));
+    NnBuffers b = nn_buffers(ctx);
+    HIPCHK(nn_features(ctx->ng, n, R, ldr, shat_dev, b.act[0], dp<double>(ctx->nn_rms), ctx->stream));
+    HIPCHK(nn_forward(ctx->gd.dim, nn_shape(ctx), n, b, ctx->stream));
+    return ACP_OK;
+}
+
 // D = Q (N(R) rms(R)) for n columns, in chunks of the activation capacity.
 constexpr int kNnChunk = 1024;
 acp_status nn_apply(acp_ctx *ctx, const double *shift, int n, const double *R, int ldr, double *D,
@@ -1393,6 +1406,25 @@ acp_status nn_apply(acp_ctx *ctx, const double *shift, int n, const double *R, i
     double *C = dp<double>(ctx->c1);
     CHECK(phi_t_times(ctx, n, D, ldd, C));
     HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, D, ldd, 0, 1, s));
+    return ACP_OK;
+}
+
+// nn_apply with the normalised shifts on the device (shat_dev, n entries).
+acp_status nn_apply_dev(acp_ctx *ctx, const double *shat_dev, int n, const double *R, int ldr, double *D, int ldd) {
+    const int ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    for (int j0 = 0; j0 < n; j0 += kNnChunk) {
+        const int m = std::min(kNnChunk, n - j0);
+        CHECK(nn_run_forward_dev(ctx, shat_dev + j0, m, R + (size_t)j0 * ldr, ldr));
+        HIPCHK(nn_scale_out(ng, m, dp<float>(ctx->nn_out), dp<double>(ctx->nn_rms), D + (size_t)j0 * ldd,
+                            ldd, s));
+    }
+    ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+    ENSURE(ctx->splitk, (size_t)kSplitSlices * ctx->ne * n * 8);
+    double *C = dp<double>(ctx->c1);
+    CHECK(phi_t_times_ws(ctx, n, D, ldd, C, dp<double>(ctx->splitk)));
+    HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, dp<double>(ctx->phi_cm), ng, 0, C, ctx->ne, 0, 1.0, D, ldd, 0,
+                1, s));
     return ACP_OK;
 }
 
@@ -1424,128 +1456,133 @@ acp_status fcg_solve(acp_ctx *ctx, int n, const double *shift_h, const double *s
     ENSURE(ctx->fc_z, bytes);
     ENSURE(ctx->fc_p, bytes);
     ENSURE(ctx->fc_q, bytes);
-    ENSURE(ctx->fc_sc, (size_t)4 * n * 8);
-    ENSURE(ctx->fc_idx, (size_t)2 * n * 4);
+    ENSURE(ctx->fc_sc, (size_t)15 * n * 8);
+    ENSURE(ctx->fc_idx, ((size_t)6 * n + 2) * 4);
+    if (!ctx->fc_pin) HIPCHK(hipHostMalloc((void **)&ctx->fc_pin, 2 * sizeof(int)));
     double *R = dp<double>(ctx->fc_r), *Z = dp<double>(ctx->fc_z), *P = dp<double>(ctx->fc_p),
            *Q = dp<double>(ctx->fc_q);
-    double *d_a = dp<double>(ctx->fc_sc), *d_b = d_a + n, *d_t = d_b + n, *d_sh = d_t + n;
-    int *d_cols = dp<int>(ctx->fc_idx), *d_ord = d_cols + n;
+    // per-column device scalars (compact order unless noted)
+    double *sc = dp<double>(ctx->fc_sc);
+    double *d_a = sc, *d_b = sc + n, *d_t = sc + 2 * (size_t)n, *d_sh = sc + 3 * (size_t)n,
+           *d_shat = sc + 4 * (size_t)n, *d_rz = sc + 5 * (size_t)n, *d_bn2 = sc + 6 * (size_t)n,
+           *d_sref = sc + 7 * (size_t)n, *d_pq = sc + 8 * (size_t)n, *d_rr = sc + 9 * (size_t)n,
+           *d_zq = sc + 10 * (size_t)n, *d_rzn = sc + 11 * (size_t)n, *d_al = sc + 12 * (size_t)n,
+           *d_nal = sc + 13 * (size_t)n, *d_be = sc + 14 * (size_t)n;
+    int *ib = dp<int>(ctx->fc_idx);
+    int *d_cols = ib, *d_ord = ib + n, *d_act = ib + 2 * (size_t)n, *d_done = ib + 3 * (size_t)n,
+        *d_iters = ib + 4 * (size_t)n, *d_sit = ib + 5 * (size_t)n, *d_flags = ib + 6 * (size_t)n,
+        *d_nopen = d_flags + 1;
     // The open systems occupy the first w columns of R, Z, P, Q (compact index i
     // is system cols[i]); X stays in system order.  When fewer than 3/4 of the w
     // columns are still open, the open ones are gathered to the front, so the
-    // network and the operator are applied to open systems only.
+    // network and the operator are applied to open systems only.  Every scalar
+    // step runs on the device; the host reads the count of open columns one
+    // iteration late (the next iteration is already queued) and synchronises
+    // only to compact.
     int w = n;
     std::vector<int> cols(n);
-    std::vector<double> shc(shift_h, shift_h + n);
+    std::vector<double> shc(shift_h, shift_h + n), bn2(n);
     for (int j = 0; j < n; ++j) cols[j] = j;
+    auto upload_columns = [&]() -> acp_status {
+        ctx->nn_shat_host = nn_shift_hat(ctx, shc.data(), w);
+        HIPCHK(hipMemcpyAsync(d_cols, cols.data(), (size_t)w * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_sh, shc.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_shat, ctx->nn_shat_host.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+        return ACP_OK;
+    };
     auto precond = [&](const double *Rin, double *Zout) -> acp_status {
-        if (mode == 1) return nn_apply(ctx, shc.data(), w, Rin, ng, Zout, ng);
+        if (mode == 1) return nn_apply_dev(ctx, d_shat, w, Rin, ng, Zout, ng);
         HIPCHK(hipMemcpyAsync(Zout, Rin, (size_t)ng * w * 8, hipMemcpyDeviceToDevice, s));
         return ACP_OK;
     };
-    auto col = [&](hipError_t (*fn)(int, int, const double *, int, const double *, int, double *, hipStream_t),
-                   const double *A1, const double *A2, std::vector<double> &h) -> acp_status {
-        HIPCHK(fn(ng, w, A1, ng, A2, ng, d_t, s));
-        HIPCHK(hipMemcpyAsync(h.data(), d_t, (size_t)w * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return ACP_OK;
-    };
-    // host vectors handed to asynchronous copies are never modified before the
-    // next stream synchronisation
-    std::vector<double> bn(n), rz(n), pq(n), rr(n), zq(n), rzn(n), al(n), nal(n), be(n);
     HIPCHK(hipMemsetAsync(X, 0, bytes, s));
     HIPCHK(hipMemcpyAsync(R, B, bytes, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_cols, cols.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_sh, shc.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
-    CHECK(col(launch_col_dot, B, B, bn));
-    std::vector<int> act(n), done(n, 0), stall_it(n, 0);   // done: converged (system order)
-    std::vector<double> stall_ref(n);
-    for (int j = 0; j < n; ++j) {
-        bn[j] = std::sqrt(bn[j]);
-        act[j] = bn[j] > 0.0;
-        done[j] = !act[j];
-        iters[j] = 0;
-        stall_ref[j] = bn[j];
-    }
+    CHECK(upload_columns());
+    HIPCHK(launch_col_dot(ng, n, B, ng, B, ng, d_bn2, s));
+    HIPCHK(fcg_init(n, d_bn2, d_act, d_done, d_iters, d_sref, d_sit, s));
+    HIPCHK(launch_fill_i32(d_flags, 1, 0, s));
+    HIPCHK(hipMemcpyAsync(bn2.data(), d_bn2, (size_t)n * 8, hipMemcpyDeviceToHost, s));
     CHECK(precond(R, Z));
     HIPCHK(hipMemcpyAsync(P, Z, bytes, hipMemcpyDeviceToDevice, s));
-    CHECK(col(launch_col_dot, R, Z, rz));
-    std::vector<int> ord;
-    for (int k = 0; k < ctx->opts.max_iter; ++k) {
-        int open = 0;
-        for (int i = 0; i < w; ++i) open += act[i];
-        if (!open) break;
-        if (4 * open < 3 * w && w > kTile) {
-            // gather the open columns of R and P to the front (through Q)
+    HIPCHK(launch_col_dot(ng, n, R, ng, Z, ng, d_rz, s));
+    HIPCHK(hipStreamSynchronize(s));   // bn2 and the shift upload's host source
+    int open_known = 0;
+    for (int j = 0; j < n; ++j) open_known += bn2[j] > 0.0;
+    std::vector<int> ord, act_h;
+    std::vector<double> rz_h, sref_h;
+    std::vector<int> sit_h;
+    for (int k = 0; k < ctx->opts.max_iter && open_known > 0; ++k) {
+        if (4 * open_known < 3 * w && w > kTile) {
+            // gather the open columns of R and P (through Q) and their scalars
+            HIPCHK(hipStreamSynchronize(s));
+            act_h.resize(w);
+            rz_h.resize(w);
+            sref_h.resize(w);
+            sit_h.resize(w);
+            HIPCHK(hipMemcpy(act_h.data(), d_act, (size_t)w * 4, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(rz_h.data(), d_rz, (size_t)w * 8, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(sref_h.data(), d_sref, (size_t)w * 8, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(sit_h.data(), d_sit, (size_t)w * 4, hipMemcpyDeviceToHost));
             ord.clear();
             for (int i = 0; i < w; ++i)
-                if (act[i]) ord.push_back(i);
+                if (act_h[i]) ord.push_back(i);
+            const int open = (int)ord.size();
+            if (open == 0) break;
             HIPCHK(hipMemcpyAsync(d_ord, ord.data(), (size_t)open * 4, hipMemcpyHostToDevice, s));
             HIPCHK(launch_col_gather(ng, open, R, ng, d_ord, Q, ng, s));
             HIPCHK(hipMemcpyAsync(R, Q, (size_t)ng * open * 8, hipMemcpyDeviceToDevice, s));
             HIPCHK(launch_col_gather(ng, open, P, ng, d_ord, Q, ng, s));
             HIPCHK(hipMemcpyAsync(P, Q, (size_t)ng * open * 8, hipMemcpyDeviceToDevice, s));
+            std::vector<double> rz2(open), bn22(open), sref2(open);
+            std::vector<int> sit2(open), ones(open, 1);
             for (int i = 0; i < open; ++i) {
                 const int o = ord[i];
                 cols[i] = cols[o];
-                bn[i] = bn[o];
-                rz[i] = rz[o];
                 shc[i] = shc[o];
-                stall_ref[i] = stall_ref[o];
-                stall_it[i] = stall_it[o];
-                act[i] = 1;
+                bn2[i] = bn2[o];
+                rz2[i] = rz_h[o];
+                sref2[i] = sref_h[o];
+                sit2[i] = sit_h[o];
             }
             w = open;
-            HIPCHK(hipMemcpyAsync(d_cols, cols.data(), (size_t)w * 4, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_sh, shc.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
-            HIPCHK(hipStreamSynchronize(s));   // ord, cols, shc reused below
+            CHECK(upload_columns());
+            HIPCHK(hipMemcpyAsync(d_rz, rz2.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_bn2, bn2.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_sref, sref2.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_sit, sit2.data(), (size_t)w * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_act, ones.data(), (size_t)w * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));   // ord, cols, shc and the locals above reused
+            open_known = open;
         }
         CHECK(apply_operator(ctx, w, d_sh, P, Q));
-        CHECK(col(launch_col_dot, P, Q, pq));
-        for (int i = 0; i < w; ++i) {
-            al[i] = 0.0;
-            if (!act[i]) continue;
-            if (!(pq[i] > 0.0)) {
-                if (mode != 1) *flags_or |= 2;   // with the network: handed to the FP64 solver
-                act[i] = 0;
-                continue;
-            }
-            al[i] = rz[i] / pq[i];
+        HIPCHK(launch_col_dot(ng, w, P, ng, Q, ng, d_pq, s));
+        HIPCHK(fcg_alpha(w, d_pq, d_rz, d_act, d_al, d_nal, mode, d_flags, s));
+        HIPCHK(launch_col_axpy_scatter(ng, w, d_al, P, ng, d_cols, X, ng, s));   // x += alpha p
+        HIPCHK(launch_col_axpby(ng, w, d_nal, Q, ng, nullptr, R, ng, s));        // r -= alpha Ap
+        HIPCHK(launch_col_dot(ng, w, R, ng, R, ng, d_rr, s));
+        HIPCHK(launch_fill_i32(d_nopen, 1, 0, s));
+        HIPCHK(fcg_conv(w, k, d_rr, d_bn2, ctx->opts.tol, d_act, d_done, d_cols, d_iters, d_sref, d_sit, mode,
+                        kFcgStall, d_nopen, s));
+        HIPCHK(hipMemcpyAsync(ctx->fc_pin + (k & 1), d_nopen, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ctx->ev[8 + (k & 1)], s));
+        if (k > 0) {   // the previous iteration's count; this one is queued behind it
+            HIPCHK(hipEventSynchronize(ctx->ev[8 + ((k - 1) & 1)]));
+            open_known = ctx->fc_pin[(k - 1) & 1];
+            if (open_known == 0) break;   // iteration k changed nothing
         }
-        for (int i = 0; i < w; ++i) nal[i] = -al[i];
-        HIPCHK(hipMemcpyAsync(d_a, al.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d_b, nal.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_col_axpy_scatter(ng, w, d_a, P, ng, d_cols, X, ng, s));   // x += alpha p
-        HIPCHK(launch_col_axpby(ng, w, d_b, Q, ng, nullptr, R, ng, s));          // r -= alpha Ap
-        CHECK(col(launch_col_dot, R, R, rr));
-        for (int i = 0; i < w; ++i)
-            if (act[i]) {
-                iters[cols[i]] += 1;
-                const double rn = std::sqrt(rr[i]);
-                if (rn <= ctx->opts.tol * bn[i]) {
-                    act[i] = 0;
-                    done[cols[i]] = 1;
-                } else if (rn <= 0.5 * stall_ref[i]) {
-                    stall_ref[i] = rn;
-                    stall_it[i] = k;
-                } else if (mode == 1 && k - stall_it[i] >= kFcgStall) {
-                    act[i] = 0;   // stagnated: handed to the FP64 solver
-                }
-            }
-        open = 0;
-        for (int i = 0; i < w; ++i) open += act[i];
-        if (!open) break;
         CHECK(precond(R, Z));
-        CHECK(col(launch_col_dot, Z, Q, zq));
-        CHECK(col(launch_col_dot, R, Z, rzn));
-        for (int i = 0; i < w; ++i) {
-            // beta = -alpha z'.Ap / r.z  (= -z'.Ap / p.Ap)
-            be[i] = (act[i] && rz[i] != 0.0) ? -al[i] * zq[i] / rz[i] : 0.0;
-            rz[i] = rzn[i];
-        }
-        HIPCHK(hipMemcpyAsync(d_t, be.data(), (size_t)w * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_col_axpby(ng, w, nullptr, Z, ng, d_t, P, ng, s));   // p = z + beta p
+        HIPCHK(launch_col_dot(ng, w, Z, ng, Q, ng, d_zq, s));
+        HIPCHK(launch_col_dot(ng, w, R, ng, Z, ng, d_rzn, s));
+        HIPCHK(fcg_beta(w, d_act, d_al, d_zq, d_rzn, d_rz, d_be, s));
+        HIPCHK(launch_col_axpby(ng, w, nullptr, Z, ng, d_be, P, ng, s));   // p = z + beta p
     }
+    std::vector<int> done(n);
+    int fl = 0;
+    HIPCHK(hipMemcpyAsync(done.data(), d_done, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(iters, d_iters, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&fl, d_flags, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *flags_or |= fl;
     int open = 0;
     for (int j = 0; j < n; ++j) open += !done[j];
     if (open && mode == 1) {
@@ -3126,6 +3163,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->df_du, &ctx->df_dr, &ctx->df_pu, &ctx->df_pr, &ctx->df_dot};
     for (DevBuf *b : bufs) release(*b);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
+    if (ctx->fc_pin) (void)hipHostFree(ctx->fc_pin);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;

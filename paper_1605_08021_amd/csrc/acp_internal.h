@@ -232,6 +232,19 @@ hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double
 hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
                       long long xs, const WideScalars &w, hipStream_t s);
 
+// ---------------------------------------------------------------- flexible CG scalars (k_fcg.hip)
+// Columns in compact order i (system cols[i]); done, iters in system order;
+// squared norms throughout (bn2 = |b|^2, sref = |r|^2 at the last halving).
+hipError_t fcg_init(int n, const double *bn2, int *act, int *done, int *iters, double *sref, int *sit,
+                    hipStream_t s);
+hipError_t fcg_alpha(int w, const double *pq, const double *rz, int *act, double *al, double *nal, int mode,
+                     int *flags, hipStream_t s);
+hipError_t fcg_conv(int w, int k, const double *rr, const double *bn2, double tol, int *act, int *done,
+                    const int *cols, int *iters, double *sref, int *sit, int mode, int kstall, int *nopen,
+                    hipStream_t s);
+hipError_t fcg_beta(int w, const int *act, const double *al, const double *zq, const double *rzn, double *rz,
+                    double *be, hipStream_t s);
+
 // ---------------------------------------------------------------- BF16 projector (k_gemm_bf16.hip)
 // bf16 of x: FP64 -> FP32 (nearest), then nearest-even to 8 significant bits.
 // Splitting needs no exact rounding: x - bf16(x) is exact in FP64, and the next
