@@ -314,6 +314,16 @@ acp_status acp_precond_apply(acp_ctx *ctx, const double *shift, int n, const dou
 acp_status acp_precond_train_step(acp_ctx *ctx, const double *shift, int n, const double *R,
                                   const double *E, double lr, double *loss, float *grad);
 
+/* Training pairs along the preconditioned iteration's own trajectory: for the
+ * systems Q(H - s_j)Q x = B(:, j) (shift host n, B dev N_g x n in range(Q)) with
+ * reference solutions Xstar (dev N_g x n), `steps` steps of steepest descent
+ * with the current network from x = 0: d = Q N(r) rms(r), alpha = r.d / d.A d
+ * (0 where d.A d <= 0), x += alpha d, r -= alpha A d; before step k,
+ * R(:, k n + j) = r_j and E(:, k n + j) = Xstar(:, j) - x_j (dev N_g x steps n
+ * each).  n <= 1024. */
+acp_status acp_precond_trajectory(acp_ctx *ctx, const double *shift, int n, const double *B,
+                                  const double *Xstar, int steps, double *R, double *E);
+
 /* ---- Ragged batch: many systems' shifted solves in one persistent launch ----
  * A batch groups contexts of the same dimension (each set up for its own
  * system: grid, orbitals, V_eff, options with the FP64 multi-shift CG).

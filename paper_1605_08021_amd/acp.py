@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_precond_forward": (I, [P, P, I, P, P]),
         "acp_precond_apply": (I, [P, P, I, P, P]),
         "acp_precond_train_step": (I, [P, P, I, P, P, C.c_double, P, P]),
+        "acp_precond_trajectory": (I, [P, P, I, P, P, I, P, P]),
         "acp_batch_create": (I, [C.POINTER(P), P, I, I]),
         "acp_batch_compress": (I, [P, P, P, P, P]),
         "acp_batch_info": (I, [P, C.POINTER(AcpBatchInfo)]),
@@ -490,6 +491,18 @@ class Context:
         D = self._empty(*R.shape)
         self._check(self.lib.acp_precond_apply(self._ctx, _hptr(sh), R.shape[1], _dptr(R), _dptr(D)))
         return D
+
+    def precond_trajectory(self, shifts, B, Xstar, steps: int):
+        """(R, E): residuals and errors along `steps` steps of steepest descent
+        with the current network (N_g x steps n each, step-major)."""
+        B, Xstar = colmajor(B), colmajor(Xstar)
+        sh = _hostd(shifts)
+        n = B.shape[1]
+        R = self._empty(B.shape[0], steps * n)
+        E = self._empty(B.shape[0], steps * n)
+        self._check(self.lib.acp_precond_trajectory(self._ctx, _hptr(sh), n, _dptr(B), _dptr(Xstar), steps,
+                                                    _dptr(R), _dptr(E)))
+        return R, E
 
     def precond_train_step(self, shifts, R, E, lr: float, want_grad: bool = False):
         R, E = colmajor(R), colmajor(E)

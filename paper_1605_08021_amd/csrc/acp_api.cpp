@@ -2597,6 +2597,46 @@ acp_status acp_precond_apply(acp_ctx *ctx, const double *shift, int n, const dou
     return ACP_OK;
 }
 
+acp_status acp_precond_trajectory(acp_ctx *ctx, const double *shift, int n, const double *B,
+                                  const double *Xstar, int steps, double *R, double *E) {
+    if (!ctx || !shift || !B || !Xstar || !R || !E || n < 1 || steps < 1) return ACP_EINVAL;
+    if (n > kNnChunk) return fail(ctx, ACP_EINVAL, "trajectory batch larger than 1024");
+    const int ng = ctx->ng;
+    hipStream_t s = ctx->stream;
+    const size_t bytes = (size_t)ng * n * 8;
+    ENSURE(ctx->fc_r, bytes);
+    ENSURE(ctx->fc_z, bytes);
+    ENSURE(ctx->fc_p, bytes);
+    ENSURE(ctx->fc_q, bytes);
+    ENSURE(ctx->fc_sc, (size_t)5 * n * 8);
+    ENSURE(ctx->fc_idx, ((size_t)n + 1) * 4);
+    ENSURE(ctx->shifts_dev, (size_t)n * 8);
+    double *r = dp<double>(ctx->fc_r), *x = dp<double>(ctx->fc_z), *D = dp<double>(ctx->fc_p),
+           *AD = dp<double>(ctx->fc_q);
+    double *sc = dp<double>(ctx->fc_sc);
+    double *rd = sc, *dad = sc + n, *al = sc + 2 * (size_t)n, *nal = sc + 3 * (size_t)n;
+    int *act = dp<int>(ctx->fc_idx), *flags = act + n;
+    HIPCHK(hipMemcpyAsync(ctx->shifts_dev.p, shift, (size_t)n * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(x, 0, bytes, s));
+    HIPCHK(hipMemcpyAsync(r, B, bytes, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < steps; ++k) {
+        double *Rk = R + (size_t)k * n * ng, *Ek = E + (size_t)k * n * ng;
+        HIPCHK(hipMemcpyAsync(Rk, r, bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(Ek, Xstar, bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(launch_axpby(ng, n, -1.0, x, ng, 1.0, Ek, ng, s));
+        CHECK(nn_apply(ctx, shift, n, r, ng, D, ng));
+        CHECK(apply_operator(ctx, n, dp<double>(ctx->shifts_dev), D, AD));
+        HIPCHK(launch_col_dot(ng, n, r, ng, D, ng, rd, s));
+        HIPCHK(launch_col_dot(ng, n, D, ng, AD, ng, dad, s));
+        HIPCHK(launch_fill_i32(act, n, 1, s));
+        HIPCHK(fcg_alpha(n, dad, rd, act, al, nal, 1, flags, s));
+        HIPCHK(launch_col_axpby(ng, n, al, D, ng, nullptr, x, ng, s));    // x += alpha d
+        HIPCHK(launch_col_axpby(ng, n, nal, AD, ng, nullptr, r, ng, s));  // r -= alpha A d
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return ACP_OK;
+}
+
 acp_status acp_precond_train_step(acp_ctx *ctx, const double *shift, int n, const double *R,
                                   const double *E, double lr, double *loss, float *grad) {
     if (!ctx || !shift || !R || !E || n < 1 || !(lr >= 0.0)) return ACP_EINVAL;

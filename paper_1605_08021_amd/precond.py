@@ -8,9 +8,8 @@ r_k = b - A x_k and errors e_k = x* - x_k, with x* solved to a tight tolerance.
 A network trained only on those sees different residuals once it drives the
 iteration itself (they carry its own error patterns), so training continues on
 pairs harvested along the preconditioned iteration's own trajectories
-(steepest descent with the current network), a few rounds.  The small vector
-updates of that harvest (x += alpha d) are plain tensor arithmetic on the
-caller's side: training-data preparation, not part of the solver.
+(steepest descent with the current network, run by the library), a few
+rounds.  Torch here only slices and concatenates device arrays.
 """
 from __future__ import annotations
 
@@ -57,20 +56,22 @@ def train(ctx, R, E, shifts, steps=300, batch=64, lr=2e-3, seed=0, log_every=0):
 
 def harvest_trajectory(ctx, shifts, B, xstar, steps=6):
     """Pairs (r_k, x* - x_k) along preconditioned steepest descent with the
-    current network: d = M(r), alpha = r.d / d.Ad, x += alpha d."""
+    current network (d = M(r), alpha = r.d / d.Ad, x += alpha d), computed by the
+    library (acp_precond_trajectory) in batches of at most 1024 systems."""
     import torch
-    x = torch.zeros_like(B)
-    r = B.clone()
-    Rs, Es = [], []
-    for _ in range(steps):
-        Rs.append(r.clone())
-        Es.append(xstar - x)
-        d = ctx.precond_apply(shifts, r)
-        Ad = ctx.residual(shifts, torch.zeros_like(d), d).neg_()
-        alpha = (r * d).sum(0) / (d * Ad).sum(0)
-        x = x + alpha * d
-        r = r - alpha * Ad
-    return torch.cat(Rs, dim=1), torch.cat(Es, dim=1), np.concatenate([np.asarray(shifts)] * steps)
+    shifts = np.asarray(shifts, dtype=np.float64)
+    n = B.shape[1]
+    Rs, Es = [[] for _ in range(steps)], [[] for _ in range(steps)]
+    for j0 in range(0, n, 1024):
+        j1 = min(n, j0 + 1024)
+        R, E = ctx.precond_trajectory(shifts[j0:j1], B[:, j0:j1], xstar[:, j0:j1], steps)
+        m = j1 - j0
+        for k in range(steps):
+            Rs[k].append(R[:, k * m:(k + 1) * m])
+            Es[k].append(E[:, k * m:(k + 1) * m])
+    R = torch.cat([t for k in range(steps) for t in Rs[k]], dim=1)
+    E = torch.cat([t for k in range(steps) for t in Es[k]], dim=1)
+    return R, E, np.concatenate([shifts] * steps)
 
 
 def solve_star(ctx, shifts, B, tol_star=1e-11):

@@ -245,3 +245,35 @@ def test_bad_network_falls_back_to_fp64(net):
     if net == "zero":
         assert fell_back >= 1
     ctx.close()
+
+
+def test_trajectory_matches_reference():
+    """acp_precond_trajectory (steepest descent with the network, in the library)
+    against the same three steps written here with the library's network and
+    operator and the vector arithmetic in torch."""
+    import torch
+    from oracle import acp as OA
+    cfg, m, gs, w, v, G, om, K = system(1)
+    dec = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
+    nodes, _ = OA.shifts_and_weights(gs.eps[:gs.n_e], cfg.n_cheb)
+    B = np.concatenate([OA.rhs(gs.phi, dec.xi)[:, :6]] * 2, axis=1)
+    sh = np.repeat(nodes[:2], 6)
+    ctx = make_ctx(1, tol=1e-11, max_iter=5000)
+    ctx.precond_init(7)
+    Bd = to_dev(B)
+    xstar, _, _ = ctx.sternheimer(sh, Bd)
+    R, E = ctx.precond_trajectory(sh, Bd, xstar, 3)
+    x = torch.zeros_like(Bd)
+    r = Bd.clone()
+    n = B.shape[1]
+    for k in range(3):
+        er = float((R[:, k * n:(k + 1) * n] - r).abs().max() / r.abs().max())
+        ee = float((E[:, k * n:(k + 1) * n] - (xstar - x)).abs().max() / xstar.abs().max())
+        print(f"[trajectory] step {k}: R {er:.2e} E {ee:.2e}", flush=True)
+        assert er <= 1e-12 and ee <= 1e-12
+        d = ctx.precond_apply(sh, r)
+        Ad = ctx.residual(sh, torch.zeros_like(d), d).neg_()
+        alpha = (r * d).sum(0) / (d * Ad).sum(0)
+        x = x + alpha * d
+        r = r - alpha * Ad
+    ctx.close()
