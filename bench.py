@@ -24,10 +24,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
                        [--form auto|fast|bf16|mixed|learned|single|plain|batch|compress|dfpt]
                        [--no-cpu-baseline] [--no-fp64-compare] [--calibrate-copy]
 
---form batch: the uneven batch instead (a ragged set of 1D chains whose shifted
-solves share one persistent launch, replayed from a hipGraph); one step = one
-compression of every system; the same systems compressed one at a time are
-timed beside it.
+--form batch: the uneven batch instead (16 ragged 1D chains and 16 ragged 2D
+lattices with 5% vacancies; the shifted solves of each half share one
+persistent launch, replayed from a hipGraph); one step = one compression of
+every system; the same systems compressed one at a time are timed beside it.
 """
 from __future__ import annotations
 
@@ -153,7 +153,8 @@ def main():
                     default="auto", help="auto: bf16 above 256 orbitals, else fast")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="bf16 form: skip the FP64-form step timed beside it")
-    ap.add_argument("--batch-systems", type=int, default=16)
+    ap.add_argument("--batch-systems", type=int, default=16, help="systems per dimension (--form batch)")
+    ap.add_argument("--batch-dims", default="1,2", help="--form batch: 1, 2 or 1,2 (the 1D and 2D halves)")
     ap.add_argument("--dyson-iters", type=int, default=0, help="k_max (0: 1 for workload 5, else 4)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -417,13 +418,15 @@ def main():
 
 def run_batch(args):
     """Uneven batch: every system's compression (point selection, right-hand sides,
-    all shifted solves, W), the solves of all systems in one persistent launch
-    replayed from a hipGraph; then the same systems one at a time."""
+    all shifted solves, W), the solves of all systems of one dimension in one
+    persistent launch replayed from a hipGraph (the 1D chains and the 2D
+    lattices are two batches: the fused kernel is specialised by stencil form);
+    then the same systems one at a time."""
     import numpy as np
     import torch
     from paper_1605_08021_amd import acp
     from paper_1605_08021_amd.workload_model import build_inputs
-    from workload.seeds import ragged_batch_configs
+    from workload.seeds import ragged_batch_configs, ragged_batch_configs_2d
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -434,21 +437,28 @@ def run_batch(args):
             return torch.from_numpy(np.ascontiguousarray(a.T)).to(dev).t()
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
-    cfgs = ragged_batch_configs(count=args.batch_systems, lo=16, hi=128)
+    dims = [int(d) for d in args.batch_dims.split(",")]
+    halves = []   # per dimension: contexts, G, omega, sizes, batch
     t0 = time.perf_counter()
-    ctxs, Gs, oms, sizes = [], [], [], []
-    for cfg in cfgs:
-        inp = build_inputs(cfg)
-        ctxs.append(acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0,
-                                     occ=cfg.f),
-                                dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol,
-                                     max_iter=20000, solver=acp.SOLVER_CG),
-                                T(inp.phi), inp.eps[: inp.n_e], T(inp.veff)))
-        Gs.append(T(inp.G))
-        oms.append(T(inp.omega))
-        sizes.append((int(inp.phi.shape[0]), int(inp.n_e), cfg.n_mu))
-    log(f"{len(cfgs)} systems ready in {time.perf_counter() - t0:.1f} s: (N_g, N_e, N_mu) = {sizes}")
-    batch = acp.Batch(ctxs, use_graph=True)
+    for dim in dims:
+        cfgs = (ragged_batch_configs(count=args.batch_systems, lo=16, hi=128) if dim == 1 else
+                ragged_batch_configs_2d(count=args.batch_systems, lo=4, hi=12))
+        ctxs, Gs, oms, sizes = [], [], [], []
+        for cfg in cfgs:
+            inp = build_inputs(cfg)
+            ctxs.append(acp.Context(dict(dim=cfg.dim, n=cfg.n, h=cfg.h, kappa=cfg.kappa, eps0=cfg.eps0,
+                                         occ=cfg.f),
+                                    dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r, tol=args.tol,
+                                         max_iter=20000, solver=acp.SOLVER_CG),
+                                    T(inp.phi), inp.eps[: inp.n_e], T(inp.veff)))
+            Gs.append(T(inp.G))
+            oms.append(T(inp.omega))
+            sizes.append((int(inp.phi.shape[0]), int(inp.n_e), cfg.n_mu))
+        log(f"{dim}D half: {len(cfgs)} systems ready ({time.perf_counter() - t0:.1f} s): "
+            f"(N_g, N_e, N_mu) = {sizes}")
+        halves.append((dim, ctxs, Gs, oms, sizes, acp.Batch(ctxs, use_graph=True)))
+    ctxs = [c for h in halves for c in h[1]]
+    sizes = [z for h in halves for z in h[4]]
 
     def timed(fn, steps):
         for c in ctxs:
@@ -461,11 +471,13 @@ def run_batch(args):
         return (time.perf_counter() - t) / steps
 
     def batched():
-        batch.compress(Gs, oms)
+        for _, _, Gs, oms, _, batch in halves:
+            batch.compress(Gs, oms)
 
     def one_by_one():
-        for c, g, o in zip(ctxs, Gs, oms):
-            c.compress(g, o)
+        for _, cs, Gs, oms, _, _ in halves:
+            for c, g, o in zip(cs, Gs, oms):
+                c.compress(g, o)
 
     for i in range(max(args.warmup, 1)):
         log(f"warmup {i + 1}: batched and one at a time")
@@ -474,14 +486,16 @@ def run_batch(args):
     t_seq = timed(one_by_one, args.steps)
     t_bat = timed(batched, args.steps)
     stats = [c.stats() for c in ctxs]
-    info = batch.info()
+    infos = [h[5].info() for h in halves]
     systems = sum(st["systems_solved"] for st in stats) / args.steps
     res = max(st["max_rel_residual"] for st in stats)
     kbytes = sum(st["krylov_bytes"] for st in stats) / args.steps
     kflops = sum(st["krylov_flops"] for st in stats) / args.steps
-    ms_launch = info["ms_last"]
+    ms_launch = sum(info["ms_last"] for info in infos)   # one launch per half and step
     achieved = kbytes / (ms_launch * 1e-3) / 1e9
-    log(f"batch info: {json.dumps(info)}")
+    log(f"batch info: {json.dumps(infos)}")
+    desc = {1: f"{args.batch_systems} 1D chains of 16-128 sites (40 points per site)",
+            2: f"{args.batch_systems} 2D lattices of 4x4-12x12 sites (12x12 points per site)"}
     out = {
         "metric": "Sternheimer RHS*shifts solved/s at 1e-8 residual",
         "value": round(systems / t_bat, 1),
@@ -495,22 +509,26 @@ def run_batch(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"uneven batch: {len(cfgs)} 1D chains of 16-128 sites (5% vacancies), "
-                               f"40 points per site, N_c=8, N_mu=4 N_e",
-                   "form": "all systems' shifted solves in one persistent multi-shift launch, hipGraph replay",
+        "config": {"workload": "uneven batch: " + " + ".join(desc[d] for d in dims)
+                               + ", 5% vacancies, N_c=8, N_mu=4 N_e",
+                   "form": "the shifted solves of all systems of one dimension in one persistent multi-shift "
+                           "launch (one batch per dimension), hipGraph replay",
                    "systems": [{"n_g": a, "n_e": b, "n_mu": c} for a, b, c in sizes],
                    "tol": args.tol},
         "max_true_rel_residual": res,
         "one_at_a_time": {"value": round(systems / t_seq, 1), "ms_per_step": round(1e3 * t_seq, 2)},
-        "batch": {k: info[k] for k in ("n_tiles", "grid", "order", "tuned", "graph_replays")},
+        "batch": [{"dim": h[0], **{k: info[k] for k in ("n_tiles", "grid", "order", "tuned", "graph_replays",
+                                                        "ms_last")}}
+                  for h, info in zip(halves, infos)],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "mscg_batch_kernel (persistent work queue over the systems' tiles)",
-                     "algorithmic_bytes_per_launch": kbytes,
+                     "algorithmic_bytes_per_launch": kbytes / len(halves),
                      "mfma_fp64_tflops": round(kflops / (ms_launch * 1e-3) / 1e12, 2),
-                     "ms_per_launch": round(ms_launch, 3)},
+                     "ms_per_launch": round(ms_launch / len(halves), 3)},
     }
-    batch.close()
+    for h in halves:
+        h[5].close()
     for c in ctxs:
         c.close()
     print(json.dumps(out), flush=True)

@@ -339,7 +339,9 @@ acp_status acp_precond_trajectory(acp_ctx *ctx, const double *shift, int n, cons
  * must not be used concurrently with it. */
 typedef struct acp_batch acp_batch;
 typedef struct {
-    int n_systems, n_tiles;
+    int n_systems;
+    int n_tiles;              /* work entries: each 16-system tile times the workgroups of its
+                                 group (about one per 640 grid rows of its system, 1-8) */
     int grid, order;          /* chosen launch: workgroups, 0 given order / 1 largest first */
     int tuned;
     long long graph_replays;

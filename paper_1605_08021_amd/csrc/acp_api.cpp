@@ -107,6 +107,7 @@ struct acp_ctx {
 struct acp_batch {
     std::vector<acp_ctx *> sys;
     int dim = 0, ne_pad = 0;
+    bool compact2d = true;            // 2D and every system's grid lines hold a multiple of 4 points
     bool use_graph = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -2165,7 +2166,7 @@ acp_status batch_enqueue(acp_batch *b, int grid) {
     }
     BHIP(launch_fill_i32(dp<int>(b->abort_flag), 1, 0, s));
     BHIP(launch_fill_u32(dp<unsigned>(b->queue), 1, 0u, s));
-    BHIP(launch_mscg_batch_fp64(b->dim, b->ne_pad, dp<MsArgs>(b->desc), dp<int>(b->wsys), dp<int>(b->wtile),
+    BHIP(launch_mscg_batch_fp64(b->compact2d ? 3 : b->dim, b->ne_pad, dp<MsArgs>(b->desc), dp<int>(b->wsys), dp<int>(b->wtile),
                                 (int)b->host_wsys.size(), dp<unsigned>(b->queue), grid, s));
     return ACP_OK;
 }
@@ -2715,6 +2716,7 @@ acp_status acp_batch_create(acp_batch **out, acp_ctx *const *systems, int n, int
             return bfail(b, ACP_EINVAL, "batched systems use the FP64 multi-shift CG (solver CG, FP64)");
         if (c->opts.n_cheb > 16) return bfail(b, ACP_EINVAL, "at most 16 shifts per system");
         b->dim = c->gd.dim;
+        b->compact2d = b->compact2d && c->gd.dim == 2 && c->gd.nx % 4 == 0;
         b->ne_pad = std::max(b->ne_pad, c->nep);
         b->sys.push_back(c);
     }

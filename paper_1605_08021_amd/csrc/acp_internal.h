@@ -189,7 +189,8 @@ constexpr int kMsMaxGroup = 16;   // workgroups per right-hand-side tile
 hipError_t launch_mscg_fp64(const MsArgs &a, hipStream_t s);
 hipError_t launch_mscg_fp32(const MsArgsT<float> &a, hipStream_t s);
 // Persistent ragged batch: systems[] are device descriptors of systems with the
-// same dim whose orbital blocks are padded to ne_pad (each with its own group
+// same dim (3: 2D grids whose lines hold a multiple of 4 points, the compact
+// stencil gather) whose orbital blocks are padded to ne_pad (each with its own group
 // size K); the work list (work_sys[w], work_tile[w] = tile * kMsMaxGroup + kg,
 // the K members of a tile consecutive) is consumed in order through *queue
 // (zero at launch); grid >= the largest K.

@@ -871,6 +871,9 @@ hipError_t launch_mscg_batch_fp64(int dim, int ne_pad, const MsArgs *systems, co
         if (dim == 1)                                                                                \
             hipLaunchKernelGGL((mscg_batch_kernel<1, N, double>), dim3(grid), dim3(NT), 0, s, systems, \
                                work_sys, work_tile, n_work, queue);                                  \
+        else if (dim == 3)                                                                           \
+            hipLaunchKernelGGL((mscg_batch_kernel<3, N, double>), dim3(grid), dim3(NT), 0, s, systems, \
+                               work_sys, work_tile, n_work, queue);                                  \
         else                                                                                         \
             hipLaunchKernelGGL((mscg_batch_kernel<2, N, double>), dim3(grid), dim3(NT), 0, s, systems, \
                                work_sys, work_tile, n_work, queue);                                  \

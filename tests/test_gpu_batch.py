@@ -1,8 +1,10 @@
 """The ragged batch: several 1D systems of different sizes (5% vacancies) whose
-shifted solves share one persistent launch.  Every system's Z and W match the
-oracle's exact-solve ACP step (same selected points), and the single-system
-path; the autotuner records its candidates; hipGraph replays reproduce the
-eager launch bit for bit, with other GPU work between replays."""
+shifted solves share one persistent launch, and the 2D half (square lattices of
+3 x 3 to 5 x 5 sites, 12 x 12 points per site, 5% vacancies) in a batch of its
+own.  Every system's Z and W match the oracle's exact-solve ACP step (same
+selected points), and the single-system path; the autotuner records its
+candidates; hipGraph replays reproduce the eager launch bit for bit, with other
+GPU work between replays."""
 import functools
 
 import numpy as np
@@ -13,7 +15,7 @@ from tests.test_gpu_acp import _xi_tol
 from oracle import acp as OA
 from oracle import chi0 as OC
 from oracle.model import build_model
-from workload.seeds import draw_sketch, ragged_batch_configs
+from workload.seeds import draw_sketch, ragged_batch_configs, ragged_batch_configs_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -40,10 +42,32 @@ def _batch_systems():
     return out
 
 
-def _contexts(tol=1e-12):
+@functools.lru_cache(maxsize=None)
+def _batch_systems_2d():
+    """Ground states from the superposed-atom potential (its lowest eigenpairs,
+    exact from the full spectrum that the oracle's solver also uses)."""
+    from types import SimpleNamespace
+    cfgs = ragged_batch_configs_2d(count=4, lo=3, hi=5, size_seed=40)   # 5x5, 4x4, 3x3, 4x4 sites
+    out = []
+    for cfg in cfgs:
+        m = build_model(cfg)
+        V = m.superposed_atoms_potential()
+        w, v = np.linalg.eigh(m.hamiltonian_dense(V))
+        n_e = m.n_e
+        gs = SimpleNamespace(phi=v[:, :n_e].copy(), eps=w, veff=V, n_e=n_e)
+        G = m.perturbations()
+        om = draw_sketch(cfg, G.shape[1])
+        dec = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
+        ref = OA.compress(gs.phi, gs.eps[:n_e], G, om, cfg.n_cheb, cfg.n_mu,
+                          OA.ExactShiftedSolver(w, v, n_e), m.f, m.grid.dv, sel=dec.sel)
+        out.append((cfg, m, gs, G, om, dec, ref))
+    return out
+
+
+def _contexts(tol=1e-12, systems=None):
     from paper_1605_08021_amd import acp
     ctxs = []
-    for cfg, m, gs, G, om, dec, ref in _batch_systems():
+    for cfg, m, gs, G, om, dec, ref in (systems or _batch_systems()):
         print(f"[gpu] batch system {cfg.name}: N_g={m.grid.n_grid} N_e={gs.n_e} N_mu={cfg.n_mu}", flush=True)
         ctxs.append(acp.Context(grid_dict(cfg), dict(n_cheb=cfg.n_cheb, n_mu=cfg.n_mu, sketch_r=cfg.r,
                                                      tol=tol, max_iter=20000),
@@ -55,12 +79,13 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-def test_batch_matches_oracle_and_single_system_path():
+@pytest.mark.parametrize("dim", [1, 2])
+def test_batch_matches_oracle_and_single_system_path(dim):
     from paper_1605_08021_amd import acp
-    systems = _batch_systems()
+    systems = _batch_systems() if dim == 1 else _batch_systems_2d()
     sizes = sorted({s[1].grid.n_grid for s in systems})
     assert len(sizes) >= 3, sizes                     # genuinely ragged
-    ctxs = _contexts()
+    ctxs = _contexts(systems=systems)
     batch = acp.Batch(ctxs)
     Gs = [to_dev(s[3]) for s in systems]
     oms = [to_dev(s[4]) for s in systems]
@@ -68,7 +93,10 @@ def test_batch_matches_oracle_and_single_system_path():
     info = batch.info()
     print("batch info:", info)
     assert info["tuned"] and info["grid"] in (64, 128, 256) and min(info["tune_ms"]) > 0
-    assert info["n_tiles"] == sum(-(-s[0].n_mu // 16) for s in systems)
+    tiles = sum(-(-s[0].n_mu // 16) for s in systems)
+    # work entries: every tile once per workgroup of its group (1 for these
+    # short chains; the 2D systems take one workgroup per ~640 grid rows)
+    assert info["n_tiles"] == tiles if dim == 1 else info["n_tiles"] > tiles
     W_batch = []
     compared = 0
     for ctx, (cfg, m, gs, G, om, dec, ref) in zip(ctxs, systems):
@@ -87,7 +115,7 @@ def test_batch_matches_oracle_and_single_system_path():
         compared += 1
         assert _rel(Z, np.concatenate(ref.Z, axis=1)) < tol
         assert _rel(W, ref.W) < tol
-    assert compared >= 4
+    assert compared >= (4 if dim == 1 else 3)
     # the same systems one at a time through acp_compress
     for ctx, W, (cfg, m, gs, G, om, dec, ref) in zip(ctxs, W_batch, systems):
         ctx.compress(to_dev(G), to_dev(om), sel_in=dec.sel)
@@ -97,13 +125,14 @@ def test_batch_matches_oracle_and_single_system_path():
         c.close()
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("dim", [1, 2])
+def test_batch_graph_replays_match_eager(dim):
     from paper_1605_08021_amd import acp
-    systems = _batch_systems()
+    systems = _batch_systems() if dim == 1 else _batch_systems_2d()
     Gs = [to_dev(s[3]) for s in systems]
     oms = [to_dev(s[4]) for s in systems]
     sels = [s[5].sel for s in systems]
-    ctxs = _contexts(tol=1e-10)
+    ctxs = _contexts(tol=1e-10, systems=systems)
     eager = acp.Batch(ctxs)
     eager.compress(Gs, oms, sel_in=sels)
     ref = [to_host(c.compress_get("w")) for c in ctxs]

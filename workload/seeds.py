@@ -172,6 +172,25 @@ def draw_ragged_sizes(cid: int, count: int, lo: int, hi: int) -> np.ndarray:
     return _rng(cid, 4).integers(lo, hi + 1, size=count)
 
 
+def ragged_batch_configs_2d(count: int = 16, lo: int = 4, hi: int = 12, *, pts_per_site: int = 12,
+                            n_cheb: int = 8, vacancy_frac: float = 0.05, cid_base: int = 500,
+                            size_seed: int = 5):
+    """The 2D half of the uneven batch: `count` square lattices of k x k sites
+    with k drawn uniformly from [lo, hi], spacing 6, Z = 2, sigma = 0.8, jitter
+    0.05, 12 x 12 grid points per site, 5% vacancies (at least one), N_c = 8,
+    N_mu = 4 N_e, r = 16.  Each system has its own seed streams (cid_base +
+    index)."""
+    sizes = draw_ragged_sizes(size_seed, count, lo, hi)
+    out = []
+    for i, k in enumerate(sizes):
+        cfg = small_config(cid_base + i, 2, int(k), pts_per_site, a=6.0, sigma=0.8, jitter=0.05,
+                           n_cheb=n_cheb, vacancy_frac=vacancy_frac, r=16)
+        n_e = draw_sites(cfg)[2]
+        out.append(dataclasses.replace(cfg, n_mu=4 * n_e,
+                                       name=f"ragged 2D lattice {i}: {k}x{k} sites, {n_e} occupied"))
+    return out
+
+
 def ragged_batch_configs(count: int = 16, lo: int = 16, hi: int = 128, *, pts_per_site: int = 40,
                          n_cheb: int = 8, vacancy_frac: float = 0.05, cid_base: int = 400,
                          size_seed: int = 4):
