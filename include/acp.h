@@ -245,6 +245,18 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
                       const double *K_local, const double *mass, double *D,
                       double *omega2);
 
+/* acp_phonon_dos -- the phonon spectrum of Sec. 2.2,
+ *   rho_D(w) = (1 / (d N_A)) sum_k delta_sigma(w - w_k),
+ * with the delta replaced by the normalised Gaussian of width sigma (as for the
+ * spectra of Sec. 4) and w_k = sign(omega2_k) sqrt(|omega2_k|).
+ *   omega2 dev n (e.g. acp_dynmat's eigenvalues, copied to the device);
+ *   n_modes = d N_A (the normalisation); w dev nw frequencies; dos dev nw (out);
+ *   stream: hipStream_t or NULL.  Needs no context: errors through
+ *   acp_last_error(NULL) (ACP_EINVAL for n < 0, n_modes < 1, sigma <= 0, nw < 0
+ *   or a null pointer with n, nw > 0). */
+acp_status acp_phonon_dos(const double *omega2, int n, int n_modes, double sigma, const double *w, int nw,
+                          double *dos, void *stream);
+
 /* acp_dfpt -- the comparator ACP is measured against (density functional
  * perturbation theory, Sec. 2.2): U = chi G for the columns of G by the
  * Dyson equation u = chi0 g + chi0 v_c u, solved by fixed-point iteration

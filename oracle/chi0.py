@@ -107,3 +107,15 @@ def dynamical_matrix(hess: np.ndarray, masses: np.ndarray, dim: int):
     D = minv[:, None] * hs * minv[None, :]
     lam = np.linalg.eigvalsh(D)
     return D, lam
+
+
+def phonon_dos(omega2: np.ndarray, n_modes: int, sigma: float, w: np.ndarray) -> np.ndarray:
+    """Phonon spectrum rho_D(w) = (1 / (d N_A)) sum_k delta_sigma(w - w_k) (Sec. 2.2),
+    the delta replaced by the normalised Gaussian of width sigma as in Sec. 4;
+    w_k = sign(omega_k^2) sqrt(|omega_k^2|) (a slightly negative omega^2 from
+    rounding becomes a small negative frequency).  n_modes = d N_A."""
+    wk = np.sign(omega2) * np.sqrt(np.abs(omega2))
+    x = np.asarray(w, dtype=np.float64)[:, None] - wk[None, :]
+    g = np.exp(-x ** 2 / (2.0 * sigma ** 2)) / np.sqrt(2.0 * np.pi * sigma ** 2)
+    return g.sum(axis=1) / n_modes
+

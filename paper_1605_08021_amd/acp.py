@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "acp_gesv": (I, [I, I, P, I, P, I, P]),
         "acp_scf": (I, [C.POINTER(AcpGrid), P, P, I, C.POINTER(AcpScfOpts), P, P, P, P, P, P, P]),
         "acp_lowest_eigenpairs": (I, [C.POINTER(AcpGrid), P, C.POINTER(AcpEigOpts), P, P, P, P, P, P]),
+        "acp_phonon_dos": (I, [P, I, I, C.c_double, P, I, P, P]),
         "acp_reset_stats": (None, [P]),
         "acp_last_error": (C.c_char_p, [P]),
         "acp_destroy": (None, [P]),
@@ -173,6 +174,24 @@ def _hostd(a) -> np.ndarray:
 
 def _hptr(a: np.ndarray) -> int:
     return a.ctypes.data
+
+
+def phonon_dos(omega2, n_modes: int, sigma: float, w, stream=None):
+    """The smeared phonon spectrum on the frequencies w (acp_phonon_dos): omega2
+    and w host arrays or device tensors; the result is a device tensor."""
+    import torch
+    lib = load_library()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    om = torch.as_tensor(omega2, dtype=torch.float64).to(dev).contiguous()
+    wd = torch.as_tensor(w, dtype=torch.float64).to(dev).contiguous()
+    out = torch.empty_like(wd)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib.acp_phonon_dos(_dptr(om), om.numel(), n_modes, float(sigma), _dptr(wd), wd.numel(), _dptr(out),
+                            C.c_void_p(stream.cuda_stream))
+    if st != ACP_OK:
+        raise ACPError(st, lib.acp_last_error(None).decode())
+    return out
 
 
 def syev(A, want_vectors: bool = True, stream=None):

@@ -3159,6 +3159,24 @@ acp_status acp_syev(int n, double *A, int lda, double *w, double *V, int ldv, vo
     return cleanup(sweeps >= 30 ? ACP_ENOCONV : ACP_OK);
 }
 
+acp_status acp_phonon_dos(const double *omega2, int n, int n_modes, double sigma, const double *w, int nw,
+                          double *dos, void *stream) {
+    auto bad = [](const char *m) {
+        acp::g_free_error = m;
+        return ACP_EINVAL;
+    };
+    if (n < 0 || n_modes < 1 || !(sigma > 0.0) || nw < 0) return bad("acp_phonon_dos: n, n_modes, sigma, nw");
+    if ((n > 0 && !omega2) || (nw > 0 && (!w || !dos))) return bad("acp_phonon_dos: null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_phonon_dos(omega2, n, n_modes, sigma, w, nw, dos, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        acp::g_free_error = "acp_phonon_dos: kernel launch";
+        return ACP_EDEVICE;
+    }
+    acp::g_free_error.clear();
+    return ACP_OK;
+}
+
 acp_status acp_get_stats(const acp_ctx *ctx, acp_stats *out) {
     if (!ctx || !out) return ACP_EINVAL;
     *out = ctx->stats;

@@ -233,6 +233,11 @@ hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double
 hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
                       long long xs, const WideScalars &w, hipStream_t s);
 
+// dos[p] = (1 / n_modes) sum_k exp(-(w[p] - w_k)^2 / (2 sigma^2)) / sqrt(2 pi sigma^2),
+// w_k = sign(omega2_k) sqrt(|omega2_k|) (all on the device).
+hipError_t launch_phonon_dos(const double *omega2, int n, int n_modes, double sigma, const double *w, int nw,
+                             double *dos, hipStream_t s);
+
 // ---------------------------------------------------------------- flexible CG scalars (k_fcg.hip)
 // Columns in compact order i (system cols[i]); done, iters in system order;
 // squared norms throughout (bn2 = |b|^2, sref = |r|^2 at the last halving).

@@ -598,4 +598,38 @@ hipError_t launch_mul_symbol(int ng, int n, const double *S, double *X, hipStrea
     return hipGetLastError();
 }
 
+namespace {
+// One thread per frequency point; the modes' frequencies staged in LDS.
+__global__ void phonon_dos_kernel(const double *omega2, int n, double scale, double inv2s2, const double *w, int nw,
+                                  double *dos) {
+    __shared__ double wk[256];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const double x = p < nw ? w[p] : 0.0;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n; k0 += 256) {
+        __syncthreads();
+        if (k0 + (int)threadIdx.x < n) {
+            const double l = omega2[k0 + threadIdx.x];
+            wk[threadIdx.x] = l < 0.0 ? -sqrt(-l) : sqrt(l);
+        }
+        __syncthreads();
+        const int m = min(256, n - k0);
+        for (int k = 0; k < m; ++k) {
+            const double d = x - wk[k];
+            acc += exp(-d * d * inv2s2);
+        }
+    }
+    if (p < nw) dos[p] = scale * acc;
+}
+}  // namespace
+
+hipError_t launch_phonon_dos(const double *omega2, int n, int n_modes, double sigma, const double *w, int nw,
+                             double *dos, hipStream_t s) {
+    if (nw <= 0) return hipSuccess;
+    const double scale = 1.0 / (n_modes * sqrt(2.0 * M_PI * sigma * sigma));
+    hipLaunchKernelGGL(phonon_dos_kernel, dim3(nblk(nw, 256)), dim3(256), 0, s, omega2, n, scale,
+                       1.0 / (2.0 * sigma * sigma), w, nw, dos);
+    return hipGetLastError();
+}
+
 }  // namespace acp

@@ -200,3 +200,25 @@ def test_reorthonormalised_orbitals():
     print(f"Loewdin: |Psi32^T Psi32 - I| = {np.abs(S - np.eye(gs.n_e)).max():.1e}, W rel err {eW:.1e}")
     assert eW < 1e-8
     ctx.close()
+
+
+def test_phonon_dos_matches_oracle():
+    """acp_phonon_dos on workload 1's dynamical-matrix eigenvalues (smear 0.01,
+    as for the 1D spectra of Sec. 4) against the oracle's formula."""
+    import torch
+    from paper_1605_08021_amd import acp
+    cfg, m, gs, w, v, G, om, K = system(1)
+    ctx = make_ctx(1, tol=1e-12)
+    U, _, _ = ctx.dyson(to_dev(G), to_dev(om))
+    D, w2 = ctx.dynmat(to_dev(G), U, K, np.ones(m.n_atoms))
+    ctx.close()
+    n_modes = cfg.dim * m.n_atoms
+    wgrid = np.linspace(-0.05, 1.2 * np.sqrt(w2.max()), 3001)
+    got = acp.phonon_dos(w2, n_modes, 0.01, wgrid).cpu().numpy()
+    ref = OC.phonon_dos(w2, n_modes, 0.01, wgrid)
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print(f"phonon DOS: rel err {err:.1e}, integral {np.trapezoid(got, wgrid):.6f}")
+    assert err <= 1e-12
+    with pytest.raises(acp.ACPError) as e:
+        acp.phonon_dos(w2, n_modes, 0.0, wgrid)
+    assert e.value.status == acp.ACP_EINVAL

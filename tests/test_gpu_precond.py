@@ -277,3 +277,63 @@ def test_trajectory_matches_reference():
         x = x + alpha * d
         r = r - alpha * Ad
     ctx.close()
+
+
+def _lattice_2d(cid, k):
+    """A square lattice of k x k sites (spacing 6, sigma 0.8, 12 x 12 points per
+    site, as workload 3) with its superposed-atom ground state."""
+    from oracle import acp as OA
+    from oracle.model import build_model
+    from workload.seeds import small_config
+    cfg = small_config(cid, 2, k, 12, a=6.0, sigma=0.8, jitter=0.05, n_cheb=8, r=16)
+    m = build_model(cfg)
+    V = m.superposed_atoms_potential()
+    w, v = np.linalg.eigh(m.hamiltonian_dense(V))
+    phi, eps = v[:, :m.n_e].copy(), w[:m.n_e].copy()
+    G = m.perturbations()
+    from workload.seeds import draw_sketch
+    dec = OA.isdf_qrcp(phi, G, draw_sketch(cfg, G.shape[1]), 4 * m.n_e)
+    return cfg, m, V, phi, eps, OA.rhs(phi, dec.xi)
+
+
+def test_2d_network_transfers_to_a_larger_lattice():
+    """a9 in 2D: the network trained on the solves of a 4 x 4 lattice (2304 grid
+    points) is loaded into the context of a 6 x 6 lattice (5184 points) and
+    preconditions its shifted systems: the same FP64 true residual as CG without
+    the network in fewer iterations."""
+    from paper_1605_08021_amd import acp
+    from paper_1605_08021_amd import precond as PC
+    from oracle import acp as OA, krylov as OK
+    from tests.gpu_common import grid_dict
+    out = []
+    for cid, k in ((951, 4), (952, 6)):
+        cfg, m, V, phi, eps, R0 = _lattice_2d(cid, k)
+        ctx = acp.Context(grid_dict(cfg), dict(n_cheb=cfg.n_cheb, n_mu=4 * m.n_e, sketch_r=cfg.r, tol=1e-8,
+                                               max_iter=5000), to_dev(phi), eps, to_dev(V))
+        nodes, _ = OA.shifts_and_weights(eps, cfg.n_cheb)
+        out.append((cfg, m, V, phi, eps, R0, ctx, nodes))
+    (cfg_a, m_a, V_a, phi_a, eps_a, R_a, ctx_a, nodes_a), (cfg_b, m_b, V_b, phi_b, eps_b, R_b, ctx_b, nodes_b) = out
+    cols = np.arange(16)
+    Btr = np.concatenate([R_a[:, cols]] * len(nodes_a), axis=1)
+    hist = PC.train_preconditioner(ctx_a, np.repeat(nodes_a, len(cols)), to_dev(Btr), seed=4321)
+    print(f"[2d] trained on the 4x4 lattice: loss {hist[0][:20].mean():.3f} -> {hist[-1][-20:].mean():.3f}")
+    ctx_b.precond_init(1)
+    ctx_b.precond_set(ctx_a.precond_get())
+    Bte = np.concatenate([R_b[:, cols]] * len(nodes_b), axis=1)
+    ste = np.repeat(nodes_b, len(cols))
+    op = OK.make_operator(m_b, V_b, phi_b, ste)
+    res = {}
+    for mode in (2, 1):
+        ctx_b.set_opts(use_learned_precond=mode)
+        ctx_b.reset_stats()
+        X, it, _ = ctx_b.sternheimer(ste, to_dev(Bte))
+        tr = OK.true_residual(op, to_host(X), Bte).max()
+        res[mode] = (it.mean(), tr, ctx_b.stats()["refinements"])
+        print(f"[2d] 6x6 lattice, mode {mode}: iterations mean {it.mean():.1f} max {it.max()}, "
+              f"true residual {tr:.2e}, fallback passes {res[mode][2]}", flush=True)
+        assert tr <= 1e-8
+    gain = res[2][0] / res[1][0]
+    print(f"[2d] iterations without / with the transferred network: {gain:.2f}")
+    assert gain > 1.5
+    ctx_a.close()
+    ctx_b.close()

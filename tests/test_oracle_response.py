@@ -133,3 +133,23 @@ def test_dynamical_matrix_with_masses_is_generalised_eigenproblem():
     ref = sla.eigh(Hs, np.diag(np.repeat(masses, d)), eigvals_only=True)
     assert np.allclose(lam, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
     assert np.allclose(D, D.T)
+
+
+def test_phonon_dos_normalisation_and_closed_forms():
+    """The smeared phonon spectrum integrates to n / (d N_A); one mode at
+    omega^2 = 4 is the Gaussian around 2; negative omega^2 gives negative
+    frequencies; the sum over modes is linear."""
+    sigma = 0.08
+    w = np.linspace(-3.0, 6.0, 9001)
+    lam = np.array([0.0, 0.25, 1.0, 4.0, 4.0, 9.0])
+    rho = C.phonon_dos(lam, 6, sigma, w)
+    assert abs(np.trapezoid(rho, w) - 1.0) < 1e-10
+    one = C.phonon_dos(np.array([4.0]), 2, sigma, w)
+    peak = 1.0 / (np.sqrt(2 * np.pi) * sigma) / 2
+    assert abs(one[np.argmin(np.abs(w - 2.0))] - peak) < 1e-12
+    assert abs(one[np.argmin(np.abs(w - 2.0 - sigma))] - peak * np.exp(-0.5)) < 1e-12
+    neg = C.phonon_dos(np.array([-1e-4]), 1, sigma, w)
+    assert abs(w[np.argmax(neg)] + 1e-2) < 2e-3
+    parts = sum(C.phonon_dos(lam[i:i + 1], 6, sigma, w) for i in range(6))
+    assert np.allclose(parts, rho, rtol=0, atol=1e-14)
+
