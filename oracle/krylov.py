@@ -118,6 +118,9 @@ def minres(apply_a, b, tol=1e-8, max_iter=5000):
 
 
 def true_residual(apply_a, x, b):
-    """||b - A x|| / ||b|| per column."""
+    """||b - A x|| / ||b|| per column; a zero column of b (whose solution is 0)
+    reports the absolute residual ||A x||."""
     r = b - apply_a(x)
-    return np.sqrt(np.sum(r * r, axis=0)) / np.sqrt(np.sum(b * b, axis=0))
+    rn = np.sqrt(np.sum(r * r, axis=0))
+    bn = np.sqrt(np.sum(b * b, axis=0))
+    return np.where(bn > 0, rn / np.where(bn > 0, bn, 1.0), rn)
