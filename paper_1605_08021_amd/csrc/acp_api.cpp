@@ -93,7 +93,7 @@ struct acp_ctx {
     // its BF16 projector: Phi split in 2 terms (orbital rows, K = grid) and in 3
     // terms (grid rows, K = orbitals), the base p in 2 terms, split-K partials of
     // Phi^T p, the deflation coefficients, the occupied energies
-    DevBuf bf_phi_cm[2], bf_phi_rm[3], bf_p[2], bf_part, bf_c, eps_dev;
+    DevBuf bf_phi_cm[2], bf_phi_rm[3], bf_p[2], bf_part, bf_c, eps_dev, bf_c2[2];
     bool bf_ready = false;
     DevBuf df_b, df_z, df_c, df_u, df_f, df_v, df_r, df_du, df_dr, df_pu, df_pr, df_dot;   // DFPT comparator
     acp_stats stats{};
@@ -1143,16 +1143,48 @@ acp_status true_residual(acp_ctx *ctx, int n, const double *shifts_dev, const do
     return ACP_OK;
 }
 
+// The BF16 form's residual pass on n solutions Zc (column-major, in place):
+// Zc <- Q Zc with C = Phi^T Zc by the FP64 GEMM (its error would stay in Z) and
+// Zc -= Phi C in BF16 (Phi in three terms, C in two: the rounding moves
+// occupied components only, by ~2^-17 |C|, C itself at the level of the
+// solver's occupied noise); V = (H - s_j) Zc and pn_j = |Phi^T V_j|^2 (FP64),
+// so that |Q (B - V)|^2 = |B - V|^2 - pn for B in range(Q).  The subtraction
+// is safe here: the form takes only eigenvectors, so |Phi^T V| stays within a
+// few decades of the residual.  shifts_dev: per column.
+acp_status project_bf16(acp_ctx *ctx, int n, const double *shifts_dev, double *Zc, double *V, double *pn) {
+    const int ng = ctx->ng, ne = ctx->ne;
+    hipStream_t s = ctx->stream;
+    CHECK(prepare_bf16(ctx));
+    const long long nek = round8(ne);
+    ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
+    ENSURE(ctx->splitk, (size_t)kSplitSlices * ne * n * 8);
+    double *C = dp<double>(ctx->c1);
+    unsigned short *cb[2];
+    for (int t = 0; t < 2; ++t) {
+        ENSURE(ctx->bf_c2[t], (size_t)nek * n * 2);
+        cb[t] = dp<unsigned short>(ctx->bf_c2[t]);
+    }
+    const unsigned short *rm[3] = {dp<unsigned short>(ctx->bf_phi_rm[0]), dp<unsigned short>(ctx->bf_phi_rm[1]),
+                                   dp<unsigned short>(ctx->bf_phi_rm[2])};
+    CHECK(phi_t_times_ws(ctx, n, Zc, ng, C, dp<double>(ctx->splitk)));
+    HIPCHK(launch_split_bf16(ne, n, C, ne, 2, cb, nek, s));
+    HIPCHK(gemm_bf16_tn(3, 2, 1, ng, n, (int)nek, rm, nek, cb, nek, 1, nullptr, 0, Zc, ng, -1.0, s));
+    HIPCHK(launch_stencil(ctx->gd, n, Zc, ng, V, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0, shifts_dev, s));
+    CHECK(phi_t_times_ws(ctx, n, V, ng, C, dp<double>(ctx->splitk)));
+    HIPCHK(launch_col_sqnorm(ne, n, C, ne, pn, s));
+    return ACP_OK;
+}
+
 acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std::vector<double> &shifts,
                                 double *Z, long long zstride, double *max_rel, bool project) {
     const int ng = ctx->ng, nc = (int)shifts.size();
     hipStream_t s = ctx->stream;
     const int chunk = std::max(16, std::min(nb, (int)std::floor(4.0 * 1024 * 1024 * 1024 / (8.0 * ng))));
     ENSURE(ctx->tmp1, (size_t)ng * chunk * 8);
-    ENSURE(ctx->dy_norm, (size_t)2 * chunk * 8);
+    ENSURE(ctx->dy_norm, (size_t)3 * chunk * 8);
     ENSURE(ctx->dy_s, (size_t)chunk * 8);
-    double *rn = dp<double>(ctx->dy_norm), *bn = rn + chunk;
-    std::vector<double> h((size_t)2 * chunk), sh(chunk);
+    double *rn = dp<double>(ctx->dy_norm), *bn = rn + chunk, *pn = bn + chunk;
+    std::vector<double> h((size_t)3 * chunk), sh(chunk);
     double m = 0.0;
     for (int c = 0; c < nc; ++c)
         for (int j0 = 0; j0 < nb; j0 += chunk) {
@@ -1160,11 +1192,8 @@ acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std
             std::fill(sh.begin(), sh.end(), shifts[c]);
             HIPCHK(hipMemcpyAsync(ctx->dy_s.p, sh.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
             double *Zc = Z + c * zstride + (size_t)j0 * ng;
-            if (project) {   // the operator's first projection writes Q Z over Z
-                ENSURE(ctx->c1, (size_t)ctx->nep * n * 8);
-                ENSURE(ctx->splitk, (size_t)kSplitSlices * ctx->ne * n * 8);
-                CHECK(apply_operator_ws(ctx, n, dp<double>(ctx->dy_s), Zc, dp<double>(ctx->tmp1), Zc,
-                                        dp<double>(ctx->c1), dp<double>(ctx->splitk)));
+            if (project) {   // Q Z over Z, V = (H - s) Q Z and |Phi^T V|^2 (project_bf16)
+                CHECK(project_bf16(ctx, n, dp<double>(ctx->dy_s), Zc, dp<double>(ctx->tmp1), pn));
             } else {
                 CHECK(apply_operator(ctx, n, dp<double>(ctx->dy_s), Zc, dp<double>(ctx->tmp1)));
             }
@@ -1172,9 +1201,14 @@ acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std
             HIPCHK(launch_col_sqnorm(ng, n, B + (size_t)j0 * ng, ng, bn, s));
             HIPCHK(hipMemcpyAsync(h.data(), rn, (size_t)n * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(h.data() + chunk, bn, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+            if (project)
+                HIPCHK(hipMemcpyAsync(h.data() + 2 * (size_t)chunk, pn, (size_t)n * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             for (int j = 0; j < n; ++j)
-                if (h[chunk + j] > 0.0) m = std::max(m, std::sqrt(h[j] / h[chunk + j]));
+                if (h[chunk + j] > 0.0) {
+                    const double r2 = project ? std::max(0.0, h[j] - h[2 * (size_t)chunk + j]) : h[j];
+                    m = std::max(m, std::sqrt(r2 / h[chunk + j]));
+                }
         }
     *max_rel = m;
     return ACP_OK;
@@ -3219,6 +3253,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->wd_p, &ctx->wd_r, &ctx->wd_w, &ctx->wd_c, &ctx->wd_sc, &ctx->wd_sig,
                       &ctx->bf_phi_cm[0], &ctx->bf_phi_cm[1], &ctx->bf_phi_rm[0], &ctx->bf_phi_rm[1],
                       &ctx->bf_phi_rm[2], &ctx->bf_p[0], &ctx->bf_p[1], &ctx->bf_part, &ctx->bf_c, &ctx->eps_dev,
+                      &ctx->bf_c2[0], &ctx->bf_c2[1],
                       &ctx->df_b, &ctx->df_z, &ctx->df_c, &ctx->df_u, &ctx->df_f, &ctx->df_v, &ctx->df_r,
                       &ctx->df_du, &ctx->df_dr, &ctx->df_pu, &ctx->df_pr, &ctx->df_dot};
     for (DevBuf *b : bufs) release(*b);

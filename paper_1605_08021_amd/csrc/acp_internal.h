@@ -274,13 +274,14 @@ hipError_t launch_split_bf16_transpose(int m, int n, const double *X, long long 
 // epi 0: split-K over nsplit slices, slice z stored to P[z ldp N + n ldp + m]
 // (FP32; ldp a multiple of 4); epi 1 (nsplit = 1): Wd[n ldw + m] += alpha D.
 // K, lda, ldb multiples of 8; supported (na, nb, epi): (1,1,*), (2,2,0),
-// (3,1,1), (2,1,1).
+// (3,1,1), (3,2,1), (2,1,1).
 hipError_t gemm_bf16_tn(int na, int nb, int epi, int M, int N, int K, const unsigned short *const *A, long long lda,
                         const unsigned short *const *B, long long ldb, int nsplit, float *P, long long ldp,
                         double *Wd, long long ldw, double alpha, hipStream_t s);
 // Number of split-K slices gemm_bf16_tn actually uses for K and nsplit.
 int bf16_split_count(int K, int nsplit);
-// Cb[j ldc + i] = bf16((T - eps_i) sum_z P[z ldp n + j ldp + i]) for i < m, 0 below ldc.
+// Cb[j ldc + i] = bf16((T - eps_i) sum_z P[z ldp n + j ldp + i]) for i < m (T alone
+// when eps is null), 0 below ldc.
 hipError_t launch_deflate_coef(int m, int n, int nsplit, const float *P, long long ldp, const double *eps, double T,
                                unsigned short *Cb, long long ldc, hipStream_t s);
 

@@ -225,8 +225,8 @@ __global__ __launch_bounds__(NTH, 2) void gemm_bf16_tn_kernel(int M, int N, int 
         }
 }
 
-// C'(i, j) = bf16((T - eps_i) * sum_z P[z psz + j ldp + i]) for i < m, zero for
-// m <= i < ldc (the padding the next GEMM reads as K).
+// C'(i, j) = bf16((T - eps_i) * sum_z P[z psz + j ldp + i]) for i < m (T alone
+// without eps), zero for m <= i < ldc (the padding the next GEMM reads as K).
 __global__ void deflate_coef_kernel(int m, int n, int nsplit, const float *__restrict__ P, long long ldp,
                                     long long psz, const double *__restrict__ eps, double T,
                                     unsigned short *__restrict__ Cb, long long ldc) {
@@ -236,7 +236,7 @@ __global__ void deflate_coef_kernel(int m, int n, int nsplit, const float *__res
     double v = 0.0;
     if (i < m) {
         for (int z = 0; z < nsplit; ++z) v += (double)P[(long long)z * psz + (long long)j * ldp + i];
-        v *= T - eps[i];
+        v *= eps ? T - eps[i] : T;
     }
     Cb[(long long)j * ldc + i] = f64_to_bf16(v);
 }
@@ -296,6 +296,8 @@ hipError_t gemm_bf16_tn(int na, int nb, int epi, int M, int N, int K, const unsi
         return launch_tn<1, 1, 0>(M, N, K, A, lda, B, ldb, nsplit, P, ldp, Wd, ldw, alpha, s);
     if (na == 3 && nb == 1 && epi == 1)
         return launch_tn<3, 1, 1>(M, N, K, A, lda, B, ldb, 1, P, ldp, Wd, ldw, alpha, s);
+    if (na == 3 && nb == 2 && epi == 1)
+        return launch_tn<3, 2, 1>(M, N, K, A, lda, B, ldb, 1, P, ldp, Wd, ldw, alpha, s);
     if (na == 2 && nb == 1 && epi == 1)
         return launch_tn<2, 1, 1>(M, N, K, A, lda, B, ldb, 1, P, ldp, Wd, ldw, alpha, s);
     if (na == 1 && nb == 1 && epi == 1)
