@@ -3018,10 +3018,11 @@ acp_status acp_dynmat(acp_ctx *ctx, const double *G, const double *U, int n_p,
     HIPCHK(launch_dynmat_assemble(n_p, ctx->grid.dim, dp<double>(ctx->dm_phi), Kd, Md,
                                   dp<double>(ctx->dm_d), dp<double>(ctx->dm_asym), s));
     HIPCHK(hipMemcpyAsync(D, ctx->dm_d.p, nn * 8, hipMemcpyDeviceToHost, s));
-    if (n_p <= 128) {   // Householder + bisection in one workgroup's LDS
+    if (n_p <= 4096) {   // Householder + bisection (one workgroup up to 128, the device above)
+        ENSURE(ctx->dm_work, sym_eigvals_work_doubles(n_p) * 8);
         HIPCHK(sym_eigvals(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig),
                            dp<double>(ctx->dm_work), s));
-    } else {            // cyclic Jacobi over the whole device
+    } else {             // cyclic Jacobi over the whole device
         ENSURE(ctx->dm_work, sym_eig_work_doubles(n_p, false) * 8);
         int sweeps = 0;
         HIPCHK(sym_eig_jacobi(n_p, dp<double>(ctx->dm_d), n_p, dp<double>(ctx->dm_eig), nullptr, 0,

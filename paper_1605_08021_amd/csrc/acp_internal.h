@@ -377,10 +377,11 @@ hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, in
 // Gauss-Jordan above 1024 unknowns.
 size_t lu_pinfo_ints(int n);
 hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *pinfo, hipStream_t s);
-// Symmetric eigenvalues (Householder + bisection up to n = 128, cyclic Jacobi
-// beyond), A overwritten; eig sorted ascending;
-// work holds n + 2 doubles + n + 2 ints.
+// Symmetric eigenvalues by Householder reduction to tridiagonal form and Sturm
+// bisection: in one workgroup's LDS up to n = 128, over the whole device above
+// (n <= 4096); A overwritten; eig ascending; work: sym_eigvals_work_doubles(n).
 hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s);
+size_t sym_eigvals_work_doubles(int n);
 // Symmetric eigenvalues (ascending, eig dev n) and, when V is not null, the
 // eigenvectors (V dev n x n, column j for eig[j]) by cyclic Jacobi over the
 // whole device (k_eig.hip); A is overwritten; work: sym_eig_work_doubles(n, V

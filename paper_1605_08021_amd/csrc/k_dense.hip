@@ -19,7 +19,7 @@
 // of the Sherman-Morrison-Woodbury update (Eq. (3.13); Gauss-Jordan above 1024
 // unknowns), the blocked inverse of the triangular factor L11, Householder
 // tridiagonalisation with Sturm bisection for the eigenvalues of the dynamical
-// matrix (cyclic Jacobi above 128), and the assembly
+// matrix (in one workgroup up to 128, over the device above), and the assembly
 // D = M^{-1/2} (sym(h^d G^T U) + K_local) M^{-1/2}.
 #include "acp_internal.h"
 
@@ -1047,12 +1047,163 @@ __global__ __launch_bounds__(1024) void tridiag_bisect_kernel(int n, const doubl
     }
 }
 
+// ---- the same reduction for larger n over the whole device (A in global
+// memory, overwritten): per column k, the reflector (one workgroup), p = A22 v
+// by row blocks x column chunks into partial sums, w = beta p - K v (one
+// workgroup, fixed order), the rank-2 update of A22; then every eigenvalue of
+// the tridiagonal (d, e) by Sturm bisection, one thread each.
+constexpr int TRI_CHUNKS = 8;
+
+namespace {
+
+__global__ __launch_bounds__(1024) void tri_reflector_kernel(int n, int k, const double *A, int lda, double *v,
+                                                             double *d, double *e, double *sc) {
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    const int m = n - k - 1;
+    const double *x = A + (k + 1) + (long long)k * lda;
+    double sq = 0.0;
+    for (int i = t; i < m; i += 1024) sq += x[i] * x[i];
+    red[t] = sq;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    const double x0 = x[0];
+    const double nrm = sqrt(red[0]);
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    const double vtv = red[0] - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+    for (int i = t; i < m; i += 1024) v[i] = x[i] - (i == 0 ? alpha : 0.0);
+    if (t == 0) {
+        d[k] = A[k + (long long)k * lda];
+        e[k] = alpha;
+        sc[0] = vtv > 0.0 ? 2.0 / vtv : 0.0;   // beta
+    }
+}
+
+// part[c][i] = sum over the c-th chunk of columns j of A22(i, j) v[j]
+__global__ __launch_bounds__(256) void tri_matvec_kernel(int n, int k, const double *A, int lda, const double *v,
+                                                         double *part) {
+    const int m = n - k - 1;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    const int jlen = (m + TRI_CHUNKS - 1) / TRI_CHUNKS;
+    const int j0 = c * jlen, j1 = min(m, j0 + jlen);
+    if (i >= m) return;
+    const double *a = A + (k + 1 + i) + (long long)(k + 1) * lda;
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) acc += a[(long long)j * lda] * v[j];
+    part[(long long)c * n + i] = acc;
+}
+
+// p = beta sum_c part, K = beta v.p / 2, w = p - K v (fixed order)
+__global__ __launch_bounds__(1024) void tri_w_kernel(int n, int k, const double *part, const double *v, double *w,
+                                                     const double *sc) {
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    const int m = n - k - 1;
+    const double beta = sc[0];
+    double vp = 0.0;
+    for (int i = t; i < m; i += 1024) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < TRI_CHUNKS; ++c) acc += part[(long long)c * n + i];
+        const double p = beta * acc;
+        w[i] = p;
+        vp += v[i] * p;
+    }
+    red[t] = vp;
+    __syncthreads();
+    for (int s2 = 512; s2 > 0; s2 >>= 1) {
+        if (t < s2) red[t] += red[t + s2];
+        __syncthreads();
+    }
+    const double K = 0.5 * beta * red[0];
+    for (int i = t; i < m; i += 1024) w[i] -= K * v[i];
+}
+
+// A22 -= v w^T + w v^T
+__global__ __launch_bounds__(256) void tri_update_kernel(int n, int k, double *A, int lda, const double *v,
+                                                         const double *w) {
+    const int m = n - k - 1;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= m || j >= m) return;
+    A[(k + 1 + i) + (long long)(k + 1 + j) * lda] -= v[i] * w[j] + w[i] * v[j];
+}
+
+// the last 2 x 2 block's diagonal and off-diagonal
+__global__ void tri_tail_kernel(int n, const double *A, int lda, double *d, double *e) {
+    if (n >= 2) {
+        d[n - 2] = A[(n - 2) + (long long)(n - 2) * lda];
+        e[n - 2] = A[(n - 1) + (long long)(n - 2) * lda];
+    }
+    d[n - 1] = A[(n - 1) + (long long)(n - 1) * lda];
+}
+
+// eig[idx] = the idx-th smallest eigenvalue of the tridiagonal (d, e): bisection
+// on the Sturm count inside the Gershgorin bracket (d, e staged in LDS).
+__global__ __launch_bounds__(256) void tri_bisect_kernel(int n, const double *dg, const double *eg, double *eig) {
+    extern __shared__ double sh[];
+    double *dd = sh, *ee = sh + n;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        dd[i] = dg[i];
+        ee[i] = i + 1 < n ? eg[i] : 0.0;
+    }
+    __syncthreads();
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+        lo = i == 0 ? dd[i] - r : fmin(lo, dd[i] - r);
+        hi = i == 0 ? dd[i] + r : fmax(hi, dd[i] + r);
+    }
+    const double scale = fmax(fabs(lo), fabs(hi));
+    const double tiny = 1e-300 + 1e-30 * scale;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n) return;
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 4e-16 * scale; ++it) {
+        const double x = 0.5 * (a + b);
+        int cnt = 0;
+        double q = dd[0] - x;
+        if (q == 0.0) q = -tiny;
+        cnt += q < 0.0;
+        for (int i = 1; i < n; ++i) {
+            q = dd[i] - x - ee[i - 1] * ee[i - 1] / q;
+            if (q == 0.0) q = -tiny;
+            cnt += q < 0.0;
+        }
+        if (cnt > idx) b = x; else a = x;
+    }
+    eig[idx] = 0.5 * (a + b);
+}
+
+}  // namespace
+
+size_t sym_eigvals_work_doubles(int n) { return (size_t)(TRI_CHUNKS + 4) * n + 8; }
+
 hipError_t sym_eigvals(int n, double *A, int lda, double *eig, double *work, hipStream_t s) {
     if (n <= JAC_LDS_MAX) {
         hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(1), dim3(1024), 0, s, n, (const double *)A, lda, eig);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, s, n, A, lda, eig, work, 40, 1e-16);
+    if ((size_t)2 * n * 8 > 64 * 1024) return hipErrorInvalidValue;   // d, e in one workgroup's LDS
+    double *v = work, *w = v + n, *d = w + n, *e = d + n, *part = e + n, *sc = part + (size_t)TRI_CHUNKS * n;
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        hipLaunchKernelGGL(tri_reflector_kernel, dim3(1), dim3(1024), 0, s, n, k, (const double *)A, lda, v, d, e,
+                           sc);
+        hipLaunchKernelGGL(tri_matvec_kernel, dim3((m + 255) / 256, TRI_CHUNKS), dim3(256), 0, s, n, k,
+                           (const double *)A, lda, (const double *)v, part);
+        hipLaunchKernelGGL(tri_w_kernel, dim3(1), dim3(1024), 0, s, n, k, (const double *)part, (const double *)v,
+                           w, (const double *)sc);
+        hipLaunchKernelGGL(tri_update_kernel, dim3((m + 255) / 256, m), dim3(256), 0, s, n, k, A, lda,
+                           (const double *)v, (const double *)w);
+    }
+    hipLaunchKernelGGL(tri_tail_kernel, dim3(1), dim3(1), 0, s, n, (const double *)A, lda, d, e);
+    hipLaunchKernelGGL(tri_bisect_kernel, dim3((n + 255) / 256), dim3(256), (size_t)2 * n * 8, s, n,
+                       (const double *)d, (const double *)e, eig);
     return hipGetLastError();
 }
 

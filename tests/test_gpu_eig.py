@@ -58,3 +58,26 @@ def test_gesv_matches_library(n):
     err = np.abs(X - ref).max() / np.abs(ref).max()
     print(f"[gesv] n = {n}: cond {cond:.1e}, rel err {err:.1e}", flush=True)
     assert err <= 1e-15 * cond * n
+
+
+@pytest.mark.parametrize("n_p", [129, 600, 2048])
+def test_dynmat_eigenvalues_above_128(n_p):
+    """acp_dynmat above 128 modes: Householder tridiagonalisation over the
+    device and Sturm bisection, against the library routine on the D it returns
+    (random G, U and local terms on workload 1's grid; 2048 is workload 5's
+    count)."""
+    from tests.gpu_common import make_ctx, to_dev
+    rng = np.random.default_rng(n_p)
+    ctx = make_ctx(1)
+    ng = ctx.grid.n[0]
+    G = rng.standard_normal((ng, n_p))
+    U = rng.standard_normal((ng, n_p)) * 1e-2
+    K = rng.standard_normal((n_p, n_p))
+    K = K + K.T
+    D, w2 = ctx.dynmat(to_dev(G), to_dev(U), K, None)
+    ctx.close()
+    ref = np.linalg.eigvalsh(0.5 * (D + D.T))
+    err = float(np.abs(np.sort(w2) - ref).max() / np.abs(ref).max())
+    print(f"[eig] dynmat n_p={n_p}: eigenvalue error {err:.1e}", flush=True)
+    assert np.all(np.diff(w2) >= 0)
+    assert err <= 1e-12
