@@ -93,7 +93,7 @@ struct acp_ctx {
     // its BF16 projector: Phi split in 2 terms (orbital rows, K = grid) and in 3
     // terms (grid rows, K = orbitals), the base p in 2 terms, split-K partials of
     // Phi^T p, the deflation coefficients, the occupied energies
-    DevBuf bf_phi_cm[2], bf_phi_rm[3], bf_p[2], bf_part, bf_c, eps_dev, bf_c2[2];
+    DevBuf bf_phi_cm[2], bf_phi_rm[3], bf_p[2], bf_part, bf_c, eps_dev, bf_c2[2], bf_corr;
     bool bf_ready = false;
     DevBuf df_b, df_z, df_c, df_u, df_f, df_v, df_r, df_du, df_dr, df_pu, df_pr, df_dot;   // DFPT comparator
     acp_stats stats{};
@@ -893,7 +893,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
                                  const double *col_shift_dev = nullptr, bool bf16 = false) {
     const int ng = ctx->ng, ne = ctx->ne, nc = (int)shifts.size();
     hipStream_t s = ctx->stream;
-    const long long ngk = round8(ng), nek = round8(ne), ldp = (ne + 3) / 4 * 4;
+    const long long ngk = round8(ng), nek = round8(ne), ldp = (ne + 3) / 4 * 4, ldcorr = (ng + 3) / 4 * 4;
     if (bf16) CHECK(prepare_bf16(ctx));
     const int base = (int)(std::max_element(shifts.begin(), shifts.end()) - shifts.begin());
     std::vector<double> sig(nc);
@@ -901,8 +901,8 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
     ENSURE(ctx->wd_sig, (size_t)nc * 8);
     HIPCHK(hipMemcpyAsync(ctx->wd_sig.p, sig.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
     constexpr int W = kWideWindow;
-    // p_c, the residual ring, w (and the BF16 split of the base p)
-    const double per_col = (nc + W + 1.0) * ng * 8.0 + (bf16 ? 4.0 * ngk : 0.0);
+    // p_c, the residual ring, w (and the BF16 split of the base p, the FP32 correction)
+    const double per_col = (nc + W + 1.0) * ng * 8.0 + (bf16 ? 4.0 * ngk + 4.0 * ldcorr : 0.0);
     int chunk = (int)std::max(16.0, std::min((double)nb, std::floor(kWideBudgetBytes / per_col)));
     if (chunk < nb) chunk = std::max(16, chunk / 16 * 16);
     ENSURE(ctx->wd_p, (size_t)nc * ng * chunk * 8);
@@ -930,6 +930,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         for (int t = 0; t < 3; ++t) phi_rm_b[t] = dp<unsigned short>(ctx->bf_phi_rm[t]);
         ENSURE(ctx->bf_part, (size_t)bf_split * ldp * chunk * 4);
         ENSURE(ctx->bf_c, (size_t)nek * chunk * 2);
+        ENSURE(ctx->bf_corr, (size_t)ldcorr * chunk * 4);
     }
     const double Tdef = bf16 ? bf16_deflation_level(ctx) : 0.0;
     // scalars: 7 nb doubles (rr rrn bn al alp btp pw), 6 nc nb doubles, the window
@@ -985,31 +986,35 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         int iter = 0, k0 = 0, live_prev = n;
         for (; iter < ctx->opts.max_iter; ++iter) {
             HIPCHK(hipEventRecord(ctx->ev[8], s));
-            // w = Q (H - s_base) p  (p in range(Q)); the projector GEMMs are timed
-            if (col_shift_dev)
-                HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, 0.0,
-                                      col_shift_dev + j0, s));
-            else
-                HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0,
-                                      -shifts[base], nullptr, s));
-            HIPCHK(hipEventRecord(ctx->ev[6], s));
+            const double *csh = col_shift_dev ? col_shift_dev + j0 : nullptr;
+            const double c0 = col_shift_dev ? 0.0 : -shifts[base];
             if (bf16) {
-                // deflated operator: w += Phi (T - Lambda) Phi^T p, both products in BF16
+                // deflated operator: w = (H - s_base) p + Phi (T - Lambda) Phi^T p, the
+                // two products in BF16, the second stored in FP32 and added by the
+                // stencil as it writes w (the projector GEMMs are timed)
                 float *part = dp<float>(ctx->bf_part);
                 unsigned short *cb = dp<unsigned short>(ctx->bf_c);
                 const unsigned short *cbv[1] = {cb};
+                float *corr = dp<float>(ctx->bf_corr);
+                HIPCHK(hipEventRecord(ctx->ev[6], s));
                 HIPCHK(gemm_bf16_tn(pterms, pterms, 0, ne, n, (int)ngk, phi_cm_b, ngk, pb, ngk, bf_split, part, ldp,
                                     nullptr, 0, 0.0, s));
                 HIPCHK(launch_deflate_coef(ne, n, bf_split, part, ldp, dp<double>(ctx->eps_dev), Tdef, cb, nek, s));
-                HIPCHK(gemm_bf16_tn(3, 1, 1, ng, n, (int)nek, phi_rm_b, nek, cbv, nek, 1, nullptr, 0, w,
-                                    ng, 1.0, s));
+                HIPCHK(gemm_bf16_tn(3, 1, 0, ng, n, (int)nek, phi_rm_b, nek, cbv, nek, 1, corr, ldcorr, nullptr, 0,
+                                    1.0, s));
+                HIPCHK(hipEventRecord(ctx->ev[7], s));
+                HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, c0, csh, s,
+                                      corr, ldcorr));
             } else {
+                // w = Q (H - s_base) p  (p in range(Q)); the projector GEMMs are timed
+                HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, c0, csh, s));
+                HIPCHK(hipEventRecord(ctx->ev[6], s));
                 HIPCHK(gemm_splitk(Op::T, Op::N, ne, n, ng, 1.0, phi, ng, w, ng, 0.0, C, ne, dp<double>(ctx->splitk),
                                    (size_t)kSplitSlices * ne * n, s, Epi::StoreProjector));
                 HIPCHK(gemm(Op::N, Op::N, ng, n, ne, -1.0, phi, ng, 0, C, ne, 0, 1.0, w, ng, 0, 1, s,
                             Epi::StoreProjector));
+                HIPCHK(hipEventRecord(ctx->ev[7], s));
             }
-            HIPCHK(hipEventRecord(ctx->ev[7], s));
             HIPCHK(launch_col_dot(ng, n, pb_base, ng, w, ng, pw, s));
             HIPCHK(launch_fill_i32(ws.nactive, 1, 0, s));
             HIPCHK(wide_step(ng, n, nc, base, dp<double>(ctx->wd_sig), tol, iter, k0, pw, w, ring + (iter % W) * rs,
@@ -1033,16 +1038,18 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
             // written, rn read; BF16: the two terms of p written, 0.5), and at a
             // window's end the deferred updates (the wl ring slots read, p_c and x_c
             // of the other nc - 1 shifts read and written)
-            const double units = 2.0 + 2.0 + 3.0 + 5.0 + (bf16 ? 0.5 : 0.0) + flush_units;
+            // (BF16: the stencil also reads the FP32 correction, 0.5)
+            const double units = 2.0 + 2.0 + 3.0 + 5.0 + (bf16 ? 1.0 : 0.0) + flush_units;
             ctx->stats.vector_bytes += 8.0 * ng * (double)live_prev * units;
             live_prev = live;
             ctx->stats.solve_kernel_launches += 1;
             ctx->stats.krylov_flops += 4.0 * ng * (double)ne * n;
             // algorithmic bytes of the projector pair: FP64, y read twice and written
             // once, Phi read once per GEMM, C written and read; BF16, the two terms
-            // of p read, w read and written, the five terms of Phi read once, C
+            // of p read, the FP32 correction written, the five terms of Phi read
+            // once, C
             if (bf16)
-                ctx->stats.krylov_bytes += (double)ng * n * (4.0 + 16.0) + 10.0 * ng * ne + 6.0 * ne * n;
+                ctx->stats.krylov_bytes += (double)ng * n * (4.0 + 4.0) + 10.0 * ng * ne + 6.0 * ne * n;
             else
                 ctx->stats.krylov_bytes += 8.0 * ((double)ng * n * 3.0 + 2.0 * ng * ne + 2.0 * ne * n);
             if (live == 0) {
@@ -3254,7 +3261,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->wd_p, &ctx->wd_r, &ctx->wd_w, &ctx->wd_c, &ctx->wd_sc, &ctx->wd_sig,
                       &ctx->bf_phi_cm[0], &ctx->bf_phi_cm[1], &ctx->bf_phi_rm[0], &ctx->bf_phi_rm[1],
                       &ctx->bf_phi_rm[2], &ctx->bf_p[0], &ctx->bf_p[1], &ctx->bf_part, &ctx->bf_c, &ctx->eps_dev,
-                      &ctx->bf_c2[0], &ctx->bf_c2[1],
+                      &ctx->bf_c2[0], &ctx->bf_c2[1], &ctx->bf_corr,
                       &ctx->df_b, &ctx->df_z, &ctx->df_c, &ctx->df_u, &ctx->df_f, &ctx->df_v, &ctx->df_r,
                       &ctx->df_du, &ctx->df_dr, &ctx->df_pu, &ctx->df_pr, &ctx->df_dot};
     for (DevBuf *b : bufs) release(*b);

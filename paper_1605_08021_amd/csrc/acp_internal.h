@@ -46,10 +46,12 @@ struct GridDesc {
 };
 
 // ---------------------------------------------------------------- stencil (K1)
-// Y(:,j) = c_lap * Delta_h X(:,j) + (c_v * V + c_0 - shift[j]) X(:,j), column-major.
+// Y(:,j) = c_lap * Delta_h X(:,j) + (c_v * V + c_0 - shift[j]) X(:,j), column-major;
+// with add (FP32, leading dimension ld_add) also + add(:,j).
 hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, double *Y,
                           int ldy, const double *V, double c_lap, double c_v, double c_0,
-                          const double *shift_dev, hipStream_t s);
+                          const double *shift_dev, hipStream_t s, const float *add = nullptr,
+                          long long ld_add = 0);
 
 // ---------------------------------------------------------------- GEMM (FP64 MFMA)
 enum class Op { N, T };
@@ -274,7 +276,7 @@ hipError_t launch_split_bf16_transpose(int m, int n, const double *X, long long 
 // epi 0: split-K over nsplit slices, slice z stored to P[z ldp N + n ldp + m]
 // (FP32; ldp a multiple of 4); epi 1 (nsplit = 1): Wd[n ldw + m] += alpha D.
 // K, lda, ldb multiples of 8; supported (na, nb, epi): (1,1,*), (2,2,0),
-// (3,1,1), (3,2,1), (2,1,1).
+// (3,1,*), (3,2,1), (2,1,1).
 hipError_t gemm_bf16_tn(int na, int nb, int epi, int M, int N, int K, const unsigned short *const *A, long long lda,
                         const unsigned short *const *B, long long ldb, int nsplit, float *P, long long ldp,
                         double *Wd, long long ldw, double alpha, hipStream_t s);

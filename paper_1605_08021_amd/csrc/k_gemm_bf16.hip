@@ -296,6 +296,8 @@ hipError_t gemm_bf16_tn(int na, int nb, int epi, int M, int N, int K, const unsi
         return launch_tn<1, 1, 0>(M, N, K, A, lda, B, ldb, nsplit, P, ldp, Wd, ldw, alpha, s);
     if (na == 3 && nb == 1 && epi == 1)
         return launch_tn<3, 1, 1>(M, N, K, A, lda, B, ldb, 1, P, ldp, Wd, ldw, alpha, s);
+    if (na == 3 && nb == 1 && epi == 0)
+        return launch_tn<3, 1, 0>(M, N, K, A, lda, B, ldb, 1, P, ldp, Wd, ldw, alpha, s);
     if (na == 3 && nb == 2 && epi == 1)
         return launch_tn<3, 2, 1>(M, N, K, A, lda, B, ldb, 1, P, ldp, Wd, ldw, alpha, s);
     if (na == 2 && nb == 1 && epi == 1)

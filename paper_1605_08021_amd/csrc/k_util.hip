@@ -18,7 +18,8 @@ namespace {
 __global__ void stencil_kernel(int dim, int nx, int ny, int ng, int n, const double *__restrict__ X,
                                int ldx, double *__restrict__ Y, int ldy,
                                const double *__restrict__ V, double c_lap_h2, double c_v,
-                               double c_0, const double *__restrict__ shift) {
+                               double c_0, const double *__restrict__ shift, const float *__restrict__ add,
+                               long long ld_add) {
     int row = blockIdx.x * blockDim.x + threadIdx.x;
     int col = blockIdx.y;
     if (row >= ng || col >= n) return;
@@ -50,7 +51,9 @@ __global__ void stencil_kernel(int dim, int nx, int ny, int ng, int n, const dou
     }
     double diag = c_0 - (shift ? shift[col] : 0.0);
     if (c_v != 0.0) diag += c_v * V[row];
-    Y[(long long)col * ldy + row] = c_lap_h2 * lap + diag * xc;
+    double y = c_lap_h2 * lap + diag * xc;
+    if (add) y += (double)add[(long long)col * ld_add + row];
+    Y[(long long)col * ldy + row] = y;
 }
 
 // 2D stencil through LDS: a block computes a 64 x 16 tile of one column
@@ -62,7 +65,8 @@ __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, con
                                                              double *__restrict__ Y, int ldy,
                                                              const double *__restrict__ V, double c_lap_h2,
                                                              double c_v, double c_0,
-                                                             const double *__restrict__ shift) {
+                                                             const double *__restrict__ shift,
+                                                             const float *__restrict__ add, long long ld_add) {
     __shared__ double tile[ST_LY][ST_LX + 1];
     const int col = blockIdx.z;
     const int x0 = blockIdx.x * ST_TX, y0 = blockIdx.y * ST_TY;
@@ -93,7 +97,9 @@ __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, con
         const int row = iy * nx + ix;
         double diag = d0;
         if (c_v != 0.0) diag += c_v * V[row];
-        Y[(long long)col * ldy + row] = c_lap_h2 * (sx + sy) + diag * xc;
+        double y = c_lap_h2 * (sx + sy) + diag * xc;
+        if (add) y += (double)add[(long long)col * ld_add + row];
+        Y[(long long)col * ldy + row] = y;
     }
 }
 
@@ -452,7 +458,7 @@ hipError_t launch_transpose(int m, int n, const double *A, int lda, double *B, i
 
 hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, double *Y, int ldy,
                           const double *V, double c_lap, double c_v, double c_0,
-                          const double *shift_dev, hipStream_t s) {
+                          const double *shift_dev, hipStream_t s, const float *add, long long ld_add) {
     if (n <= 0) return hipSuccess;
     if (g.dim == 2) {
         for (int c0 = 0; c0 < n; c0 += 65535) {   // columns in grid z
@@ -460,13 +466,14 @@ hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, do
             dim3 grid(nblk(g.nx, ST_TX), nblk(g.ny, ST_TY), nc);
             hipLaunchKernelGGL(stencil2d_tile_kernel, grid, dim3(256), 0, s, g.nx, g.ny, X + (long long)c0 * ldx,
                                ldx, Y + (long long)c0 * ldy, ldy, V, c_lap / (g.h * g.h), c_v, c_0,
-                               shift_dev ? shift_dev + c0 : nullptr);
+                               shift_dev ? shift_dev + c0 : nullptr, add ? add + (long long)c0 * ld_add : nullptr,
+                               ld_add);
         }
         return hipGetLastError();
     }
     dim3 grid(nblk(g.ng, 256), n);
     hipLaunchKernelGGL(stencil_kernel, grid, dim3(256), 0, s, g.dim, g.nx, g.ny, g.ng, n, X, ldx,
-                       Y, ldy, V, c_lap / (g.h * g.h), c_v, c_0, shift_dev);
+                       Y, ldy, V, c_lap / (g.h * g.h), c_v, c_0, shift_dev, add, ld_add);
     return hipGetLastError();
 }
 
