@@ -320,14 +320,15 @@ def main():
         tflops = st["krylov_flops"] / (st["ms_solve_kernel"] * 1e-3) / 1e12
         if bf16:
             # the same pair in BF16 (gemm_bf16_tn_kernel<2,2,0>: Phi^T p with both
-            # operands in two terms, <3,1,1>: w += Phi (T - Lambda) C with Phi in
-            # three), timed together with the small kernel between them; achieved =
-            # the same algorithmic 4 N_g N_e flops per column and iteration, against
-            # the dense BF16 peak (the split terms execute 3x as many)
+            # operands in two terms, <3,1,0>: Phi (T - Lambda) C with Phi in three,
+            # stored in FP32 for the stencil to add), timed together with the small
+            # kernel between them; achieved = the same algorithmic 4 N_g N_e flops per
+            # column and iteration, against the dense BF16 peak (the split terms
+            # execute 3x as many)
             roofline = {"bound": "mfma", "achieved": round(tflops, 2), "peak": BF16_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
                         "traffic": measured_traffic(f"config {args.config}", BF16_TRAFFIC_FILE, BF16_SOURCES),
-                        "kernel": "gemm_bf16_tn_kernel<2,2,0> + <3,1,1> (projector GEMMs of the many-orbital "
+                        "kernel": "gemm_bf16_tn_kernel<2,2,0> + <3,1,0> (projector GEMMs of the many-orbital "
                                   "multi-shift CG, v_mfma_f32_16x16x32_bf16, FP32 accumulation)",
                         "algorithmic_flops_per_launch": st["krylov_flops"] / gemm_launches,
                         "executed_mfma_tflops": round(3.0 * tflops, 2),

@@ -93,7 +93,7 @@ struct acp_ctx {
     // its BF16 projector: Phi split in 2 terms (orbital rows, K = grid) and in 3
     // terms (grid rows, K = orbitals), the base p in 2 terms, split-K partials of
     // Phi^T p, the deflation coefficients, the occupied energies
-    DevBuf bf_phi_cm[2], bf_phi_rm[3], bf_p[2], bf_part, bf_c, eps_dev, bf_c2[2], bf_corr;
+    DevBuf bf_phi_cm[2], bf_phi_rm[3], bf_p[2], bf_part, bf_c, eps_dev, bf_c2[2], bf_corr, bf_dotw;
     bool bf_ready = false;
     DevBuf df_b, df_z, df_c, df_u, df_f, df_v, df_r, df_du, df_dr, df_pu, df_pr, df_dot;   // DFPT comparator
     acp_stats stats{};
@@ -931,7 +931,11 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         ENSURE(ctx->bf_part, (size_t)bf_split * ldp * chunk * 4);
         ENSURE(ctx->bf_c, (size_t)nek * chunk * 2);
         ENSURE(ctx->bf_corr, (size_t)ldcorr * chunk * 4);
+        if (ctx->gd.dim == 2) ENSURE(ctx->bf_dotw, stencil_dot_work_doubles(ctx->gd, chunk) * 8);
     }
+    // with the BF16 projector the stencil writes the final w, so p.w comes from
+    // its tiles (2D) instead of another pass over p and w
+    const bool fuse_dot = bf16 && ctx->gd.dim == 2;
     const double Tdef = bf16 ? bf16_deflation_level(ctx) : 0.0;
     // scalars: 7 nb doubles (rr rrn bn al alp btp pw), 6 nc nb doubles, the window
     // coefficients, then ints (colact, act, upd, it, touched, flags, nactive)
@@ -1004,7 +1008,8 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
                                     1.0, s));
                 HIPCHK(hipEventRecord(ctx->ev[7], s));
                 HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, c0, csh, s,
-                                      corr, ldcorr));
+                                      corr, ldcorr, fuse_dot ? pw : nullptr,
+                                      fuse_dot ? dp<double>(ctx->bf_dotw) : nullptr));
             } else {
                 // w = Q (H - s_base) p  (p in range(Q)); the projector GEMMs are timed
                 HIPCHK(launch_stencil(ctx->gd, n, pb_base, ng, w, ng, dp<double>(ctx->veff), -0.5, 1.0, c0, csh, s));
@@ -1015,7 +1020,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
                             Epi::StoreProjector));
                 HIPCHK(hipEventRecord(ctx->ev[7], s));
             }
-            HIPCHK(launch_col_dot(ng, n, pb_base, ng, w, ng, pw, s));
+            if (!fuse_dot) HIPCHK(launch_col_dot(ng, n, pb_base, ng, w, ng, pw, s));
             HIPCHK(launch_fill_i32(ws.nactive, 1, 0, s));
             HIPCHK(wide_step(ng, n, nc, base, dp<double>(ctx->wd_sig), tol, iter, k0, pw, w, ring + (iter % W) * rs,
                              ring + ((iter + 1) % W) * rs, P, Zj, zstride, ws, s, bf16 ? pb : nullptr, ngk));
@@ -1039,7 +1044,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
             // window's end the deferred updates (the wl ring slots read, p_c and x_c
             // of the other nc - 1 shifts read and written)
             // (BF16: the stencil also reads the FP32 correction, 0.5)
-            const double units = 2.0 + 2.0 + 3.0 + 5.0 + (bf16 ? 1.0 : 0.0) + flush_units;
+            const double units = 2.0 + (fuse_dot ? 0.0 : 2.0) + 3.0 + 5.0 + (bf16 ? 1.0 : 0.0) + flush_units;
             ctx->stats.vector_bytes += 8.0 * ng * (double)live_prev * units;
             live_prev = live;
             ctx->stats.solve_kernel_launches += 1;
@@ -3261,7 +3266,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->wd_p, &ctx->wd_r, &ctx->wd_w, &ctx->wd_c, &ctx->wd_sc, &ctx->wd_sig,
                       &ctx->bf_phi_cm[0], &ctx->bf_phi_cm[1], &ctx->bf_phi_rm[0], &ctx->bf_phi_rm[1],
                       &ctx->bf_phi_rm[2], &ctx->bf_p[0], &ctx->bf_p[1], &ctx->bf_part, &ctx->bf_c, &ctx->eps_dev,
-                      &ctx->bf_c2[0], &ctx->bf_c2[1], &ctx->bf_corr,
+                      &ctx->bf_c2[0], &ctx->bf_c2[1], &ctx->bf_corr, &ctx->bf_dotw,
                       &ctx->df_b, &ctx->df_z, &ctx->df_c, &ctx->df_u, &ctx->df_f, &ctx->df_v, &ctx->df_r,
                       &ctx->df_du, &ctx->df_dr, &ctx->df_pu, &ctx->df_pr, &ctx->df_dot};
     for (DevBuf *b : bufs) release(*b);

@@ -47,11 +47,14 @@ struct GridDesc {
 
 // ---------------------------------------------------------------- stencil (K1)
 // Y(:,j) = c_lap * Delta_h X(:,j) + (c_v * V + c_0 - shift[j]) X(:,j), column-major;
-// with add (FP32, leading dimension ld_add) also + add(:,j).
+// with add (FP32, leading dimension ld_add) also + add(:,j); with dot (2D only)
+// dot[j] = X(:,j).Y(:,j) through per-tile partials in dot_work
+// (stencil_dot_work_doubles(g, n)), summed in a fixed order.
 hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, double *Y,
                           int ldy, const double *V, double c_lap, double c_v, double c_0,
                           const double *shift_dev, hipStream_t s, const float *add = nullptr,
-                          long long ld_add = 0);
+                          long long ld_add = 0, double *dot = nullptr, double *dot_work = nullptr);
+size_t stencil_dot_work_doubles(const GridDesc &g, int n);
 
 // ---------------------------------------------------------------- GEMM (FP64 MFMA)
 enum class Op { N, T };

@@ -66,8 +66,10 @@ __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, con
                                                              const double *__restrict__ V, double c_lap_h2,
                                                              double c_v, double c_0,
                                                              const double *__restrict__ shift,
-                                                             const float *__restrict__ add, long long ld_add) {
+                                                             const float *__restrict__ add, long long ld_add,
+                                                             double *__restrict__ dot_part) {
     __shared__ double tile[ST_LY][ST_LX + 1];
+    __shared__ double red[256];
     const int col = blockIdx.z;
     const int x0 = blockIdx.x * ST_TX, y0 = blockIdx.y * ST_TY;
     const double *x = X + (long long)col * ldx;
@@ -81,12 +83,12 @@ __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, con
     __syncthreads();
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int ix = x0 + tx;
-    if (ix >= nx) return;
     const double d0 = c_0 - (shift ? shift[col] : 0.0);
+    double xy = 0.0;   // this thread's share of x.y over the tile
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ly = ty + 4 * r, iy = y0 + ly;
-        if (iy >= ny) break;
+        if (ix >= nx || iy >= ny) break;
         const double xc = tile[ly + 4][tx + 4];
         double sx = fd8(0) * xc, sy = fd8(0) * xc;
 #pragma unroll
@@ -100,7 +102,32 @@ __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, con
         double y = c_lap_h2 * (sx + sy) + diag * xc;
         if (add) y += (double)add[(long long)col * ld_add + row];
         Y[(long long)col * ldy + row] = y;
+        xy += xc * y;
     }
+    if (dot_part) {   // the tile's x.y, summed in a fixed order
+        red[threadIdx.x] = xy;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dot_part[(long long)col * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    }
+}
+
+// out[j] = sum_t part[j m + t] (fixed order), one block per column.
+__global__ __launch_bounds__(256) void col_sum_kernel(int m, const double *part, double *out) {
+    __shared__ double red[256];
+    const double *pc = part + (long long)blockIdx.x * m;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < m; t += 256) acc += pc[t];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 __global__ void scale_copy_kernel(int m, int n, double alpha, const double *X, int ldx, double *Y,
@@ -456,19 +483,27 @@ hipError_t launch_transpose(int m, int n, const double *A, int lda, double *B, i
     return hipGetLastError();
 }
 
+size_t stencil_dot_work_doubles(const GridDesc &g, int n) {
+    return g.dim == 2 ? (size_t)nblk(g.nx, ST_TX) * nblk(g.ny, ST_TY) * n : 0;
+}
+
 hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, double *Y, int ldy,
                           const double *V, double c_lap, double c_v, double c_0,
-                          const double *shift_dev, hipStream_t s, const float *add, long long ld_add) {
+                          const double *shift_dev, hipStream_t s, const float *add, long long ld_add,
+                          double *dot, double *dot_work) {
     if (n <= 0) return hipSuccess;
+    if (dot && g.dim != 2) return hipErrorInvalidValue;
     if (g.dim == 2) {
+        const int tiles = (int)(nblk(g.nx, ST_TX) * nblk(g.ny, ST_TY));
         for (int c0 = 0; c0 < n; c0 += 65535) {   // columns in grid z
             const int nc = std::min(65535, n - c0);
             dim3 grid(nblk(g.nx, ST_TX), nblk(g.ny, ST_TY), nc);
             hipLaunchKernelGGL(stencil2d_tile_kernel, grid, dim3(256), 0, s, g.nx, g.ny, X + (long long)c0 * ldx,
                                ldx, Y + (long long)c0 * ldy, ldy, V, c_lap / (g.h * g.h), c_v, c_0,
                                shift_dev ? shift_dev + c0 : nullptr, add ? add + (long long)c0 * ld_add : nullptr,
-                               ld_add);
+                               ld_add, dot ? dot_work + (long long)c0 * tiles : nullptr);
         }
+        if (dot) hipLaunchKernelGGL(col_sum_kernel, dim3(n), dim3(256), 0, s, tiles, dot_work, dot);
         return hipGetLastError();
     }
     dim3 grid(nblk(g.ng, 256), n);
