@@ -89,7 +89,7 @@ struct acp_ctx {
     int *fc_pin = nullptr;                          // its open-column counts (pinned host, 2 ints)
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
-    DevBuf wd_p, wd_r, wd_w, wd_c, wd_sc, wd_sig;   // multi-shift CG with GEMM projector (many orbitals)
+    DevBuf wd_p, wd_r, wd_w, wd_c, wd_sc, wd_sig, wd_p0;   // multi-shift CG with GEMM projector (many orbitals)
     // its BF16 projector: Phi split in 2 terms (orbital rows, K = grid) and in 3
     // terms (grid rows, K = orbitals), the base p in 2 terms, split-K partials of
     // Phi^T p, the deflation coefficients, the occupied energies
@@ -901,13 +901,15 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
     ENSURE(ctx->wd_sig, (size_t)nc * 8);
     HIPCHK(hipMemcpyAsync(ctx->wd_sig.p, sig.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
     constexpr int W = kWideWindow;
-    // p_c, the residual ring, w (and the BF16 split of the base p, the FP32 correction)
-    const double per_col = (nc + W + 1.0) * ng * 8.0 + (bf16 ? 4.0 * ngk + 4.0 * ldcorr : 0.0);
+    // p_c, the residual ring, w, the base p at the window start (and the BF16
+    // split of the base p, the FP32 correction)
+    const double per_col = (nc + W + 2.0) * ng * 8.0 + (bf16 ? 4.0 * ngk + 4.0 * ldcorr : 0.0);
     int chunk = (int)std::max(16.0, std::min((double)nb, std::floor(kWideBudgetBytes / per_col)));
     if (chunk < nb) chunk = std::max(16, chunk / 16 * 16);
     ENSURE(ctx->wd_p, (size_t)nc * ng * chunk * 8);
     ENSURE(ctx->wd_r, (size_t)W * ng * chunk * 8);
     ENSURE(ctx->wd_w, (size_t)ng * chunk * 8);
+    ENSURE(ctx->wd_p0, (size_t)ng * chunk * 8);
     ENSURE(ctx->wd_c, (size_t)ne * chunk * 8);
     ENSURE(ctx->splitk, (size_t)kSplitSlices * ne * chunk * 8);
     // BF16 form: split-K slices of Phi^T p so that the grid has >= ~1024 workgroups
@@ -946,7 +948,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
     double *sd = dp<double>(ctx->wd_sc);
     int *si = (int *)(sd + nd);
     double *P = dp<double>(ctx->wd_p), *ring = dp<double>(ctx->wd_r), *w = dp<double>(ctx->wd_w);
-    double *C = dp<double>(ctx->wd_c);
+    double *C = dp<double>(ctx->wd_c), *P0 = dp<double>(ctx->wd_p0);
     const double *phi = dp<double>(ctx->phi_cm);
     std::vector<int> it_h((size_t)nc * chunk);
     for (int j0 = 0; j0 < nb; j0 += chunk) {
@@ -990,6 +992,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
         int iter = 0, k0 = 0, live_prev = n;
         for (; iter < ctx->opts.max_iter; ++iter) {
             HIPCHK(hipEventRecord(ctx->ev[8], s));
+            const int k0w = k0;   // the window this iteration belongs to
             const double *csh = col_shift_dev ? col_shift_dev + j0 : nullptr;
             const double c0 = col_shift_dev ? 0.0 : -shifts[base];
             if (bf16) {
@@ -1023,12 +1026,12 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
             if (!fuse_dot) HIPCHK(launch_col_dot(ng, n, pb_base, ng, w, ng, pw, s));
             HIPCHK(launch_fill_i32(ws.nactive, 1, 0, s));
             HIPCHK(wide_step(ng, n, nc, base, dp<double>(ctx->wd_sig), tol, iter, k0, pw, w, ring + (iter % W) * rs,
-                             ring + ((iter + 1) % W) * rs, P, Zj, zstride, ws, s, bf16 ? pb : nullptr, ngk));
+                             ring + ((iter + 1) % W) * rs, P, Zj, zstride, ws, P0, s, bf16 ? pb : nullptr, ngk));
             double flush_units = 0.0;
             if (iter - k0 + 1 == W) {   // window full: the other shifts' deferred updates
-                HIPCHK(wide_flush(ng, n, nc, base, k0, W, ring, P, Zj, zstride, ws, s));
+                HIPCHK(wide_flush(ng, n, nc, base, k0, W, ring, P, Zj, zstride, ws, P0, s));
                 k0 = iter + 1;
-                if (nc > 1) flush_units = W + 4.0 * (nc - 1);
+                flush_units = W + 4.0 * (nc - 1) + 3.0;   // ring, other shifts, base x (and its P0)
             }
             HIPCHK(hipEventRecord(ctx->ev[9], s));
             int live = 0;
@@ -1043,8 +1046,11 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
             // written, rn read; BF16: the two terms of p written, 0.5), and at a
             // window's end the deferred updates (the wl ring slots read, p_c and x_c
             // of the other nc - 1 shifts read and written)
-            // (BF16: the stencil also reads the FP32 correction, 0.5)
-            const double units = 2.0 + (fuse_dot ? 0.0 : 2.0) + 3.0 + 5.0 + (bf16 ? 1.0 : 0.0) + flush_units;
+            // (BF16: the stencil also reads the FP32 correction, 0.5); the base's x moves
+            // at the flush, its update reads and writes p and reads rn (3) and writes
+            // P0 at a window's first iteration
+            const double units = 2.0 + (fuse_dot ? 0.0 : 2.0) + 3.0 + 3.0 + (iter == k0w ? 1.0 : 0.0) +
+                                 (bf16 ? 1.0 : 0.0) + flush_units;
             ctx->stats.vector_bytes += 8.0 * ng * (double)live_prev * units;
             live_prev = live;
             ctx->stats.solve_kernel_launches += 1;
@@ -1062,7 +1068,7 @@ acp_status solve_multishift_wide(acp_ctx *ctx, const double *B, int nb, const st
                 break;
             }
         }
-        HIPCHK(wide_flush(ng, n, nc, base, k0, iter - k0, ring, P, Zj, zstride, ws, s));
+        HIPCHK(wide_flush(ng, n, nc, base, k0, iter - k0, ring, P, Zj, zstride, ws, P0, s));
         int fl = 0;
         HIPCHK(hipMemcpyAsync(it_h.data(), ws.it, (size_t)nc * n * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&fl, ws.flags, 4, hipMemcpyDeviceToHost, s));
@@ -3263,7 +3269,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->vc_g, &ctx->cm_x[0], &ctx->cm_x[1], &ctx->cm_p[0], &ctx->cm_p[1],
                       &ctx->cm_r[0], &ctx->cm_r[1], &ctx->cm_pa[0], &ctx->cm_pa[1], &ctx->cm_state[0],
                       &ctx->cm_state[1], &ctx->cm_map, &ctx->cm_map0,
-                      &ctx->wd_p, &ctx->wd_r, &ctx->wd_w, &ctx->wd_c, &ctx->wd_sc, &ctx->wd_sig,
+                      &ctx->wd_p, &ctx->wd_r, &ctx->wd_w, &ctx->wd_c, &ctx->wd_sc, &ctx->wd_sig, &ctx->wd_p0,
                       &ctx->bf_phi_cm[0], &ctx->bf_phi_cm[1], &ctx->bf_phi_rm[0], &ctx->bf_phi_rm[1],
                       &ctx->bf_phi_rm[2], &ctx->bf_p[0], &ctx->bf_p[1], &ctx->bf_part, &ctx->bf_c, &ctx->eps_dev,
                       &ctx->bf_c2[0], &ctx->bf_c2[1], &ctx->bf_corr, &ctx->bf_dotw,

@@ -229,14 +229,16 @@ hipError_t wide_init(int nb, int nc, const double *bsq, const WideScalars &w, hi
 // N_g x nb (stride N_g nb); X: nc blocks with stride xs.
 // With pb (two arrays, leading dimension ldpb) the base p is also written as
 // its two-term BF16 split (the operand of the reduced-precision projector).
+// The base shift's x is deferred to the flush: at a window's first iteration
+// (iter == k0) its p is kept in P0 (N_g x nb).
 hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, int k0,
                      const double *pw, const double *w_vec, const double *r, double *rn, double *P, double *X,
-                     long long xs, const WideScalars &w, hipStream_t s, unsigned short *const *pb = nullptr,
+                     long long xs, const WideScalars &w, double *P0, hipStream_t s, unsigned short *const *pb = nullptr,
                      long long ldpb = 0);
 // End of a window of wl steps started at k0: the other shifts' p_c and x_c from
 // the ring of residuals (slot q holds r^k for k mod kWideWindow = q, stride N_g nb).
 hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
-                      long long xs, const WideScalars &w, hipStream_t s);
+                      long long xs, const WideScalars &w, const double *P0, hipStream_t s);
 
 // dos[p] = (1 / n_modes) sum_k exp(-(w[p] - w_k)^2 / (2 sigma^2)) / sqrt(2 pi sigma^2),
 // w_k = sign(omega2_k) sqrt(|omega2_k|) (all on the device).

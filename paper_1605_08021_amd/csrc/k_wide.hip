@@ -15,8 +15,9 @@
 // final recurrence residual.
 //
 // Deferred updates: the base shift's search direction p (the stencil's input)
-// and its solution move every iteration; every other shift's p_c and x_c move
-// once per window of kWideWindow iterations.  Within a window started at k0,
+// moves every iteration; its solution, and every other shift's p_c and x_c,
+// move once per window of kWideWindow iterations (the base's p at the window's
+// start is kept for that).  Within a window started at k0,
 //   p_c^k = B p_c^{k0} + sum_{s} gamma_s r^{k0+1+s},
 //   x_c^k = x_c^{k0} + A p_c^{k0} + sum_{s} chi_s r^{k0+1+s},
 // with the coefficients advanced by each step (A += a B, chi += a gamma, then
@@ -126,10 +127,21 @@ __global__ void wide_shift_scalars_kernel(int nb, int nc, int base, const double
     const double beta = rr[j] > 0.0 ? rrn[j] / rr[j] : 0.0;
     const bool live = act[idx] != 0;
     if (c == base) {
-        upd[idx] = (live ? 1 : 0) | 2;
+        // p moves every iteration (it feeds the operator); x is deferred to the
+        // window's flush like the other shifts' (zeta = 1: a_c = alpha, b_c = beta),
+        // its coefficients advancing only while the base shift is live
+        upd[idx] = 2;
         ac[idx] = a;
         zn[idx] = 1.0;
         bc[idx] = beta;
+        if (live) {
+            touched[idx] = 1;
+            co[1] += a * co[0];
+            for (int q = 0; q < wpos; ++q) co[2 + W + q] += a * co[2 + q];
+        }
+        co[0] *= beta;
+        for (int q = 0; q < wpos; ++q) co[2 + q] *= beta;
+        co[2 + wpos] = 1.0;
         if (live) {
             it[idx] = iter + 1;
             if (sqrt(rrn[j]) <= tol * bn[j]) {
@@ -169,12 +181,14 @@ __global__ void wide_shift_scalars_kernel(int nb, int nc, int base, const double
     }
 }
 
-// The base shift every iteration: x_b += a_k p (with the old p), p = r^{k+1} + b_k p.
-// With pb0 the new p is also written as its BF16 split at j ldpb + i (two
-// terms with pb1, else one).
+// The base shift every iteration: p = r^{k+1} + b_k p (its x moves at the
+// window's flush); at a window's first iteration the old p is kept in P0 for
+// that flush.  With pb0 the new p is also written as its BF16 split at
+// j ldpb + i (two terms with pb1, else one).
 __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd, const double *ac,
                                         const double *bc, const double *rn, double *P, double *X,
-                                        unsigned short *pb0, unsigned short *pb1, long long ldpb) {
+                                        unsigned short *pb0, unsigned short *pb1, long long ldpb, double *P0,
+                                        int save_p0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= ng) return;
@@ -182,6 +196,7 @@ __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd
     if (!u) return;
     const long long off = (long long)j * ng + i;
     const double p = P[off];
+    if (save_p0) P0[off] = p;
     if (u & 1) X[off] += ac[base * nb + j] * p;
     if (u & 2) {
         const double pn = rn[off] + bc[base * nb + j] * p;
@@ -194,11 +209,13 @@ __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd
     }
 }
 
-// End of a window of wl steps started at k0: for every other shift touched in
-// it, x_c += A p_c + sum_s chi_s r^{k0+1+s}, p_c = B p_c + sum_s gamma_s r^{k0+1+s}.
+// End of a window of wl steps started at k0: for every shift touched in it,
+// x_c += A p_c + sum_s chi_s r^{k0+1+s}, and for the others than the base
+// p_c = B p_c + sum_s gamma_s r^{k0+1+s} (the base's p_c at the window start is
+// P0; its current p was kept up to date every iteration).
 __global__ void wide_flush_kernel(int ng, int nb, int nc, int base, int k0, int wl, const double *ring,
                                   long long rs, const double *coef, const int *touched, double *P, double *X,
-                                  long long xs) {
+                                  long long xs, const double *P0) {
     constexpr int W = kWideWindow;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
@@ -209,9 +226,9 @@ __global__ void wide_flush_kernel(int ng, int nb, int nc, int base, int k0, int 
 #pragma unroll
     for (int q = 0; q < W; ++q) rv[q] = q < wl ? ring[((k0 + 1 + q) % W) * rs + off] : 0.0;
     for (int c = 0; c < nc; ++c) {
-        if (c == base || !touched[c * nb + j]) continue;
+        if (!touched[c * nb + j]) continue;
         const double *co = coef + (size_t)(c * nb + j) * (2 + 2 * W);
-        const double p = P[c * cs + off];
+        const double p = c == base ? P0[off] : P[c * cs + off];
         double xn = X[c * xs + off] + co[1] * p, pn = co[0] * p;
 #pragma unroll
         for (int q = 0; q < W; ++q) {
@@ -219,7 +236,7 @@ __global__ void wide_flush_kernel(int ng, int nb, int nc, int base, int k0, int 
             pn += co[2 + q] * rv[q];
         }
         X[c * xs + off] = xn;
-        P[c * cs + off] = pn;
+        if (c != base) P[c * cs + off] = pn;
     }
 }
 
@@ -249,7 +266,8 @@ hipError_t wide_init(int nb, int nc, const double *bsq, const WideScalars &w, hi
 
 hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double tol, int iter, int k0,
                      const double *pw, const double *w_vec, const double *r, double *rn, double *P, double *X,
-                     long long xs, const WideScalars &w, hipStream_t s, unsigned short *const *pb, long long ldpb) {
+                     long long xs, const WideScalars &w, double *P0, hipStream_t s, unsigned short *const *pb,
+                     long long ldpb) {
     hipLaunchKernelGGL(wide_alpha_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, (const double *)w.rr, pw,
                        w.colact, w.al, w.flags);
     hipLaunchKernelGGL(wide_residual_kernel, dim3(nb), dim3(256), 0, s, ng, (const double *)w.al,
@@ -261,17 +279,17 @@ hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double
     hipLaunchKernelGGL(wide_base_update_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, base,
                        (const int *)w.upd, (const double *)w.ac, (const double *)w.bc, (const double *)rn,
                        P + (size_t)base * nb * ng, X + (size_t)base * xs, pb ? pb[0] : nullptr,
-                       pb ? pb[1] : nullptr, ldpb);
+                       pb ? pb[1] : nullptr, ldpb, P0, iter == k0 ? 1 : 0);
     hipLaunchKernelGGL(wide_column_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, nc, (const int *)w.act,
                        w.colact, w.rr, (const double *)w.rrn, w.alp, (const double *)w.al, w.btp, w.nactive);
     return hipGetLastError();
 }
 
 hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
-                      long long xs, const WideScalars &w, hipStream_t s) {
-    if (wl <= 0 || nc < 2) return hipSuccess;
+                      long long xs, const WideScalars &w, const double *P0, hipStream_t s) {
+    if (wl <= 0) return hipSuccess;
     hipLaunchKernelGGL(wide_flush_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, nc, base, k0, wl, ring,
-                       (long long)ng * nb, (const double *)w.coef, (const int *)w.touched, P, X, xs);
+                       (long long)ng * nb, (const double *)w.coef, (const int *)w.touched, P, X, xs, P0);
     return hipGetLastError();
 }
 
