@@ -80,10 +80,19 @@ __global__ __launch_bounds__(256) void wide_residual_kernel(int ng, const double
         const double *wj = w + (long long)j * ng;
         const double *rj = r + (long long)j * ng;
         double *rnj = rn + (long long)j * ng;
-        for (int i = threadIdx.x; i < ng; i += 256) {
-            const double v = rj[i] - a * wj[i];
-            rnj[i] = v;
-            acc += v * v;
+        if ((ng & 1) == 0) {   // pairs of rows: 16-byte accesses (even N_g keeps them aligned)
+            for (int i = 2 * threadIdx.x; i < ng; i += 512) {
+                const double2 rv = *(const double2 *)(rj + i), wv = *(const double2 *)(wj + i);
+                const double2 v = make_double2(rv.x - a * wv.x, rv.y - a * wv.y);
+                *(double2 *)(rnj + i) = v;
+                acc += v.x * v.x + v.y * v.y;
+            }
+        } else {
+            for (int i = threadIdx.x; i < ng; i += 256) {
+                const double v = rj[i] - a * wj[i];
+                rnj[i] = v;
+                acc += v * v;
+            }
         }
     }
     red[threadIdx.x] = acc;
@@ -213,9 +222,9 @@ __global__ void wide_base_update_kernel(int ng, int nb, int base, const int *upd
 // x_c += A p_c + sum_s chi_s r^{k0+1+s}, and for the others than the base
 // p_c = B p_c + sum_s gamma_s r^{k0+1+s} (the base's p_c at the window start is
 // P0; its current p was kept up to date every iteration).
-__global__ void wide_flush_kernel(int ng, int nb, int nc, int base, int k0, int wl, const double *ring,
-                                  long long rs, const double *coef, const int *touched, double *P, double *X,
-                                  long long xs, const double *P0) {
+__global__ void wide_flush1_kernel(int ng, int nb, int nc, int base, int k0, int wl, const double *ring,
+                                   long long rs, const double *coef, const int *touched, double *P, double *X,
+                                   long long xs, const double *P0) {
     constexpr int W = kWideWindow;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
@@ -237,6 +246,40 @@ __global__ void wide_flush_kernel(int ng, int nb, int nc, int base, int k0, int 
         }
         X[c * xs + off] = xn;
         if (c != base) P[c * cs + off] = pn;
+    }
+}
+
+// The same with two consecutive rows per thread (16-byte accesses; for even
+// N_g, where every column's pairs of rows are aligned).
+__global__ void wide_flush_kernel(int ng, int nb, int nc, int base, int k0, int wl, const double *ring,
+                                  long long rs, const double *coef, const int *touched, double *P, double *X,
+                                  long long xs, const double *P0) {
+    constexpr int W = kWideWindow;
+    const int i = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int j = blockIdx.y;
+    if (i >= ng) return;
+    const long long off = (long long)j * ng + i;
+    const long long cs = (long long)nb * ng;
+    double2 rv[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q)
+        rv[q] = q < wl ? *(const double2 *)(ring + ((k0 + 1 + q) % W) * rs + off) : make_double2(0.0, 0.0);
+    for (int c = 0; c < nc; ++c) {
+        if (!touched[c * nb + j]) continue;
+        const double *co = coef + (size_t)(c * nb + j) * (2 + 2 * W);
+        const double2 p = *(const double2 *)(c == base ? P0 + off : P + c * cs + off);
+        const double2 x = *(const double2 *)(X + c * xs + off);
+        double2 xn = make_double2(x.x + co[1] * p.x, x.y + co[1] * p.y);
+        double2 pn = make_double2(co[0] * p.x, co[0] * p.y);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            xn.x += co[2 + W + q] * rv[q].x;
+            xn.y += co[2 + W + q] * rv[q].y;
+            pn.x += co[2 + q] * rv[q].x;
+            pn.y += co[2 + q] * rv[q].y;
+        }
+        *(double2 *)(X + c * xs + off) = xn;
+        if (c != base) *(double2 *)(P + c * cs + off) = pn;
     }
 }
 
@@ -288,7 +331,12 @@ hipError_t wide_step(int ng, int nb, int nc, int base, const double *sig, double
 hipError_t wide_flush(int ng, int nb, int nc, int base, int k0, int wl, const double *ring, double *P, double *X,
                       long long xs, const WideScalars &w, const double *P0, hipStream_t s) {
     if (wl <= 0) return hipSuccess;
-    hipLaunchKernelGGL(wide_flush_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, nc, base, k0, wl, ring,
+    if (ng & 1) {
+        hipLaunchKernelGGL(wide_flush1_kernel, dim3((ng + 255) / 256, nb), dim3(256), 0, s, ng, nb, nc, base, k0, wl,
+                           ring, (long long)ng * nb, (const double *)w.coef, (const int *)w.touched, P, X, xs, P0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(wide_flush_kernel, dim3((ng / 2 + 255) / 256, nb), dim3(256), 0, s, ng, nb, nc, base, k0, wl, ring,
                        (long long)ng * nb, (const double *)w.coef, (const int *)w.touched, P, X, xs, P0);
     return hipGetLastError();
 }
