@@ -165,11 +165,172 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(
     }
 }
 
+// The same product with 128 x 128 x 16 tiles for large outputs: each wave owns a
+// 64 x 64 quarter = 4 x 4 MFMA blocks, halving the operand bytes per flop that
+// the tiles request from L2; the epilogue goes through LDS in two halves of 64
+// columns.
+constexpr int BM2 = 128, BN2 = 128, LDA2 = BM2 + 2, LDB2 = BN2 + 2, LDC2 = BM2 + 1;
+constexpr int SMEM2 = 2 * BK * LDA2 > (BN2 / 2) * LDC2 ? 2 * BK * LDA2 : (BN2 / 2) * LDC2;
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(NT, 2) void gemm_f64_big_kernel(
+    int M, int N, int K, double alpha, const double *__restrict__ A, int lda, long long sa,
+    const double *__restrict__ B, int ldb, long long sb, double beta, double *__restrict__ C,
+    int ldc, long long sc, const double *__restrict__ E, int lde, long long se) {
+    __shared__ double smem[SMEM2];
+    double *As = smem;                   // [BK][LDA2]
+    double *Bs = smem + BK * LDA2;       // [BK][LDB2]
+
+    const int bz = blockIdx.z;
+    A += bz * sa;
+    B += bz * sb;
+    C += bz * sc;
+    if (EPI == 1) E += bz * se;
+
+    int bm, bn;
+    {   // XCD-aware tile order, as in gemm_f64_kernel
+        const int mt = gridDim.x, nt = gridDim.y;
+        const int T = mt * nt;
+        const int lin = blockIdx.x + mt * blockIdx.y;
+        const int x = lin & 7, slot = lin >> 3;
+        const int q = T >> 3, rem = T & 7;
+        const int tile = x * q + (x < rem ? x : rem) + slot;
+        if (mt <= nt) {
+            bm = tile % mt;
+            bn = tile / mt;
+        } else {
+            bn = tile % nt;
+            bm = tile / nt;
+        }
+    }
+    const int m0 = bm * BM2, n0 = bn * BN2;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    double ra[8], rb[8];
+    auto load_tiles = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int mm, kk;
+            if (!TA) { mm = t & 127; kk = (t >> 7) + 2 * q; }
+            else     { kk = t & 15; mm = (t >> 4) + 16 * q; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            double v = 0.0;
+            if (gm < M && gk < K) v = TA ? A[gk + (long long)gm * lda] : A[gm + (long long)gk * lda];
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int nn, kk;
+            if (!TB) { kk = t & 15; nn = (t >> 4) + 16 * q; }
+            else     { nn = t & 127; kk = (t >> 7) + 2 * q; }
+            const int gn = n0 + nn, gk = k0 + kk;
+            double v = 0.0;
+            if (gn < N && gk < K) v = TB ? B[gn + (long long)gk * ldb] : B[gk + (long long)gn * ldb];
+            rb[q] = v;
+        }
+    };
+    auto store_tiles = [&]() {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int mm, kk;
+            if (!TA) { mm = t & 127; kk = (t >> 7) + 2 * q; }
+            else     { kk = t & 15; mm = (t >> 4) + 16 * q; }
+            As[kk * LDA2 + mm] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int nn, kk;
+            if (!TB) { kk = t & 15; nn = (t >> 4) + 16 * q; }
+            else     { nn = t & 127; kk = (t >> 7) + 2 * q; }
+            Bs[kk * LDB2 + nn] = rb[q];
+        }
+    };
+
+    load_tiles(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (k0 + BK < K) load_tiles(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int ka = kk + (lane >> 4);
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[ka * LDA2 + wm + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[ka * LDB2 + wn + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+
+    // epilogue through LDS, 64 columns at a time: Cs[col][row]
+    double *Cs = smem;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+        if (wn == 64 * h) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = wm + 16 * i + (lane >> 4) + 4 * e;
+                        const int col = 16 * j + (lane & 15);
+                        Cs[col * LDC2 + row] = acc[i][j][e];
+                    }
+        }
+        __syncthreads();
+        for (int idx = t; idx < BM2 * (BN2 / 2); idx += NT) {
+            const int row = idx & (BM2 - 1);
+            const int col = idx >> 7;
+            const int gm = m0 + row, gn = n0 + 64 * h + col;
+            if (gm < M && gn < N) {
+                double v = alpha * Cs[col * LDC2 + row];
+                double *cp = C + gm + (long long)gn * ldc;
+                if (EPI != 1) {
+                    if (beta != 0.0) v += beta * (*cp);
+                    *cp = v;
+                } else {
+                    *cp += v * E[gm + (long long)gn * lde];
+                }
+            }
+        }
+    }
+}
+
 template <bool TA, bool TB>
 hipError_t dispatch_epi(int m, int n, int k, double alpha, const double *A, int lda, long long sa,
                         const double *B, int ldb, long long sb, double beta, double *C, int ldc,
                         long long sc, int batch, hipStream_t s, Epi epi, const double *E,
                         int lde, long long se) {
+    // large outputs (at least ~2 tiles of 128 x 128 per CU) take the 128-wide tiles
+    const long long big_tiles = (long long)((m + BM2 - 1) / BM2) * ((n + BN2 - 1) / BN2) * batch;
+    if (m >= BM2 && n >= BN2 && big_tiles >= 512) {
+        dim3 grid((m + BM2 - 1) / BM2, (n + BN2 - 1) / BN2, batch);
+        if (epi == Epi::Store)
+            hipLaunchKernelGGL((gemm_f64_big_kernel<TA, TB, 0>), grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sa, B,
+                               ldb, sb, beta, C, ldc, sc, E, lde, se);
+        else if (epi == Epi::StoreProjector)
+            hipLaunchKernelGGL((gemm_f64_big_kernel<TA, TB, 2>), grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sa, B,
+                               ldb, sb, beta, C, ldc, sc, E, lde, se);
+        else
+            hipLaunchKernelGGL((gemm_f64_big_kernel<TA, TB, 1>), grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sa, B,
+                               ldb, sb, beta, C, ldc, sc, E, lde, se);
+        return hipGetLastError();
+    }
     dim3 grid((m + BM - 1) / BM, (n + BN - 1) / BN, batch);
     if (epi == Epi::Store)
         hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, 0>), grid, dim3(NT), 0, s, m, n, k, alpha, A,
