@@ -211,7 +211,7 @@ hipError_t launch_minres_fp64(const KrylovArgs &a, hipStream_t s);
 // ---------------------------------------------------------------- multi-shift CG, many orbitals
 // Scalar state of the wide multi-shift CG (k_wide.hip): per column j (nb) and
 // per (shift c, column j) at c * nb + j.
-constexpr int kWideWindow = 8;   // iterations between the deferred updates of the other shifts
+constexpr int kWideWindow = 16;  // iterations between the deferred updates (flush)
 struct WideScalars {
     double *rr, *rrn, *bn, *al, *alp, *btp;          // nb each
     double *z, *zp, *ac, *zn, *bc, *res;             // nc * nb each
