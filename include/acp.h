@@ -127,6 +127,13 @@ typedef struct {
                                  (Loewdin: Psi (Psi^T Psi)^{-1/2}, the nearest orthonormal
                                  set) when max |Psi^T Psi - I| exceeds 1e-10, e.g. orbitals
                                  stored in reduced precision; 0 = reject them (ACP_EINVAL) */
+    int deterministic;        /* 1 = bitwise reproducible runs: every reduction already runs in
+                                 a fixed order (no floating-point atomics); this also fixes the
+                                 launch shape that the fused multi-shift solver otherwise
+                                 chooses by timing (workgroups per tile, lockstep) and drops
+                                 its suspensions planned from the previous solve, both of which
+                                 regroup partial sums.  (The batch's timed grid and work order
+                                 do not change any tile's arithmetic.) */
 } acp_opts;
 
 typedef struct {

@@ -46,7 +46,7 @@ class AcpOpts(C.Structure):
                 ("isdf_tol", C.c_double), ("node_mode", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("solver", C.c_int), ("precision", C.c_int),
                 ("dyson_max_iter", C.c_int), ("dyson_tol", C.c_double),
-                ("inner_tol", C.c_double), ("use_learned_precond", C.c_int), ("reorthonormalize", C.c_int)]
+                ("inner_tol", C.c_double), ("use_learned_precond", C.c_int), ("reorthonormalize", C.c_int), ("deterministic", C.c_int)]
 
 
 class AcpStats(C.Structure):

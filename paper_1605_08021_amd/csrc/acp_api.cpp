@@ -620,6 +620,15 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     if (tuned != ctx->ms_tuned.end()) SG = ctx->ms_tuned_sg[key];
     if (const char *ov = std::getenv("ACP_MSCG_LOCKSTEP")) SG = std::atoi(ov) ? sg_xcd : 1;
     std::vector<std::pair<int, int>> cands;   // (K, SG)
+    if (K == 0 && ctx->opts.deterministic) {
+        // a fixed shape instead of timing the candidates: the largest group size
+        // that fits, no lockstep
+        int kd = 1;
+        for (int k = 1; k <= kMsMaxGroup; k *= 2)
+            if (k * rhs_tiles <= cap && k <= std::max(1, nblk / 4)) kd = k;
+        K = kd;
+        SG = 1;
+    }
     if (K == 0) {
         for (int k = 1; k <= kMsMaxGroup; k *= 2)
             if (k * rhs_tiles <= cap && k <= std::max(1, nblk / 4)) {
@@ -693,7 +702,7 @@ acp_status solve_multishift(acp_ctx *ctx, int rhs_tiles, const KrylovInputs<T> &
     std::vector<int> stops;
     const int wl = nc <= 8 ? 16 : 8;
     const char *cmp = std::getenv("ACP_MSCG_COMPACT");
-    if (cands.size() == 1 && !prof && !(cmp && !std::atoi(cmp)) && rhs_tiles > 1) {
+    if (cands.size() == 1 && !prof && !(cmp && !std::atoi(cmp)) && rhs_tiles > 1 && !ctx->opts.deterministic) {
         if (const char *ov = std::getenv("ACP_MSCG_STOPS")) {
             int last = 0;
             for (const char *q = ov; *q;) {

@@ -222,3 +222,21 @@ def test_phonon_dos_matches_oracle():
     with pytest.raises(acp.ACPError) as e:
         acp.phonon_dos(w2, n_modes, 0.0, wgrid)
     assert e.value.status == acp.ACP_EINVAL
+
+
+def test_deterministic_option_reproduces_bitwise():
+    """With acp_opts.deterministic the fused multi-shift solver's launch shape is
+    fixed (no timing, no planned suspensions): two contexts, and two calls on
+    one context (the second would otherwise use the autotuned shape and the
+    suspensions planned from the first), give bitwise the same Z and W."""
+    cfg, m, gs, w, v, G, om, K = system(1)
+    dec = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
+    out = []
+    for _ in range(2):
+        ctx = make_ctx(1, tol=1e-10, deterministic=1)
+        for _ in range(2):
+            ctx.compress(to_dev(G), to_dev(om), sel_in=dec.sel)
+            out.append((to_host(ctx.compress_get("z")), to_host(ctx.compress_get("w"))))
+        ctx.close()
+    for Z, W in out[1:]:
+        assert np.array_equal(Z, out[0][0]) and np.array_equal(W, out[0][1])
