@@ -61,6 +61,10 @@ __global__ void stencil_kernel(int dim, int nx, int ny, int ng, int n, const dou
 // staged in LDS (24 x 72 doubles), so that each input is read from memory about
 // 1.7 times instead of 17.
 constexpr int ST_TX = 64, ST_TY = 16, ST_LX = ST_TX + 8, ST_LY = ST_TY + 8;
+// WRAP1: every halo index lies within one period of the grid (nx >= 68 and
+// ny >= 20 for these tiles), so that one conditional add or subtract wraps it;
+// otherwise the remainder is taken.
+template <bool WRAP1>
 __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, const double *__restrict__ X, int ldx,
                                                              double *__restrict__ Y, int ldy,
                                                              const double *__restrict__ V, double c_lap_h2,
@@ -69,20 +73,39 @@ __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, con
                                                              const float *__restrict__ add, long long ld_add,
                                                              double *__restrict__ dot_part) {
     __shared__ double tile[ST_LY][ST_LX + 1];
-    __shared__ double red[256];
+    __shared__ double red[4];
     const int col = blockIdx.z;
     const int x0 = blockIdx.x * ST_TX, y0 = blockIdx.y * ST_TY;
     const double *x = X + (long long)col * ldx;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int ix = x0 + tx;
+    // this thread's potential and correction, read before the barrier so that
+    // the loads overlap the staging of the tile
+    double vr[4];
+    float ar[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int iy = y0 + ty + 4 * r;
+        const bool in = ix < nx && iy < ny;
+        const int row = iy * nx + ix;
+        vr[r] = (in && c_v != 0.0) ? V[row] : 0.0;
+        ar[r] = (in && add) ? add[(long long)col * ld_add + row] : 0.0f;
+    }
     for (int idx = threadIdx.x; idx < ST_LY * ST_LX; idx += 256) {
         const int ly = idx / ST_LX, lx = idx - ly * ST_LX;
-        int gx = (x0 + lx - 4) % nx, gy = (y0 + ly - 4) % ny;
-        if (gx < 0) gx += nx;
-        if (gy < 0) gy += ny;
+        int gx = x0 + lx - 4, gy = y0 + ly - 4;
+        if (WRAP1) {
+            gx += gx < 0 ? nx : (gx >= nx ? -nx : 0);
+            gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
+        } else {
+            gx %= nx;
+            gy %= ny;
+            if (gx < 0) gx += nx;
+            if (gy < 0) gy += ny;
+        }
         tile[ly][lx] = x[gy * nx + gx];
     }
     __syncthreads();
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int ix = x0 + tx;
     const double d0 = c_0 - (shift ? shift[col] : 0.0);
     double xy = 0.0;   // this thread's share of x.y over the tile
 #pragma unroll
@@ -97,21 +120,18 @@ __global__ __launch_bounds__(256) void stencil2d_tile_kernel(int nx, int ny, con
             sy += fd8(k) * (tile[ly + 4 + k][tx + 4] + tile[ly + 4 - k][tx + 4]);
         }
         const int row = iy * nx + ix;
-        double diag = d0;
-        if (c_v != 0.0) diag += c_v * V[row];
-        double y = c_lap_h2 * (sx + sy) + diag * xc;
-        if (add) y += (double)add[(long long)col * ld_add + row];
+        const double y = c_lap_h2 * (sx + sy) + (d0 + c_v * vr[r]) * xc + (double)ar[r];
         Y[(long long)col * ldy + row] = y;
         xy += xc * y;
     }
-    if (dot_part) {   // the tile's x.y, summed in a fixed order
-        red[threadIdx.x] = xy;
+    if (dot_part) {   // the tile's x.y: butterfly within each wave, then the 4 waves in order
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) xy += __shfl_xor(xy, o, 64);
+        if (tx == 0) red[ty] = xy;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) dot_part[(long long)col * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        if (threadIdx.x == 0)
+            dot_part[(long long)col * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] =
+                (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 
@@ -498,7 +518,9 @@ hipError_t launch_stencil(const GridDesc &g, int n, const double *X, int ldx, do
         for (int c0 = 0; c0 < n; c0 += 65535) {   // columns in grid z
             const int nc = std::min(65535, n - c0);
             dim3 grid(nblk(g.nx, ST_TX), nblk(g.ny, ST_TY), nc);
-            hipLaunchKernelGGL(stencil2d_tile_kernel, grid, dim3(256), 0, s, g.nx, g.ny, X + (long long)c0 * ldx,
+            const bool wrap1 = g.nx >= ST_TX + 4 && g.ny >= ST_TY + 4;
+            hipLaunchKernelGGL(wrap1 ? stencil2d_tile_kernel<true> : stencil2d_tile_kernel<false>, grid, dim3(256),
+                               0, s, g.nx, g.ny, X + (long long)c0 * ldx,
                                ldx, Y + (long long)c0 * ldy, ldy, V, c_lap / (g.h * g.h), c_v, c_0,
                                shift_dev ? shift_dev + c0 : nullptr, add ? add + (long long)c0 * ld_add : nullptr,
                                ld_add, dot ? dot_work + (long long)c0 * tiles : nullptr);

@@ -30,6 +30,27 @@ def test_apply_h_matches_oracle(cid):
     ctx.close()
 
 
+@pytest.mark.parametrize("shape", [(96, 80), (150, 41), (68, 20), (67, 19)])
+def test_apply_h_2d_tiles_wrap(shape):
+    """2D grids ragged against the 64 x 16 stencil tiles: from 68 x 20 up the
+    halo wraps with one add or subtract, below it by the remainder (67 x 19)."""
+    from paper_1605_08021_amd import acp
+    g = Grid(shape, 0.5)
+    rng = np.random.default_rng(8)
+    V = rng.standard_normal(g.n_grid)
+    phi, _ = np.linalg.qr(rng.standard_normal((g.n_grid, 5)))
+    ctx = acp.Context(dict(dim=2, n=shape, h=0.5, kappa=0.05, eps0=1.0, occ=2.0),
+                      dict(n_cheb=2, n_mu=8, sketch_r=2), to_dev(phi), np.linspace(-1, -0.5, 5),
+                      to_dev(V))
+    X = rng.standard_normal((g.n_grid, 7))
+    sh = rng.standard_normal(7)
+    Y = to_host(ctx.apply_h(to_dev(X), sh))
+    from oracle.model import laplacian_apply
+    ref = -0.5 * laplacian_apply(g, X) + V[:, None] * X - sh[None, :] * X
+    assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max()
+    ctx.close()
+
+
 def test_apply_h_2d_ragged():
     """2D grid with sides that are not multiples of any tile size."""
     from paper_1605_08021_amd import acp
