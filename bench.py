@@ -389,8 +389,8 @@ def main():
         "preconditioner_training": train_info,
         "iters_min_max_last_solve": [st["iters_min"], st["iters_max"]],
         "phase_ms_per_step": {k: round(st[k] / args.steps, 2) for k in
-                              ("ms_isdf", "ms_rhs", "ms_solve", "ms_w", "ms_dyson_small",
-                               "ms_dynmat")},
+                              ("ms_isdf", "ms_rhs", "ms_solve", "ms_residual", "ms_w",
+                               "ms_dyson_small", "ms_dynmat")},
         "roofline": roofline,
     }
     if wide:

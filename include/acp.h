@@ -158,6 +158,9 @@ typedef struct {
                                     shifted updates) for the live columns (accumulated) */
     double ms_vectors;           /* their time: each iteration's stretch (HIP events) minus the
                                     projector pair (accumulated) */
+    double ms_residual;          /* the FP64 true-residual pass after each solve (in the BF16
+                                    form with the projection of the solutions onto range(Q)),
+                                    HIP events (accumulated) */
 } acp_stats;
 
 typedef struct acp_ctx acp_ctx;

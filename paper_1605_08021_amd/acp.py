@@ -59,7 +59,7 @@ class AcpStats(C.Structure):
                 ("solve_kernel_launches", C.c_int64), ("d_asymmetry", C.c_double),
                 ("krylov_bytes", C.c_double), ("krylov_flops", C.c_double),
                 ("krylov_group", C.c_int), ("n_mu", C.c_int), ("vector_bytes", C.c_double),
-                ("ms_vectors", C.c_double)]
+                ("ms_vectors", C.c_double), ("ms_residual", C.c_double)]
 
 
 class AcpEigOpts(C.Structure):

@@ -1155,6 +1155,7 @@ acp_status true_residual(acp_ctx *ctx, int n, const double *shifts_dev, const do
                          const double *X, double *max_rel) {
     const int ng = ctx->ng;
     ENSURE(ctx->tmp1, (size_t)ng * n * 8);
+    HIPCHK(hipEventRecord(ctx->ev[8], ctx->stream));
     CHECK(apply_operator(ctx, n, shifts_dev, X, dp<double>(ctx->tmp1)));
     ENSURE(ctx->dy_norm, (size_t)2 * n * 8);
     double *rn = dp<double>(ctx->dy_norm), *bn = rn + n;
@@ -1162,7 +1163,9 @@ acp_status true_residual(acp_ctx *ctx, int n, const double *shifts_dev, const do
     HIPCHK(launch_col_sqnorm(ng, n, B, ng, bn, ctx->stream));
     std::vector<double> h(2 * n);
     HIPCHK(hipMemcpyAsync(h.data(), rn, 2 * n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev[9], ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->stats.ms_residual += event_ms(ctx->ev[8], ctx->ev[9]);
     double m = 0.0;
     for (int j = 0; j < n; ++j)
         if (h[n + j] > 0.0) m = std::max(m, std::sqrt(h[j] / h[n + j]));
@@ -1206,13 +1209,17 @@ acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std
                                 double *Z, long long zstride, double *max_rel, bool project) {
     const int ng = ctx->ng, nc = (int)shifts.size();
     hipStream_t s = ctx->stream;
-    const int chunk = std::max(16, std::min(nb, (int)std::floor(4.0 * 1024 * 1024 * 1024 / (8.0 * ng))));
+    // columns per pass: at most 4 GiB of residuals, in passes of equal size
+    const int cmax = std::max(16, std::min(nb, (int)std::floor(4.0 * 1024 * 1024 * 1024 / (8.0 * ng))));
+    const int passes = (nb + cmax - 1) / cmax;
+    const int chunk = std::max(16, (nb + passes - 1) / passes);
     ENSURE(ctx->tmp1, (size_t)ng * chunk * 8);
     ENSURE(ctx->dy_norm, (size_t)3 * chunk * 8);
     ENSURE(ctx->dy_s, (size_t)chunk * 8);
     double *rn = dp<double>(ctx->dy_norm), *bn = rn + chunk, *pn = bn + chunk;
     std::vector<double> h((size_t)3 * chunk), sh(chunk);
     double m = 0.0;
+    HIPCHK(hipEventRecord(ctx->ev[8], s));
     for (int c = 0; c < nc; ++c)
         for (int j0 = 0; j0 < nb; j0 += chunk) {
             const int n = std::min(chunk, nb - j0);
@@ -1237,6 +1244,9 @@ acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std
                     m = std::max(m, std::sqrt(r2 / h[chunk + j]));
                 }
         }
+    HIPCHK(hipEventRecord(ctx->ev[9], s));
+    HIPCHK(hipEventSynchronize(ctx->ev[9]));
+    ctx->stats.ms_residual += event_ms(ctx->ev[8], ctx->ev[9]);
     *max_rel = m;
     return ACP_OK;
 }
