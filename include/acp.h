@@ -437,8 +437,9 @@ acp_status acp_scf(const acp_grid *grid, const double *m, const double *rho0, in
 
 /* acp_gesv -- X = A^{-1} B for a dense FP64 matrix (the small solve
  * (I - T) S = G(Pi, :) of each Dyson iteration, Eq. (3.13)): blocked LU with
- * partial pivoting up to n = 1024 (32-column panels factored in registers,
- * GEMM trailing updates), Gauss-Jordan with partial pivoting above.
+ * partial pivoting up to n = 4096 (panels factored in registers: 8 columns while
+ * more than 1024 rows remain, 32 after; GEMM trailing updates), Gauss-Jordan
+ * with partial pivoting above.
  * A dev n x n (lda >= n) and B dev n x nrhs (ldb >= n) are overwritten (B <- X);
  * synchronises the stream. */
 acp_status acp_gesv(int n, int nrhs, double *A, int lda, double *B, int ldb, void *stream);

@@ -380,8 +380,9 @@ hipError_t gauss_jordan_solve(int n, int nrhs, double *A, int lda, double *B, in
                               int *piv_scratch, hipStream_t s);
 // A X = B (A n x n, B n x nrhs, column-major, both overwritten: B <- X) by a
 // blocked LU with partial pivoting; pinfo: device scratch of lu_pinfo_ints(n)
-// ints.  B = A + n lda with ldb = lda lets one GEMM update both.  Falls back to
-// Gauss-Jordan above 1024 unknowns.
+// ints.  B = A + n lda with ldb = lda lets one GEMM update both.  Panels of 8
+// columns while more than 1024 rows remain, 32 after; Gauss-Jordan above 4096
+// unknowns.
 size_t lu_pinfo_ints(int n);
 hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *pinfo, hipStream_t s);
 // Symmetric eigenvalues by Householder reduction to tridiagonal form and Sturm

@@ -689,7 +689,8 @@ hipError_t launch_isdf_l11_inverse(int n, const int *sel, const double *L, int n
 // and the trailing matrix and B are updated by a GEMM on the matrix cores.
 // Columns left of a panel are not permuted: B is eliminated along with A, so
 // the multipliers of earlier panels are never used again.  Back substitution
-// then proceeds by blocks.
+// then proceeds by blocks of LU_NB rows (U does not depend on where the panels
+// began).  Panels of more than LU_MAXM rows go through lu_panel_tall_kernel.
 constexpr int LU_NB = 32;
 constexpr int LU_MAXM = 1024;     // panel rows, one per thread
 constexpr int LU_NT = 1024;
@@ -792,6 +793,126 @@ __global__ __launch_bounds__(LU_NT) void lu_panel_kernel(int m, int nb, double *
     if (t == 0) pinfo[LU_PI_ND] = sh.nd;
 }
 
+// Panels of more than LU_MAXM rows (up to LU_TALL_MAXM): LU_TALL_NB columns,
+// each thread keeping the LU_TALL_R rows t, t + LU_NT, ... in registers; the
+// same pivot rule (largest magnitude, ties to the smallest row) and the same
+// permutation record as lu_panel_kernel.  Launched with LU_NT threads.
+constexpr int LU_TALL_NB = 8;
+constexpr int LU_TALL_R = 4;
+constexpr int LU_TALL_MAXM = LU_TALL_R * LU_NT;
+
+struct LuTallShared {
+    double rows[2][2][LU_TALL_NB];   // [parity][row J | pivot row]
+    double wv[2][LU_NT / 64];
+    int wi[2][LU_NT / 64];
+    int idx[LU_TALL_MAXM];
+    int nd;
+};
+
+__global__ __launch_bounds__(LU_NT) void lu_panel_tall_kernel(int m, int nb, double *A, int lda, int *pinfo) {
+    __shared__ LuTallShared sh;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int nw = LU_NT / 64;
+    double P[LU_TALL_R][LU_TALL_NB];
+#pragma unroll
+    for (int r = 0; r < LU_TALL_R; ++r) {
+        const int i = t + LU_NT * r;
+#pragma unroll
+        for (int c = 0; c < LU_TALL_NB; ++c) P[r][c] = (i < m && c < nb) ? A[i + (long long)c * lda] : 0.0;
+    }
+    for (int i = t; i < m; i += LU_NT) sh.idx[i] = i;
+    if (t == 0) sh.nd = 0;
+    __syncthreads();
+#pragma unroll
+    for (int J = 0; J < LU_TALL_NB; ++J) {
+        if (J < nb) {
+            const int par = J & 1;
+            double bv = -1.0;
+            int bi = 0x7fffffff;
+#pragma unroll
+            for (int r = 0; r < LU_TALL_R; ++r) {
+                const int i = t + LU_NT * r;
+                if (i < m && i >= J && fabs(P[r][J]) > bv) {
+                    bv = fabs(P[r][J]);
+                    bi = i;
+                }
+            }
+            wave_argmax(bv, bi);
+            if (lane == 63) {
+                sh.wv[par][wave] = bv;
+                sh.wi[par][wave] = bi;
+            }
+            __syncthreads();
+            double b = lane < nw ? sh.wv[par][lane] : -2.0;
+            int p = lane < nw ? sh.wi[par][lane] : 0x7fffffff;
+            wave_argmax(b, p);
+            p = __builtin_amdgcn_readlane(p, 63);
+            if (p >= m) p = J;   // no comparable entry (NaN column): no exchange
+            const int pt = p % LU_NT, pr = p / LU_NT;
+            if (t == J) {   // row J < LU_TALL_NB is slot 0 of thread J
+#pragma unroll
+                for (int c = 0; c < LU_TALL_NB; ++c) sh.rows[par][0][c] = P[0][c];
+            }
+            if (t == pt) {
+#pragma unroll
+                for (int r = 0; r < LU_TALL_R; ++r)
+                    if (r == pr) {
+#pragma unroll
+                        for (int c = 0; c < LU_TALL_NB; ++c) sh.rows[par][1][c] = P[r][c];
+                    }
+            }
+            if (t == 0) {
+                const int a = sh.idx[J];
+                sh.idx[J] = sh.idx[p];
+                sh.idx[p] = a;
+            }
+            __syncthreads();
+            if (p != J) {
+                if (t == J) {
+#pragma unroll
+                    for (int c = 0; c < LU_TALL_NB; ++c) P[0][c] = sh.rows[par][1][c];
+                }
+                if (t == pt) {
+#pragma unroll
+                    for (int r = 0; r < LU_TALL_R; ++r)
+                        if (r == pr) {
+#pragma unroll
+                            for (int c = 0; c < LU_TALL_NB; ++c) P[r][c] = sh.rows[par][0][c];
+                        }
+                }
+            }
+            const double piv = sh.rows[par][1][J];
+#pragma unroll
+            for (int r = 0; r < LU_TALL_R; ++r) {
+                const int i = t + LU_NT * r;
+                if (i < m && i > J) {
+                    const double l = P[r][J] / piv;
+                    P[r][J] = l;
+#pragma unroll
+                    for (int c = J + 1; c < LU_TALL_NB; ++c) P[r][c] -= l * sh.rows[par][1][c];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < LU_TALL_R; ++r) {
+        const int i = t + LU_NT * r;
+#pragma unroll
+        for (int c = 0; c < LU_TALL_NB; ++c)
+            if (i < m && c < nb) A[i + (long long)c * lda] = P[r][c];
+    }
+    __syncthreads();
+    if (t < nb) pinfo[LU_PI_TOP + t] = sh.idx[t];
+    for (int i = t; i < m; i += LU_NT)
+        if (i >= nb && sh.idx[i] != i) {
+            const int e = atomicAdd(&sh.nd, 1);   // at most nb displaced rows
+            pinfo[LU_PI_DST + e] = i;
+            pinfo[LU_PI_SRC + e] = sh.idx[i];
+        }
+    __syncthreads();
+    if (t == 0) pinfo[LU_PI_ND] = sh.nd;
+}
+
 // col[0..nb) = x[0..nb) for nb <= LU_NB; a partial block goes through the
 // caller's LDS staging area (one column per thread).
 __device__ __forceinline__ void store_block(double *col, const double (&x)[LU_NB], int nb,
@@ -877,18 +998,28 @@ __global__ __launch_bounds__(64) void lu_trsm_upper_kernel(int nrhs, int r0, int
     store_block(col, x, nb, stage);
 }
 
-size_t lu_pinfo_ints(int n) { return (size_t)((n + LU_NB - 1) / LU_NB) * LU_PINFO; }
+// Panels: LU_TALL_NB columns while more than LU_MAXM rows remain, LU_NB after.
+size_t lu_pinfo_ints(int n) {
+    const int tall = n > LU_MAXM ? (n - LU_MAXM + LU_TALL_NB - 1) / LU_TALL_NB : 0;
+    return (size_t)(tall + (LU_MAXM + LU_NB - 1) / LU_NB + 1) * LU_PINFO;
+}
 
 hipError_t lu_solve(int n, int nrhs, double *A, int lda, double *B, int ldb, int *pinfo, hipStream_t s) {
-    if (n > LU_MAXM) return gauss_jordan_solve(n, nrhs, A, lda, B, ldb, nullptr, s);
+    if (n > LU_TALL_MAXM) return gauss_jordan_solve(n, nrhs, A, lda, B, ldb, nullptr, s);
     hipError_t e;
     // B stored right after A with the same leading dimension: one GEMM updates both
     const bool joint = B == A + (long long)n * lda && ldb == lda;
-    for (int k0 = 0; k0 < n; k0 += LU_NB) {
-        const int nb = std::min(LU_NB, n - k0), m = n - k0;
-        int *pi = pinfo + (size_t)(k0 / LU_NB) * LU_PINFO;
-        hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3((m + 63) / 64 * 64), 0, s, m, nb, A + k0 + (long long)k0 * lda,
-                           lda, pi);
+    int npanel = 0;
+    for (int k0 = 0, nb = 0; k0 < n; k0 += nb) {
+        const int m = n - k0;
+        nb = std::min(m > LU_MAXM ? LU_TALL_NB : LU_NB, m);
+        int *pi = pinfo + (size_t)(npanel++) * LU_PINFO;
+        if (m > LU_MAXM)
+            hipLaunchKernelGGL(lu_panel_tall_kernel, dim3(1), dim3(LU_NT), 0, s, m, nb, A + k0 + (long long)k0 * lda,
+                               lda, pi);
+        else
+            hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3((m + 63) / 64 * 64), 0, s, m, nb,
+                               A + k0 + (long long)k0 * lda, lda, pi);
         const int ncols = (n - k0 - nb) + nrhs;
         hipLaunchKernelGGL(lu_rowblock_kernel, dim3(nblk(ncols, 64)), dim3(64), 0, s, n, nrhs, k0, nb, A, lda,
                            B, ldb, (const int *)pi);

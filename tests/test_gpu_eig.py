@@ -41,11 +41,12 @@ def test_syev_matches_library(n):
     assert np.array_equal(w2, w)
 
 
-@pytest.mark.parametrize("n", [600, 1025, 4096])
+@pytest.mark.parametrize("n", [600, 1025, 1500, 4096, 4097])
 def test_gesv_matches_library(n):
-    """Dense solve of the Dyson step: blocked LU (n <= 1024) and Gauss-Jordan
-    above, against numpy.linalg.solve on a nonsymmetric, well-conditioned
-    matrix with a pivoting pattern (small diagonal)."""
+    """Dense solve of the Dyson step: blocked LU (32-column panels up to 1024
+    rows, 8-column panels of up to 4096 rows before them) and Gauss-Jordan
+    above 4096, against numpy.linalg.solve on a nonsymmetric,
+    well-conditioned matrix with a pivoting pattern (small diagonal)."""
     from paper_1605_08021_amd import acp
     rng = np.random.default_rng(n)
     A = rng.standard_normal((n, n)) / np.sqrt(n) + np.eye(n) * 0.01
