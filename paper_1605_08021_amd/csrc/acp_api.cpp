@@ -86,6 +86,7 @@ struct acp_ctx {
     size_t pin_bytes = 0;
     DevBuf nn_wf[4], nn_wb[4], nn_act[4], nn_g[4];
     DevBuf fc_r, fc_z, fc_p, fc_q, fc_sc, fc_idx;   // flexible CG
+    DevBuf rf_idx, rf_sh;                           // FP32 refinement: open columns, their shifts
     int *fc_pin = nullptr;                          // its open-column counts (pinned host, 2 ints)
     DevBuf dy_v, dy_t, dy_s, dy_g, dy_gk, dy_norm, dy_piv, vc_g;
     DevBuf dm_phi, dm_k, dm_mass, dm_d, dm_eig, dm_work, dm_asym, splitk;
@@ -465,7 +466,6 @@ acp_status ms_run_phased(acp_ctx *ctx, MsArgsT<T> a, int K0, int SG0, const std:
     if (ctx->pin_bytes < pin_need) {
         HIPCHK(hipStreamSynchronize(s));   // no copy of an earlier solve still reads it
         if (ctx->pin) (void)hipHostFree(ctx->pin);
-    if (ctx->fc_pin) (void)hipHostFree(ctx->fc_pin);
         ctx->pin = nullptr;
         ctx->pin_bytes = 0;
         HIPCHK(hipHostMalloc(&ctx->pin, pin_need, hipHostMallocDefault));
@@ -1266,8 +1266,8 @@ acp_status ensure_phi32(acp_ctx *ctx) {
 // columns, shifts per column in shifts_dev, padded to a multiple of 16) holds
 // the FP32 first solve.  Repeat: R = B - A X in FP64; stop once every column has
 // ||R_j|| <= tol ||B_j||; otherwise solve A D = R with FP32 storage to inner_tol
-// for the columns still above tol (the others get a zero right-hand side and
-// stop at once) and accumulate X += D in FP64.
+// for the columns still above tol, gathered into as few 16-column tiles as they
+// fill, and accumulate X += D into their columns in FP64.
 constexpr int kMaxRefine = 8;
 acp_status refine_fp32(acp_ctx *ctx, int n, const double *shifts_dev, const double *B, double *X,
                        int *flags_or, double *max_rel) {
@@ -1278,12 +1278,19 @@ acp_status refine_fp32(acp_ctx *ctx, int n, const double *shifts_dev, const doub
     CHECK(ensure_phi32(ctx));
     ENSURE(ctx->tmp1, (size_t)ng * n * 8);
     ENSURE(ctx->dy_norm, (size_t)2 * n * 8);
-    ENSURE(ctx->colmask, (size_t)npad * 8);
     ENSURE(ctx->krhs32, (size_t)npad * ng * 4);
+    ENSURE(ctx->tmp2, (size_t)ng * n * 8);
+    ENSURE(ctx->rf_idx, (size_t)n * 4);
+    ENSURE(ctx->rf_sh, (size_t)(npad + n) * 8);
     double *AX = dp<double>(ctx->tmp1);
     double *rn = dp<double>(ctx->dy_norm), *bn = rn + n;
     HIPCHK(launch_col_sqnorm(ng, n, B, ng, bn, s));
-    std::vector<double> h(2 * n), mask(npad, 0.0);
+    std::vector<double> h(2 * n), mask(npad, 0.0), shh(n), shc(npad), ones(n, 1.0);
+    std::vector<int> ord(n);
+    HIPCHK(hipMemcpyAsync(shh.data(), shifts_dev, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double *shc_dev = dp<double>(ctx->rf_sh), *ones_dev = shc_dev + npad;
+    HIPCHK(hipMemcpyAsync(ones_dev, ones.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
     double m = 0.0;
     for (int ref = 0;; ++ref) {
         CHECK(apply_operator(ctx, n, shifts_dev, X, AX));
@@ -1315,15 +1322,26 @@ acp_status refine_fp32(acp_ctx *ctx, int n, const double *shifts_dev, const doub
             CHECK(phi_t_times(ctx, n, AX, ng, C));
             HIPCHK(gemm(Op::N, Op::N, ng, n, ctx->ne, -1.0, phi, ng, 0, C, ctx->ne, 0, 1.0, AX, ng, 0, 1, s));
         }
-        HIPCHK(hipMemcpyAsync(ctx->colmask.p, mask.data(), (size_t)npad * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_to_tiled_f32(ng, n, npad, AX, ng, dp<double>(ctx->colmask),
-                                   dp<float>(ctx->krhs32), s));
+        // the open columns only, gathered into as few 16-column tiles as they fill
+        // (a tile runs as long as its slowest column), with their own shifts
+        int no = 0;
+        for (int j = 0; j < n; ++j)
+            if (mask[j] != 0.0) ord[no++] = j;
+        const int ntc = (no + kTile - 1) / kTile, npc = ntc * kTile;
+        for (int j = 0; j < npc; ++j) shc[j] = shh[ord[std::min(j, no - 1)]];
+        int *idx = dp<int>(ctx->rf_idx);
+        double *Rc = dp<double>(ctx->tmp2);
+        HIPCHK(hipMemcpyAsync(idx, ord.data(), (size_t)no * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(shc_dev, shc.data(), (size_t)npc * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_col_gather(ng, no, AX, ng, idx, Rc, ng, s));
+        HIPCHK(launch_to_tiled_f32(ng, no, npc, Rc, ng, nullptr, dp<float>(ctx->krhs32), s));
         KrylovInputs<float> in{dp<float>(ctx->phi_rm32), dp<float>(ctx->phi_cm32),
                                dp<float>(ctx->krhs32)};
         int f = 0;
-        CHECK(solve_tiled<float>(ctx, ntiles, ntiles, shifts_dev, in, ctx->opts.inner_tol, &f));
+        CHECK(solve_tiled<float>(ctx, ntc, ntc, shc_dev, in, ctx->opts.inner_tol, &f));
         *flags_or |= f & ~1;   // an inner solve short of inner_tol is judged by the next residual
-        HIPCHK(launch_from_tiled_add(ng, n, dp<double>(ctx->kx), X, ng, s));
+        HIPCHK(launch_from_tiled(ng, no, dp<double>(ctx->kx), Rc, ng, s));
+        HIPCHK(launch_col_axpy_scatter(ng, no, ones_dev, Rc, ng, idx, X, ng, s));   // X += D
         ctx->stats.refinements += 1;
     }
     // the solution of Eq. (3.6) lies in range(Q); the FP32 passes leave an occupied
@@ -3285,6 +3303,7 @@ void acp_destroy(acp_ctx *ctx) {
                       &ctx->nn_act[0], &ctx->nn_act[1], &ctx->nn_act[2], &ctx->nn_act[3],
                       &ctx->nn_g[0], &ctx->nn_g[1], &ctx->nn_g[2], &ctx->nn_g[3],
                       &ctx->fc_r, &ctx->fc_z, &ctx->fc_p, &ctx->fc_q, &ctx->fc_sc, &ctx->fc_idx, &ctx->dy_piv,
+                      &ctx->rf_idx, &ctx->rf_sh,
                       &ctx->vc_g, &ctx->cm_x[0], &ctx->cm_x[1], &ctx->cm_p[0], &ctx->cm_p[1],
                       &ctx->cm_r[0], &ctx->cm_r[1], &ctx->cm_pa[0], &ctx->cm_pa[1], &ctx->cm_state[0],
                       &ctx->cm_state[1], &ctx->cm_map, &ctx->cm_map0,

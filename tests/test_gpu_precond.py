@@ -337,3 +337,31 @@ def test_2d_network_transfers_to_a_larger_lattice():
     assert gain > 1.5
     ctx_a.close()
     ctx_b.close()
+
+
+def test_flexible_cg_after_a_multishift_solve_on_one_context():
+    """The host-driven CG's pinned open-column counters outlive a compression on
+    the same context (whose fused multi-shift solve allocates its own pinned
+    staging): the plain flexible CG run before and after it gives the same
+    answer bit for bit, at the FP64 tolerance."""
+    from oracle import acp as OA, krylov as OK
+    cfg, m, gs, w, v, G, om, K = system(1)
+    dec = OA.isdf_qrcp(gs.phi, G, om, cfg.n_mu)
+    nodes, _ = OA.shifts_and_weights(gs.eps[:gs.n_e], cfg.n_cheb)
+    R0 = OA.rhs(gs.phi, dec.xi)
+    cols = np.arange(0, 12)
+    B = np.concatenate([R0[:, cols]] * len(nodes), axis=1)
+    sh = np.repeat(nodes, len(cols))
+    op = OK.make_operator(m, gs.veff, gs.phi, sh)
+    ctx = make_ctx(1, tol=1e-8, max_iter=5000)
+    ctx.set_opts(use_learned_precond=2)
+    Xa = to_host(ctx.sternheimer(sh, to_dev(B))[0])
+    ctx.set_opts(use_learned_precond=0)
+    ctx.compress(to_dev(G), to_dev(om))
+    ctx.set_opts(use_learned_precond=2)
+    Xb = to_host(ctx.sternheimer(sh, to_dev(B))[0])
+    tr = OK.true_residual(op, Xb, B).max()
+    print(f"[fcg after compress] true residual {tr:.2e}", flush=True)
+    assert np.array_equal(Xa, Xb)
+    assert tr <= 1e-8
+    ctx.close()
