@@ -1209,8 +1209,8 @@ acp_status true_residual_blocks(acp_ctx *ctx, const double *B, int nb, const std
                                 double *Z, long long zstride, double *max_rel, bool project) {
     const int ng = ctx->ng, nc = (int)shifts.size();
     hipStream_t s = ctx->stream;
-    // columns per pass: at most 4 GiB of residuals, in passes of equal size
-    const int cmax = std::max(16, std::min(nb, (int)std::floor(4.0 * 1024 * 1024 * 1024 / (8.0 * ng))));
+    // columns per pass: at most 8 GiB of residuals, in passes of equal size
+    const int cmax = std::max(16, std::min(nb, (int)std::floor(8.0 * 1024 * 1024 * 1024 / (8.0 * ng))));
     const int passes = (nb + cmax - 1) / cmax;
     const int chunk = std::max(16, (nb + passes - 1) / passes);
     ENSURE(ctx->tmp1, (size_t)ng * chunk * 8);
